@@ -1,0 +1,160 @@
+"""CPU oracle for s-line graphs — TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. The GPU library never calls it and
+shares no code with it. The arithmetic lives in ``slg_oracle.c`` (plain C,
+OpenMP over rows): for every pair of hyperedges (i, j), i < j, both in E_s,
+it counts |e_i n e_j| by flagging the members of e_i and testing those of
+e_j, and keeps the pair when the count is at least s (Section II-B: E_s,
+s-incidence, L_s(H) = <E_s, F>, and L = H^T H). The multi-s ensemble
+(Algorithm 3's output) is the same definition evaluated once per s.
+
+All functions take a ``hypergen.Incidence`` and return numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "slg_oracle.c")
+_LIB = os.path.join(_HERE, "libslg_oracle.so")
+_lib = None
+
+_i64 = ctypes.c_int64
+_p = ctypes.c_void_p
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (OpenMP); returns the library path."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        lib.slgo_validate.argtypes = [_i64, _i64, _p, _p]
+        lib.slgo_validate.restype = ctypes.c_int
+        lib.slgo_rows_count.argtypes = [_i64, _i64, _p, _p, _i64, _i64, _p, _i64, _p, ctypes.c_int]
+        lib.slgo_rows_count.restype = ctypes.c_int
+        lib.slgo_rows_emit.argtypes = [_i64, _i64, _p, _p, _i64, _i64, _p, _i64, _p, _p, _p,
+                                       ctypes.c_int]
+        lib.slgo_rows_emit.restype = ctypes.c_int
+        lib.slgo_two_paths.argtypes = [_i64, _i64, _p, _p, _i64]
+        lib.slgo_two_paths.restype = _i64
+        lib.slgo_row_two_paths.argtypes = [_i64, _i64, _p, _p, _i64, _p, _i64, _p, ctypes.c_int]
+        lib.slgo_row_two_paths.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _csr(inc):
+    he_ptr = np.ascontiguousarray(inc.he_ptr, dtype=np.int64)
+    he_idx = np.ascontiguousarray(inc.he_idx, dtype=np.int32)
+    if he_idx.size == 0:
+        he_idx = np.zeros(1, np.int32)  # a valid address for an empty array
+    return he_ptr, he_idx
+
+
+def validate(inc) -> int:
+    """0 = valid; 1 bad pointers; 2 id out of range; 3 row not a sorted set."""
+    he_ptr, he_idx = _csr(inc)
+    return int(_load().slgo_validate(inc.m, inc.n, _ptr(he_ptr), _ptr(he_idx)))
+
+
+class Rows:
+    """Rows of an s-line graph: ``rows[r]`` owns ``j/w[ptr[r]:ptr[r+1]]``."""
+
+    def __init__(self, rows, ptr, j, w):
+        self.rows, self.ptr, self.j, self.w = rows, ptr, j, w
+
+    def row(self, r: int):
+        a, b = self.ptr[r], self.ptr[r + 1]
+        return self.j[a:b], self.w[a:b]
+
+
+def line_graph_rows(inc, s: int, rows: Optional[Sequence[int]] = None,
+                    size_min: Optional[int] = None, threads: int = 0) -> Rows:
+    """Rows ``rows`` (default: all) of L_s over E_{size_min} (default s)."""
+    if s < 1:
+        raise ValueError("s must be >= 1")
+    size_min = s if size_min is None else int(size_min)
+    lib = _load()
+    he_ptr, he_idx = _csr(inc)
+    rows_a = (np.arange(inc.m, dtype=np.int64) if rows is None
+              else np.ascontiguousarray(rows, dtype=np.int64))
+    nr = rows_a.shape[0]
+    counts = np.zeros(max(nr, 1), np.int64)
+    rp = rows_a if nr else np.zeros(1, np.int64)
+    if lib.slgo_rows_count(inc.m, inc.n, _ptr(he_ptr), _ptr(he_idx), size_min, s,
+                           _ptr(rp), nr, _ptr(counts), threads):
+        raise MemoryError("oracle: allocation failed")
+    ptr = np.zeros(nr + 1, np.int64)
+    np.cumsum(counts[:nr], out=ptr[1:])
+    total = int(ptr[-1])
+    j = np.zeros(max(total, 1), np.int32)
+    w = np.zeros(max(total, 1), np.int32)
+    if lib.slgo_rows_emit(inc.m, inc.n, _ptr(he_ptr), _ptr(he_idx), size_min, s, _ptr(rp), nr,
+                          _ptr(ptr), _ptr(j), _ptr(w), threads):
+        raise RuntimeError("oracle: emit disagreed with count")
+    return Rows(rows_a, ptr, j[:total], w[:total])
+
+
+class LineGraph:
+    """A whole s-line graph: CSR over all m rows plus the COO arrays."""
+
+    def __init__(self, s, row_ptr, i, j, w):
+        self.s, self.row_ptr, self.i, self.j, self.w = s, row_ptr, i, j, w
+
+    @property
+    def num_edges(self) -> int:
+        return int(self.j.shape[0])
+
+    def pairs(self) -> Dict[tuple, int]:
+        return {(int(a), int(b)): int(c) for a, b, c in zip(self.i, self.j, self.w)}
+
+
+def line_graph(inc, s: int, size_min: Optional[int] = None, threads: int = 0) -> LineGraph:
+    """L_s(H) (Section II-B), sorted by (i, j), i < j, original ids."""
+    r = line_graph_rows(inc, s, None, size_min, threads)
+    i = np.repeat(np.arange(inc.m, dtype=np.int32), np.diff(r.ptr))
+    return LineGraph(s, r.ptr, i, r.j, r.w)
+
+
+def ensemble(inc, s_values: Sequence[int], threads: int = 0) -> List[LineGraph]:
+    """One L_s per requested s (the outputs of the ensemble algorithm)."""
+    return [line_graph(inc, int(s), threads=threads) for s in s_values]
+
+
+def two_paths(inc, size_min: int) -> int:
+    """Number of 2-paths (e_i, v, e_j), i < j, e_i, e_j in E_{size_min}."""
+    he_ptr, he_idx = _csr(inc)
+    return int(_load().slgo_two_paths(inc.m, inc.n, _ptr(he_ptr), _ptr(he_idx), size_min))
+
+
+def row_two_paths(inc, size_min: int, rows: Sequence[int], threads: int = 0) -> np.ndarray:
+    """Per sampled row i: the number of 2-paths (e_i, v, e_j) with j > i."""
+    he_ptr, he_idx = _csr(inc)
+    rows_a = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.zeros(max(rows_a.shape[0], 1), np.int64)
+    rp = rows_a if rows_a.size else np.zeros(1, np.int64)
+    if _load().slgo_row_two_paths(inc.m, inc.n, _ptr(he_ptr), _ptr(he_idx), size_min, _ptr(rp),
+                                  rows_a.shape[0], _ptr(out), threads):
+        raise MemoryError("oracle: allocation failed")
+    return out[:rows_a.shape[0]]

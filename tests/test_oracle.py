@@ -1,0 +1,224 @@
+"""Pins for the CPU oracle: facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself, chosen so
+that a plausible slip (dropped term, wrong threshold, i <= j instead of
+i < j, H H^T instead of H^T H, pruning the wrong side) fails at least one.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from hypothesis import given, settings, strategies as st
+
+import hypergen as hg
+import oracle
+from helpers import brute_force_sets, edges_of, load_toy, rows_of
+
+
+# --- the worked example of Section I (hand-enumerated fixture) -------------
+
+def test_toy_line_graphs_match_fixture():
+    inc, keep, lines, _ = load_toy()
+    assert oracle.validate(inc) == 0
+    for s in (1, 2, 3, 4):
+        lg = oracle.line_graph(inc, s)
+        assert edges_of(lg) == lines.get(s, []), f"L_{s}"
+        # row_ptr covers all m rows and is consistent with the COO
+        assert lg.row_ptr.shape == (inc.m + 1,)
+        assert np.all(np.diff(lg.row_ptr) >= 0)
+        # E_s membership printed by the paper (E_4 = {3}, 1-based)
+        assert [i for i in range(inc.m) if inc.sizes()[i] >= s] == keep[s]
+
+
+def test_toy_dual_adjacency():
+    """adj(b, c) = 3 (Section II-A) is an edge weight of L_1 of the dual."""
+    inc, _, _, dual = load_toy()
+    lg = oracle.line_graph(inc.dual(), 1)
+    pairs = lg.pairs()
+    for (i, j, w) in dual[1]:
+        assert pairs[(i, j)] == w
+
+
+def test_toy_two_paths():
+    inc, _, lines, _ = load_toy()
+    # vertex degrees a..f = 2,3,3,2,2,1 -> 1+3+3+1+1+0 = 9
+    assert oracle.two_paths(inc, 1) == 9
+    assert sum(w for (_, _, w) in lines[1]) == 9
+    # E_3 drops hyperedge 3, so e's degree falls to 1 -> 8
+    assert oracle.two_paths(inc, 3) == 8
+    assert oracle.two_paths(inc, 4) == 0
+
+
+# --- L = H^T H (Section II-B) through an independent sparse product --------
+
+def _hth(inc):
+    rows = np.repeat(np.arange(inc.m), np.diff(inc.he_ptr))
+    H = sp.csr_matrix((np.ones(inc.nnz, np.int64), (inc.he_idx.astype(np.int64), rows)),
+                      shape=(inc.n, inc.m))  # n x m, b_ij = 1 iff v_i in e_j
+    return (H.T @ H).toarray()
+
+
+@pytest.mark.parametrize("seed,m,n,kmax,expo", [
+    (1, 300, 120, 12, None),
+    (2, 400, 60, 25, 0.8),
+    (3, 250, 40, 30, 1.5),
+    (4, 500, 1000, 8, None),
+])
+def test_weights_equal_HtH_offdiagonal(seed, m, n, kmax, expo):
+    inc = hg.random_small(seed, m, n, kmax, expo)
+    L = _hth(inc)
+    sizes = inc.sizes()
+    assert np.array_equal(np.diag(L), sizes)  # diagonal = |e_i|
+    for s in (1, 2, 3, 5):
+        lg = oracle.line_graph(inc, s)
+        iu, ju = np.triu_indices(inc.m, k=1)
+        keep = (L[iu, ju] >= s) & (sizes[iu] >= s) & (sizes[ju] >= s)
+        exp = list(zip(iu[keep].tolist(), ju[keep].tolist(), L[iu, ju][keep].tolist()))
+        assert edges_of(lg) == exp, f"s={s}"
+
+
+# --- closed form for the number of 2-paths --------------------------------
+
+@pytest.mark.parametrize("seed,expo", [(5, None), (6, 0.8), (7, 1.5)])
+def test_two_paths_closed_form(seed, expo):
+    inc = hg.random_small(seed, 400, 150, 15, expo)
+    sizes = inc.sizes()
+    rows = np.repeat(np.arange(inc.m), sizes)
+    for s in (1, 2, 4):
+        kept = sizes[rows] >= s
+        d = np.bincount(inc.he_idx[kept], minlength=inc.n).astype(np.int64)
+        closed = int((d * (d - 1) // 2).sum())
+        assert oracle.two_paths(inc, s) == closed
+        # every 2-path lands on exactly one intersecting pair of E_s
+        lg1 = oracle.line_graph(inc, 1, size_min=s)
+        assert int(lg1.w.astype(np.int64).sum()) == closed
+        per_row = oracle.row_two_paths(inc, s, np.arange(inc.m))
+        assert int(per_row.sum()) == closed
+
+
+# --- graphs are 2-uniform hypergraphs (Section I) -------------------------
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_two_uniform_is_textbook_line_graph(seed):
+    rng = np.random.default_rng(seed)
+    nv = 60
+    all_pairs = list(itertools.combinations(range(nv), 2))
+    pick = rng.choice(len(all_pairs), size=150, replace=False)
+    graph_edges = [all_pairs[k] for k in sorted(pick)]
+    inc = hg.from_rows(graph_edges, n=nv)
+    lg = oracle.line_graph(inc, 1)
+    exp = [(a, b, 1) for a, b in itertools.combinations(range(len(graph_edges)), 2)
+           if set(graph_edges[a]) & set(graph_edges[b])]
+    assert edges_of(lg) == exp
+    deg = np.bincount(np.array(graph_edges).ravel(), minlength=nv)
+    assert lg.num_edges == int((deg * (deg - 1) // 2).sum())
+    assert oracle.line_graph(inc, 2).num_edges == 0
+
+
+# --- invariants ----------------------------------------------------------
+
+def test_nested_filtration_and_weight_bounds():
+    inc = hg.random_small(11, 600, 80, 20, 0.8)
+    sizes = inc.sizes()
+    prev = None
+    for s in range(1, 9):
+        lg = oracle.line_graph(inc, s)
+        pairs = lg.pairs()
+        for (i, j), w in pairs.items():
+            assert i < j
+            assert s <= w <= min(sizes[i], sizes[j])
+        if prev is not None:
+            # L_{s} is contained in L_{s-1} with the same weights
+            for k, w in pairs.items():
+                assert prev[k] == w
+            assert set(prev) - set(pairs) == {k for k, w in prev.items() if w < s}
+        prev = pairs
+
+
+def test_vertex_and_hyperedge_permutation():
+    inc = hg.random_small(12, 300, 70, 15, 0.8)
+    rng = np.random.default_rng(3)
+    vperm = rng.permutation(inc.n)
+    rows = rows_of(inc)
+    inc_v = hg.from_rows([[int(vperm[v]) for v in r] for r in rows], n=inc.n)
+    eperm = rng.permutation(inc.m)  # new id of old hyperedge k is eperm[k]
+    new_rows = [None] * inc.m
+    for k, r in enumerate(rows):
+        new_rows[eperm[k]] = r
+    inc_e = hg.from_rows(new_rows, n=inc.n)
+    for s in (1, 2, 3):
+        base = oracle.line_graph(inc, s).pairs()
+        assert oracle.line_graph(inc_v, s).pairs() == base
+        mapped = {(min(eperm[i], eperm[j]), max(eperm[i], eperm[j])): w for (i, j), w in base.items()}
+        assert oracle.line_graph(inc_e, s).pairs() == mapped
+
+
+def test_duplicate_hyperedges_are_distinct_and_joined():
+    inc = hg.from_rows([[0, 1, 2], [3, 4], [0, 1, 2], [5]], n=6)
+    assert edges_of(oracle.line_graph(inc, 3)) == [(0, 2, 3)]
+    assert edges_of(oracle.line_graph(inc, 1)) == [(0, 2, 3)]
+
+
+def test_disjoint_union_is_block_result():
+    a = hg.random_small(21, 120, 40, 10, None)
+    b = hg.random_small(22, 90, 30, 10, 1.5)
+    rows = rows_of(a) + [[v + a.n for v in r] for r in rows_of(b)]
+    u = hg.from_rows(rows, n=a.n + b.n)
+    for s in (1, 2, 3):
+        pa = oracle.line_graph(a, s).pairs()
+        pb = oracle.line_graph(b, s).pairs()
+        exp = dict(pa)
+        exp.update({(i + a.m, j + a.m): w for (i, j), w in pb.items()})
+        assert oracle.line_graph(u, s).pairs() == exp
+
+
+def test_edge_cases():
+    empty = hg.from_rows([], n=0)
+    assert oracle.line_graph(empty, 1).num_edges == 0
+    hollow = hg.from_rows([[], [], []], n=4)
+    lg = oracle.line_graph(hollow, 1)
+    assert lg.num_edges == 0 and list(lg.row_ptr) == [0, 0, 0, 0]
+    inc = hg.tiny_uniform()
+    assert oracle.line_graph(inc, int(inc.sizes().max()) + 1).num_edges == 0
+    with pytest.raises(ValueError):
+        oracle.line_graph(inc, 0)
+
+
+def test_validate_rejects_malformed():
+    inc = hg.from_rows([[0, 1, 2], [1, 3]], n=4)
+    assert oracle.validate(inc) == 0
+    bad = hg.Incidence(2, 4, inc.he_ptr.copy(), inc.he_idx.copy(), inc.v_ptr, inc.v_idx)
+    bad.he_idx[1] = 0  # row 0 becomes [0, 0, 2]: not a set
+    assert oracle.validate(bad) == 3
+    bad2 = hg.Incidence(2, 4, inc.he_ptr.copy(), inc.he_idx.copy(), inc.v_ptr, inc.v_idx)
+    bad2.he_idx[-1] = 9
+    assert oracle.validate(bad2) == 2
+    bad3 = hg.Incidence(2, 4, np.array([0, 4, 3]), inc.he_idx, inc.v_ptr, inc.v_idx)
+    assert oracle.validate(bad3) == 1
+
+
+def test_tiny_uniform_rows_against_sets():
+    inc = hg.tiny_uniform()
+    rows = rows_of(inc)
+    for s in (1, 2, 3, 4):
+        assert edges_of(oracle.line_graph(inc, s)) == brute_force_sets(rows, s)
+
+
+@settings(max_examples=60, deadline=None)
+@given(st.lists(st.sets(st.integers(0, 11), max_size=8), max_size=14), st.integers(1, 4))
+def test_random_sets_brute_force(sets_, s):
+    rows = [sorted(x) for x in sets_]
+    inc = hg.from_rows(rows, n=12)
+    assert edges_of(oracle.line_graph(inc, s)) == brute_force_sets(rows, s)
+
+
+def test_sampled_rows_match_full_graph():
+    inc = hg.random_small(31, 500, 100, 12, 0.8)
+    full = oracle.line_graph(inc, 2)
+    sample = [0, 7, 99, 250, 498, 499]
+    r = oracle.line_graph_rows(inc, 2, sample)
+    for k, i in enumerate(sample):
+        j, w = r.row(k)
+        a, b = full.row_ptr[i], full.row_ptr[i + 1]
+        assert np.array_equal(j, full.j[a:b]) and np.array_equal(w, full.w[a:b])
