@@ -1,0 +1,179 @@
+/*
+ * slg.h — s-line graphs of non-uniform hypergraphs on AMD MI355X (gfx950).
+ *
+ * The problem (Section II-B): for a hypergraph H = (V, E) with n = |V|
+ * vertices and m = |E| hyperedges, and an integer s >= 1,
+ *   E_s = { e in E : |e| >= s },
+ *   L_s(H) = <E_s, F>,  {e_i, e_j} in F  iff  |e_i n e_j| >= s,
+ * and each edge carries its overlap |e_i n e_j| = (H^T H)[i, j].
+ * The library computes F by the two-hop traversal hyperedge -> vertex ->
+ * hyperedge (the "ikj" form of Section III-B, Algorithm 2), after dropping
+ * hyperedges with |e| < s (degree-based pruning), and emits each pair once
+ * with i < j (the upper triangle). Given a set of thresholds it computes
+ * the whole ensemble in one counting pass (Algorithm 3, Section III-D).
+ *
+ * Conventions for every entry point:
+ *   - ids are 0-based; i, j index hyperedges in the caller's numbering
+ *     (no relabelling leaks out); vertices index [0, n).
+ *   - "device" pointers are addresses in the GPU's memory (e.g. from torch
+ *     or hipMalloc); "host" pointers are ordinary CPU memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *     all device work of a call is ordered on it.
+ *   - every call returns a slg_status; on failure the context's last error
+ *     string (slg_last_error) says why. No call throws.
+ *   - a context and everything made from it belong to one host thread at a
+ *     time; they are not safe to share across threads without a lock.
+ */
+#ifndef SLG_H
+#define SLG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SLG_OK = 0,
+    SLG_ERR_INVALID_ARG = 1,   /* bad pointer, size or s-set */
+    SLG_ERR_INVALID_GRAPH = 2, /* CSR check failed (only with SLG_VALIDATE) */
+    SLG_ERR_OUT_OF_MEMORY = 3, /* device allocation failed / budget exceeded */
+    SLG_ERR_DEVICE = 4,        /* a HIP runtime call failed */
+    SLG_ERR_OVERFLOW = 5,      /* m, n or nnz >= 2^31 */
+    SLG_ERR_CANCELLED = 6      /* a chunk callback asked to stop */
+} slg_status;
+
+/* Largest number of thresholds in one ensemble call. */
+#define SLG_MAX_S 16
+
+typedef struct slg_context slg_context;
+typedef struct slg_graph slg_graph;
+typedef struct slg_plan slg_plan;
+typedef struct slg_result slg_result;
+
+/*
+ * The input: the incidence of H held as both CSR orientations
+ * (Section II-A: the bipartite graph B(H) / incidence matrix H; the ikj
+ * traversal of Section III-B reads H^T.Adj and H.Adj).
+ *   he_ptr[m+1], he_idx[nnz]: members of hyperedge i are
+ *       he_idx[he_ptr[i] .. he_ptr[i+1]), strictly increasing (e_i is a set).
+ *   v_ptr[n+1], v_idx[nnz]: hyperedges containing vertex v are
+ *       v_idx[v_ptr[v] .. v_ptr[v+1]), strictly increasing; the exact
+ *       transpose of the hyperedge CSR.
+ * All four arrays are DEVICE pointers. Empty hyperedges and isolated
+ * vertices are allowed; duplicate hyperedges are distinct hyperedges.
+ */
+typedef struct {
+    int64_t num_vertices;   /* n */
+    int64_t num_hyperedges; /* m */
+    int64_t nnz;            /* number of incidences */
+    const int64_t *he_ptr;
+    const int32_t *he_idx;
+    const int64_t *v_ptr;
+    const int32_t *v_idx;
+} slg_incidence;
+
+/*
+ * Optional device allocator for result buffers (e.g. torch's caching
+ * allocator). alloc returns a device pointer of at least `bytes` usable on
+ * `stream`, or NULL; release frees it. NULL allocator = the library's own
+ * stream-ordered allocator (hipMallocAsync).
+ */
+typedef struct {
+    void *(*alloc)(void *user, size_t bytes, void *stream);
+    void (*release)(void *user, void *ptr, void *stream);
+    void *user;
+} slg_allocator;
+
+/* Flags for slg_graph_register. */
+#define SLG_VALIDATE 1u /* check both CSRs on the device before accepting */
+
+/* Library version string (static storage). */
+const char *slg_version(void);
+
+/*
+ * Create a context on HIP device `device`. mem_budget_bytes bounds the
+ * device memory one call may hold for scratch and results (0 = no bound);
+ * slg_line_graph_stream sizes its chunks to it. `alloc` may be NULL.
+ * Errors: INVALID_ARG (out == NULL), DEVICE (no such device).
+ */
+slg_status slg_context_create(int device, uint64_t mem_budget_bytes, const slg_allocator *alloc,
+                              slg_context **out);
+slg_status slg_context_destroy(slg_context *ctx);
+
+/* Why the last failing call on ctx failed (static or context-owned text). */
+const char *slg_last_error(const slg_context *ctx);
+
+/*
+ * Register a hypergraph. The incidence arrays are borrowed: they must stay
+ * valid and unchanged until slg_graph_release. With SLG_VALIDATE the
+ * library checks on the device, ordered on `stream`, that: pointer arrays
+ * start at 0, are non-decreasing and end at nnz; ids are in range; rows of
+ * both CSRs are strictly increasing; the vertex CSR is the transpose.
+ * Errors: INVALID_ARG (NULL pointers with nnz > 0, negative sizes),
+ * OVERFLOW (m, n or nnz >= 2^31), INVALID_GRAPH (a check failed).
+ */
+slg_status slg_graph_register(slg_context *ctx, const slg_incidence *inc, uint32_t flags,
+                              void *stream, slg_graph **out);
+slg_status slg_graph_release(slg_graph *g);
+
+/*
+ * Plan the s-line graph(s) of g for thresholds s[0..num_s) (host array,
+ * strictly increasing, s[0] >= 1, num_s <= SLG_MAX_S). Runs, on `stream`:
+ * degree pruning at s_min = s[0] (Algorithm 2's pruning test; Algorithm 3
+ * prunes by its smallest s), the per-hyperedge 2-path work estimate, the
+ * counting pass that fixes every output size, and the prefix sums that
+ * place each row. Blocks until the edge counts are known on the host.
+ * num_s == 1 is the plain s-line graph (Algorithm 2); num_s > 1 is the
+ * single-pass ensemble (Algorithm 3).
+ * Errors: INVALID_ARG (bad s-set), OUT_OF_MEMORY, DEVICE.
+ */
+slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num_s,
+                           void *stream, slg_plan **out);
+
+/*
+ * Facts of a plan for threshold index k (0 <= k < num_s):
+ *   num_edges  = |F| of L_{s[k]}(H);
+ *   two_paths  = number of 2-paths (e_i, v, e_j), i < j, e_i, e_j in
+ *                E_{s[0]} traversed by the plan (the same for every k).
+ * Either output pointer may be NULL.
+ */
+slg_status slg_plan_info(const slg_plan *p, int32_t k, int64_t *num_edges, int64_t *two_paths);
+
+/*
+ * Write every L_{s[k]} of the plan into caller-owned DEVICE buffers, one
+ * set per k (host arrays of num_s device pointers each):
+ *   row_ptr[k]: int64[m+1], CSR row offsets over all m hyperedges;
+ *   col[k], w[k]: int32[num_edges(k)], the j and the overlap of each edge;
+ *   row[k]: int32[num_edges(k)], the i of each edge (COO), or NULL to skip.
+ * Edges are sorted by (i, j) ascending with i < j. CSR and COO share col/w.
+ * Work is enqueued on `stream`; the call returns without waiting.
+ * Errors: INVALID_ARG (NULL buffer for an L_s with edges).
+ */
+slg_status slg_plan_emit(slg_plan *p, int64_t *const *row_ptr, int32_t *const *row,
+                         int32_t *const *col, int32_t *const *w, void *stream);
+
+/* Free a plan's device scratch (ordered on the stream it was made on). */
+slg_status slg_plan_destroy(slg_plan *p);
+
+/*
+ * One-shot form of plan + emit: result buffers come from the context's
+ * allocator and stay owned by the library until slg_result_free.
+ * Same s-set rules and errors as slg_plan_create.
+ */
+slg_status slg_line_graph(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num_s,
+                          void *stream, slg_result **out);
+slg_status slg_result_info(const slg_result *r, int32_t k, int64_t *num_edges, int64_t *two_paths);
+/* Device pointers into the result for threshold index k. */
+slg_status slg_result_coo(const slg_result *r, int32_t k, const int32_t **i, const int32_t **j,
+                          const int32_t **w);
+slg_status slg_result_csr(const slg_result *r, int32_t k, const int64_t **row_ptr,
+                          const int32_t **col, const int32_t **w);
+slg_status slg_result_free(slg_result *r);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLG_H */

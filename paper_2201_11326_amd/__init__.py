@@ -1,0 +1,332 @@
+"""s-line graphs of non-uniform hypergraphs on AMD MI355X.
+
+Thin Python binding over the C ABI of ``libslg.so`` (include/slg.h):
+argument marshalling only. Every step of the computation runs in the
+library's HIP kernels; torch supplies device memory and streams. If the
+library has not been built this module raises on first use — there is no
+CPU fallback.
+
+    import paper_2201_11326_amd as slg
+    ctx = slg.Context()
+    g = ctx.register_incidence(inc)           # hypergen.Incidence -> device
+    outs = ctx.line_graph(g, [1, 2, 4, 8])    # one L_s per threshold
+    outs[0].row_ptr, outs[0].row, outs[0].col, outs[0].w   # torch tensors
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB_PATH = os.path.join(HERE, "libslg.so")
+HEADER = os.path.join(ROOT, "include", "slg.h")
+
+SLG_OK = 0
+SLG_ERR_INVALID_ARG = 1
+SLG_ERR_INVALID_GRAPH = 2
+SLG_ERR_OUT_OF_MEMORY = 3
+SLG_ERR_DEVICE = 4
+SLG_ERR_OVERFLOW = 5
+SLG_ERR_CANCELLED = 6
+SLG_MAX_S = 16
+SLG_VALIDATE = 1
+
+_STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "INVALID_GRAPH", 3: "OUT_OF_MEMORY", 4: "DEVICE",
+                 5: "OVERFLOW", 6: "CANCELLED"}
+
+_p = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+
+
+class SlgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"slg {_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Incidence(ctypes.Structure):
+    _fields_ = [("num_vertices", _i64), ("num_hyperedges", _i64), ("nnz", _i64),
+                ("he_ptr", _p), ("he_idx", _p), ("v_ptr", _p), ("v_idx", _p)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(_p, _p, ctypes.c_size_t, _p)
+_FREE_FN = ctypes.CFUNCTYPE(None, _p, _p, _p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("release", _FREE_FN), ("user", _p)]
+
+
+_lib = None
+
+
+def header_symbols() -> List[str]:
+    """Entry points declared in include/slg.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(slg_[a-z_]+)\s*\(", text)))
+
+
+def lib() -> ctypes.CDLL:
+    """Load libslg.so (built by __graft_entry__.build() / build.py)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2201_11326_amd.build` "
+                           "or __graft_entry__.build(). There is no fallback path.")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "slg_version": (ctypes.c_char_p, []),
+        "slg_context_create": (_i32, [ctypes.c_int, _u64, _p, ctypes.POINTER(_p)]),
+        "slg_context_destroy": (_i32, [_p]),
+        "slg_last_error": (ctypes.c_char_p, [_p]),
+        "slg_graph_register": (_i32, [_p, ctypes.POINTER(Incidence), _u32, _p, ctypes.POINTER(_p)]),
+        "slg_graph_release": (_i32, [_p]),
+        "slg_plan_create": (_i32, [_p, _p, ctypes.POINTER(_i32), _i32, _p, ctypes.POINTER(_p)]),
+        "slg_plan_info": (_i32, [_p, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+        "slg_plan_emit": (_i32, [_p, ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p),
+                                 ctypes.POINTER(_p), _p]),
+        "slg_plan_destroy": (_i32, [_p]),
+        "slg_line_graph": (_i32, [_p, _p, ctypes.POINTER(_i32), _i32, _p, ctypes.POINTER(_p)]),
+        "slg_result_info": (_i32, [_p, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+        "slg_result_coo": (_i32, [_p, _i32, ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
+        "slg_result_csr": (_i32, [_p, _i32, ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
+        "slg_result_free": (_i32, [_p]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def version() -> str:
+    return lib().slg_version().decode()
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _s_array(s: Sequence[int]):
+    vals = [int(x) for x in s]
+    return (_i32 * max(len(vals), 1))(*vals), len(vals)
+
+
+class _DeviceView:
+    """Zero-copy __cuda_array_interface__ view of library-owned device memory."""
+
+    def __init__(self, ptr: int, n: int, typestr: str, owner):
+        self._owner = owner
+        self.__cuda_array_interface__ = {"shape": (int(n),), "typestr": typestr,
+                                         "data": (int(ptr or 0), False), "version": 3, "strides": None}
+
+
+class LineGraph:
+    """One L_s: CSR ``row_ptr`` (int64, m+1) plus COO ``row``/``col``/``w`` (int32)."""
+
+    def __init__(self, s: int, row_ptr, row, col, w, two_paths: int, owner=None):
+        self.s, self.row_ptr, self.row, self.col, self.w = s, row_ptr, row, col, w
+        self.two_paths = int(two_paths)
+        self._owner = owner
+
+    @property
+    def num_edges(self) -> int:
+        return int(self.col.shape[0])
+
+    def cpu(self):
+        return LineGraph(self.s, self.row_ptr.cpu(), None if self.row is None else self.row.cpu(),
+                         self.col.cpu(), self.w.cpu(), self.two_paths)
+
+
+class Graph:
+    """A registered hypergraph; keeps its device CSR tensors alive."""
+
+    def __init__(self, ctx: "Context", handle: int, tensors, m: int, n: int):
+        self.ctx, self.handle, self._tensors, self.m, self.n = ctx, handle, tensors, m, n
+
+    def release(self):
+        if self.handle:
+            lib().slg_graph_release(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Counting pass done: edge counts known; emit() writes caller tensors."""
+
+    def __init__(self, ctx: "Context", handle: int, s: List[int], m: int):
+        self.ctx, self.handle, self.s, self.m = ctx, handle, s, m
+
+    def info(self, k: int):
+        e, w = _i64(), _i64()
+        self.ctx._check(lib().slg_plan_info(self.handle, k, ctypes.byref(e), ctypes.byref(w)))
+        return int(e.value), int(w.value)
+
+    @property
+    def two_paths(self) -> int:
+        return self.info(0)[1]
+
+    def num_edges(self) -> List[int]:
+        return [self.info(k)[0] for k in range(len(self.s))]
+
+    def emit(self, row_ptr, row, col, w, stream=None):
+        K = len(self.s)
+        arr = lambda ts: (_p * K)(*[0 if t is None else t.data_ptr() for t in ts])
+        rp, rw, cl, ww = arr(row_ptr), arr(row) if row is not None else None, arr(col), arr(w)
+        self.ctx._check(lib().slg_plan_emit(self.handle, rp, rw, cl, ww, _stream_handle(stream)))
+
+    def destroy(self):
+        if self.handle:
+            lib().slg_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Context:
+    def __init__(self, device: int = 0, mem_budget_bytes: int = 0, torch_allocator: bool = True):
+        import torch
+        self.device = device
+        L = lib()
+        self._alloc = None
+        alloc_ptr = None
+        if torch_allocator:
+            def _a(user, nbytes, stream):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream or 0)
+                except Exception:
+                    return None
+
+            def _f(user, ptr, stream):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._alloc = Allocator(_ALLOC_FN(_a), _FREE_FN(_f), None)
+            alloc_ptr = ctypes.byref(self._alloc)
+        h = _p()
+        st = L.slg_context_create(device, mem_budget_bytes, alloc_ptr, ctypes.byref(h))
+        if st != SLG_OK:
+            raise SlgError(st, "slg_context_create failed")
+        self.handle = h.value
+
+    def _check(self, status: int):
+        if status != SLG_OK:
+            msg = lib().slg_last_error(self.handle)
+            raise SlgError(status, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().slg_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- graphs ------------------------------------------------------------
+    def register(self, m: int, n: int, he_ptr, he_idx, v_ptr, v_idx, validate: bool = False,
+                 stream=None) -> Graph:
+        """Register device tensors (int64 ptrs, int32 ids) of both CSRs."""
+        inc = Incidence(n, m, int(he_idx.numel()), he_ptr.data_ptr(), he_idx.data_ptr(),
+                        v_ptr.data_ptr(), v_idx.data_ptr())
+        h = _p()
+        self._check(lib().slg_graph_register(self.handle, ctypes.byref(inc),
+                                             SLG_VALIDATE if validate else 0,
+                                             _stream_handle(stream), ctypes.byref(h)))
+        return Graph(self, h.value, (he_ptr, he_idx, v_ptr, v_idx), m, n)
+
+    def register_incidence(self, inc, validate: bool = False, stream=None) -> Graph:
+        """Copy a host hypergen.Incidence to the device and register it."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        t = lambda a, dt: torch.as_tensor(a, dtype=dt).to(dev)
+        he_ptr = t(inc.he_ptr, torch.int64)
+        he_idx = t(inc.he_idx if inc.nnz else [0], torch.int32)[: inc.nnz]
+        v_ptr = t(inc.v_ptr, torch.int64)
+        v_idx = t(inc.v_idx if inc.nnz else [0], torch.int32)[: inc.nnz]
+        return self.register(inc.m, inc.n, he_ptr, he_idx, v_ptr, v_idx, validate, stream)
+
+    # -- s-line graphs -------------------------------------------------------
+    def plan(self, g: Graph, s: Sequence[int], stream=None) -> Plan:
+        arr, k = _s_array(s)
+        h = _p()
+        self._check(lib().slg_plan_create(self.handle, g.handle, arr, k, _stream_handle(stream),
+                                          ctypes.byref(h)))
+        return Plan(self, h.value, [int(x) for x in s], g.m)
+
+    def line_graph(self, g: Graph, s: Sequence[int], stream=None, coo: bool = True) -> List[LineGraph]:
+        """L_s for every s (one counting pass for the whole set), into torch tensors."""
+        import torch
+        p = self.plan(g, s, stream)
+        try:
+            dev = torch.device("cuda", self.device)
+            outs = []
+            for k, sk in enumerate(p.s):
+                e, wpaths = p.info(k)
+                outs.append(LineGraph(sk, torch.empty(g.m + 1, dtype=torch.int64, device=dev),
+                                      torch.empty(e, dtype=torch.int32, device=dev) if coo else None,
+                                      torch.empty(e, dtype=torch.int32, device=dev),
+                                      torch.empty(e, dtype=torch.int32, device=dev), wpaths))
+            p.emit([o.row_ptr for o in outs], [o.row for o in outs] if coo else None,
+                   [o.col for o in outs], [o.w for o in outs], stream)
+        finally:
+            p.destroy()
+        return outs
+
+    def line_graph_result(self, g: Graph, s: Sequence[int], stream=None) -> List[LineGraph]:
+        """The one-shot ABI call (slg_line_graph): library-owned result buffers."""
+        import torch
+        arr, k = _s_array(s)
+        h = _p()
+        self._check(lib().slg_line_graph(self.handle, g.handle, arr, k, _stream_handle(stream),
+                                         ctypes.byref(h)))
+        res = _Result(h.value)
+        outs = []
+        for kk, sk in enumerate(s):
+            e, wpaths = _i64(), _i64()
+            self._check(lib().slg_result_info(res.handle, kk, ctypes.byref(e), ctypes.byref(wpaths)))
+            ip, jp, wp, rp = _p(), _p(), _p(), _p()
+            self._check(lib().slg_result_coo(res.handle, kk, ctypes.byref(ip), ctypes.byref(jp),
+                                             ctypes.byref(wp)))
+            self._check(lib().slg_result_csr(res.handle, kk, ctypes.byref(rp), None, None))
+            view = lambda ptr, n, ts: torch.as_tensor(_DeviceView(ptr, n, ts, res), device=f"cuda:{self.device}")
+            ne = int(e.value)
+            outs.append(LineGraph(int(sk), view(rp.value, g.m + 1, "<i8"), view(ip.value, ne, "<i4"),
+                                  view(jp.value, ne, "<i4"), view(wp.value, ne, "<i4"), int(wpaths.value),
+                                  owner=res))
+        return outs
+
+
+class _Result:
+    def __init__(self, handle):
+        self.handle = handle
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().slg_result_free(self.handle)
+        except Exception:
+            pass

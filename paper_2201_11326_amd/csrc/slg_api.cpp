@@ -1,0 +1,496 @@
+// Host side of the C ABI declared in include/slg.h: contexts, graph
+// registration and validation, the plan (prune -> work estimate -> count ->
+// prefix sums), the emit pass and the one-shot result object.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "slg.h"
+#include "slg_internal.h"
+
+using namespace slg;
+
+struct slg_context {
+    int device = 0;
+    uint64_t budget = 0;
+    bool has_alloc = false;
+    slg_allocator alloc{};
+    std::string last_error;
+    int64_t *pinned = nullptr;  // host staging for readbacks
+};
+
+struct slg_graph {
+    slg_context *ctx = nullptr;
+    slg_incidence inc{};
+};
+
+namespace {
+
+constexpr int kPinnedSlots = 64;
+
+slg_status fail(slg_context *ctx, slg_status st, const char *fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->last_error = buf;
+    }
+    return st;
+}
+
+#define SLG_HIP(ctx, call)                                                                       \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) {                                                                  \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? SLG_ERR_OUT_OF_MEMORY : SLG_ERR_DEVICE, \
+                        "%s: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__);     \
+        }                                                                                        \
+    } while (0)
+
+// Stream-ordered scratch owned by a plan.
+struct Scratch {
+    hipStream_t st = nullptr;
+    std::vector<void *> ptrs;
+    hipError_t get(void **p, size_t bytes) {
+        *p = nullptr;
+        if (bytes == 0) bytes = 8;
+        hipError_t e = hipMallocAsync(p, bytes, st);
+        if (e == hipSuccess) ptrs.push_back(*p);
+        return e;
+    }
+    template <typename T>
+    hipError_t get(T **p, size_t count) {
+        return get(reinterpret_cast<void **>(p), count * sizeof(T));
+    }
+    void release() {
+        for (void *p : ptrs) (void)hipFreeAsync(p, st);
+        ptrs.clear();
+    }
+};
+
+bool valid_s(const int32_t *s, int32_t k) {
+    if (!s || k < 1 || k > SLG_MAX_S || s[0] < 1) return false;
+    for (int32_t t = 1; t < k; ++t)
+        if (s[t] <= s[t - 1]) return false;
+    return true;
+}
+
+}  // namespace
+
+struct slg_plan {
+    slg_context *ctx = nullptr;
+    slg_graph *g = nullptr;
+    hipStream_t st = nullptr;
+    EmitParams prm{};
+    Pruned pr{};
+    Scratch scratch;
+    int64_t *slot_base = nullptr;  // [m+1]
+    int64_t S = 0;                 // number of slots
+    Slots slots{};
+    int32_t *lists[kNumLists] = {};
+    int64_t list_count[kNumLists] = {};
+    int64_t *slot_cnt = nullptr;   // [K][S]
+    int64_t *slot_off = nullptr;   // [K][S+1]
+    int64_t two_paths = 0;
+    int64_t num_edges[SLG_MAX_S] = {};
+};
+
+struct slg_result {
+    slg_context *ctx = nullptr;
+    hipStream_t st = nullptr;
+    int32_t k = 0;
+    int64_t m = 0;
+    int64_t two_paths = 0;
+    int64_t num_edges[SLG_MAX_S] = {};
+    int64_t *row_ptr[SLG_MAX_S] = {};
+    int32_t *row[SLG_MAX_S] = {};
+    int32_t *col[SLG_MAX_S] = {};
+    int32_t *w[SLG_MAX_S] = {};
+    std::vector<void *> owned;
+};
+
+extern "C" {
+
+const char *slg_version(void) { return "slg 0.1.0 (gfx950)"; }
+
+slg_status slg_context_create(int device, uint64_t mem_budget_bytes, const slg_allocator *alloc,
+                              slg_context **out) {
+    if (!out) return SLG_ERR_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return SLG_ERR_DEVICE;
+    slg_context *ctx = new (std::nothrow) slg_context();
+    if (!ctx) return SLG_ERR_OUT_OF_MEMORY;
+    ctx->device = device;
+    ctx->budget = mem_budget_bytes;
+    if (alloc && alloc->alloc && alloc->release) {
+        ctx->has_alloc = true;
+        ctx->alloc = *alloc;
+    }
+    if (hipSetDevice(device) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&ctx->pinned), kPinnedSlots * sizeof(int64_t),
+                      hipHostMallocDefault) != hipSuccess) {
+        delete ctx;
+        return SLG_ERR_DEVICE;
+    }
+    // keep freed scratch in the stream-ordered pool between calls
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    *out = ctx;
+    return SLG_OK;
+}
+
+slg_status slg_context_destroy(slg_context *ctx) {
+    if (!ctx) return SLG_ERR_INVALID_ARG;
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx;
+    return SLG_OK;
+}
+
+const char *slg_last_error(const slg_context *ctx) {
+    if (!ctx) return "null context";
+    return ctx->last_error.c_str();
+}
+
+slg_status slg_graph_register(slg_context *ctx, const slg_incidence *inc, uint32_t flags,
+                              void *stream, slg_graph **out) {
+    if (!ctx || !inc || !out) return fail(ctx, SLG_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    const int64_t m = inc->num_hyperedges, n = inc->num_vertices, nnz = inc->nnz;
+    if (m < 0 || n < 0 || nnz < 0) return fail(ctx, SLG_ERR_INVALID_ARG, "negative size");
+    if (m >= (int64_t(1) << 31) || n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 31))
+        return fail(ctx, SLG_ERR_OVERFLOW, "m, n and nnz must be below 2^31");
+    if (!inc->he_ptr || !inc->v_ptr || (nnz > 0 && (!inc->he_idx || !inc->v_idx)))
+        return fail(ctx, SLG_ERR_INVALID_ARG, "null CSR array");
+    SLG_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (flags & SLG_VALIDATE) {
+        Scratch sc;
+        sc.st = st;
+        int64_t *err = nullptr;
+        SLG_HIP(ctx, sc.get(&err, 1));
+        SLG_HIP(ctx, launch_fill_i64(err, 1, 0, st));
+        int *e32 = reinterpret_cast<int *>(err);
+        SLG_HIP(ctx, launch_validate_ptr(inc->he_ptr, m, nnz, e32, st));
+        SLG_HIP(ctx, launch_validate_ptr(inc->v_ptr, n, nnz, e32, st));
+        SLG_HIP(ctx, hipMemcpyAsync(ctx->pinned, err, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        SLG_HIP(ctx, hipStreamSynchronize(st));
+        int64_t code = ctx->pinned[0];
+        if (!code) {  // pointers are sound: rows may be read
+            SLG_HIP(ctx, launch_validate_rows(inc->he_ptr, inc->he_idx, m, n, e32, st));
+            SLG_HIP(ctx, launch_validate_rows(inc->v_ptr, inc->v_idx, n, m, e32, st));
+            SLG_HIP(ctx, hipMemcpyAsync(ctx->pinned, err, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            SLG_HIP(ctx, hipStreamSynchronize(st));
+            code = ctx->pinned[0];
+        }
+        if (!code) {  // ids in range: check the transpose
+            SLG_HIP(ctx, launch_validate_transpose(inc->he_ptr, inc->he_idx, m, inc->v_ptr, inc->v_idx,
+                                                   n, e32, st));
+            SLG_HIP(ctx, hipMemcpyAsync(ctx->pinned, err, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+            SLG_HIP(ctx, hipStreamSynchronize(st));
+            code = ctx->pinned[0];
+        }
+        sc.release();
+        if (code & 2) return fail(ctx, SLG_ERR_INVALID_GRAPH, "CSR pointer array malformed");
+        if (code & 4) return fail(ctx, SLG_ERR_INVALID_GRAPH, "CSR row holds an out-of-range or repeated id");
+        if (code & 8) return fail(ctx, SLG_ERR_INVALID_GRAPH, "vertex CSR is not the transpose");
+    }
+    slg_graph *g = new (std::nothrow) slg_graph();
+    if (!g) return fail(ctx, SLG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    g->ctx = ctx;
+    g->inc = *inc;
+    *out = g;
+    return SLG_OK;
+}
+
+slg_status slg_graph_release(slg_graph *g) {
+    if (!g) return SLG_ERR_INVALID_ARG;
+    delete g;
+    return SLG_OK;
+}
+
+slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num_s,
+                           void *stream, slg_plan **out) {
+    if (!ctx || !g || !out) return fail(ctx, SLG_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    if (!valid_s(s, num_s))
+        return fail(ctx, SLG_ERR_INVALID_ARG, "s must be strictly increasing, s[0] >= 1, 1 <= num_s <= %d",
+                    SLG_MAX_S);
+    SLG_HIP(ctx, hipSetDevice(ctx->device));
+    slg_plan *p = new (std::nothrow) slg_plan();
+    if (!p) return fail(ctx, SLG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    p->ctx = ctx;
+    p->g = g;
+    p->st = static_cast<hipStream_t>(stream);
+    p->scratch.st = p->st;
+    p->prm.k = num_s;
+    for (int t = 0; t < num_s; ++t) p->prm.s[t] = s[t];
+    slg_status rc = SLG_OK;
+    auto bail = [&](slg_status code) {
+        p->scratch.release();
+        (void)hipStreamSynchronize(p->st);
+        delete p;
+        return code;
+    };
+#define PLAN_HIP(call)                                                                             \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return bail(fail(ctx, e_ == hipErrorOutOfMemory ? SLG_ERR_OUT_OF_MEMORY : SLG_ERR_DEVICE, \
+                             "%s: %s", #call, hipGetErrorString(e_)));                              \
+    } while (0)
+
+    const slg_incidence &inc = g->inc;
+    const int64_t m = inc.num_hyperedges, n = inc.num_vertices, nnz = inc.nnz;
+    const int32_t s_min = s[0];
+    hipStream_t st = p->st;
+    Scratch &sc = p->scratch;
+
+    // K1: vertex lists restricted to E_{s_min}
+    Pruned &pr = p->pr;
+    pr.m = m;
+    pr.n = n;
+    pr.nnz = nnz;
+    pr.he_ptr = inc.he_ptr;
+    pr.he_idx = inc.he_idx;
+    if (s_min > 1 && nnz > 0) {
+        uint8_t *flag;
+        int64_t *pos, *part;
+        int64_t *vs_ptr;
+        int32_t *vs_idx;
+        PLAN_HIP(sc.get(&flag, nnz));
+        PLAN_HIP(sc.get(&pos, nnz + 1));
+        PLAN_HIP(sc.get(&part, scan_partials_size(nnz)));
+        PLAN_HIP(sc.get(&vs_ptr, n + 1));
+        PLAN_HIP(sc.get(&vs_idx, nnz));
+        PLAN_HIP(launch_keep_incidence(nnz, inc.v_idx, inc.he_ptr, m, s_min, flag, st));
+        PLAN_HIP(launch_exclusive_scan_u8(flag, nnz, pos, part, st));
+        PLAN_HIP(launch_compact_vertex_lists(n, nnz, inc.v_ptr, inc.v_idx, flag, pos, vs_ptr, vs_idx, st));
+        pr.vs_ptr = vs_ptr;
+        pr.vs_idx = vs_idx;
+    } else {
+        pr.vs_ptr = inc.v_ptr;
+        pr.vs_idx = inc.v_idx;
+    }
+
+    // K2: tails, 2-path work and slot counts per row
+    int32_t *tail_beg, *jmax, *nslots;
+    int64_t *work, *work_pre, *counters, *part_m;
+    uint8_t *rclass;
+    PLAN_HIP(sc.get(&tail_beg, nnz));
+    PLAN_HIP(sc.get(&work, m));
+    PLAN_HIP(sc.get(&work_pre, m + 1));
+    PLAN_HIP(sc.get(&jmax, m));
+    PLAN_HIP(sc.get(&nslots, m));
+    PLAN_HIP(sc.get(&rclass, m));
+    PLAN_HIP(sc.get(&counters, 16));
+    PLAN_HIP(sc.get(&part_m, scan_partials_size(m)));
+    PLAN_HIP(sc.get(&p->slot_base, m + 1));
+    PLAN_HIP(launch_fill_i64(counters, 16, 0, st));
+    pr.tail_beg = tail_beg;
+    unsigned long long *class_count = reinterpret_cast<unsigned long long *>(counters);
+    int *err = reinterpret_cast<int *>(counters + 8);
+    unsigned long long *list_fill = reinterpret_cast<unsigned long long *>(counters + 9);
+    PLAN_HIP(launch_row_plan(pr, s_min, tail_beg, work, jmax, nslots, rclass, class_count, err, st));
+    PLAN_HIP(launch_exclusive_scan_i32(nslots, m, p->slot_base, part_m, st));
+    PLAN_HIP(launch_exclusive_scan_i64(work, m, work_pre, part_m, st));
+    int64_t *hb = ctx->pinned;
+    PLAN_HIP(hipMemcpyAsync(hb, counters, 9 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    PLAN_HIP(hipMemcpyAsync(hb + 9, p->slot_base + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    PLAN_HIP(hipMemcpyAsync(hb + 10, work_pre + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    PLAN_HIP(hipStreamSynchronize(st));
+    if (hb[8] & 0xffffffff)
+        return bail(fail(ctx, SLG_ERR_INVALID_GRAPH,
+                         "malformed incidence (bad pointer, id out of range, or vertex CSR not the transpose)"));
+    for (int c = 0; c < kNumLists; ++c) p->list_count[c] = hb[c];
+    p->S = hb[9];
+    p->two_paths = hb[10];
+
+    // slot table and tier lists
+    int32_t *slot_row, *slot_ja, *slot_jb;
+    PLAN_HIP(sc.get(&slot_row, p->S));
+    PLAN_HIP(sc.get(&slot_ja, p->S));
+    PLAN_HIP(sc.get(&slot_jb, p->S));
+    for (int c = 0; c < kNumLists; ++c) PLAN_HIP(sc.get(&p->lists[c], p->list_count[c]));
+    PLAN_HIP(launch_fill_slots(m, p->slot_base, nslots, jmax, work, rclass, slot_row, slot_ja, slot_jb,
+                               p->lists, list_fill, st));
+    p->slots.count = p->S;
+    p->slots.row = slot_row;
+    p->slots.ja = slot_ja;
+    p->slots.jb = slot_jb;
+
+    // K3-K5 counting pass: per slot, per threshold, the number of edges
+    const int K = num_s;
+    PLAN_HIP(sc.get(&p->slot_cnt, (size_t)K * p->S));
+    PLAN_HIP(sc.get(&p->slot_off, (size_t)K * (p->S + 1)));
+    int64_t *part_s;
+    PLAN_HIP(sc.get(&part_s, scan_partials_size(p->S)));
+    for (int c = 0; c < kLightClasses; ++c)
+        PLAN_HIP(launch_light(c, false, p->lists[c], p->list_count[c], p->slots, pr, p->prm, p->slot_cnt,
+                              nullptr, 0, st));
+    PLAN_HIP(launch_heavy(false, p->lists[kLightClasses], p->list_count[kLightClasses], p->slots, pr, p->prm,
+                          p->slot_cnt, nullptr, 0, st));
+    for (int k = 0; k < K; ++k) {
+        PLAN_HIP(launch_exclusive_scan_i64(p->slot_cnt + (size_t)k * p->S, p->S,
+                                           p->slot_off + (size_t)k * (p->S + 1), part_s, st));
+        PLAN_HIP(hipMemcpyAsync(hb + 16 + k, p->slot_off + (size_t)k * (p->S + 1) + p->S, sizeof(int64_t),
+                                hipMemcpyDeviceToHost, st));
+    }
+    PLAN_HIP(hipStreamSynchronize(st));
+    for (int k = 0; k < K; ++k) p->num_edges[k] = hb[16 + k];
+#undef PLAN_HIP
+    (void)rc;
+    *out = p;
+    return SLG_OK;
+}
+
+slg_status slg_plan_info(const slg_plan *p, int32_t k, int64_t *num_edges, int64_t *two_paths) {
+    if (!p || k < 0 || k >= p->prm.k) return SLG_ERR_INVALID_ARG;
+    if (num_edges) *num_edges = p->num_edges[k];
+    if (two_paths) *two_paths = p->two_paths;
+    return SLG_OK;
+}
+
+slg_status slg_plan_emit(slg_plan *p, int64_t *const *row_ptr, int32_t *const *row,
+                         int32_t *const *col, int32_t *const *w, void *stream) {
+    if (!p || !row_ptr || !col || !w) return fail(p ? p->ctx : nullptr, SLG_ERR_INVALID_ARG, "null argument");
+    slg_context *ctx = p->ctx;
+    const int K = p->prm.k;
+    EmitParams prm = p->prm;
+    for (int k = 0; k < K; ++k) {
+        if (!row_ptr[k]) return fail(ctx, SLG_ERR_INVALID_ARG, "null row_ptr[%d]", k);
+        if (p->num_edges[k] > 0 && (!col[k] || !w[k]))
+            return fail(ctx, SLG_ERR_INVALID_ARG, "null col/w for threshold %d", k);
+        prm.row_ptr[k] = row_ptr[k];
+        prm.row[k] = row ? row[k] : nullptr;
+        prm.col[k] = col[k];
+        prm.w[k] = w[k];
+    }
+    SLG_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (st != p->st) {  // order after the plan's own work
+        hipEvent_t ev;
+        SLG_HIP(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        SLG_HIP(ctx, hipEventRecord(ev, p->st));
+        SLG_HIP(ctx, hipStreamWaitEvent(st, ev, 0));
+        SLG_HIP(ctx, hipEventDestroy(ev));
+    }
+    for (int c = 0; c < kLightClasses; ++c)
+        SLG_HIP(ctx, launch_light(c, true, p->lists[c], p->list_count[c], p->slots, p->pr, prm, nullptr,
+                                  p->slot_off, 0, st));
+    SLG_HIP(ctx, launch_heavy(true, p->lists[kLightClasses], p->list_count[kLightClasses], p->slots, p->pr,
+                              prm, nullptr, p->slot_off, 0, st));
+    SLG_HIP(ctx, launch_row_ptr(0, p->pr.m, p->slot_base, p->slot_off, p->S, prm, 0, st));
+    if (st != p->st) {  // scratch is freed on the plan's stream
+        hipEvent_t ev;
+        SLG_HIP(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        SLG_HIP(ctx, hipEventRecord(ev, st));
+        SLG_HIP(ctx, hipStreamWaitEvent(p->st, ev, 0));
+        SLG_HIP(ctx, hipEventDestroy(ev));
+    }
+    return SLG_OK;
+}
+
+slg_status slg_plan_destroy(slg_plan *p) {
+    if (!p) return SLG_ERR_INVALID_ARG;
+    p->scratch.release();
+    delete p;
+    return SLG_OK;
+}
+
+slg_status slg_line_graph(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num_s,
+                          void *stream, slg_result **out) {
+    if (!ctx || !out) return fail(ctx, SLG_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    slg_plan *p = nullptr;
+    slg_status rc = slg_plan_create(ctx, g, s, num_s, stream, &p);
+    if (rc != SLG_OK) return rc;
+    slg_result *r = new (std::nothrow) slg_result();
+    if (!r) {
+        slg_plan_destroy(p);
+        return fail(ctx, SLG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+    r->ctx = ctx;
+    r->st = static_cast<hipStream_t>(stream);
+    r->k = num_s;
+    r->m = g->inc.num_hyperedges;
+    r->two_paths = p->two_paths;
+    auto get = [&](void **ptr, size_t bytes) -> bool {
+        if (bytes == 0) bytes = 8;
+        if (ctx->has_alloc) {
+            *ptr = ctx->alloc.alloc(ctx->alloc.user, bytes, stream);
+        } else if (hipMallocAsync(ptr, bytes, r->st) != hipSuccess) {
+            *ptr = nullptr;
+        }
+        if (*ptr) r->owned.push_back(*ptr);
+        return *ptr != nullptr;
+    };
+    bool ok = true;
+    for (int k = 0; k < num_s && ok; ++k) {
+        const int64_t e = p->num_edges[k];
+        r->num_edges[k] = e;
+        ok = get(reinterpret_cast<void **>(&r->row_ptr[k]), (r->m + 1) * sizeof(int64_t)) &&
+             get(reinterpret_cast<void **>(&r->row[k]), e * sizeof(int32_t)) &&
+             get(reinterpret_cast<void **>(&r->col[k]), e * sizeof(int32_t)) &&
+             get(reinterpret_cast<void **>(&r->w[k]), e * sizeof(int32_t));
+    }
+    if (ok) rc = slg_plan_emit(p, r->row_ptr, r->row, r->col, r->w, stream);
+    slg_plan_destroy(p);
+    if (!ok || rc != SLG_OK) {
+        slg_result_free(r);
+        return ok ? rc : fail(ctx, SLG_ERR_OUT_OF_MEMORY, "result allocation failed");
+    }
+    *out = r;
+    return SLG_OK;
+}
+
+slg_status slg_result_info(const slg_result *r, int32_t k, int64_t *num_edges, int64_t *two_paths) {
+    if (!r || k < 0 || k >= r->k) return SLG_ERR_INVALID_ARG;
+    if (num_edges) *num_edges = r->num_edges[k];
+    if (two_paths) *two_paths = r->two_paths;
+    return SLG_OK;
+}
+
+slg_status slg_result_coo(const slg_result *r, int32_t k, const int32_t **i, const int32_t **j,
+                          const int32_t **w) {
+    if (!r || k < 0 || k >= r->k) return SLG_ERR_INVALID_ARG;
+    if (i) *i = r->row[k];
+    if (j) *j = r->col[k];
+    if (w) *w = r->w[k];
+    return SLG_OK;
+}
+
+slg_status slg_result_csr(const slg_result *r, int32_t k, const int64_t **row_ptr,
+                          const int32_t **col, const int32_t **w) {
+    if (!r || k < 0 || k >= r->k) return SLG_ERR_INVALID_ARG;
+    if (row_ptr) *row_ptr = r->row_ptr[k];
+    if (col) *col = r->col[k];
+    if (w) *w = r->w[k];
+    return SLG_OK;
+}
+
+slg_status slg_result_free(slg_result *r) {
+    if (!r) return SLG_ERR_INVALID_ARG;
+    slg_context *ctx = r->ctx;
+    for (void *ptr : r->owned) {
+        if (ctx && ctx->has_alloc)
+            ctx->alloc.release(ctx->alloc.user, ptr, r->st);
+        else
+            (void)hipFreeAsync(ptr, r->st);
+    }
+    delete r;
+    return SLG_OK;
+}
+
+}  // extern "C"

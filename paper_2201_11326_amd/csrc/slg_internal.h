@@ -1,0 +1,106 @@
+// Internal interface between the host API (slg_api.cpp) and the gfx950
+// kernels (slg_kernels.hip). Not installed; the public ABI is include/slg.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "slg.h"
+
+namespace slg {
+
+// ---- tuning constants of the hot path ------------------------------------
+constexpr int kWave = 64;              // CDNA wavefront width
+constexpr int kLightMax = 512;         // rows with <= this many 2-paths: wave-sort tier
+constexpr int kLightClasses = 4;       // 64, 128, 256, 512 keys per wave
+constexpr int kHeavyThreads = 512;     // workgroup of the bitmap-rank tier
+constexpr int kRangeBits = 1 << 17;    // hyperedge-id range of one heavy slot (bitmap bits)
+constexpr int kRangeWords = kRangeBits / 32;
+constexpr int kRankCap = 4096;         // overlap counters per rank window (LDS)
+constexpr int64_t kSlotWork = 1 << 16; // 2-paths per heavy slot before a row is split
+
+// Row classes written by the planning kernel.
+enum RowClass : uint8_t { kNone = 0, kLight0 = 1, kHeavy = kLight0 + kLightClasses };
+constexpr int kNumLists = kLightClasses + 1;  // light classes + heavy slots
+
+// Per-call parameters, passed by value and staged in LDS by each kernel so
+// that a runtime threshold index reads LDS, not a private copy.
+struct EmitParams {
+    int32_t k;                      // number of thresholds
+    int32_t s[SLG_MAX_S];           // strictly increasing, s[0] = s_min
+    int32_t *row[SLG_MAX_S];        // COO i per threshold (may be null)
+    int32_t *col[SLG_MAX_S];        // j per threshold
+    int32_t *w[SLG_MAX_S];          // overlap per threshold
+    int64_t *row_ptr[SLG_MAX_S];    // CSR offsets per threshold
+};
+
+// Device-side view of one hypergraph after pruning.
+struct Pruned {
+    int64_t m, n, nnz;
+    const int64_t *he_ptr;
+    const int32_t *he_idx;
+    const int64_t *vs_ptr;    // vertex lists restricted to E_{s_min}
+    const int32_t *vs_idx;
+    const int32_t *tail_beg;  // per incidence (i, v): first position in v's list after i
+};
+
+// Slot table: a slot is (row i, hyperedge-id range [ja, jb)) with its own
+// output segment; a light row is one slot.
+struct Slots {
+    int64_t count;
+    const int32_t *row;
+    const int32_t *ja;
+    const int32_t *jb;
+};
+
+// ---- launchers (all enqueue on `st`, return hipError_t) -------------------
+hipError_t launch_exclusive_scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *partials,
+                                     hipStream_t st);
+hipError_t launch_exclusive_scan_i32(const int32_t *in, int64_t n, int64_t *out, int64_t *partials,
+                                     hipStream_t st);
+hipError_t launch_exclusive_scan_u8(const uint8_t *in, int64_t n, int64_t *out, int64_t *partials,
+                                    hipStream_t st);
+int64_t scan_partials_size(int64_t n);
+
+// K1: keep flags per incidence of the vertex CSR, then compaction.
+hipError_t launch_keep_incidence(int64_t nnz, const int32_t *v_idx, const int64_t *he_ptr, int64_t m,
+                                 int32_t s_min, uint8_t *flag, hipStream_t st);
+hipError_t launch_compact_vertex_lists(int64_t n, int64_t nnz, const int64_t *v_ptr,
+                                       const int32_t *v_idx, const uint8_t *flag,
+                                       const int64_t *pos, int64_t *vs_ptr, int32_t *vs_idx,
+                                       hipStream_t st);
+
+// K1/K2: per kept row, tail offsets, 2-path work, last partner, slot count.
+hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t *tail_beg, int64_t *work,
+                           int32_t *jmax, int32_t *nslots, uint8_t *rclass,
+                           unsigned long long *class_count, int *err, hipStream_t st);
+hipError_t launch_fill_slots(int64_t m, const int64_t *slot_base, const int32_t *nslots,
+                             const int32_t *jmax, const int64_t *work, const uint8_t *rclass,
+                             int32_t *slot_row, int32_t *slot_ja, int32_t *slot_jb,
+                             int32_t *const *lists, unsigned long long *list_fill,
+                             hipStream_t st);
+
+// K3/K4/K5: count (EMIT=false) or emit (EMIT=true) per slot.
+hipError_t launch_light(int cls, bool emit, const int32_t *list, int64_t count, const Slots &sl,
+                        const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
+                        const int64_t *slot_off, int64_t out_base, hipStream_t st);
+hipError_t launch_heavy(bool emit, const int32_t *list, int64_t count, const Slots &sl,
+                        const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
+                        const int64_t *slot_off, int64_t out_base, hipStream_t st);
+
+// K6: row_ptr[k][i] = slot_off[k][slot_base[i]] - out_base, i in [row_lo, row_hi].
+hipError_t launch_row_ptr(int64_t row_lo, int64_t row_hi, const int64_t *slot_base,
+                          const int64_t *slot_off, int64_t slots, const EmitParams &ep,
+                          int64_t out_base, hipStream_t st);
+hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t value, hipStream_t st);
+
+// Validation kernels (SLG_VALIDATE).
+hipError_t launch_validate_ptr(const int64_t *ptr, int64_t rows, int64_t nnz, int *err,
+                               hipStream_t st);
+hipError_t launch_validate_rows(const int64_t *ptr, const int32_t *idx, int64_t rows,
+                                int64_t limit, int *err, hipStream_t st);
+hipError_t launch_validate_transpose(const int64_t *he_ptr, const int32_t *he_idx, int64_t m,
+                                     const int64_t *v_ptr, const int32_t *v_idx, int64_t n, int *err,
+                                     hipStream_t st);
+
+}  // namespace slg

@@ -1,0 +1,268 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bit-exact integer comparisons: row pointers, i, j and overlap of every edge.
+"""
+import numpy as np
+import pytest
+
+import hypergen as hg
+import oracle
+from gpu_util import (assert_matches_oracle, assert_rows_match_oracle, assert_well_formed, planted,
+                      run_gpu)
+from helpers import load_toy
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2201_11326_amd as slg
+    c = slg.Context(0)
+    yield c
+    c.close()
+
+
+def test_library_is_native(ctx):
+    import paper_2201_11326_amd as slg
+    assert slg.version().startswith("slg")
+
+
+def test_toy_example_each_s_and_ensemble(ctx):
+    inc, keep, lines, _ = load_toy()
+    for s in (1, 2, 3, 4):
+        (lg,) = run_gpu(ctx, inc, [s])
+        got = list(zip(lg.row.tolist(), lg.col.tolist(), lg.w.tolist()))
+        assert got == lines.get(s, []), f"L_{s}"
+        assert_matches_oracle(inc, lg, s, "toy")
+    outs = run_gpu(ctx, inc, [1, 2, 3, 4])
+    for lg in outs:
+        assert_matches_oracle(inc, lg, lg.s, "toy ensemble")
+    assert outs[0].two_paths == 9  # sum_v C(d(v), 2) for the example
+
+
+def test_toy_dual_is_s_clique(ctx):
+    inc, _, _, dual = load_toy()
+    (lg,) = run_gpu(ctx, inc.dual(), [1])
+    pairs = {(i, j): w for i, j, w in zip(lg.row.tolist(), lg.col.tolist(), lg.w.tolist())}
+    for (i, j, w) in dual[1]:
+        assert pairs[(i, j)] == w  # adj(b, c) = 3
+    assert_matches_oracle(inc.dual(), lg, 1, "dual")
+
+
+def test_tiny_uniform_full(ctx):
+    inc = hg.tiny_uniform()
+    for s in (1, 2, 3, 4):
+        (lg,) = run_gpu(ctx, inc, [s])
+        assert_matches_oracle(inc, lg, s, "tiny")
+        assert lg.two_paths == oracle.two_paths(inc, s)
+    outs = run_gpu(ctx, inc, [1, 2, 3, 4])
+    for lg in outs:
+        assert_matches_oracle(inc, lg, lg.s, "tiny ensemble")
+
+
+@pytest.mark.parametrize("seed,m,n,kmax,expo,s_list", [
+    (101, 3000, 400, 30, 0.8, [1]),
+    (102, 3000, 200, 40, 1.5, [2]),
+    (103, 2500, 150, 60, 1.5, [1, 2, 3, 5, 8]),
+    (104, 4000, 5000, 12, None, [1, 2]),
+    (105, 2000, 60, 25, 0.8, [3, 4]),
+    (106, 1500, 1000, 6, 1.5, [1, 3]),
+])
+def test_random_skewed_full(ctx, seed, m, n, kmax, expo, s_list):
+    inc = hg.random_small(seed, m, n, kmax, expo)  # includes empty hyperedges
+    outs = run_gpu(ctx, inc, s_list)
+    for lg in outs:
+        assert_matches_oracle(inc, lg, lg.s, f"seed {seed}")
+        assert_well_formed(inc, lg, lg.s)
+    assert outs[0].two_paths == oracle.two_paths(inc, s_list[0])
+
+
+def test_heavy_rank_windows_full(ctx):
+    # half of the rows share vertex 0: partner sets of several thousand per
+    # row, more than one LDS rank window per slot
+    inc = planted(12000, 40000, [([0], 2, 0), ([1, 2], 6, 0)], 3, seed=7)
+    outs = run_gpu(ctx, inc, [1, 2, 3])
+    for lg in outs:
+        assert_matches_oracle(inc, lg, lg.s, "windows")
+
+
+def test_heavy_range_split_sampled(ctx):
+    # rows span more hyperedge ids than one slot's bitmap covers
+    m = 300_000
+    inc = planted(m, 1_000_000, [([0], 300, 0), ([1], 900, 0)], 2, seed=8)
+    outs = run_gpu(ctx, inc, [1, 2])
+    rng = np.random.default_rng(0)
+    rows = np.unique(np.concatenate([np.arange(0, m, 300)[:400], rng.integers(0, m, 150), [m - 1]]))
+    for lg in outs:
+        assert_well_formed(inc, lg, lg.s)
+        assert_rows_match_oracle(inc, lg, lg.s, rows, "range split")
+
+
+def test_heavy_work_split_sampled(ctx):
+    # 20 shared vertices in 4,000 rows: w_i up to 8e4 2-paths, split by work
+    m = 200_000
+    inc = planted(m, 500_000, [(list(range(20)), 50, 0)], 2, seed=9)
+    outs = run_gpu(ctx, inc, [1, 20])
+    rows = np.concatenate([np.arange(0, m, 50)[:600], [1, 2, 3, m - 2, m - 1]])
+    for lg in outs:
+        assert_well_formed(inc, lg, lg.s)
+        assert_rows_match_oracle(inc, lg, lg.s, np.unique(rows), "work split")
+    assert outs[1].num_edges == 4000 * 3999 // 2  # the planted clique, overlap 20
+
+
+def test_edge_cases(ctx):
+    empty = hg.from_rows([], n=0)
+    (lg,) = run_gpu(ctx, empty, [1])
+    assert lg.num_edges == 0 and lg.row_ptr.tolist() == [0]
+    hollow = hg.from_rows([[], [], []], n=5)
+    (lg,) = run_gpu(ctx, hollow, [1])
+    assert lg.num_edges == 0 and lg.row_ptr.tolist() == [0, 0, 0, 0]
+    inc = hg.tiny_uniform()
+    (lg,) = run_gpu(ctx, inc, [int(inc.sizes().max()) + 1])
+    assert lg.num_edges == 0
+    dup = hg.from_rows([[0, 1, 2], [3, 4], [0, 1, 2], [5], [0, 1, 2]], n=8)
+    for lg in run_gpu(ctx, dup, [1, 3]):
+        assert_matches_oracle(dup, lg, lg.s, "duplicates")
+    single = hg.from_rows([[0, 1, 2, 3]], n=4)
+    (lg,) = run_gpu(ctx, single, [1])
+    assert lg.num_edges == 0
+
+
+def test_two_uniform_graph(ctx):
+    rng = np.random.default_rng(5)
+    nv = 300
+    pairs = set()
+    while len(pairs) < 2000:
+        a, b = sorted(rng.integers(0, nv, 2).tolist())
+        if a != b:
+            pairs.add((a, b))
+    inc = hg.from_rows(sorted(pairs), n=nv)
+    l1, l2 = run_gpu(ctx, inc, [1, 2])
+    assert_matches_oracle(inc, l1, 1, "2-uniform")
+    assert np.all(l1.w.numpy() == 1) and l2.num_edges == 0
+    deg = np.diff(inc.v_ptr)
+    assert l1.num_edges == int((deg * (deg - 1) // 2).sum())
+
+
+def test_ensemble_equals_single_runs_and_is_deterministic(ctx):
+    inc = hg.random_small(201, 5000, 300, 40, 1.5)
+    ens = run_gpu(ctx, inc, [1, 2, 4, 8])
+    again = run_gpu(ctx, inc, [1, 2, 4, 8])
+    for a, b in zip(ens, again):
+        assert np.array_equal(a.col.numpy(), b.col.numpy()) and np.array_equal(a.w.numpy(), b.w.numpy())
+    for lg in ens:
+        (single,) = run_gpu(ctx, inc, [lg.s])
+        for f in ("row_ptr", "row", "col", "w"):
+            assert np.array_equal(getattr(lg, f).numpy(), getattr(single, f).numpy()), f
+
+
+def test_one_shot_result_matches_plan(ctx):
+    inc = hg.random_small(202, 3000, 200, 30, 0.8)
+    a = run_gpu(ctx, inc, [1, 3])
+    b = run_gpu(ctx, inc, [1, 3], one_shot=True)
+    for x, y in zip(a, b):
+        for f in ("row_ptr", "row", "col", "w"):
+            assert np.array_equal(getattr(x, f).numpy(), getattr(y, f).numpy()), f
+
+
+def test_side_stream(ctx):
+    import torch
+    inc = hg.random_small(203, 2000, 100, 20, 1.5)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        outs = run_gpu(ctx, inc, [1, 2], stream=st)
+    torch.cuda.synchronize()
+    for lg in outs:
+        assert_matches_oracle(inc, lg, lg.s, "side stream")
+
+
+def test_power_law_config_ensemble_sampled(ctx):
+    """The power-law workload (n=1e6, m=5e5) with S = {1, 2, 4, 8}."""
+    import paper_2201_11326_amd as slg
+    import torch
+    inc = hg.power_law()
+    g = ctx.register_incidence(inc)
+    outs = ctx.line_graph(g, [1, 2, 4, 8])
+    assert outs[0].two_paths == oracle.two_paths(inc, 1)
+    sizes = np.diff(inc.he_ptr)
+    # heaviest rows by 2-path work plus the ends and a random sample
+    rng = np.random.default_rng(1)
+    big = np.argsort(-sizes)[:24]
+    rows = np.unique(np.concatenate([big, [0, 1, inc.m - 2, inc.m - 1], rng.integers(0, inc.m, 40)]))
+    for lg in outs:
+        # row-wise parity on the sampled rows
+        rp = lg.row_ptr.cpu().numpy()
+        ref = oracle.line_graph_rows(inc, lg.s, rows)
+        for k, i in enumerate(ref.rows):
+            a, b = int(rp[i]), int(rp[i + 1])
+            rj, rw = ref.row(k)
+            assert np.array_equal(lg.col[a:b].cpu().numpy(), rj), f"s={lg.s} row {i}"
+            assert np.array_equal(lg.w[a:b].cpu().numpy(), rw), f"s={lg.s} row {i}"
+        # properties at full size, checked on the device
+        assert int(lg.row_ptr[-1]) == lg.num_edges
+        assert bool((lg.row_ptr[1:] >= lg.row_ptr[:-1]).all())
+        assert bool((lg.col > lg.row).all()) and bool((lg.w >= lg.s).all())
+    # single-s run equals the ensemble's member
+    (s8,) = ctx.line_graph(g, [8])
+    assert torch.equal(s8.col, outs[3].col) and torch.equal(s8.w, outs[3].w)
+    assert torch.equal(s8.row_ptr, outs[3].row_ptr)
+    del outs
+    g.release()
+
+
+def test_errors(ctx):
+    import paper_2201_11326_amd as slg
+    inc = hg.tiny_uniform()
+    g = ctx.register_incidence(inc)
+    for bad in ([], [0], [2, 2], [3, 1], list(range(1, 18))):
+        with pytest.raises(slg.SlgError) as e:
+            ctx.line_graph(g, bad)
+        assert e.value.status == slg.SLG_ERR_INVALID_ARG
+    g.release()
+
+
+def test_validate_rejects_malformed(ctx):
+    import paper_2201_11326_amd as slg
+    import torch
+    inc = hg.random_small(301, 300, 50, 8, None, kmin=2)
+    ok = ctx.register_incidence(inc, validate=True)
+    ok.release()
+    dev = torch.device("cuda", 0)
+    T = lambda a, dt: torch.as_tensor(np.asarray(a), dtype=dt, device=dev)
+
+    def reg(he_ptr, he_idx, v_ptr, v_idx):
+        return ctx.register(inc.m, inc.n, T(he_ptr, torch.int64), T(he_idx, torch.int32),
+                            T(v_ptr, torch.int64), T(v_idx, torch.int32), validate=True)
+
+    unsorted = inc.he_idx.copy()
+    unsorted[0], unsorted[1] = unsorted[1], unsorted[0]
+    out_of_range = inc.he_idx.copy()
+    out_of_range[5] = inc.n + 3
+    bad_ptr = inc.he_ptr.copy()
+    bad_ptr[-1] -= 1
+    v_bad = inc.v_idx.copy()
+    nz = np.nonzero(np.diff(inc.v_ptr) > 0)[0][0]
+    v_bad[inc.v_ptr[nz]] = (v_bad[inc.v_ptr[nz]] + 1) % inc.m  # breaks the transpose
+    cases = [(inc.he_ptr, unsorted, inc.v_ptr, inc.v_idx),
+             (inc.he_ptr, out_of_range, inc.v_ptr, inc.v_idx),
+             (bad_ptr, inc.he_idx, inc.v_ptr, inc.v_idx)]
+    for c in cases:
+        with pytest.raises(slg.SlgError) as e:
+            reg(*c)
+        assert e.value.status == slg.SLG_ERR_INVALID_GRAPH
+    # a vertex CSR that is not the transpose: caught with VALIDATE, and by
+    # the planner even without it
+    srt = v_bad.copy()
+    for v in range(inc.n):
+        a, b = inc.v_ptr[v], inc.v_ptr[v + 1]
+        srt[a:b] = np.sort(srt[a:b])
+    if np.all(np.diff(srt[inc.v_ptr[nz]:inc.v_ptr[nz + 1]]) > 0):
+        with pytest.raises(slg.SlgError) as e:
+            reg(inc.he_ptr, inc.he_idx, inc.v_ptr, srt)
+        assert e.value.status == slg.SLG_ERR_INVALID_GRAPH
+        g = ctx.register(inc.m, inc.n, T(inc.he_ptr, torch.int64), T(inc.he_idx, torch.int32),
+                         T(inc.v_ptr, torch.int64), T(srt, torch.int32), validate=False)
+        with pytest.raises(slg.SlgError) as e:
+            ctx.line_graph(g, [1])
+        assert e.value.status == slg.SLG_ERR_INVALID_GRAPH
+        g.release()
