@@ -154,6 +154,17 @@ slg_status slg_plan_info(const slg_plan *p, int32_t k, int64_t *num_edges, int64
 slg_status slg_plan_emit(slg_plan *p, int64_t *const *row_ptr, int32_t *const *row,
                          int32_t *const *col, int32_t *const *w, void *stream);
 
+/*
+ * Shape of a plan, for measurement and tuning: fills up to `cap` entries of
+ * out[] (host array) with, in order:
+ *   [0] slots (output segments), [1..4] rows in the four wavefront-sort
+ *   classes (<= 64, 128, 256, 512 2-paths), [5] heavy slots, [6] heavy slots
+ *   of rows with >= 65535 members, [7] 2-paths (as slg_plan_info),
+ *   [8] 2-paths in heavy slots, [9] entries of the heavy boundary table.
+ * Returns the number of entries written in *count (may be NULL).
+ */
+slg_status slg_plan_stats(const slg_plan *p, int64_t *out, int32_t cap, int32_t *count);
+
 /* Free a plan's device scratch (ordered on the stream it was made on). */
 slg_status slg_plan_destroy(slg_plan *p);
 

@@ -95,6 +95,7 @@ def lib() -> ctypes.CDLL:
         "slg_plan_emit": (_i32, [_p, ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p),
                                  ctypes.POINTER(_p), _p]),
         "slg_plan_destroy": (_i32, [_p]),
+        "slg_plan_stats": (_i32, [_p, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i32)]),
         "slg_line_graph": (_i32, [_p, _p, ctypes.POINTER(_i32), _i32, _p, ctypes.POINTER(_p)]),
         "slg_result_info": (_i32, [_p, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
         "slg_result_coo": (_i32, [_p, _i32, ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
@@ -186,6 +187,15 @@ class Plan:
 
     def num_edges(self) -> List[int]:
         return [self.info(k)[0] for k in range(len(self.s))]
+
+    STAT_NAMES = ("slots", "light64", "light128", "light256", "light512", "heavy_slots",
+                  "heavy_wide_slots", "two_paths", "heavy_two_paths", "bound_entries")
+
+    def stats(self) -> dict:
+        out = (_i64 * 16)()
+        n = _i32()
+        self.ctx._check(lib().slg_plan_stats(self.handle, out, 16, ctypes.byref(n)))
+        return {name: int(out[t]) for t, name in enumerate(self.STAT_NAMES[: n.value])}
 
     def emit(self, row_ptr, row, col, w, stream=None):
         K = len(self.s)

@@ -17,6 +17,7 @@ using namespace slg;
 
 struct slg_context {
     int device = 0;
+    int heavy_resident = 0;  // persistent workgroups of the heavy tier
     uint64_t budget = 0;
     bool has_alloc = false;
     slg_allocator alloc{};
@@ -94,11 +95,16 @@ struct slg_plan {
     int64_t *slot_base = nullptr;  // [m+1]
     int64_t S = 0;                 // number of slots
     Slots slots{};
+    int32_t *bounds = nullptr;
+    int64_t *tickets = nullptr;    // work counters of the persistent heavy launches
+    HeavyDesc *heavy[2] = {};      // heavy and heavy-wide slot descriptors
     int32_t *lists[kNumLists] = {};
     int64_t list_count[kNumLists] = {};
     int64_t *slot_cnt = nullptr;   // [K][S]
     int64_t *slot_off = nullptr;   // [K][S+1]
     int64_t two_paths = 0;
+    int64_t heavy_two_paths = 0;
+    int64_t nbounds = 0;
     int64_t num_edges[SLG_MAX_S] = {};
 };
 
@@ -141,6 +147,7 @@ slg_status slg_context_create(int device, uint64_t mem_budget_bytes, const slg_a
         delete ctx;
         return SLG_ERR_DEVICE;
     }
+    ctx->heavy_resident = heavy_resident(device);
     // keep freed scratch in the stream-ordered pool between calls
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
@@ -286,7 +293,7 @@ slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int
 
     // K2: tails, 2-path work and slot counts per row
     int32_t *tail_beg, *jmax, *nslots;
-    int64_t *work, *work_pre, *counters, *part_m;
+    int64_t *work, *work_pre, *counters, *part_m, *bsize, *bbase;
     uint8_t *rclass;
     PLAN_HIP(sc.get(&tail_beg, nnz));
     PLAN_HIP(sc.get(&work, m));
@@ -294,6 +301,8 @@ slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int
     PLAN_HIP(sc.get(&jmax, m));
     PLAN_HIP(sc.get(&nslots, m));
     PLAN_HIP(sc.get(&rclass, m));
+    PLAN_HIP(sc.get(&bsize, m));
+    PLAN_HIP(sc.get(&bbase, m + 1));
     PLAN_HIP(sc.get(&counters, 16));
     PLAN_HIP(sc.get(&part_m, scan_partials_size(m)));
     PLAN_HIP(sc.get(&p->slot_base, m + 1));
@@ -302,13 +311,17 @@ slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int
     unsigned long long *class_count = reinterpret_cast<unsigned long long *>(counters);
     int *err = reinterpret_cast<int *>(counters + 8);
     unsigned long long *list_fill = reinterpret_cast<unsigned long long *>(counters + 9);
-    PLAN_HIP(launch_row_plan(pr, s_min, tail_beg, work, jmax, nslots, rclass, class_count, err, st));
+    PLAN_HIP(launch_row_plan(pr, s_min, tail_beg, work, jmax, nslots, rclass, bsize, class_count, err,
+                             reinterpret_cast<unsigned long long *>(counters + 15), st));
     PLAN_HIP(launch_exclusive_scan_i32(nslots, m, p->slot_base, part_m, st));
     PLAN_HIP(launch_exclusive_scan_i64(work, m, work_pre, part_m, st));
+    PLAN_HIP(launch_exclusive_scan_i64(bsize, m, bbase, part_m, st));
     int64_t *hb = ctx->pinned;
     PLAN_HIP(hipMemcpyAsync(hb, counters, 9 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     PLAN_HIP(hipMemcpyAsync(hb + 9, p->slot_base + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     PLAN_HIP(hipMemcpyAsync(hb + 10, work_pre + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    PLAN_HIP(hipMemcpyAsync(hb + 11, bbase + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    PLAN_HIP(hipMemcpyAsync(hb + 12, counters + 15, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     PLAN_HIP(hipStreamSynchronize(st));
     if (hb[8] & 0xffffffff)
         return bail(fail(ctx, SLG_ERR_INVALID_GRAPH,
@@ -316,19 +329,27 @@ slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int
     for (int c = 0; c < kNumLists; ++c) p->list_count[c] = hb[c];
     p->S = hb[9];
     p->two_paths = hb[10];
+    const int64_t nbounds = hb[11];
+    p->nbounds = nbounds;
+    p->heavy_two_paths = hb[12];
+    if (nbounds >= (int64_t(1) << 40))
+        return bail(fail(ctx, SLG_ERR_OVERFLOW, "boundary table too large"));
 
-    // slot table and tier lists
-    int32_t *slot_row, *slot_ja, *slot_jb;
+    // slot table, tier lists and the heavy rows' boundary table
+    int32_t *slot_row;
     PLAN_HIP(sc.get(&slot_row, p->S));
-    PLAN_HIP(sc.get(&slot_ja, p->S));
-    PLAN_HIP(sc.get(&slot_jb, p->S));
-    for (int c = 0; c < kNumLists; ++c) PLAN_HIP(sc.get(&p->lists[c], p->list_count[c]));
-    PLAN_HIP(launch_fill_slots(m, p->slot_base, nslots, jmax, work, rclass, slot_row, slot_ja, slot_jb,
-                               p->lists, list_fill, st));
+    PLAN_HIP(sc.get(&p->bounds, nbounds));
+    PLAN_HIP(sc.get(&p->tickets, 4));
+    for (int c = 0; c < kLightClasses; ++c) PLAN_HIP(sc.get(&p->lists[c], p->list_count[c]));
+    for (int h = 0; h < 2; ++h) PLAN_HIP(sc.get(&p->heavy[h], p->list_count[kLightClasses + h]));
+    int64_t *hat;  // first descriptor of each heavy row in its list
+    PLAN_HIP(sc.get(&hat, m));
+    PLAN_HIP(launch_fill_slots(m, inc.he_ptr, p->slot_base, nslots, jmax, rclass, bbase, hat, slot_row,
+                               p->lists, p->heavy, list_fill, st));
+    for (int h = 0; h < 2; ++h)
+        PLAN_HIP(launch_bounds(pr, p->heavy[h], p->list_count[kLightClasses + h], p->bounds, st));
     p->slots.count = p->S;
     p->slots.row = slot_row;
-    p->slots.ja = slot_ja;
-    p->slots.jb = slot_jb;
 
     // K3-K5 counting pass: per slot, per threshold, the number of edges
     const int K = num_s;
@@ -339,8 +360,10 @@ slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int
     for (int c = 0; c < kLightClasses; ++c)
         PLAN_HIP(launch_light(c, false, p->lists[c], p->list_count[c], p->slots, pr, p->prm, p->slot_cnt,
                               nullptr, 0, st));
-    PLAN_HIP(launch_heavy(false, p->lists[kLightClasses], p->list_count[kLightClasses], p->slots, pr, p->prm,
-                          p->slot_cnt, nullptr, 0, st));
+    for (int wide = 0; wide < 2; ++wide)
+        PLAN_HIP(launch_heavy(false, wide, p->heavy[wide], p->list_count[kLightClasses + wide], p->S,
+                              p->bounds, pr, p->prm, p->slot_cnt, nullptr, 0, p->tickets + wide,
+                              ctx->heavy_resident, st));
     for (int k = 0; k < K; ++k) {
         PLAN_HIP(launch_exclusive_scan_i64(p->slot_cnt + (size_t)k * p->S, p->S,
                                            p->slot_off + (size_t)k * (p->S + 1), part_s, st));
@@ -389,8 +412,10 @@ slg_status slg_plan_emit(slg_plan *p, int64_t *const *row_ptr, int32_t *const *r
     for (int c = 0; c < kLightClasses; ++c)
         SLG_HIP(ctx, launch_light(c, true, p->lists[c], p->list_count[c], p->slots, p->pr, prm, nullptr,
                                   p->slot_off, 0, st));
-    SLG_HIP(ctx, launch_heavy(true, p->lists[kLightClasses], p->list_count[kLightClasses], p->slots, p->pr,
-                              prm, nullptr, p->slot_off, 0, st));
+    for (int wide = 0; wide < 2; ++wide)
+        SLG_HIP(ctx, launch_heavy(true, wide, p->heavy[wide], p->list_count[kLightClasses + wide], p->S,
+                                  p->bounds, p->pr, prm, nullptr, p->slot_off, 0, p->tickets + 2 + wide,
+                                  ctx->heavy_resident, st));
     SLG_HIP(ctx, launch_row_ptr(0, p->pr.m, p->slot_base, p->slot_off, p->S, prm, 0, st));
     if (st != p->st) {  // scratch is freed on the plan's stream
         hipEvent_t ev;
@@ -399,6 +424,17 @@ slg_status slg_plan_emit(slg_plan *p, int64_t *const *row_ptr, int32_t *const *r
         SLG_HIP(ctx, hipStreamWaitEvent(p->st, ev, 0));
         SLG_HIP(ctx, hipEventDestroy(ev));
     }
+    return SLG_OK;
+}
+
+slg_status slg_plan_stats(const slg_plan *p, int64_t *out, int32_t cap, int32_t *count) {
+    if (!p || (!out && cap > 0) || cap < 0) return SLG_ERR_INVALID_ARG;
+    const int64_t vals[10] = {p->S, p->list_count[0], p->list_count[1], p->list_count[2],
+                              p->list_count[3], p->list_count[4], p->list_count[5], p->two_paths,
+                              p->heavy_two_paths, p->nbounds};
+    int32_t n = cap < 10 ? cap : 10;
+    for (int32_t t = 0; t < n; ++t) out[t] = vals[t];
+    if (count) *count = n;
     return SLG_OK;
 }
 

@@ -16,12 +16,18 @@ constexpr int kLightClasses = 4;       // 64, 128, 256, 512 keys per wave
 constexpr int kHeavyThreads = 512;     // workgroup of the bitmap-rank tier
 constexpr int kRangeBits = 1 << 17;    // hyperedge-id range of one heavy slot (bitmap bits)
 constexpr int kRangeWords = kRangeBits / 32;
-constexpr int kRankCap = 4096;         // overlap counters per rank window (LDS)
-constexpr int64_t kSlotWork = 1 << 16; // 2-paths per heavy slot before a row is split
+constexpr int kRankCap = 8192;         // overlap counters per rank window (LDS, u16)
+constexpr int64_t kSlotWork = 8192;    // 2-paths per heavy slot before a row is split
+constexpr int kWideMembers = 65535;    // rows this large need u32 overlap counters
 
 // Row classes written by the planning kernel.
-enum RowClass : uint8_t { kNone = 0, kLight0 = 1, kHeavy = kLight0 + kLightClasses };
-constexpr int kNumLists = kLightClasses + 1;  // light classes + heavy slots
+enum RowClass : uint8_t {
+    kNone = 0,
+    kLight0 = 1,
+    kHeavy = kLight0 + kLightClasses,  // bitmap-rank tier, u16 counters
+    kHeavyWide = kHeavy + 1            // bitmap-rank tier, u32 counters
+};
+constexpr int kNumLists = kLightClasses + 2;  // light classes + heavy + heavy-wide slots
 
 // Per-call parameters, passed by value and staged in LDS by each kernel so
 // that a runtime threshold index reads LDS, not a private copy.
@@ -44,13 +50,21 @@ struct Pruned {
     const int32_t *tail_beg;  // per incidence (i, v): first position in v's list after i
 };
 
-// Slot table: a slot is (row i, hyperedge-id range [ja, jb)) with its own
-// output segment; a light row is one slot.
+// Slot table: a slot is (row i, hyperedge-id range) with its own output
+// segment; a light row is one slot, a heavy row one or more.
 struct Slots {
     int64_t count;
     const int32_t *row;
-    const int32_t *ja;
-    const int32_t *jb;
+};
+
+// One heavy slot, stored in processing order. The row's boundary table
+// holds, for member q of e_i, bounds[bptr + q] = first position of q's tail
+// with a partner >= ja, and bounds[bptr + k + q] = the same for jb (the next
+// slot's start, or the tail end for the row's last slot).
+struct HeavyDesc {
+    int32_t row, ja, jb, k;  // row i, partner range [ja, jb), k = |e_i|
+    int32_t slot, last;      // output segment; 1 on the row's last slot
+    int64_t bptr;
 };
 
 // ---- launchers (all enqueue on `st`, return hipError_t) -------------------
@@ -72,21 +86,28 @@ hipError_t launch_compact_vertex_lists(int64_t n, int64_t nnz, const int64_t *v_
 
 // K1/K2: per kept row, tail offsets, 2-path work, last partner, slot count.
 hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t *tail_beg, int64_t *work,
-                           int32_t *jmax, int32_t *nslots, uint8_t *rclass,
-                           unsigned long long *class_count, int *err, hipStream_t st);
-hipError_t launch_fill_slots(int64_t m, const int64_t *slot_base, const int32_t *nslots,
-                             const int32_t *jmax, const int64_t *work, const uint8_t *rclass,
-                             int32_t *slot_row, int32_t *slot_ja, int32_t *slot_jb,
-                             int32_t *const *lists, unsigned long long *list_fill,
-                             hipStream_t st);
+                           int32_t *jmax, int32_t *nslots, uint8_t *rclass, int64_t *bsize,
+                           unsigned long long *class_count, int *err,
+                           unsigned long long *heavy_work, hipStream_t st);
+hipError_t launch_fill_slots(int64_t m, const int64_t *he_ptr, const int64_t *slot_base,
+                             const int32_t *nslots, const int32_t *jmax, const uint8_t *rclass,
+                             const int64_t *bbase, int64_t *hat, int32_t *slot_row, int32_t *const *lists,
+                             HeavyDesc *const *heavy, unsigned long long *list_fill, hipStream_t st);
+hipError_t launch_bounds(const Pruned &g, const HeavyDesc *desc, int64_t count, int32_t *bounds,
+                         hipStream_t st);
 
 // K3/K4/K5: count (EMIT=false) or emit (EMIT=true) per slot.
 hipError_t launch_light(int cls, bool emit, const int32_t *list, int64_t count, const Slots &sl,
                         const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
                         const int64_t *slot_off, int64_t out_base, hipStream_t st);
-hipError_t launch_heavy(bool emit, const int32_t *list, int64_t count, const Slots &sl,
-                        const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
-                        const int64_t *slot_off, int64_t out_base, hipStream_t st);
+// Persistent launch: `resident` workgroups (0 = a default) take slots from
+// the device counter `ticket` (reset here, before the launch).
+hipError_t launch_heavy(bool emit, bool wide, const HeavyDesc *desc, int64_t count, int64_t slots,
+                        const int32_t *bounds, const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
+                        const int64_t *slot_off, int64_t out_base, int64_t *ticket, int resident,
+                        hipStream_t st);
+// Workgroups of the heavy kernel that fit on the device at once.
+int heavy_resident(int device);
 
 // K6: row_ptr[k][i] = slot_off[k][slot_base[i]] - out_base, i in [row_lo, row_hi].
 hipError_t launch_row_ptr(int64_t row_lo, int64_t row_hi, const int64_t *slot_base,

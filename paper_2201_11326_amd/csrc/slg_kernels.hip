@@ -90,6 +90,35 @@ __device__ __forceinline__ T block_excl_scan(T x, T *wsum, T &total) {
     return pre + incl - x;
 }
 
+// As block_excl_scan, without the trailing barrier: the caller guarantees
+// a workgroup barrier before `wsum` is written again.
+template <int NT, typename T>
+__device__ __forceinline__ T block_excl_scan_open(T x, T *wsum, T &total) {
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    T incl = wave_incl_scan(x);
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    T pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+        T t = wsum[w];
+        pre += (w < wave) ? t : T(0);
+        tot += t;
+    }
+    total = tot;
+    return pre + incl - x;
+}
+
+// Copy the by-value parameter block into LDS, one dword per thread (the
+// caller follows with a workgroup barrier).
+__device__ __forceinline__ void stage_params(EmitParams *dst, const EmitParams &src) {
+    constexpr int kWords = (int)(sizeof(EmitParams) / 4);
+    static_assert(sizeof(EmitParams) % 4 == 0, "EmitParams is dword-sized");
+    const int32_t *from = reinterpret_cast<const int32_t *>(&src);
+    int32_t *to = reinterpret_cast<int32_t *>(dst);
+    for (int x = threadIdx.x; x < kWords; x += blockDim.x) to[x] = from[x];
+}
+
 // First position in a[lo, hi) holding a value >= key (a sorted ascending).
 __device__ __forceinline__ int lower_bound_i32(const int32_t *__restrict__ a, int lo, int hi,
                                                int key) {
@@ -228,10 +257,14 @@ __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min,
                                                        int32_t *__restrict__ jmax_out,
                                                        int32_t *__restrict__ nslots,
                                                        uint8_t *__restrict__ rclass,
+                                                       int64_t *__restrict__ bsize,
                                                        unsigned long long *__restrict__ class_count,
-                                                       int *__restrict__ err) {
+                                                       int *__restrict__ err,
+                                                       unsigned long long *__restrict__ heavy_work) {
     __shared__ unsigned long long ccount[kNumLists];
+    __shared__ unsigned long long hwork;
     if (threadIdx.x < kNumLists) ccount[threadIdx.x] = 0;
+    if (threadIdx.x == 0) hwork = 0;
     __syncthreads();
     const int lane = lane_id();
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
@@ -278,7 +311,7 @@ __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min,
                     cls = kLight0 + light_class(w);
                     ns = 1;
                 } else {
-                    cls = kHeavy;
+                    cls = (p1 - p0 >= kWideMembers) ? kHeavyWide : kHeavy;
                     const int64_t range = (int64_t)jm - i;  // partners lie in [i+1, jm]
                     const int64_t by_range = (range + kRangeBits - 1) / kRangeBits;
                     const int64_t by_work = (w + kSlotWork - 1) / kSlotWork;
@@ -290,21 +323,25 @@ __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min,
             jmax_out[i] = jm;
             nslots[i] = (int32_t)ns;
             rclass[i] = (uint8_t)cls;
+            bsize[i] = cls >= kHeavy ? (ns + 1) * (p1 - p0) : 0;
             if (cls != kNone) atomicAdd(&ccount[cls - 1], (unsigned long long)ns);
+            if (cls >= kHeavy) atomicAdd(&hwork, (unsigned long long)w);
         }
     }
     __syncthreads();
     if (threadIdx.x < kNumLists && ccount[threadIdx.x])
         atomicAdd(&class_count[threadIdx.x], ccount[threadIdx.x]);
+    if (threadIdx.x == 0 && hwork) atomicAdd(heavy_work, hwork);
 }
 
-// One thread per row: write the row's slots and append them to the tier lists.
+// One thread per row: write the row's slots and append them to the tier
+// lists (light: slot ids; heavy: slot descriptors).
 __global__ __launch_bounds__(256) void fill_slots_kernel(
-    int64_t m, const int64_t *__restrict__ slot_base, const int32_t *__restrict__ nslots,
-    const int32_t *__restrict__ jmax, const uint8_t *__restrict__ rclass,
-    int32_t *__restrict__ slot_row, int32_t *__restrict__ slot_ja, int32_t *__restrict__ slot_jb,
-    int32_t *l0, int32_t *l1, int32_t *l2, int32_t *l3, int32_t *lh,
-    unsigned long long *__restrict__ list_fill) {
+    int64_t m, const int64_t *__restrict__ he_ptr, const int64_t *__restrict__ slot_base,
+    const int32_t *__restrict__ nslots, const int32_t *__restrict__ jmax,
+    const uint8_t *__restrict__ rclass, const int64_t *__restrict__ bbase,
+    int32_t *__restrict__ slot_row, int32_t *l0, int32_t *l1, int32_t *l2, int32_t *l3,
+    int64_t *__restrict__ hat, unsigned long long *__restrict__ list_fill) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = lane_id();
     int cls = kNone;
@@ -331,19 +368,51 @@ __global__ __launch_bounds__(256) void fill_slots_kernel(
         if (mine) {
             lists[c][at + bits_below(mask)] = (int32_t)base;
             slot_row[base] = (int32_t)i;
-            slot_ja[base] = (int32_t)i + 1;
-            slot_jb[base] = jm + 1;
         }
     }
-    if (cls == kHeavy && ns > 0) {
-        const unsigned long long at = atomicAdd(&list_fill[kLightClasses], (unsigned long long)ns);
-        const int64_t range = (int64_t)jm - i;
-        for (int t = 0; t < ns; ++t) {
-            const int64_t s = base + t;
-            slot_row[s] = (int32_t)i;
-            slot_ja[s] = (int32_t)(i + 1 + range * t / ns);
-            slot_jb[s] = (int32_t)(i + 1 + range * (t + 1) / ns);
-            lh[at + t] = (int32_t)s;
+    // heavy rows: reserve the row's descriptors (written by heavy_desc_kernel),
+    // one atomic per wavefront and class
+#pragma unroll
+    for (int c = kHeavy; c <= kHeavyWide; ++c) {
+        const int mine = (cls == c) ? ns : 0;
+        const int incl = wave_incl_scan(mine);
+        const int tot = __shfl(incl, 63);
+        if (!tot) continue;
+        unsigned long long at = 0;
+        if (lane == 63) at = atomicAdd(&list_fill[c - 1], (unsigned long long)tot);
+        at = __shfl(at, 63);
+        if (mine) hat[i] = (int64_t)(at + incl - mine);
+    }
+}
+
+// One wavefront per heavy row, one lane per slot: the slot descriptors.
+__global__ __launch_bounds__(256) void heavy_desc_kernel(
+    int64_t m, const int64_t *__restrict__ he_ptr, const int64_t *__restrict__ slot_base,
+    const int32_t *__restrict__ nslots, const int32_t *__restrict__ jmax,
+    const uint8_t *__restrict__ rclass, const int64_t *__restrict__ bbase,
+    const int64_t *__restrict__ hat, int32_t *__restrict__ slot_row, HeavyDesc *hh, HeavyDesc *hw) {
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; i < m; i += nwaves) {
+        const int cls = rclass[i];
+        if (cls < kHeavy) continue;
+        const int ns = nslots[i];
+        HeavyDesc *lst = (cls == kHeavy ? hh : hw) + hat[i];
+        const int64_t base = slot_base[i];
+        const int64_t range = (int64_t)jmax[i] - i;
+        const int k = (int)(he_ptr[i + 1] - he_ptr[i]);
+        const int64_t bb = bbase[i];
+        for (int t = lane; t < ns; t += 64) {
+            HeavyDesc d;
+            d.row = (int32_t)i;
+            d.ja = (int32_t)(i + 1 + range * t / ns);
+            d.jb = (int32_t)(i + 1 + range * (t + 1) / ns);
+            d.k = k;
+            d.slot = (int32_t)(base + t);
+            d.last = t == ns - 1;
+            d.bptr = bb + (int64_t)t * k;
+            slot_row[base + t] = (int32_t)i;
+            lst[t] = d;
         }
     }
 }
@@ -394,7 +463,7 @@ __global__ __launch_bounds__(256) void light_kernel(const int32_t *__restrict__ 
     constexpr int P = 64 * KPL;
     __shared__ int32_t buf[4][P];
     __shared__ EmitParams sp;  // thresholds and outputs, indexed by a uniform k
-    if (threadIdx.x == 0) sp = prm;
+    stage_params(&sp, prm);
     __syncthreads();
     const EmitParams *ep = &sp;
     const int lane = lane_id();
@@ -482,112 +551,220 @@ __global__ __launch_bounds__(256) void light_kernel(const int32_t *__restrict__ 
 // ---------------------------------------------------------------------------
 // K3-K5 heavy tier: one workgroup per slot, LDS bitmap + rank counters
 // ---------------------------------------------------------------------------
-constexpr int kHW = kHeavyThreads / 64;  // wavefronts per heavy workgroup
+constexpr int kHW = kHeavyThreads / 64;              // wavefronts per heavy workgroup
+constexpr int kSuperWords = 1024;                    // words per rank superblock (32768 bits)
+constexpr int kSupers = kRangeWords / kSuperWords;
+
+template <bool WIDE>
+struct CounterCap {  // u16 counters packed in pairs, or u32 counters
+    static constexpr int ranks = WIDE ? kRankCap / 2 : kRankCap;
+};
 
 struct HeavySmem {
-    uint32_t bitmap[kRangeWords];       // partner j present in the slot range
-    uint32_t wpre[kRangeWords + 1];     // exclusive prefix popcount per word
-    uint32_t cnt[kRankCap];             // overlap counter per rank in window
-    int32_t keys[kRankCap];             // partner id per rank in window (emit)
-    int32_t seg_a[kHeavyThreads];       // tail segment start per vertex batch
-    int32_t seg_pre[kHeavyThreads + 1]; // flattened start per vertex batch
+    uint32_t bitmap[kRangeWords];        // partner j of the slot range present
+    uint16_t wpre[kRangeWords];          // low 16 bits of the word's exclusive popcount prefix
+    uint32_t sup[kSupers + 1];           // full prefix at each superblock start; sup[kSupers] = total
+    uint32_t cnt[kRankCap / 2];          // overlap counters of the current rank window
+    int32_t buf[kRankCap];               // pass-1 partners, then partner id per rank (emit)
+    int32_t seg_a[kHeavyThreads];        // segment start per member of the batch
+    int32_t seg_pre[kHeavyThreads + 1];  // flattened start per member of the batch
     int32_t wsum[kHW];
     int32_t wtot[SLG_MAX_S][kHW];
     unsigned long long acc[SLG_MAX_S];
     long long obase[SLG_MAX_S];
 };
 
-// Calls f(j) for every 2-path (e_i, v, e_j) with j in [ka, kb), over the
-// incidences [p0, p1) of row i. Tails are clipped to the range by binary
-// search; the flattened 2-path list of each batch of vertices is cut into
-// equal pieces, one per wavefront, so a heavy vertex's tail is shared by all
-// wavefronts of the workgroup. Ends with a workgroup barrier.
-template <typename F>
-__device__ __forceinline__ void for_each_2path(const Pruned &g, int64_t p0, int64_t p1, int ka,
-                                               int kb, HeavySmem &sm, F &&f) {
-    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-    for (int64_t vb = p0; vb < p1; vb += kHeavyThreads) {
-        const int64_t p = vb + tid;
-        int a = 0, len = 0;
-        if (p < p1) {
-            const int v = g.he_idx[p];
-            int beg = g.tail_beg[p];
-            int end = (int)g.vs_ptr[v + 1];
-            if (beg < end) {
-                if (g.vs_idx[beg] < ka) beg = lower_bound_i32(g.vs_idx, beg, end, ka);
-                if (beg < end && g.vs_idx[end - 1] >= kb) end = lower_bound_i32(g.vs_idx, beg, end, kb);
-                a = beg;
-                len = end > beg ? end - beg : 0;
-            }
+// Rank of the first bit of word x (x < number of words in use).
+__device__ __forceinline__ uint32_t word_rank(const HeavySmem &sm, int x) {
+    const uint32_t base = sm.sup[x / kSuperWords];
+    if ((x % kSuperWords) == 0) return base;
+    return base + ((uint32_t)(sm.wpre[x] - (uint16_t)base) & 0xFFFFu);
+}
+
+// Lay out segments [a, a+len) of one batch of members for the balanced
+// walk; returns the batch's 2-path count. Ends with a workgroup barrier.
+__device__ __forceinline__ int layout_segments(int a, int len, HeavySmem &sm) {
+    const int tid = threadIdx.x;
+    int total;
+    const int excl = block_excl_scan_open<kHeavyThreads>(len, sm.wsum, total);
+    sm.seg_a[tid] = a;
+    sm.seg_pre[tid] = excl;
+    if (tid == 0) sm.seg_pre[kHeavyThreads] = total;
+    __syncthreads();
+    return total;
+}
+
+// Segment of member q = qb + tid from the boundary table, optionally clipped
+// to [ka, kb) by binary search.
+template <bool CLIP>
+__device__ __forceinline__ void member_segment(const int32_t *__restrict__ vs_idx,
+                                               const int32_t *__restrict__ bounds, int64_t bptr,
+                                               int k, int qb, int ka, int kb, int &a, int &len) {
+    const int q = qb + threadIdx.x;
+    a = 0;
+    len = 0;
+    if (q < k) {
+        a = bounds[bptr + q];
+        int b = bounds[bptr + k + q];
+        if (CLIP && a < b) {
+            if (vs_idx[a] < ka) a = lower_bound_i32(vs_idx, a, b, ka);
+            if (a < b && vs_idx[b - 1] >= kb) b = lower_bound_i32(vs_idx, a, b, kb);
         }
-        int total;
-        const int excl = block_excl_scan<kHeavyThreads>(len, sm.wsum, total);
-        sm.seg_a[tid] = a;
-        sm.seg_pre[tid] = excl;
-        if (tid == 0) sm.seg_pre[kHeavyThreads] = total;
-        __syncthreads();
-        if (total > 0) {
-            const int per = (total + kHW - 1) / kHW;
-            const int c0 = wave * per;
-            const int c1 = min(total, c0 + per);
-            if (c0 < c1) {
-                int lo = 0, hi = kHeavyThreads;  // seg_pre[lo] <= c0 < seg_pre[hi]
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (sm.seg_pre[mid] <= c0)
-                        lo = mid;
-                    else
-                        hi = mid;
-                }
-                int u = lo, pos = c0;
-                while (pos < c1) {
-                    const int ue = min(c1, sm.seg_pre[u + 1]);
-                    const int base = sm.seg_a[u] - sm.seg_pre[u];
-                    for (int q = pos + lane; q < ue; q += 64) f(g.vs_idx[base + q]);
-                    pos = ue;
-                    ++u;
-                }
-            }
-        }
-        __syncthreads();
+        len = b > a ? b - a : 0;
     }
 }
 
-template <bool EMIT>
-__global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(const int32_t *__restrict__ list,
-                                                              int64_t count, Slots sl, Pruned g,
+// Largest u in [lo, hi] with seg_pre[u] <= f (seg_pre is non-decreasing).
+__device__ __forceinline__ int segment_of(const int32_t *seg_pre, int lo, int hi, int f) {
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg_pre[mid] <= f)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Calls f(f_idx, j) for every partner of the laid-out segments, f_idx being
+// the position in the batch's flattened 2-path list. Each wavefront takes
+// an equal share of the list (so a heavy vertex's tail is shared by all
+// wavefronts) and walks it in pieces of 64*kWalkUnroll positions: every
+// lane finds the segment of each of its positions by binary search between
+// the piece's first and last segment, then issues all its loads together,
+// so a piece costs one round trip however many tails it touches.
+constexpr int kWalkUnroll = 8;
+
+template <typename F>
+__device__ __forceinline__ void walk_segments(const int32_t *__restrict__ vs_idx, int total,
+                                              const HeavySmem &sm, F &&f) {
+    if (total <= 0) return;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const int per = (total + kHW - 1) / kHW;
+    const int c0 = wave * per;
+    const int c1 = min(total, c0 + per);
+    if (c0 >= c1) return;
+    int ufirst = segment_of(sm.seg_pre, 0, kHeavyThreads - 1, c0);
+    for (int pb = c0; pb < c1; pb += 64 * kWalkUnroll) {
+        const int plast = min(c1, pb + 64 * kWalkUnroll) - 1;
+        const int ulast = segment_of(sm.seg_pre, ufirst, kHeavyThreads - 1, plast);
+        int jr[kWalkUnroll];
+#pragma unroll
+        for (int r = 0; r < kWalkUnroll; ++r) {
+            const int fq = min(pb + lane + 64 * r, plast);
+            const int u = segment_of(sm.seg_pre, ufirst, ulast, fq);
+            jr[r] = vs_idx[sm.seg_a[u] + (fq - sm.seg_pre[u])];
+        }
+#pragma unroll
+        for (int r = 0; r < kWalkUnroll; ++r) {
+            const int fr = pb + lane + 64 * r;
+            if (fr <= plast) f(fr, jr[r]);
+        }
+        ufirst = ulast;
+    }
+}
+
+template <bool WIDE>
+__device__ __forceinline__ void count_add(uint32_t *cnt, uint32_t r) {
+    if (WIDE)
+        atomicAdd(&cnt[r], 1u);
+    else
+        atomicAdd(&cnt[r >> 1], 1u << ((r & 1u) << 4));
+}
+
+template <bool WIDE>
+__device__ __forceinline__ int count_get(const uint32_t *cnt, int r) {
+    if (WIDE) return (int)cnt[r];
+    return (int)((cnt[r >> 1] >> ((r & 1) << 4)) & 0xFFFFu);
+}
+
+template <bool EMIT, bool WIDE>
+__global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(const HeavyDesc *__restrict__ desc,
+                                                              int64_t count, int64_t S,
+                                                              const int32_t *__restrict__ bounds,
+                                                              const int32_t *__restrict__ vs_idx,
                                                               EmitParams prm,
                                                               int64_t *__restrict__ slot_cnt,
                                                               const int64_t *__restrict__ slot_off,
-                                                              int64_t out_base) {
+                                                              int64_t out_base,
+                                                              unsigned long long *__restrict__ ticket) {
+    constexpr int kCap = CounterCap<WIDE>::ranks;
     __shared__ HeavySmem sm;
     __shared__ EmitParams sp;  // thresholds and outputs, indexed by a uniform k
+    __shared__ int64_t next_slot;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
-    if (tid == 0) sp = prm;
+    stage_params(&sp, prm);
+    if (tid == 0) next_slot = (int64_t)atomicAdd(ticket, 1ull);
+    for (int x = tid; x < kRangeWords; x += kHeavyThreads) sm.bitmap[x] = 0u;
+    for (int x = tid; x < kRankCap / 2; x += kHeavyThreads) sm.cnt[x] = 0u;
     __syncthreads();
     const EmitParams *ep = &sp;
     const int K = ep->k;
-    const int64_t S = sl.count;
     const bool only_presence = !EMIT && K == 1 && ep->s[0] <= 1;
+    int64_t it = next_slot;
+    if (it >= count) return;
 
-    for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
-        const int slot = list[it];
-        const int i = sl.row[slot], ja = sl.ja[slot], jb = sl.jb[slot];
+    // Persistent workgroups take slots from a ticket counter. Software
+    // pipeline: the next slot's descriptor and this thread's member segment
+    // are loaded while the current slot is processed.
+    HeavyDesc nd = desc[it];
+    int na = 0, nb = 0;
+    if (tid < nd.k) {
+        na = bounds[nd.bptr + tid];
+        nb = bounds[nd.bptr + nd.k + tid];
+    }
+    while (true) {
+        const HeavyDesc d = nd;
+        const int ra = na, rb = nb;
+        if (tid == 0) next_slot = (int64_t)atomicAdd(ticket, 1ull);
+
+        const int i = d.row, ja = d.ja, jb = d.jb, k = d.k, slot = d.slot;
         const int nw = (jb - ja + 31) >> 5;
-        const int64_t p0 = g.he_ptr[i], p1 = g.he_ptr[i + 1];
-        for (int x = tid; x < nw; x += kHeavyThreads) sm.bitmap[x] = 0u;
+        const unsigned span = (unsigned)(jb - ja);
+        // bitmap and counters are all-zero here: cleared before the first
+        // slot and at the end of every slot
         if (tid < SLG_MAX_S) {
             sm.acc[tid] = 0;
             sm.obase[tid] = (EMIT && tid < K) ? slot_off[(int64_t)tid * (S + 1) + slot] - out_base : 0;
         }
         __syncthreads();
+        const int64_t it_next = next_slot;
+        const bool have_next = it_next < count;
+        if (have_next) nd = desc[it_next];
 
-        // pass 1: mark every partner j of the slot's range
-        const unsigned span = (unsigned)(jb - ja);
-        for_each_2path(g, p0, p1, ja, jb, sm, [&](int j) {
+        // pass 1: mark every partner j of the slot's range; keep the partners
+        // in LDS when they fit, so that pass 2 reads no global memory
+        const bool one_batch = k <= kHeavyThreads;
+        int total1 = 0;
+        bool cached = false;
+        auto mark = [&](int, int j) {
             const unsigned off = (unsigned)(j - ja);
             if (off < span) atomicOr(&sm.bitmap[off >> 5], 1u << (off & 31));
-        });
+        };
+        if (one_batch) {
+            const int len = (tid < k && rb > ra) ? rb - ra : 0;
+            total1 = layout_segments(ra, len, sm);
+            cached = total1 <= kRankCap;
+            if (cached)
+                walk_segments(vs_idx, total1, sm, [&](int f, int j) {
+                    sm.buf[f] = j;
+                    mark(f, j);
+                });
+            else
+                walk_segments(vs_idx, total1, sm, mark);
+            __syncthreads();
+        } else {
+            for (int qb = 0; qb < k; qb += kHeavyThreads) {
+                int a, len;
+                member_segment<false>(vs_idx, bounds, d.bptr, k, qb, 0, 0, a, len);
+                walk_segments(vs_idx, layout_segments(a, len, sm), sm, mark);
+                __syncthreads();
+            }
+        }
+        if (have_next && tid < nd.k) {  // prefetch the next slot's segments
+            na = bounds[nd.bptr + tid];
+            nb = bounds[nd.bptr + nd.k + tid];
+        }
 
         // rank of a partner = number of marked partners below it
         constexpr int kWPT = kRangeWords / kHeavyThreads;
@@ -600,107 +777,173 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(const int32_t *__r
             mine += loc[r];
         }
         int distinct;
-        int run = block_excl_scan<kHeavyThreads>(mine, sm.wsum, distinct);
+        int run = block_excl_scan_open<kHeavyThreads>(mine, sm.wsum, distinct);
 #pragma unroll
         for (int r = 0; r < kWPT; ++r) {
             const int x = tid * kWPT + r;
-            if (x < nw) sm.wpre[x] = run;
+            sm.wpre[x] = (uint16_t)run;
+            if ((x % kSuperWords) == 0) sm.sup[x / kSuperWords] = (uint32_t)run;
             run += loc[r];
         }
-        if (tid == 0) sm.wpre[nw] = distinct;
+        if (tid == 0) sm.sup[kSupers] = (uint32_t)distinct;
         __syncthreads();
 
         if (only_presence) {  // L_1 alone: every marked partner is an edge
             if (tid == 0) slot_cnt[slot] = distinct;
+            for (int x = tid; x < nw; x += kHeavyThreads) sm.bitmap[x] = 0u;
             __syncthreads();
+            if (!have_next) break;
             continue;
         }
 
-        // windows of at most kRankCap ranks, cut at word boundaries
+        // windows of at most kCap ranks, cut at word boundaries
         int w0 = 0;
         while (w0 < nw) {
-            const int r0 = sm.wpre[w0];
-            int lo = w0 + 1, hi = nw;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if ((int)sm.wpre[mid] - r0 <= kRankCap)
-                    lo = mid;
+            const uint32_t r0 = word_rank(sm, w0);
+            int wl = w0 + 1, wh = nw;
+            if ((uint32_t)distinct - r0 <= (uint32_t)kCap) wl = wh = nw;  // one window holds the rest
+            while (wl < wh) {
+                const int mid = (wl + wh + 1) >> 1;
+                if ((mid == nw ? (uint32_t)distinct : word_rank(sm, mid)) - r0 <= (uint32_t)kCap)
+                    wl = mid;
                 else
-                    hi = mid - 1;
+                    wh = mid - 1;
             }
-            const int w1 = lo;
-            const int nr = (int)sm.wpre[w1] - r0;
+            const int w1 = wl;
+            const int nr = (int)((w1 == nw ? (uint32_t)distinct : word_rank(sm, w1)) - r0);
             if (nr > 0) {
-                const int ka = ja + 32 * w0;
-                const int kb = min(jb, ja + 32 * w1);
-                for (int x = tid; x < nr; x += kHeavyThreads) sm.cnt[x] = 0u;
-                __syncthreads();
+                const int nwords = WIDE ? nr : (nr + 1) >> 1;
                 // pass 2: count every 2-path into its partner's rank
-                for_each_2path(g, p0, p1, ka, kb, sm, [&](int j) {
+                auto add = [&](int, int j) {
                     const unsigned off = (unsigned)(j - ja);
                     if (off >= span) return;
                     const int x = (int)(off >> 5);
-                    const unsigned r = sm.wpre[x] + __popc(sm.bitmap[x] & ((1u << (off & 31)) - 1u)) - (unsigned)r0;
-                    if (r < (unsigned)nr) atomicAdd(&sm.cnt[r], 1u);
-                });
+                    const uint32_t r = word_rank(sm, x) + __popc(sm.bitmap[x] & ((1u << (off & 31)) - 1u)) - r0;
+                    if (r < (uint32_t)nr) count_add<WIDE>(sm.cnt, r);
+                };
+                const bool whole = w0 == 0 && w1 == nw;
+                if (cached && (whole || !EMIT)) {
+                    int f = tid;
+                    for (; f + 3 * kHeavyThreads < total1; f += 4 * kHeavyThreads) {
+                        const int j0 = sm.buf[f], j1 = sm.buf[f + kHeavyThreads];
+                        const int j2 = sm.buf[f + 2 * kHeavyThreads], j3 = sm.buf[f + 3 * kHeavyThreads];
+                        add(f, j0);
+                        add(f, j1);
+                        add(f, j2);
+                        add(f, j3);
+                    }
+                    for (; f < total1; f += kHeavyThreads) add(f, sm.buf[f]);
+                    __syncthreads();
+                } else if (one_batch && whole) {
+                    walk_segments(vs_idx, total1, sm, add);  // segments of pass 1 still laid out
+                    __syncthreads();
+                } else {
+                    const int ka = ja + 32 * w0;
+                    const int kb = min(jb, ja + 32 * w1);
+                    for (int qb = 0; qb < k; qb += kHeavyThreads) {
+                        int a, len;
+                        member_segment<true>(vs_idx, bounds, d.bptr, k, qb, ka, kb, a, len);
+                        walk_segments(vs_idx, layout_segments(a, len, sm), sm, add);
+                        __syncthreads();
+                    }
+                }
                 if (EMIT) {
                     for (int x = w0 + tid; x < w1; x += kHeavyThreads) {
                         unsigned bits = sm.bitmap[x];
-                        int r = (int)sm.wpre[x] - r0;
+                        int r = (int)(word_rank(sm, x) - r0);
                         const int jbase = ja + 32 * x;
                         while (bits) {
-                            sm.keys[r++] = jbase + __ffs(bits) - 1;
+                            sm.buf[r++] = jbase + __ffs(bits) - 1;
                             bits &= bits - 1u;
                         }
                     }
                     __syncthreads();
                 }
-                // threshold per s_k; ranks are in partner order
-                for (int rb = 0; rb < nr; rb += kHeavyThreads) {
-                    const int r = rb + tid;
-                    const bool valid = r < nr;
-                    const int c = valid ? (int)sm.cnt[r] : 0;
-                    if (!EMIT) {
-                        for (int k = 0; k < K; ++k) {
-                            const unsigned long long mask = __ballot(c >= ep->s[k]);
-                            if (lane == 0 && mask) atomicAdd(&sm.acc[k], (unsigned long long)__popcll(mask));
-                        }
-                    } else {
-                        const int key = valid ? sm.keys[r] : 0;
-                        for (int k = 0; k < K; ++k) {
-                            const unsigned long long mask = __ballot(c >= ep->s[k]);
-                            if (lane == 0) sm.wtot[k][wave] = __popcll(mask);
-                        }
-                        __syncthreads();
-                        for (int k = 0; k < K; ++k) {
-                            const bool surv = c >= ep->s[k];
+                // threshold per s_k over this wavefront's contiguous ranks
+                const int per = (((nr + kHW - 1) / kHW) + 63) & ~63;
+                const int rlo = wave * per;
+                const int rhi = min(nr, rlo + per);
+                for (int kk = 0; kk < K; ++kk) {
+                    const int sk = ep->s[kk];
+                    int nsurv = 0;
+                    for (int rbase = rlo; rbase < rhi; rbase += 64) {
+                        const int r = rbase + lane;
+                        const int c = r < rhi ? count_get<WIDE>(sm.cnt, r) : 0;
+                        nsurv += __popcll(__ballot(c >= sk));
+                    }
+                    if (EMIT) {
+                        if (lane == 0) sm.wtot[kk][wave] = nsurv;
+                    } else if (lane == 0 && nsurv) {
+                        atomicAdd(&sm.acc[kk], (unsigned long long)nsurv);
+                    }
+                }
+                if (EMIT) {
+                    __syncthreads();
+                    for (int kk = 0; kk < K; ++kk) {
+                        const int sk = ep->s[kk];
+                        int64_t base = sm.obase[kk];
+                        for (int w = 0; w < wave; ++w) base += sm.wtot[kk][w];
+                        int32_t *col = ep->col[kk];
+                        int32_t *wo = ep->w[kk];
+                        int32_t *ro = ep->row[kk];
+                        for (int rbase = rlo; rbase < rhi; rbase += 64) {
+                            const int r = rbase + lane;
+                            const int c = r < rhi ? count_get<WIDE>(sm.cnt, r) : 0;
+                            const bool surv = c >= sk;
                             const unsigned long long mask = __ballot(surv);
-                            int pre = 0;
-                            for (int w = 0; w < wave; ++w) pre += sm.wtot[k][w];
                             if (surv) {
-                                const int64_t pos = sm.obase[k] + pre + bits_below(mask);
-                                ep->col[k][pos] = key;
-                                ep->w[k][pos] = c;
-                                int32_t *ro = ep->row[k];
+                                const int64_t pos = base + bits_below(mask);
+                                col[pos] = sm.buf[r];
+                                wo[pos] = c;
                                 if (ro) ro[pos] = i;
                             }
+                            base += __popcll(mask);
                         }
-                        __syncthreads();
-                        if (tid < K) {
-                            int tot = 0;
-                            for (int w = 0; w < kHW; ++w) tot += sm.wtot[tid][w];
-                            sm.obase[tid] += tot;
-                        }
-                        __syncthreads();
+                    }
+                    __syncthreads();
+                    if (tid < K) {
+                        int tot = 0;
+                        for (int w = 0; w < kHW; ++w) tot += sm.wtot[tid][w];
+                        sm.obase[tid] += tot;
                     }
                 }
                 __syncthreads();
+                for (int x = tid; x < nwords; x += kHeavyThreads) sm.cnt[x] = 0u;
+                if (w1 < nw) __syncthreads();  // the next window counts into cleared counters
             }
             w0 = w1;
         }
+        for (int x = tid; x < nw; x += kHeavyThreads) sm.bitmap[x] = 0u;
         __syncthreads();
         if (!EMIT && tid < K) slot_cnt[(int64_t)tid * S + slot] = (int64_t)sm.acc[tid];
-        __syncthreads();
+        if (!have_next) break;
+    }
+}
+
+// One wavefront per heavy slot: the segment start of every member of the
+// row at the slot's first partner id (and, on the row's last slot, the
+// tail end). Partners of member q form a sorted tail, so the start is a
+// lower bound; quick tests skip the search when the tail misses the slot.
+__global__ __launch_bounds__(256) void bounds_kernel(
+    const HeavyDesc *__restrict__ desc, int64_t count, const int64_t *__restrict__ he_ptr,
+    const int32_t *__restrict__ he_idx, const int64_t *__restrict__ vs_ptr,
+    const int32_t *__restrict__ vs_idx, const int32_t *__restrict__ tail_beg,
+    int32_t *__restrict__ bounds) {
+    const int lane = lane_id();
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+    if (w >= count) return;
+    const HeavyDesc d = desc[w];
+    const int64_t p0 = he_ptr[d.row];
+    for (int q = lane; q < d.k; q += 64) {
+        const int64_t p = p0 + q;
+        const int v = he_idx[p];
+        const int beg = tail_beg[p];
+        const int end = (int)vs_ptr[v + 1];
+        int val = beg;
+        if (beg < end && vs_idx[beg] < d.ja)
+            val = vs_idx[end - 1] < d.ja ? end : lower_bound_i32(vs_idx, beg, end, d.ja);
+        bounds[d.bptr + q] = val;
+        if (d.last) bounds[d.bptr + d.k + q] = end;
     }
 }
 
@@ -711,7 +954,7 @@ __global__ void row_ptr_kernel(int64_t row_lo, int64_t row_hi, const int64_t *__
                                const int64_t *__restrict__ slot_off, int64_t S, EmitParams prm,
                                int64_t out_base) {
     __shared__ EmitParams sp;
-    if (threadIdx.x == 0) sp = prm;
+    stage_params(&sp, prm);
     __syncthreads();
     const int64_t i = row_lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i > row_hi) return;
@@ -795,6 +1038,17 @@ inline unsigned wave_grid(int64_t rows, int waves_per_block, int64_t cap) {
 // ---------------------------------------------------------------------------
 int64_t scan_partials_size(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
+int heavy_resident(int device) {
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, heavy_kernel<true, false>, kHeavyThreads, 0) !=
+        hipSuccess)
+        per = 0;
+    if (cus <= 0) cus = 256;
+    if (per <= 0) per = 1;
+    return cus * per;
+}
+
 hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t value, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     fill_i64_kernel<<<grid_for(n, 256), 256, 0, st>>>(p, n, value);
@@ -831,24 +1085,25 @@ hipError_t launch_compact_vertex_lists(int64_t n, int64_t nnz, const int64_t *v_
 }
 
 hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t *tail_beg, int64_t *work,
-                           int32_t *jmax, int32_t *nslots, uint8_t *rclass,
-                           unsigned long long *class_count, int *err, hipStream_t st) {
+                           int32_t *jmax, int32_t *nslots, uint8_t *rclass, int64_t *bsize,
+                           unsigned long long *class_count, int *err,
+                           unsigned long long *heavy_work, hipStream_t st) {
     if (g.m <= 0) return hipSuccess;
     row_plan_kernel<<<wave_grid(g.m, 4, 8192), 256, 0, st>>>(g, s_min, tail_beg, work, jmax, nslots,
-                                                              rclass, class_count, err);
+                                                              rclass, bsize, class_count, err, heavy_work);
     return hipGetLastError();
 }
 
-hipError_t launch_fill_slots(int64_t m, const int64_t *slot_base, const int32_t *nslots,
-                             const int32_t *jmax, const int64_t *work, const uint8_t *rclass,
-                             int32_t *slot_row, int32_t *slot_ja, int32_t *slot_jb,
-                             int32_t *const *lists, unsigned long long *list_fill,
-                             hipStream_t st) {
-    (void)work;
+hipError_t launch_fill_slots(int64_t m, const int64_t *he_ptr, const int64_t *slot_base,
+                             const int32_t *nslots, const int32_t *jmax, const uint8_t *rclass,
+                             const int64_t *bbase, int64_t *hat, int32_t *slot_row, int32_t *const *lists,
+                             HeavyDesc *const *heavy, unsigned long long *list_fill, hipStream_t st) {
     if (m <= 0) return hipSuccess;
-    fill_slots_kernel<<<grid_for(m, 256), 256, 0, st>>>(m, slot_base, nslots, jmax, rclass, slot_row,
-                                                         slot_ja, slot_jb, lists[0], lists[1],
-                                                         lists[2], lists[3], lists[4], list_fill);
+    fill_slots_kernel<<<grid_for(m, 256), 256, 0, st>>>(m, he_ptr, slot_base, nslots, jmax, rclass, bbase,
+                                                         slot_row, lists[0], lists[1], lists[2], lists[3],
+                                                         hat, list_fill);
+    heavy_desc_kernel<<<wave_grid(m, 4, 8192), 256, 0, st>>>(m, he_ptr, slot_base, nslots, jmax, rclass,
+                                                              bbase, hat, slot_row, heavy[0], heavy[1]);
     return hipGetLastError();
 }
 
@@ -877,17 +1132,32 @@ hipError_t launch_light(int cls, bool emit, const int32_t *list, int64_t count, 
     return hipGetLastError();
 }
 
-hipError_t launch_heavy(bool emit, const int32_t *list, int64_t count, const Slots &sl,
-                        const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
-                        const int64_t *slot_off, int64_t out_base, hipStream_t st) {
+hipError_t launch_heavy(bool emit, bool wide, const HeavyDesc *desc, int64_t count, int64_t slots,
+                        const int32_t *bounds, const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
+                        const int64_t *slot_off, int64_t out_base, int64_t *ticket, int resident,
+                        hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)(count < (1 << 20) ? count : (1 << 20));
-    if (emit)
-        heavy_kernel<true><<<grid, kHeavyThreads, 0, st>>>(list, count, sl, g, ep, slot_cnt, slot_off,
-                                                           out_base);
-    else
-        heavy_kernel<false><<<grid, kHeavyThreads, 0, st>>>(list, count, sl, g, ep, slot_cnt, slot_off,
-                                                            out_base);
+    hipError_t e = launch_fill_i64(ticket, 1, 0, st);
+    if (e != hipSuccess) return e;
+    const int64_t want = resident > 0 ? resident : 512;
+    const unsigned grid = (unsigned)(count < want ? count : want);
+    unsigned long long *tk = reinterpret_cast<unsigned long long *>(ticket);
+#define SLG_HEAVY(E, W)                                                                             \
+    heavy_kernel<E, W><<<grid, kHeavyThreads, 0, st>>>(desc, count, slots, bounds, g.vs_idx, ep, slot_cnt, \
+                                                       slot_off, out_base, tk)
+    if (emit && wide) SLG_HEAVY(true, true);
+    else if (emit) SLG_HEAVY(true, false);
+    else if (wide) SLG_HEAVY(false, true);
+    else SLG_HEAVY(false, false);
+#undef SLG_HEAVY
+    return hipGetLastError();
+}
+
+hipError_t launch_bounds(const Pruned &g, const HeavyDesc *desc, int64_t count, int32_t *bounds,
+                         hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    bounds_kernel<<<grid_for(count, 4), 256, 0, st>>>(desc, count, g.he_ptr, g.he_idx, g.vs_ptr, g.vs_idx,
+                                                       g.tail_beg, bounds);
     return hipGetLastError();
 }
 

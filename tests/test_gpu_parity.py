@@ -266,3 +266,14 @@ def test_validate_rejects_malformed(ctx):
             ctx.line_graph(g, [1])
         assert e.value.status == slg.SLG_ERR_INVALID_GRAPH
         g.release()
+
+
+def test_wide_rows_full(ctx):
+    # one hyperedge with 70,000 members: its overlaps need 32-bit counters
+    rng = np.random.default_rng(11)
+    rows = [list(range(70_000))]
+    rows += [sorted(set(rng.integers(0, 100_000, 6).tolist())) for _ in range(1500)]
+    rows += [list(range(0, 70_000, 2)), list(range(1, 70_000, 3))]
+    inc = hg.from_rows(rows, n=100_000)
+    for lg in run_gpu(ctx, inc, [1, 2, 3, 20_000]):
+        assert_matches_oracle(inc, lg, lg.s, "wide")
