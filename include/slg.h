@@ -160,10 +160,31 @@ slg_status slg_plan_emit(slg_plan *p, int64_t *const *row_ptr, int32_t *const *r
  *   [0] slots (output segments), [1..4] rows in the four wavefront-sort
  *   classes (<= 64, 128, 256, 512 2-paths), [5] heavy slots, [6] heavy slots
  *   of rows with >= 65535 members, [7] 2-paths (as slg_plan_info),
- *   [8] 2-paths in heavy slots, [9] entries of the heavy boundary table.
+ *   [8] 2-paths in heavy slots, [9] entries of the heavy boundary table,
+ *   [10] edges written by heavy slots, summed over all thresholds.
  * Returns the number of entries written in *count (may be NULL).
  */
 slg_status slg_plan_stats(const slg_plan *p, int64_t *out, int32_t cap, int32_t *count);
+
+/*
+ * Opt-in device timing, for measurement. When enabled, every kernel launch
+ * of the path is bracketed by HIP events recorded on the stream it runs on,
+ * and the elapsed times are summed per stage. slg_context_get_timing waits
+ * for the recorded events, then fills up to `cap` entries of out[] (host
+ * array) with one record per stage that ran: its name (static storage),
+ * the number of timed launches and their summed duration in milliseconds.
+ * Stages: prune, row_plan, plan_scans, slots, bounds, count_light,
+ * count_heavy, count_heavy_wide, count_scans, emit_light, emit_heavy,
+ * emit_heavy_wide, row_ptr. Timing adds two event records per launch.
+ */
+typedef struct {
+    const char *name;
+    int64_t launches;
+    double milliseconds;
+} slg_stage_time;
+slg_status slg_context_set_timing(slg_context *ctx, int enable);
+slg_status slg_context_get_timing(slg_context *ctx, slg_stage_time *out, int32_t cap, int32_t *count);
+slg_status slg_context_reset_timing(slg_context *ctx);
 
 /* Free a plan's device scratch (ordered on the stream it was made on). */
 slg_status slg_plan_destroy(slg_plan *p);

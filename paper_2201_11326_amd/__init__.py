@@ -63,6 +63,10 @@ class Allocator(ctypes.Structure):
     _fields_ = [("alloc", _ALLOC_FN), ("release", _FREE_FN), ("user", _p)]
 
 
+class StageTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", _i64), ("milliseconds", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -97,6 +101,9 @@ def lib() -> ctypes.CDLL:
         "slg_plan_destroy": (_i32, [_p]),
         "slg_plan_stats": (_i32, [_p, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i32)]),
         "slg_line_graph": (_i32, [_p, _p, ctypes.POINTER(_i32), _i32, _p, ctypes.POINTER(_p)]),
+        "slg_context_set_timing": (_i32, [_p, ctypes.c_int]),
+        "slg_context_get_timing": (_i32, [_p, ctypes.POINTER(StageTime), _i32, ctypes.POINTER(_i32)]),
+        "slg_context_reset_timing": (_i32, [_p]),
         "slg_result_info": (_i32, [_p, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
         "slg_result_coo": (_i32, [_p, _i32, ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
         "slg_result_csr": (_i32, [_p, _i32, ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
@@ -189,7 +196,7 @@ class Plan:
         return [self.info(k)[0] for k in range(len(self.s))]
 
     STAT_NAMES = ("slots", "light64", "light128", "light256", "light512", "heavy_slots",
-                  "heavy_wide_slots", "two_paths", "heavy_two_paths", "bound_entries")
+                  "heavy_wide_slots", "two_paths", "heavy_two_paths", "bound_entries", "heavy_edges")
 
     def stats(self) -> dict:
         out = (_i64 * 16)()
@@ -239,6 +246,21 @@ class Context:
         if st != SLG_OK:
             raise SlgError(st, "slg_context_create failed")
         self.handle = h.value
+
+    # -- measurement ---------------------------------------------------------
+    def set_timing(self, enable: bool = True):
+        self._check(lib().slg_context_set_timing(self.handle, 1 if enable else 0))
+
+    def timing(self) -> dict:
+        """{stage: (launches, milliseconds)} summed since the last reset."""
+        out = (StageTime * 32)()
+        n = _i32()
+        self._check(lib().slg_context_get_timing(self.handle, out, 32, ctypes.byref(n)))
+        return {out[t].name.decode(): (int(out[t].launches), float(out[t].milliseconds))
+                for t in range(n.value)}
+
+    def reset_timing(self):
+        self._check(lib().slg_context_reset_timing(self.handle))
 
     def _check(self, status: int):
         if status != SLG_OK:

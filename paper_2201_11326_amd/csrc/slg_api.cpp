@@ -15,9 +15,28 @@
 
 using namespace slg;
 
+namespace {
+enum Stage {
+    kStPrune, kStRowPlan, kStPlanScans, kStSlots, kStBounds, kStCountLight, kStCountHeavy,
+    kStCountHeavyWide, kStCountScans, kStEmitLight, kStEmitHeavy, kStEmitHeavyWide, kStRowPtr, kNumStages
+};
+const char *const kStageNames[kNumStages] = {
+    "prune", "row_plan", "plan_scans", "slots", "bounds", "count_light", "count_heavy",
+    "count_heavy_wide", "count_scans", "emit_light", "emit_heavy", "emit_heavy_wide", "row_ptr"};
+struct PendingTime {
+    int stage;
+    hipEvent_t start, stop;
+};
+}  // namespace
+
 struct slg_context {
     int device = 0;
     int heavy_resident = 0;  // persistent workgroups of the heavy tier
+    bool timing = false;
+    std::vector<PendingTime> pending;
+    std::vector<hipEvent_t> event_pool;
+    int64_t stage_launches[kNumStages] = {};
+    double stage_ms[kNumStages] = {};
     uint64_t budget = 0;
     bool has_alloc = false;
     slg_allocator alloc{};
@@ -76,6 +95,36 @@ struct Scratch {
     }
 };
 
+// Brackets the launches of one stage with events on their stream when the
+// context's timing is on.
+struct StageTimer {
+    slg_context *ctx;
+    int stage;
+    hipStream_t st;
+    hipEvent_t start = nullptr, stop = nullptr;
+    StageTimer(slg_context *c, int sg, hipStream_t s) : ctx(c), stage(sg), st(s) {
+        if (!ctx || !ctx->timing) return;
+        start = take();
+        stop = take();
+        if (start && stop) (void)hipEventRecord(start, st);
+    }
+    ~StageTimer() {
+        if (start && stop) {
+            (void)hipEventRecord(stop, st);
+            ctx->pending.push_back({stage, start, stop});
+        }
+    }
+    hipEvent_t take() {
+        if (!ctx->event_pool.empty()) {
+            hipEvent_t e = ctx->event_pool.back();
+            ctx->event_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+    }
+};
+
 bool valid_s(const int32_t *s, int32_t k) {
     if (!s || k < 1 || k > SLG_MAX_S || s[0] < 1) return false;
     for (int32_t t = 1; t < k; ++t)
@@ -104,6 +153,7 @@ struct slg_plan {
     int64_t *slot_off = nullptr;   // [K][S+1]
     int64_t two_paths = 0;
     int64_t heavy_two_paths = 0;
+    int64_t heavy_edges = 0;
     int64_t nbounds = 0;
     int64_t num_edges[SLG_MAX_S] = {};
 };
@@ -160,6 +210,12 @@ slg_status slg_context_create(int device, uint64_t mem_budget_bytes, const slg_a
 
 slg_status slg_context_destroy(slg_context *ctx) {
     if (!ctx) return SLG_ERR_INVALID_ARG;
+    for (const PendingTime &pt : ctx->pending) {
+        (void)hipEventSynchronize(pt.stop);
+        ctx->event_pool.push_back(pt.start);
+        ctx->event_pool.push_back(pt.stop);
+    }
+    for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
     return SLG_OK;
@@ -281,6 +337,7 @@ slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int
         PLAN_HIP(sc.get(&part, scan_partials_size(nnz)));
         PLAN_HIP(sc.get(&vs_ptr, n + 1));
         PLAN_HIP(sc.get(&vs_idx, nnz));
+        StageTimer tm(ctx, kStPrune, st);
         PLAN_HIP(launch_keep_incidence(nnz, inc.v_idx, inc.he_ptr, m, s_min, flag, st));
         PLAN_HIP(launch_exclusive_scan_u8(flag, nnz, pos, part, st));
         PLAN_HIP(launch_compact_vertex_lists(n, nnz, inc.v_ptr, inc.v_idx, flag, pos, vs_ptr, vs_idx, st));
@@ -311,11 +368,17 @@ slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int
     unsigned long long *class_count = reinterpret_cast<unsigned long long *>(counters);
     int *err = reinterpret_cast<int *>(counters + 8);
     unsigned long long *list_fill = reinterpret_cast<unsigned long long *>(counters + 9);
-    PLAN_HIP(launch_row_plan(pr, s_min, tail_beg, work, jmax, nslots, rclass, bsize, class_count, err,
-                             reinterpret_cast<unsigned long long *>(counters + 15), st));
-    PLAN_HIP(launch_exclusive_scan_i32(nslots, m, p->slot_base, part_m, st));
-    PLAN_HIP(launch_exclusive_scan_i64(work, m, work_pre, part_m, st));
-    PLAN_HIP(launch_exclusive_scan_i64(bsize, m, bbase, part_m, st));
+    {
+        StageTimer tm(ctx, kStRowPlan, st);
+        PLAN_HIP(launch_row_plan(pr, s_min, tail_beg, work, jmax, nslots, rclass, bsize, class_count, err,
+                                 reinterpret_cast<unsigned long long *>(counters + 15), st));
+    }
+    {
+        StageTimer tm(ctx, kStPlanScans, st);
+        PLAN_HIP(launch_exclusive_scan_i32(nslots, m, p->slot_base, part_m, st));
+        PLAN_HIP(launch_exclusive_scan_i64(work, m, work_pre, part_m, st));
+        PLAN_HIP(launch_exclusive_scan_i64(bsize, m, bbase, part_m, st));
+    }
     int64_t *hb = ctx->pinned;
     PLAN_HIP(hipMemcpyAsync(hb, counters, 9 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     PLAN_HIP(hipMemcpyAsync(hb + 9, p->slot_base + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -339,15 +402,21 @@ slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int
     int32_t *slot_row;
     PLAN_HIP(sc.get(&slot_row, p->S));
     PLAN_HIP(sc.get(&p->bounds, nbounds));
-    PLAN_HIP(sc.get(&p->tickets, 4));
+    PLAN_HIP(sc.get(&p->tickets, 5));
     for (int c = 0; c < kLightClasses; ++c) PLAN_HIP(sc.get(&p->lists[c], p->list_count[c]));
     for (int h = 0; h < 2; ++h) PLAN_HIP(sc.get(&p->heavy[h], p->list_count[kLightClasses + h]));
     int64_t *hat;  // first descriptor of each heavy row in its list
     PLAN_HIP(sc.get(&hat, m));
-    PLAN_HIP(launch_fill_slots(m, inc.he_ptr, p->slot_base, nslots, jmax, rclass, bbase, hat, slot_row,
-                               p->lists, p->heavy, list_fill, st));
-    for (int h = 0; h < 2; ++h)
-        PLAN_HIP(launch_bounds(pr, p->heavy[h], p->list_count[kLightClasses + h], p->bounds, st));
+    {
+        StageTimer tm(ctx, kStSlots, st);
+        PLAN_HIP(launch_fill_slots(m, inc.he_ptr, p->slot_base, nslots, jmax, rclass, bbase, hat, slot_row,
+                                   p->lists, p->heavy, list_fill, st));
+    }
+    {
+        StageTimer tm(ctx, kStBounds, st);
+        for (int h = 0; h < 2; ++h)
+            PLAN_HIP(launch_bounds(pr, p->heavy[h], p->list_count[kLightClasses + h], p->bounds, st));
+    }
     p->slots.count = p->S;
     p->slots.row = slot_row;
 
@@ -357,21 +426,37 @@ slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int
     PLAN_HIP(sc.get(&p->slot_off, (size_t)K * (p->S + 1)));
     int64_t *part_s;
     PLAN_HIP(sc.get(&part_s, scan_partials_size(p->S)));
-    for (int c = 0; c < kLightClasses; ++c)
-        PLAN_HIP(launch_light(c, false, p->lists[c], p->list_count[c], p->slots, pr, p->prm, p->slot_cnt,
-                              nullptr, 0, st));
-    for (int wide = 0; wide < 2; ++wide)
+    {
+        StageTimer tm(ctx, kStCountLight, st);
+        for (int c = 0; c < kLightClasses; ++c)
+            PLAN_HIP(launch_light(c, false, p->lists[c], p->list_count[c], p->slots, pr, p->prm, p->slot_cnt,
+                                  nullptr, 0, st));
+    }
+    PLAN_HIP(launch_fill_i64(p->tickets, 4, 0, st));
+    for (int wide = 0; wide < 2; ++wide) {
+        if (p->list_count[kLightClasses + wide] <= 0) continue;
+        StageTimer tm(ctx, wide ? kStCountHeavyWide : kStCountHeavy, st);
         PLAN_HIP(launch_heavy(false, wide, p->heavy[wide], p->list_count[kLightClasses + wide], p->S,
                               p->bounds, pr, p->prm, p->slot_cnt, nullptr, 0, p->tickets + wide,
                               ctx->heavy_resident, st));
-    for (int k = 0; k < K; ++k) {
-        PLAN_HIP(launch_exclusive_scan_i64(p->slot_cnt + (size_t)k * p->S, p->S,
-                                           p->slot_off + (size_t)k * (p->S + 1), part_s, st));
-        PLAN_HIP(hipMemcpyAsync(hb + 16 + k, p->slot_off + (size_t)k * (p->S + 1) + p->S, sizeof(int64_t),
-                                hipMemcpyDeviceToHost, st));
     }
+    {
+        StageTimer tm(ctx, kStCountScans, st);
+        for (int k = 0; k < K; ++k) {
+            PLAN_HIP(launch_exclusive_scan_i64(p->slot_cnt + (size_t)k * p->S, p->S,
+                                               p->slot_off + (size_t)k * (p->S + 1), part_s, st));
+            PLAN_HIP(hipMemcpyAsync(hb + 16 + k, p->slot_off + (size_t)k * (p->S + 1) + p->S, sizeof(int64_t),
+                                    hipMemcpyDeviceToHost, st));
+        }
+    }
+    PLAN_HIP(launch_fill_i64(p->tickets + 4, 1, 0, st));
+    for (int h = 0; h < 2; ++h)
+        PLAN_HIP(launch_heavy_edges(p->heavy[h], p->list_count[kLightClasses + h], p->slot_cnt, p->S, K,
+                                    p->tickets + 4, st));
+    PLAN_HIP(hipMemcpyAsync(hb + 40, p->tickets + 4, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     PLAN_HIP(hipStreamSynchronize(st));
     for (int k = 0; k < K; ++k) p->num_edges[k] = hb[16 + k];
+    p->heavy_edges = hb[40];
 #undef PLAN_HIP
     (void)rc;
     *out = p;
@@ -409,14 +494,24 @@ slg_status slg_plan_emit(slg_plan *p, int64_t *const *row_ptr, int32_t *const *r
         SLG_HIP(ctx, hipStreamWaitEvent(st, ev, 0));
         SLG_HIP(ctx, hipEventDestroy(ev));
     }
-    for (int c = 0; c < kLightClasses; ++c)
-        SLG_HIP(ctx, launch_light(c, true, p->lists[c], p->list_count[c], p->slots, p->pr, prm, nullptr,
-                                  p->slot_off, 0, st));
-    for (int wide = 0; wide < 2; ++wide)
+    {
+        StageTimer tm(ctx, kStEmitLight, st);
+        for (int c = 0; c < kLightClasses; ++c)
+            SLG_HIP(ctx, launch_light(c, true, p->lists[c], p->list_count[c], p->slots, p->pr, prm, nullptr,
+                                      p->slot_off, 0, st));
+    }
+    SLG_HIP(ctx, launch_fill_i64(p->tickets + 2, 2, 0, st));
+    for (int wide = 0; wide < 2; ++wide) {
+        if (p->list_count[kLightClasses + wide] <= 0) continue;
+        StageTimer tm(ctx, wide ? kStEmitHeavyWide : kStEmitHeavy, st);
         SLG_HIP(ctx, launch_heavy(true, wide, p->heavy[wide], p->list_count[kLightClasses + wide], p->S,
                                   p->bounds, p->pr, prm, nullptr, p->slot_off, 0, p->tickets + 2 + wide,
                                   ctx->heavy_resident, st));
-    SLG_HIP(ctx, launch_row_ptr(0, p->pr.m, p->slot_base, p->slot_off, p->S, prm, 0, st));
+    }
+    {
+        StageTimer tm(ctx, kStRowPtr, st);
+        SLG_HIP(ctx, launch_row_ptr(0, p->pr.m, p->slot_base, p->slot_off, p->S, prm, 0, st));
+    }
     if (st != p->st) {  // scratch is freed on the plan's stream
         hipEvent_t ev;
         SLG_HIP(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -429,12 +524,55 @@ slg_status slg_plan_emit(slg_plan *p, int64_t *const *row_ptr, int32_t *const *r
 
 slg_status slg_plan_stats(const slg_plan *p, int64_t *out, int32_t cap, int32_t *count) {
     if (!p || (!out && cap > 0) || cap < 0) return SLG_ERR_INVALID_ARG;
-    const int64_t vals[10] = {p->S, p->list_count[0], p->list_count[1], p->list_count[2],
+    const int64_t vals[11] = {p->S, p->list_count[0], p->list_count[1], p->list_count[2],
                               p->list_count[3], p->list_count[4], p->list_count[5], p->two_paths,
-                              p->heavy_two_paths, p->nbounds};
-    int32_t n = cap < 10 ? cap : 10;
+                              p->heavy_two_paths, p->nbounds, p->heavy_edges};
+    int32_t n = cap < 11 ? cap : 11;
     for (int32_t t = 0; t < n; ++t) out[t] = vals[t];
     if (count) *count = n;
+    return SLG_OK;
+}
+
+slg_status slg_context_set_timing(slg_context *ctx, int enable) {
+    if (!ctx) return SLG_ERR_INVALID_ARG;
+    ctx->timing = enable != 0;
+    return SLG_OK;
+}
+
+slg_status slg_context_get_timing(slg_context *ctx, slg_stage_time *out, int32_t cap, int32_t *count) {
+    if (!ctx || cap < 0 || (cap > 0 && !out)) return fail(ctx, SLG_ERR_INVALID_ARG, "bad timing query");
+    for (const PendingTime &pt : ctx->pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(pt.stop) == hipSuccess && hipEventElapsedTime(&ms, pt.start, pt.stop) == hipSuccess) {
+            ctx->stage_ms[pt.stage] += ms;
+            ctx->stage_launches[pt.stage] += 1;
+        }
+        ctx->event_pool.push_back(pt.start);
+        ctx->event_pool.push_back(pt.stop);
+    }
+    ctx->pending.clear();
+    int32_t n = 0;
+    for (int sg = 0; sg < kNumStages; ++sg) {
+        if (!ctx->stage_launches[sg]) continue;
+        if (n < cap) {
+            out[n].name = kStageNames[sg];
+            out[n].launches = ctx->stage_launches[sg];
+            out[n].milliseconds = ctx->stage_ms[sg];
+        }
+        ++n;
+    }
+    if (count) *count = n < cap ? n : cap;
+    return SLG_OK;
+}
+
+slg_status slg_context_reset_timing(slg_context *ctx) {
+    if (!ctx) return SLG_ERR_INVALID_ARG;
+    int32_t n = 0;
+    (void)slg_context_get_timing(ctx, nullptr, 0, &n);  // drain pending events
+    for (int sg = 0; sg < kNumStages; ++sg) {
+        ctx->stage_launches[sg] = 0;
+        ctx->stage_ms[sg] = 0.0;
+    }
     return SLG_OK;
 }
 

@@ -101,11 +101,13 @@ hipError_t launch_light(int cls, bool emit, const int32_t *list, int64_t count, 
                         const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
                         const int64_t *slot_off, int64_t out_base, hipStream_t st);
 // Persistent launch: `resident` workgroups (0 = a default) take slots from
-// the device counter `ticket` (reset here, before the launch).
+// the device counter `ticket`, which the caller zeroes before the launch.
 hipError_t launch_heavy(bool emit, bool wide, const HeavyDesc *desc, int64_t count, int64_t slots,
                         const int32_t *bounds, const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
                         const int64_t *slot_off, int64_t out_base, int64_t *ticket, int resident,
                         hipStream_t st);
+hipError_t launch_heavy_edges(const HeavyDesc *desc, int64_t count, const int64_t *slot_cnt, int64_t S,
+                              int32_t K, int64_t *out, hipStream_t st);
 // Workgroups of the heavy kernel that fit on the device at once.
 int heavy_resident(int device);
 

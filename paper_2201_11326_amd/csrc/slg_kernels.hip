@@ -920,6 +920,27 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(const HeavyDesc *_
     }
 }
 
+// Edges of every threshold emitted by heavy slots (for measurement).
+__global__ __launch_bounds__(256) void heavy_edges_kernel(const HeavyDesc *__restrict__ desc,
+                                                          int64_t count, const int64_t *__restrict__ slot_cnt,
+                                                          int64_t S, int32_t K,
+                                                          unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long ws[4];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long sum = 0;
+    if (t < count) {
+        const int slot = desc[t].slot;
+        for (int k = 0; k < K; ++k) sum += (unsigned long long)slot_cnt[(int64_t)k * S + slot];
+    }
+    sum = wave_sum(sum);
+    if (lane_id() == 0) ws[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long b = ws[0] + ws[1] + ws[2] + ws[3];
+        if (b) atomicAdd(out, b);
+    }
+}
+
 // One wavefront per heavy slot: the segment start of every member of the
 // row at the slot's first partner id (and, on the row's last slot, the
 // tail end). Partners of member q form a sorted tail, so the start is a
@@ -1137,8 +1158,6 @@ hipError_t launch_heavy(bool emit, bool wide, const HeavyDesc *desc, int64_t cou
                         const int64_t *slot_off, int64_t out_base, int64_t *ticket, int resident,
                         hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    hipError_t e = launch_fill_i64(ticket, 1, 0, st);
-    if (e != hipSuccess) return e;
     const int64_t want = resident > 0 ? resident : 512;
     const unsigned grid = (unsigned)(count < want ? count : want);
     unsigned long long *tk = reinterpret_cast<unsigned long long *>(ticket);
@@ -1150,6 +1169,14 @@ hipError_t launch_heavy(bool emit, bool wide, const HeavyDesc *desc, int64_t cou
     else if (wide) SLG_HEAVY(false, true);
     else SLG_HEAVY(false, false);
 #undef SLG_HEAVY
+    return hipGetLastError();
+}
+
+hipError_t launch_heavy_edges(const HeavyDesc *desc, int64_t count, const int64_t *slot_cnt, int64_t S,
+                              int32_t K, int64_t *out, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    heavy_edges_kernel<<<grid_for(count, 256), 256, 0, st>>>(desc, count, slot_cnt, S, K,
+                                                              reinterpret_cast<unsigned long long *>(out));
     return hipGetLastError();
 }
 

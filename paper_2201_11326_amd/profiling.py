@@ -1,0 +1,146 @@
+"""Measurement helpers around rocprofv3 (no part of the compute path).
+
+  python -m paper_2201_11326_amd.profiling probe
+      The power-law ensemble twice, preceded by a plain 1 GiB device copy
+      whose HBM traffic is known; run it under `rocprofv3 --pmc FETCH_SIZE`
+      and again under `--pmc WRITE_SIZE`.
+  python -m paper_2201_11326_amd.profiling stats DB [--match NAME]
+      Per-kernel launch count / total / average / min / max duration from a
+      rocprofv3 --kernel-trace database.
+  python -m paper_2201_11326_amd.profiling traffic FETCH_DB WRITE_DB
+      HBM bytes per launch of the heavy emit kernel, scaled by what the same
+      counters read for the calibration copy (1 GiB read + 1 GiB written).
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import hashlib
+import os
+import re
+import sqlite3
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+KERNEL_SRC = os.path.join(HERE, "csrc", "slg_kernels.hip")
+COPY_BYTES = 1 << 30
+HEAVY_EMIT = "heavy_kernel<true, false>"
+
+
+def short_name(kname: str) -> str:
+    k = kname.replace("void ", "").replace("slg::(anonymous namespace)::", "")
+    return k.split("(")[0]
+
+
+def probe() -> None:
+    sys.path.insert(0, ROOT)
+    import torch
+
+    import hypergen as hg
+    import paper_2201_11326_amd as slg
+    x = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)  # calibration: 1 GiB read, 1 GiB written
+    torch.cuda.synchronize()
+    del x, y
+    inc = hg.power_law()
+    ctx = slg.Context(0)
+    g = ctx.register_incidence(inc)
+    for _ in range(2):
+        outs = ctx.line_graph(g, [1, 2, 4, 8])
+        torch.cuda.synchronize()
+        del outs
+    print("probe done", flush=True)
+
+
+def kernel_rows(db: str):
+    con = sqlite3.connect(db)
+    cols = [r[1] for r in con.execute("pragma table_info(kernels)")]
+    name_col = "name" if "name" in cols else "kernel_name"
+    return [(short_name(n), (e - s) / 1e6) for n, s, e in
+            con.execute(f"select {name_col}, start, end from kernels")]
+
+
+def stats(db: str, match: str = "") -> str:
+    agg = collections.OrderedDict()
+    for name, ms in kernel_rows(db):
+        if match and match not in name:
+            continue
+        a = agg.setdefault(name, [0, 0.0, float("inf"), 0.0])
+        a[0] += 1
+        a[1] += ms
+        a[2] = min(a[2], ms)
+        a[3] = max(a[3], ms)
+    total = sum(v[1] for v in agg.values()) or 1.0
+    out = [f"{'kernel':44s} {'calls':>6s} {'total_ms':>10s} {'avg_ms':>9s} {'min_ms':>9s} {'max_ms':>9s} {'pct':>6s}"]
+    for name, (c, t, lo, hi) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        out.append(f"{name[:44]:44s} {c:6d} {t:10.3f} {t / c:9.3f} {lo:9.3f} {hi:9.3f} {100 * t / total:6.1f}")
+    return "\n".join(out)
+
+
+def counter_per_kernel(db: str, counter: str):
+    con = sqlite3.connect(db)
+    per = collections.defaultdict(list)
+    for kname, cname, val in con.execute(
+            "select kernel_name, counter_name, value from counters_collection"):
+        if cname == counter:
+            per[short_name(kname)].append(val)
+    return per
+
+
+def traffic(fetch_db: str, write_db: str) -> str:
+    f = counter_per_kernel(fetch_db, "FETCH_SIZE")
+    w = counter_per_kernel(write_db, "WRITE_SIZE")
+    copy = [k for k in f if "copy" in k.lower() or "elementwise" in k.lower()]
+    # the calibration copy is the largest-traffic copy-like kernel
+    ck = max(copy, key=lambda k: max(f[k])) if copy else None
+    fetch_factor = COPY_BYTES / (max(f[ck]) * 1024) if ck else 1.0
+    write_factor = COPY_BYTES / (max(w.get(ck, [0])) * 1024) if ck and w.get(ck) else 1.0
+    fe = f.get(HEAVY_EMIT, [])
+    we = w.get(HEAVY_EMIT, [])
+    fetch_b = fetch_factor * 1024 * sum(fe) / max(len(fe), 1)
+    write_b = write_factor * 1024 * sum(we) / max(len(we), 1)
+    with open(KERNEL_SRC, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    lines = [
+        "# HBM traffic of the heavy emit kernel (power-law ensemble S={1,2,4,8})",
+        "",
+        f"kernel: {HEAVY_EMIT}",
+        f"kernel_source_sha256: {sha}",
+        f"calibration kernel: {ck} (1 GiB read + 1 GiB written)",
+        f"calibration FETCH_SIZE KiB: {max(f[ck]) if ck else None}; factor {fetch_factor:.4f}",
+        f"calibration WRITE_SIZE KiB: {max(w[ck]) if ck and w.get(ck) else None}; factor {write_factor:.4f}",
+        f"launches measured: {len(fe)} (FETCH_SIZE), {len(we)} (WRITE_SIZE)",
+        f"FETCH_SIZE KiB per launch (raw): {sum(fe) / max(len(fe), 1):.1f}",
+        f"WRITE_SIZE KiB per launch (raw): {sum(we) / max(len(we), 1):.1f}",
+        f"hbm_fetch_bytes_per_launch: {fetch_b:.6e}",
+        f"hbm_write_bytes_per_launch: {write_b:.6e}",
+        f"hbm_bytes_per_launch: {fetch_b + write_b:.6e}",
+    ]
+    return "\n".join(lines)
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    sub.add_parser("probe")
+    a = sub.add_parser("stats")
+    a.add_argument("db")
+    a.add_argument("--match", default="")
+    b = sub.add_parser("traffic")
+    b.add_argument("fetch_db")
+    b.add_argument("write_db")
+    args = ap.parse_args(argv)
+    if args.cmd == "probe":
+        probe()
+    elif args.cmd == "stats":
+        print(stats(args.db, args.match))
+    else:
+        print(traffic(args.fetch_db, args.write_db))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
