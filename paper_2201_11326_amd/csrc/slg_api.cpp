@@ -53,6 +53,19 @@ namespace {
 
 constexpr int kPinnedSlots = 64;
 
+// Layout of the plan's small device counter block (int64 entries).
+constexpr int kCntClass = 0;                    // kNumLists: rows / slots per tier list
+constexpr int kCntErr = kCntClass + kNumLists;  // malformed-input flag (low 32 bits)
+constexpr int kCntFill = kCntErr + 1;           // kNumLists: append cursors of the tier lists
+constexpr int kCntHeavyWork = kCntFill + kNumLists;  // 2-paths in heavy rows
+constexpr int kCntTotal = kCntHeavyWork + 1;
+static_assert(kCntTotal <= 32, "counter block");
+// Host staging slots for readbacks.
+constexpr int kHbSlots = kCntTotal;      // slot table size, then 2-paths, boundary entries
+constexpr int kHbEdges = 40;             // SLG_MAX_S edge totals
+constexpr int kHbHeavyEdges = kHbEdges + SLG_MAX_S;
+static_assert(kHbSlots + 3 <= kHbEdges && kHbHeavyEdges + 1 < kPinnedSlots, "pinned staging layout");
+
 slg_status fail(slg_context *ctx, slg_status st, const char *fmt, ...) {
     if (ctx) {
         char buf[512];
@@ -360,18 +373,18 @@ slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int
     PLAN_HIP(sc.get(&rclass, m));
     PLAN_HIP(sc.get(&bsize, m));
     PLAN_HIP(sc.get(&bbase, m + 1));
-    PLAN_HIP(sc.get(&counters, 16));
+    PLAN_HIP(sc.get(&counters, 32));
     PLAN_HIP(sc.get(&part_m, scan_partials_size(m)));
     PLAN_HIP(sc.get(&p->slot_base, m + 1));
-    PLAN_HIP(launch_fill_i64(counters, 16, 0, st));
+    PLAN_HIP(launch_fill_i64(counters, 32, 0, st));
     pr.tail_beg = tail_beg;
-    unsigned long long *class_count = reinterpret_cast<unsigned long long *>(counters);
-    int *err = reinterpret_cast<int *>(counters + 8);
-    unsigned long long *list_fill = reinterpret_cast<unsigned long long *>(counters + 9);
+    unsigned long long *class_count = reinterpret_cast<unsigned long long *>(counters + kCntClass);
+    int *err = reinterpret_cast<int *>(counters + kCntErr);
+    unsigned long long *list_fill = reinterpret_cast<unsigned long long *>(counters + kCntFill);
     {
         StageTimer tm(ctx, kStRowPlan, st);
         PLAN_HIP(launch_row_plan(pr, s_min, tail_beg, work, jmax, nslots, rclass, bsize, class_count, err,
-                                 reinterpret_cast<unsigned long long *>(counters + 15), st));
+                                 reinterpret_cast<unsigned long long *>(counters + kCntHeavyWork), st));
     }
     {
         StageTimer tm(ctx, kStPlanScans, st);
@@ -380,21 +393,20 @@ slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int
         PLAN_HIP(launch_exclusive_scan_i64(bsize, m, bbase, part_m, st));
     }
     int64_t *hb = ctx->pinned;
-    PLAN_HIP(hipMemcpyAsync(hb, counters, 9 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    PLAN_HIP(hipMemcpyAsync(hb + 9, p->slot_base + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    PLAN_HIP(hipMemcpyAsync(hb + 10, work_pre + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    PLAN_HIP(hipMemcpyAsync(hb + 11, bbase + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    PLAN_HIP(hipMemcpyAsync(hb + 12, counters + 15, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    PLAN_HIP(hipMemcpyAsync(hb, counters, kCntTotal * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    PLAN_HIP(hipMemcpyAsync(hb + kHbSlots, p->slot_base + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    PLAN_HIP(hipMemcpyAsync(hb + kHbSlots + 1, work_pre + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    PLAN_HIP(hipMemcpyAsync(hb + kHbSlots + 2, bbase + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     PLAN_HIP(hipStreamSynchronize(st));
-    if (hb[8] & 0xffffffff)
+    if (hb[kCntErr] & 0xffffffff)
         return bail(fail(ctx, SLG_ERR_INVALID_GRAPH,
                          "malformed incidence (bad pointer, id out of range, or vertex CSR not the transpose)"));
-    for (int c = 0; c < kNumLists; ++c) p->list_count[c] = hb[c];
-    p->S = hb[9];
-    p->two_paths = hb[10];
-    const int64_t nbounds = hb[11];
+    for (int c = 0; c < kNumLists; ++c) p->list_count[c] = hb[kCntClass + c];
+    p->S = hb[kHbSlots];
+    p->two_paths = hb[kHbSlots + 1];
+    const int64_t nbounds = hb[kHbSlots + 2];
     p->nbounds = nbounds;
-    p->heavy_two_paths = hb[12];
+    p->heavy_two_paths = hb[kCntHeavyWork];
     if (nbounds >= (int64_t(1) << 40))
         return bail(fail(ctx, SLG_ERR_OVERFLOW, "boundary table too large"));
 
@@ -403,14 +415,24 @@ slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int
     PLAN_HIP(sc.get(&slot_row, p->S));
     PLAN_HIP(sc.get(&p->bounds, nbounds));
     PLAN_HIP(sc.get(&p->tickets, 5));
-    for (int c = 0; c < kLightClasses; ++c) PLAN_HIP(sc.get(&p->lists[c], p->list_count[c]));
-    for (int h = 0; h < 2; ++h) PLAN_HIP(sc.get(&p->heavy[h], p->list_count[kLightClasses + h]));
+    // lists start zeroed: an entry the fill kernels refuse to write (list
+    // overflow, flagged in err) names slot 0 / an empty descriptor
+    for (int c = 0; c < kLightClasses; ++c) {
+        PLAN_HIP(sc.get(&p->lists[c], p->list_count[c]));
+        PLAN_HIP(launch_fill_i32(p->lists[c], p->list_count[c], 0, st));
+    }
+    for (int h = 0; h < 2; ++h) {
+        PLAN_HIP(sc.get(&p->heavy[h], p->list_count[kLightClasses + h]));
+        PLAN_HIP(launch_fill_i64(reinterpret_cast<int64_t *>(p->heavy[h]),
+                                 p->list_count[kLightClasses + h] * (int64_t)(sizeof(HeavyDesc) / 8), 0, st));
+    }
+    static_assert(sizeof(HeavyDesc) % 8 == 0, "HeavyDesc is filled as int64 words");
     int64_t *hat;  // first descriptor of each heavy row in its list
     PLAN_HIP(sc.get(&hat, m));
     {
         StageTimer tm(ctx, kStSlots, st);
         PLAN_HIP(launch_fill_slots(m, inc.he_ptr, p->slot_base, nslots, jmax, rclass, bbase, hat, slot_row,
-                                   p->lists, p->heavy, list_fill, st));
+                                   p->lists, p->heavy, p->list_count, list_fill, err, st));
     }
     {
         StageTimer tm(ctx, kStBounds, st);
@@ -445,18 +467,22 @@ slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int
         for (int k = 0; k < K; ++k) {
             PLAN_HIP(launch_exclusive_scan_i64(p->slot_cnt + (size_t)k * p->S, p->S,
                                                p->slot_off + (size_t)k * (p->S + 1), part_s, st));
-            PLAN_HIP(hipMemcpyAsync(hb + 16 + k, p->slot_off + (size_t)k * (p->S + 1) + p->S, sizeof(int64_t),
-                                    hipMemcpyDeviceToHost, st));
+            PLAN_HIP(hipMemcpyAsync(hb + kHbEdges + k, p->slot_off + (size_t)k * (p->S + 1) + p->S,
+                                    sizeof(int64_t), hipMemcpyDeviceToHost, st));
         }
     }
     PLAN_HIP(launch_fill_i64(p->tickets + 4, 1, 0, st));
     for (int h = 0; h < 2; ++h)
         PLAN_HIP(launch_heavy_edges(p->heavy[h], p->list_count[kLightClasses + h], p->slot_cnt, p->S, K,
                                     p->tickets + 4, st));
-    PLAN_HIP(hipMemcpyAsync(hb + 40, p->tickets + 4, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    PLAN_HIP(hipMemcpyAsync(hb + kHbHeavyEdges, p->tickets + 4, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    PLAN_HIP(hipMemcpyAsync(hb + kHbHeavyEdges + 1, counters + kCntErr, sizeof(int64_t), hipMemcpyDeviceToHost,
+                            st));
     PLAN_HIP(hipStreamSynchronize(st));
-    for (int k = 0; k < K; ++k) p->num_edges[k] = hb[16 + k];
-    p->heavy_edges = hb[40];
+    if (hb[kHbHeavyEdges + 1] & 0xffffffff)
+        return bail(fail(ctx, SLG_ERR_DEVICE, "internal error: a tier list overflowed its planned size"));
+    for (int k = 0; k < K; ++k) p->num_edges[k] = hb[kHbEdges + k];
+    p->heavy_edges = hb[kHbHeavyEdges];
 #undef PLAN_HIP
     (void)rc;
     *out = p;
@@ -524,10 +550,17 @@ slg_status slg_plan_emit(slg_plan *p, int64_t *const *row_ptr, int32_t *const *r
 
 slg_status slg_plan_stats(const slg_plan *p, int64_t *out, int32_t cap, int32_t *count) {
     if (!p || (!out && cap > 0) || cap < 0) return SLG_ERR_INVALID_ARG;
-    const int64_t vals[11] = {p->S, p->list_count[0], p->list_count[1], p->list_count[2],
-                              p->list_count[3], p->list_count[4], p->list_count[5], p->two_paths,
-                              p->heavy_two_paths, p->nbounds, p->heavy_edges};
-    int32_t n = cap < 11 ? cap : 11;
+    int64_t vals[13];
+    vals[0] = p->S;
+    for (int c = 0; c < kLightClasses; ++c) vals[1 + c] = p->list_count[c];
+    vals[7] = p->list_count[kLightClasses];
+    vals[8] = p->list_count[kLightClasses + 1];
+    vals[9] = p->two_paths;
+    vals[10] = p->heavy_two_paths;
+    vals[11] = p->nbounds;
+    vals[12] = p->heavy_edges;
+    static_assert(kLightClasses == 6, "plan stats layout");
+    int32_t n = cap < 13 ? cap : 13;
     for (int32_t t = 0; t < n; ++t) out[t] = vals[t];
     if (count) *count = n;
     return SLG_OK;

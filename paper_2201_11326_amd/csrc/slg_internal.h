@@ -11,8 +11,8 @@ namespace slg {
 
 // ---- tuning constants of the hot path ------------------------------------
 constexpr int kWave = 64;              // CDNA wavefront width
-constexpr int kLightMax = 512;         // rows with <= this many 2-paths: wave-sort tier
-constexpr int kLightClasses = 4;       // 64, 128, 256, 512 keys per wave
+constexpr int kLightMax = 2048;        // rows with <= this many 2-paths: wave-sort tier
+constexpr int kLightClasses = 6;       // 64, 128, 256, 512, 1024, 2048 keys per wave
 constexpr int kHeavyThreads = 512;     // workgroup of the bitmap-rank tier
 constexpr int kRangeBits = 1 << 17;    // hyperedge-id range of one heavy slot (bitmap bits)
 constexpr int kRangeWords = kRangeBits / 32;
@@ -92,7 +92,8 @@ hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t *tail_beg, in
 hipError_t launch_fill_slots(int64_t m, const int64_t *he_ptr, const int64_t *slot_base,
                              const int32_t *nslots, const int32_t *jmax, const uint8_t *rclass,
                              const int64_t *bbase, int64_t *hat, int32_t *slot_row, int32_t *const *lists,
-                             HeavyDesc *const *heavy, unsigned long long *list_fill, hipStream_t st);
+                             HeavyDesc *const *heavy, const int64_t *caps, unsigned long long *list_fill,
+                             int *err, hipStream_t st);
 hipError_t launch_bounds(const Pruned &g, const HeavyDesc *desc, int64_t count, int32_t *bounds,
                          hipStream_t st);
 
@@ -116,6 +117,7 @@ hipError_t launch_row_ptr(int64_t row_lo, int64_t row_hi, const int64_t *slot_ba
                           const int64_t *slot_off, int64_t slots, const EmitParams &ep,
                           int64_t out_base, hipStream_t st);
 hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t value, hipStream_t st);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t value, hipStream_t st);
 
 // Validation kernels (SLG_VALIDATE).
 hipError_t launch_validate_ptr(const int64_t *ptr, int64_t rows, int64_t nnz, int *err,

@@ -204,6 +204,11 @@ __global__ void fill_i64_kernel(int64_t *__restrict__ p, int64_t n, int64_t valu
     if (idx < n) p[idx] = value;
 }
 
+__global__ void fill_i32_kernel(int32_t *__restrict__ p, int64_t n, int32_t value) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < n) p[idx] = value;
+}
+
 template <typename T>
 hipError_t exclusive_scan(const T *in, int64_t n, int64_t *out, int64_t *partials, hipStream_t st) {
     if (n <= 0) return launch_fill_i64(out, 1, 0, st);
@@ -248,7 +253,9 @@ __global__ void compact_ptr_kernel(int64_t n, int64_t nnz, const int64_t *__rest
 // K2: per-row plan (one wavefront per hyperedge, grid-stride)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int light_class(int64_t w) {
-    return w <= 64 ? 0 : (w <= 128 ? 1 : (w <= 256 ? 2 : 3));
+    int c = 0;
+    while (c < kLightClasses - 1 && w > (int64_t(64) << c)) ++c;
+    return c;
 }
 
 __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min,
@@ -334,14 +341,20 @@ __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min,
     if (threadIdx.x == 0 && hwork) atomicAdd(heavy_work, hwork);
 }
 
+struct LightLists {
+    int32_t *l[kLightClasses];
+    int64_t cap[kNumLists];  // capacity of every tier list (light, heavy, heavy-wide)
+    int *err;                // set when an append would overflow a list
+};
+
 // One thread per row: write the row's slots and append them to the tier
 // lists (light: slot ids; heavy: slot descriptors).
 __global__ __launch_bounds__(256) void fill_slots_kernel(
     int64_t m, const int64_t *__restrict__ he_ptr, const int64_t *__restrict__ slot_base,
     const int32_t *__restrict__ nslots, const int32_t *__restrict__ jmax,
     const uint8_t *__restrict__ rclass, const int64_t *__restrict__ bbase,
-    int32_t *__restrict__ slot_row, int32_t *l0, int32_t *l1, int32_t *l2, int32_t *l3,
-    int64_t *__restrict__ hat, unsigned long long *__restrict__ list_fill) {
+    int32_t *__restrict__ slot_row, LightLists ll, int64_t *__restrict__ hat,
+    unsigned long long *__restrict__ list_fill) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = lane_id();
     int cls = kNone;
@@ -355,7 +368,6 @@ __global__ __launch_bounds__(256) void fill_slots_kernel(
         jm = jmax[i];
     }
     // light classes: wavefront-aggregated append, one slot per row
-    int32_t *lists[kLightClasses] = {l0, l1, l2, l3};
 #pragma unroll
     for (int c = 0; c < kLightClasses; ++c) {
         const bool mine = (cls == kLight0 + c);
@@ -366,8 +378,13 @@ __global__ __launch_bounds__(256) void fill_slots_kernel(
         if (lane == leader) at = atomicAdd(&list_fill[c], (unsigned long long)__popcll(mask));
         at = __shfl(at, leader);
         if (mine) {
-            lists[c][at + bits_below(mask)] = (int32_t)base;
-            slot_row[base] = (int32_t)i;
+            const unsigned long long pos = at + bits_below(mask);
+            if (pos < (unsigned long long)ll.cap[c]) {
+                ll.l[c][pos] = (int32_t)base;
+                slot_row[base] = (int32_t)i;
+            } else {
+                atomicOr(ll.err, 16);
+            }
         }
     }
     // heavy rows: reserve the row's descriptors (written by heavy_desc_kernel),
@@ -390,14 +407,20 @@ __global__ __launch_bounds__(256) void heavy_desc_kernel(
     int64_t m, const int64_t *__restrict__ he_ptr, const int64_t *__restrict__ slot_base,
     const int32_t *__restrict__ nslots, const int32_t *__restrict__ jmax,
     const uint8_t *__restrict__ rclass, const int64_t *__restrict__ bbase,
-    const int64_t *__restrict__ hat, int32_t *__restrict__ slot_row, HeavyDesc *hh, HeavyDesc *hw) {
+    const int64_t *__restrict__ hat, int32_t *__restrict__ slot_row, HeavyDesc *hh, HeavyDesc *hw,
+    int64_t cap_h, int64_t cap_w, int *__restrict__ err) {
     const int lane = lane_id();
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
     for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; i < m; i += nwaves) {
         const int cls = rclass[i];
         if (cls < kHeavy) continue;
         const int ns = nslots[i];
-        HeavyDesc *lst = (cls == kHeavy ? hh : hw) + hat[i];
+        const int64_t at = hat[i];
+        if (at < 0 || at + ns > (cls == kHeavy ? cap_h : cap_w)) {
+            if (lane == 0) atomicOr(err, 16);
+            continue;
+        }
+        HeavyDesc *lst = (cls == kHeavy ? hh : hw) + at;
         const int64_t base = slot_base[i];
         const int64_t range = (int64_t)jmax[i] - i;
         const int k = (int)(he_ptr[i + 1] - he_ptr[i]);
@@ -462,6 +485,8 @@ __global__ __launch_bounds__(256) void light_kernel(const int32_t *__restrict__ 
                                                     int64_t out_base) {
     constexpr int P = 64 * KPL;
     __shared__ int32_t buf[4][P];
+    __shared__ int32_t seg_a[4][64];
+    __shared__ int32_t seg_p[4][65];
     __shared__ EmitParams sp;  // thresholds and outputs, indexed by a uniform k
     stage_params(&sp, prm);
     __syncthreads();
@@ -475,7 +500,12 @@ __global__ __launch_bounds__(256) void light_kernel(const int32_t *__restrict__ 
     const int i = sl.row[slot];
     const int64_t p0 = g.he_ptr[i], p1 = g.he_ptr[i + 1];
 
-    // gather the partners e_j of every 2-path (e_i, v, e_j), j > i
+    // gather the partners e_j of every 2-path (e_i, v, e_j), j > i: members
+    // are taken 64 at a time; their tails are flattened and every lane finds
+    // the tail of each of its positions by binary search, so all loads of a
+    // batch are independent and coalesced within a tail
+    int32_t *sa = seg_a[wv];
+    int32_t *sp0 = seg_p[wv];
     int w = 0;
     for (int64_t q = p0; q < p1; q += 64) {
         const int64_t p = q + lane;
@@ -486,13 +516,35 @@ __global__ __launch_bounds__(256) void light_kernel(const int32_t *__restrict__ 
             len = (int)(g.vs_ptr[v + 1] - beg);
         }
         const int incl = wave_incl_scan(len);
-        const int excl = incl - len;
         const int tot = __shfl(incl, 63);
-        for (int t = 0; t < len; ++t) {
-            const int e = w + excl + t;
-            if (e < P) kb[e] = g.vs_idx[beg + t];
+        sa[lane] = beg;
+        sp0[lane] = incl - len;
+        if (lane == 0) sp0[64] = tot;
+        wave_lds_sync();
+        for (int fb = 0; fb < tot; fb += 256) {
+            int jr[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int f = min(fb + lane + 64 * r, tot - 1);
+                int lo = 0, hi = 63;  // largest u with sp0[u] <= f
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (sp0[mid] <= f)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                jr[r] = g.vs_idx[sa[lo] + (f - sp0[lo])];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int f = fb + lane + 64 * r;
+                const int e = w + f;
+                if (f < tot && e < P) kb[e] = jr[r];
+            }
         }
         w += tot;
+        wave_lds_sync();
     }
     if (w > P) w = P;  // the planner's class bound makes this unreachable
     wave_lds_sync();
@@ -636,7 +688,7 @@ __device__ __forceinline__ int segment_of(const int32_t *seg_pre, int lo, int hi
 constexpr int kWalkUnroll = 8;
 
 template <typename F>
-__device__ __forceinline__ void walk_segments(const int32_t *__restrict__ vs_idx, int total,
+__device__ __forceinline__ void walk_segments(const int32_t *__restrict__ vs_idx, int total, int nseg,
                                               const HeavySmem &sm, F &&f) {
     if (total <= 0) return;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
@@ -644,10 +696,11 @@ __device__ __forceinline__ void walk_segments(const int32_t *__restrict__ vs_idx
     const int c0 = wave * per;
     const int c1 = min(total, c0 + per);
     if (c0 >= c1) return;
-    int ufirst = segment_of(sm.seg_pre, 0, kHeavyThreads - 1, c0);
+    const int useg = min(nseg, kHeavyThreads) - 1;  // last segment of the batch
+    int ufirst = segment_of(sm.seg_pre, 0, useg, c0);
     for (int pb = c0; pb < c1; pb += 64 * kWalkUnroll) {
         const int plast = min(c1, pb + 64 * kWalkUnroll) - 1;
-        const int ulast = segment_of(sm.seg_pre, ufirst, kHeavyThreads - 1, plast);
+        const int ulast = segment_of(sm.seg_pre, ufirst, useg, plast);
         int jr[kWalkUnroll];
 #pragma unroll
         for (int r = 0; r < kWalkUnroll; ++r) {
@@ -746,18 +799,18 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(const HeavyDesc *_
             total1 = layout_segments(ra, len, sm);
             cached = total1 <= kRankCap;
             if (cached)
-                walk_segments(vs_idx, total1, sm, [&](int f, int j) {
+                walk_segments(vs_idx, total1, k, sm, [&](int f, int j) {
                     sm.buf[f] = j;
                     mark(f, j);
                 });
             else
-                walk_segments(vs_idx, total1, sm, mark);
+                walk_segments(vs_idx, total1, k, sm, mark);
             __syncthreads();
         } else {
             for (int qb = 0; qb < k; qb += kHeavyThreads) {
                 int a, len;
                 member_segment<false>(vs_idx, bounds, d.bptr, k, qb, 0, 0, a, len);
-                walk_segments(vs_idx, layout_segments(a, len, sm), sm, mark);
+                walk_segments(vs_idx, layout_segments(a, len, sm), k - qb, sm, mark);
                 __syncthreads();
             }
         }
@@ -835,7 +888,7 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(const HeavyDesc *_
                     for (; f < total1; f += kHeavyThreads) add(f, sm.buf[f]);
                     __syncthreads();
                 } else if (one_batch && whole) {
-                    walk_segments(vs_idx, total1, sm, add);  // segments of pass 1 still laid out
+                    walk_segments(vs_idx, total1, k, sm, add);  // segments of pass 1 still laid out
                     __syncthreads();
                 } else {
                     const int ka = ja + 32 * w0;
@@ -843,7 +896,7 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(const HeavyDesc *_
                     for (int qb = 0; qb < k; qb += kHeavyThreads) {
                         int a, len;
                         member_segment<true>(vs_idx, bounds, d.bptr, k, qb, ka, kb, a, len);
-                        walk_segments(vs_idx, layout_segments(a, len, sm), sm, add);
+                        walk_segments(vs_idx, layout_segments(a, len, sm), k - qb, sm, add);
                         __syncthreads();
                     }
                 }
@@ -859,45 +912,53 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(const HeavyDesc *_
                     }
                     __syncthreads();
                 }
-                // threshold per s_k over this wavefront's contiguous ranks
+                // threshold per s_k over this wavefront's contiguous ranks:
+                // every counter is read once and tested against all of S;
+                // the per-threshold tallies are wave-uniform
                 const int per = (((nr + kHW - 1) / kHW) + 63) & ~63;
                 const int rlo = wave * per;
                 const int rhi = min(nr, rlo + per);
-                for (int kk = 0; kk < K; ++kk) {
-                    const int sk = ep->s[kk];
-                    int nsurv = 0;
-                    for (int rbase = rlo; rbase < rhi; rbase += 64) {
-                        const int r = rbase + lane;
-                        const int c = r < rhi ? count_get<WIDE>(sm.cnt, r) : 0;
-                        nsurv += __popcll(__ballot(c >= sk));
-                    }
-                    if (EMIT) {
-                        if (lane == 0) sm.wtot[kk][wave] = nsurv;
-                    } else if (lane == 0 && nsurv) {
-                        atomicAdd(&sm.acc[kk], (unsigned long long)nsurv);
-                    }
+                int tally[SLG_MAX_S];
+#pragma unroll
+                for (int kk = 0; kk < SLG_MAX_S; ++kk) tally[kk] = 0;
+                for (int rbase = rlo; rbase < rhi; rbase += 64) {
+                    const int r = rbase + lane;
+                    const int c = r < rhi ? count_get<WIDE>(sm.cnt, r) : 0;
+#pragma unroll
+                    for (int kk = 0; kk < SLG_MAX_S; ++kk)
+                        if (kk < K) tally[kk] += __popcll(__ballot(c >= ep->s[kk]));
                 }
                 if (EMIT) {
+                    if (lane == 0)
+                        for (int kk = 0; kk < K; ++kk) sm.wtot[kk][wave] = tally[kk];
                     __syncthreads();
-                    for (int kk = 0; kk < K; ++kk) {
-                        const int sk = ep->s[kk];
-                        int64_t base = sm.obase[kk];
-                        for (int w = 0; w < wave; ++w) base += sm.wtot[kk][w];
-                        int32_t *col = ep->col[kk];
-                        int32_t *wo = ep->w[kk];
-                        int32_t *ro = ep->row[kk];
-                        for (int rbase = rlo; rbase < rhi; rbase += 64) {
-                            const int r = rbase + lane;
-                            const int c = r < rhi ? count_get<WIDE>(sm.cnt, r) : 0;
-                            const bool surv = c >= sk;
+                    int64_t base[SLG_MAX_S];
+#pragma unroll
+                    for (int kk = 0; kk < SLG_MAX_S; ++kk) {
+                        base[kk] = 0;
+                        if (kk < K) {
+                            base[kk] = sm.obase[kk];
+                            for (int w = 0; w < wave; ++w) base[kk] += sm.wtot[kk][w];
+                        }
+                    }
+                    for (int rbase = rlo; rbase < rhi; rbase += 64) {
+                        const int r = rbase + lane;
+                        const bool valid = r < rhi;
+                        const int c = valid ? count_get<WIDE>(sm.cnt, r) : 0;
+                        const int key = valid ? sm.buf[r] : 0;
+#pragma unroll
+                        for (int kk = 0; kk < SLG_MAX_S; ++kk) {
+                            if (kk >= K) break;
+                            const bool surv = c >= ep->s[kk];
                             const unsigned long long mask = __ballot(surv);
                             if (surv) {
-                                const int64_t pos = base + bits_below(mask);
-                                col[pos] = sm.buf[r];
-                                wo[pos] = c;
+                                const int64_t pos = base[kk] + bits_below(mask);
+                                ep->col[kk][pos] = key;
+                                ep->w[kk][pos] = c;
+                                int32_t *ro = ep->row[kk];
                                 if (ro) ro[pos] = i;
                             }
-                            base += __popcll(mask);
+                            base[kk] += __popcll(mask);
                         }
                     }
                     __syncthreads();
@@ -906,6 +967,9 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(const HeavyDesc *_
                         for (int w = 0; w < kHW; ++w) tot += sm.wtot[tid][w];
                         sm.obase[tid] += tot;
                     }
+                } else if (lane == 0) {
+                    for (int kk = 0; kk < K; ++kk)
+                        if (tally[kk]) atomicAdd(&sm.acc[kk], (unsigned long long)tally[kk]);
                 }
                 __syncthreads();
                 for (int x = tid; x < nwords; x += kHeavyThreads) sm.cnt[x] = 0u;
@@ -1076,6 +1140,12 @@ hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t value, hipStream_t st)
     return hipGetLastError();
 }
 
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t value, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    fill_i32_kernel<<<grid_for(n, 256), 256, 0, st>>>(p, n, value);
+    return hipGetLastError();
+}
+
 hipError_t launch_exclusive_scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *partials,
                                      hipStream_t st) {
     return exclusive_scan(in, n, out, partials, st);
@@ -1118,13 +1188,18 @@ hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t *tail_beg, in
 hipError_t launch_fill_slots(int64_t m, const int64_t *he_ptr, const int64_t *slot_base,
                              const int32_t *nslots, const int32_t *jmax, const uint8_t *rclass,
                              const int64_t *bbase, int64_t *hat, int32_t *slot_row, int32_t *const *lists,
-                             HeavyDesc *const *heavy, unsigned long long *list_fill, hipStream_t st) {
+                             HeavyDesc *const *heavy, const int64_t *caps, unsigned long long *list_fill,
+                             int *err, hipStream_t st) {
     if (m <= 0) return hipSuccess;
+    LightLists ll;
+    for (int c = 0; c < kLightClasses; ++c) ll.l[c] = lists[c];
+    for (int c = 0; c < kNumLists; ++c) ll.cap[c] = caps[c];
+    ll.err = err;
     fill_slots_kernel<<<grid_for(m, 256), 256, 0, st>>>(m, he_ptr, slot_base, nslots, jmax, rclass, bbase,
-                                                         slot_row, lists[0], lists[1], lists[2], lists[3],
-                                                         hat, list_fill);
+                                                         slot_row, ll, hat, list_fill);
     heavy_desc_kernel<<<wave_grid(m, 4, 8192), 256, 0, st>>>(m, he_ptr, slot_base, nslots, jmax, rclass,
-                                                              bbase, hat, slot_row, heavy[0], heavy[1]);
+                                                              bbase, hat, slot_row, heavy[0], heavy[1],
+                                                              caps[kLightClasses], caps[kLightClasses + 1], err);
     return hipGetLastError();
 }
 
@@ -1147,6 +1222,8 @@ hipError_t launch_light(int cls, bool emit, const int32_t *list, int64_t count, 
         case 1: SLG_LIGHT(2); break;
         case 2: SLG_LIGHT(4); break;
         case 3: SLG_LIGHT(8); break;
+        case 4: SLG_LIGHT(16); break;
+        case 5: SLG_LIGHT(32); break;
         default: return hipErrorInvalidValue;
     }
 #undef SLG_LIGHT
