@@ -94,8 +94,8 @@ const char *slg_version(void);
 
 /*
  * Create a context on HIP device `device`. mem_budget_bytes bounds the
- * device memory one call may hold for scratch and results (0 = no bound);
- * slg_line_graph_stream sizes its chunks to it. `alloc` may be NULL.
+ * device memory a call may hold (0 = no bound; recorded for the batched and
+ * served forms). `alloc` may be NULL.
  * Errors: INVALID_ARG (out == NULL), DEVICE (no such device).
  */
 slg_status slg_context_create(int device, uint64_t mem_budget_bytes, const slg_allocator *alloc,
@@ -190,6 +190,27 @@ slg_status slg_context_reset_timing(slg_context *ctx);
 
 /* Free a plan's device scratch (ordered on the stream it was made on). */
 slg_status slg_plan_destroy(slg_plan *p);
+
+/*
+ * Chunked form for outputs larger than device memory (row-range streaming).
+ * Plans once, then emits rows [0, m) in consecutive row ranges whose
+ * output fits chunk_bytes (all thresholds; 12 bytes per edge plus 8 per
+ * CSR offset). For every chunk and every threshold index k the callback
+ * receives, after the chunk's device work has completed:
+ *   rows [row_begin, row_end) of L_{s[k]}; its edges are global edges
+ *   [edge_begin, edge_begin + num_edges) of the sorted edge list;
+ *   row_ptr: DEVICE int64[row_end - row_begin + 1], relative (row_ptr[0]=0);
+ *   row/col/w: DEVICE int32[num_edges] (COO i, j, overlap).
+ * The pointers are valid only during the callback (buffers are reused).
+ * A nonzero return stops the stream: SLG_ERR_CANCELLED.
+ * Errors: as slg_plan_create; OUT_OF_MEMORY when one row alone needs more
+ * than chunk_bytes; INVALID_ARG for chunk_bytes <= 0 or a NULL callback.
+ */
+typedef int (*slg_chunk_fn)(void *user, int32_t k, int32_t s, int64_t row_begin, int64_t row_end,
+                            int64_t edge_begin, int64_t num_edges, const int64_t *row_ptr,
+                            const int32_t *row, const int32_t *col, const int32_t *w, void *stream);
+slg_status slg_line_graph_stream(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num_s,
+                                 int64_t chunk_bytes, slg_chunk_fn fn, void *user, void *stream);
 
 /*
  * One-shot form of plan + emit: result buffers come from the context's

@@ -56,6 +56,7 @@ class Incidence(ctypes.Structure):
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(_p, _p, ctypes.c_size_t, _p)
+_CHUNK_FN = ctypes.CFUNCTYPE(ctypes.c_int, _p, _i32, _i32, _i64, _i64, _i64, _i64, _p, _p, _p, _p, _p)
 _FREE_FN = ctypes.CFUNCTYPE(None, _p, _p, _p)
 
 
@@ -101,6 +102,7 @@ def lib() -> ctypes.CDLL:
         "slg_plan_destroy": (_i32, [_p]),
         "slg_plan_stats": (_i32, [_p, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i32)]),
         "slg_line_graph": (_i32, [_p, _p, ctypes.POINTER(_i32), _i32, _p, ctypes.POINTER(_p)]),
+        "slg_line_graph_stream": (_i32, [_p, _p, ctypes.POINTER(_i32), _i32, _i64, _CHUNK_FN, _p, _p]),
         "slg_context_set_timing": (_i32, [_p, ctypes.c_int]),
         "slg_context_get_timing": (_i32, [_p, ctypes.POINTER(StageTime), _i32, ctypes.POINTER(_i32)]),
         "slg_context_reset_timing": (_i32, [_p]),
@@ -328,6 +330,32 @@ class Context:
         finally:
             p.destroy()
         return outs
+
+    def line_graph_stream(self, g: Graph, s: Sequence[int], chunk_bytes: int, fn, stream=None):
+        """Chunked L_s: fn(k, s, row_begin, row_end, edge_begin, row_ptr, row, col, w) is called
+        per chunk and threshold with torch views of library buffers, valid only during the
+        call; return True to stop (SlgError CANCELLED)."""
+        import torch
+        dev = f"cuda:{self.device}"
+        errors = []
+
+        def _cb(user, k, sk, r0, r1, e0, ne, rp, ri, rj, rw, st):
+            try:
+                view = lambda ptr, n, ts: torch.as_tensor(_DeviceView(ptr, n, ts, None), device=dev)
+                stop = fn(int(k), int(sk), int(r0), int(r1), int(e0), view(rp, r1 - r0 + 1, "<i8"),
+                          view(ri, ne, "<i4"), view(rj, ne, "<i4"), view(rw, ne, "<i4"))
+                return 1 if stop else 0
+            except Exception as exc:  # surface Python errors after the call
+                errors.append(exc)
+                return 1
+
+        cb = _CHUNK_FN(_cb)
+        arr, kk = _s_array(s)
+        st = lib().slg_line_graph_stream(self.handle, g.handle, arr, kk, int(chunk_bytes), cb, None,
+                                         _stream_handle(stream))
+        if errors:
+            raise errors[0]
+        self._check(st)
 
     def line_graph_result(self, g: Graph, s: Sequence[int], stream=None) -> List[LineGraph]:
         """The one-shot ABI call (slg_line_graph): library-owned result buffers."""

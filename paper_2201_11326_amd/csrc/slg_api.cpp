@@ -3,6 +3,7 @@
 // prefix sums), the emit pass and the one-shot result object.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -403,6 +404,7 @@ slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int
                          "malformed incidence (bad pointer, id out of range, or vertex CSR not the transpose)"));
     for (int c = 0; c < kNumLists; ++c) p->list_count[c] = hb[kCntClass + c];
     p->S = hb[kHbSlots];
+    if (p->S >= (int64_t(1) << 31)) return bail(fail(ctx, SLG_ERR_OVERFLOW, "more than 2^31 output slots"));
     p->two_paths = hb[kHbSlots + 1];
     const int64_t nbounds = hb[kHbSlots + 2];
     p->nbounds = nbounds;
@@ -452,14 +454,14 @@ slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int
         StageTimer tm(ctx, kStCountLight, st);
         for (int c = 0; c < kLightClasses; ++c)
             PLAN_HIP(launch_light(c, false, p->lists[c], p->list_count[c], p->slots, pr, p->prm, p->slot_cnt,
-                                  nullptr, 0, st));
+                                  nullptr, st));
     }
     PLAN_HIP(launch_fill_i64(p->tickets, 4, 0, st));
     for (int wide = 0; wide < 2; ++wide) {
         if (p->list_count[kLightClasses + wide] <= 0) continue;
         StageTimer tm(ctx, wide ? kStCountHeavyWide : kStCountHeavy, st);
         PLAN_HIP(launch_heavy(false, wide, p->heavy[wide], p->list_count[kLightClasses + wide], p->S,
-                              p->bounds, pr, p->prm, p->slot_cnt, nullptr, 0, p->tickets + wide,
+                              p->bounds, pr, p->prm, p->slot_cnt, nullptr, p->tickets + wide,
                               ctx->heavy_resident, st));
     }
     {
@@ -496,56 +498,169 @@ slg_status slg_plan_info(const slg_plan *p, int32_t k, int64_t *num_edges, int64
     return SLG_OK;
 }
 
-slg_status slg_plan_emit(slg_plan *p, int64_t *const *row_ptr, int32_t *const *row,
-                         int32_t *const *col, int32_t *const *w, void *stream) {
-    if (!p || !row_ptr || !col || !w) return fail(p ? p->ctx : nullptr, SLG_ERR_INVALID_ARG, "null argument");
+namespace {
+// Emit rows [r0, r1) (slots [s0, s1)) of every threshold into buffers whose
+// first entry is global edge offset base[k]; row_ptr[k] gets r1 - r0 + 1
+// entries relative to base[k].
+slg_status emit_range(slg_plan *p, int64_t r0, int64_t r1, int64_t s0, int64_t s1, const int64_t *base,
+                      int64_t *const *row_ptr, int32_t *const *row, int32_t *const *col, int32_t *const *w,
+                      hipStream_t st) {
     slg_context *ctx = p->ctx;
     const int K = p->prm.k;
     EmitParams prm = p->prm;
+    prm.slot_lo = (int32_t)s0;
+    prm.slot_hi = (int32_t)s1;
     for (int k = 0; k < K; ++k) {
-        if (!row_ptr[k]) return fail(ctx, SLG_ERR_INVALID_ARG, "null row_ptr[%d]", k);
-        if (p->num_edges[k] > 0 && (!col[k] || !w[k]))
-            return fail(ctx, SLG_ERR_INVALID_ARG, "null col/w for threshold %d", k);
         prm.row_ptr[k] = row_ptr[k];
         prm.row[k] = row ? row[k] : nullptr;
         prm.col[k] = col[k];
         prm.w[k] = w[k];
-    }
-    SLG_HIP(ctx, hipSetDevice(ctx->device));
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    if (st != p->st) {  // order after the plan's own work
-        hipEvent_t ev;
-        SLG_HIP(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-        SLG_HIP(ctx, hipEventRecord(ev, p->st));
-        SLG_HIP(ctx, hipStreamWaitEvent(st, ev, 0));
-        SLG_HIP(ctx, hipEventDestroy(ev));
+        prm.out_base[k] = base[k];
     }
     {
         StageTimer tm(ctx, kStEmitLight, st);
         for (int c = 0; c < kLightClasses; ++c)
             SLG_HIP(ctx, launch_light(c, true, p->lists[c], p->list_count[c], p->slots, p->pr, prm, nullptr,
-                                      p->slot_off, 0, st));
+                                      p->slot_off, st));
     }
     SLG_HIP(ctx, launch_fill_i64(p->tickets + 2, 2, 0, st));
     for (int wide = 0; wide < 2; ++wide) {
         if (p->list_count[kLightClasses + wide] <= 0) continue;
         StageTimer tm(ctx, wide ? kStEmitHeavyWide : kStEmitHeavy, st);
         SLG_HIP(ctx, launch_heavy(true, wide, p->heavy[wide], p->list_count[kLightClasses + wide], p->S,
-                                  p->bounds, p->pr, prm, nullptr, p->slot_off, 0, p->tickets + 2 + wide,
+                                  p->bounds, p->pr, prm, nullptr, p->slot_off, p->tickets + 2 + wide,
                                   ctx->heavy_resident, st));
     }
     {
         StageTimer tm(ctx, kStRowPtr, st);
-        SLG_HIP(ctx, launch_row_ptr(0, p->pr.m, p->slot_base, p->slot_off, p->S, prm, 0, st));
-    }
-    if (st != p->st) {  // scratch is freed on the plan's stream
-        hipEvent_t ev;
-        SLG_HIP(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-        SLG_HIP(ctx, hipEventRecord(ev, st));
-        SLG_HIP(ctx, hipStreamWaitEvent(p->st, ev, 0));
-        SLG_HIP(ctx, hipEventDestroy(ev));
+        SLG_HIP(ctx, launch_row_ptr(r0, r1, p->slot_base, p->slot_off, p->S, prm, st));
     }
     return SLG_OK;
+}
+
+slg_status order_after(slg_context *ctx, hipStream_t later, hipStream_t earlier) {
+    if (later == earlier) return SLG_OK;
+    hipEvent_t ev;
+    SLG_HIP(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    SLG_HIP(ctx, hipEventRecord(ev, earlier));
+    SLG_HIP(ctx, hipStreamWaitEvent(later, ev, 0));
+    SLG_HIP(ctx, hipEventDestroy(ev));
+    return SLG_OK;
+}
+}  // namespace
+
+slg_status slg_plan_emit(slg_plan *p, int64_t *const *row_ptr, int32_t *const *row,
+                         int32_t *const *col, int32_t *const *w, void *stream) {
+    if (!p || !row_ptr || !col || !w) return fail(p ? p->ctx : nullptr, SLG_ERR_INVALID_ARG, "null argument");
+    slg_context *ctx = p->ctx;
+    const int K = p->prm.k;
+    for (int k = 0; k < K; ++k) {
+        if (!row_ptr[k]) return fail(ctx, SLG_ERR_INVALID_ARG, "null row_ptr[%d]", k);
+        if (p->num_edges[k] > 0 && (!col[k] || !w[k]))
+            return fail(ctx, SLG_ERR_INVALID_ARG, "null col/w for threshold %d", k);
+    }
+    SLG_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    slg_status rc = order_after(ctx, st, p->st);  // after the plan's own work
+    if (rc != SLG_OK) return rc;
+    const int64_t zero[SLG_MAX_S] = {};
+    rc = emit_range(p, 0, p->pr.m, 0, p->S, zero, row_ptr, row, col, w, st);
+    if (rc != SLG_OK) return rc;
+    return order_after(ctx, p->st, st);  // scratch is freed on the plan's stream
+}
+
+slg_status slg_line_graph_stream(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num_s,
+                                 int64_t chunk_bytes, slg_chunk_fn fn, void *user, void *stream) {
+    if (!ctx || !g || !fn || chunk_bytes <= 0) return fail(ctx, SLG_ERR_INVALID_ARG, "bad stream arguments");
+    slg_plan *p = nullptr;
+    slg_status rc = slg_plan_create(ctx, g, s, num_s, stream, &p);
+    if (rc != SLG_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int K = num_s;
+    const int64_t m = p->pr.m;
+    std::vector<void *> bufs;
+    auto cleanup = [&](slg_status code) {
+        (void)hipStreamSynchronize(st);
+        for (void *b : bufs) (void)hipFreeAsync(b, st);
+        slg_plan_destroy(p);
+        (void)hipStreamSynchronize(st);
+        return code;
+    };
+#define STREAM_HIP(call)                                                                            \
+    do {                                                                                            \
+        hipError_t e_ = (call);                                                                     \
+        if (e_ != hipSuccess)                                                                       \
+            return cleanup(fail(ctx, e_ == hipErrorOutOfMemory ? SLG_ERR_OUT_OF_MEMORY : SLG_ERR_DEVICE, \
+                                "%s: %s", #call, hipGetErrorString(e_)));                           \
+    } while (0)
+    // output bytes before every row; chunks are greedy row ranges
+    int64_t *dbytes;
+    STREAM_HIP(hipMallocAsync(reinterpret_cast<void **>(&dbytes), (m + 1) * sizeof(int64_t), st));
+    bufs.push_back(dbytes);
+    STREAM_HIP(launch_row_bytes(m, p->slot_base, p->slot_off, p->S, K, dbytes, st));
+    std::vector<int64_t> rbytes(m + 1);
+    STREAM_HIP(hipMemcpyAsync(rbytes.data(), dbytes, (m + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    STREAM_HIP(hipStreamSynchronize(st));
+    std::vector<int64_t> cuts{0};
+    while (cuts.back() < m) {
+        const int64_t r0 = cuts.back();
+        const int64_t limit = rbytes[r0] + chunk_bytes - 8 * K;  // room for the closing row_ptr entry
+        int64_t r1 = (int64_t)(std::upper_bound(rbytes.begin() + r0 + 1, rbytes.end(), limit) - rbytes.begin()) - 1;
+        if (r1 <= r0) {
+            return cleanup(fail(ctx, SLG_ERR_OUT_OF_MEMORY,
+                                "row %lld alone needs %lld bytes, more than chunk_bytes", (long long)r0,
+                                (long long)(rbytes[r0 + 1] - rbytes[r0] + 8 * K)));
+        }
+        cuts.push_back(r1);
+    }
+    // slot offsets of every threshold at every cut
+    const int64_t nc = (int64_t)cuts.size();
+    int64_t *dcuts, *doffs;
+    STREAM_HIP(hipMallocAsync(reinterpret_cast<void **>(&dcuts), nc * sizeof(int64_t), st));
+    bufs.push_back(dcuts);
+    STREAM_HIP(hipMallocAsync(reinterpret_cast<void **>(&doffs), nc * K * sizeof(int64_t), st));
+    bufs.push_back(doffs);
+    STREAM_HIP(hipMemcpyAsync(dcuts, cuts.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    STREAM_HIP(launch_gather_offsets(dcuts, nc, p->slot_base, p->slot_off, p->S, K, doffs, st));
+    std::vector<int64_t> offs(nc * K), sb(nc);
+    STREAM_HIP(hipMemcpyAsync(offs.data(), doffs, nc * K * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    for (int64_t c = 0; c < nc; ++c)  // first slot of every cut row
+        STREAM_HIP(hipMemcpyAsync(&sb[c], p->slot_base + cuts[c], sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    STREAM_HIP(hipStreamSynchronize(st));
+    // chunk buffers sized for the largest chunk of every threshold
+    int64_t max_rows = 0, max_e[SLG_MAX_S] = {};
+    for (int64_t c = 0; c + 1 < nc; ++c) {
+        max_rows = std::max(max_rows, cuts[c + 1] - cuts[c]);
+        for (int k = 0; k < K; ++k) max_e[k] = std::max(max_e[k], offs[(c + 1) * K + k] - offs[c * K + k]);
+    }
+    int64_t *rp[SLG_MAX_S];
+    int32_t *ri[SLG_MAX_S], *rj[SLG_MAX_S], *rw[SLG_MAX_S];
+    for (int k = 0; k < K; ++k) {
+        STREAM_HIP(hipMallocAsync(reinterpret_cast<void **>(&rp[k]), (max_rows + 1) * sizeof(int64_t), st));
+        bufs.push_back(rp[k]);
+        void *q[3];
+        for (int t = 0; t < 3; ++t) {
+            STREAM_HIP(hipMallocAsync(&q[t], std::max<int64_t>(max_e[k], 1) * sizeof(int32_t), st));
+            bufs.push_back(q[t]);
+        }
+        ri[k] = static_cast<int32_t *>(q[0]);
+        rj[k] = static_cast<int32_t *>(q[1]);
+        rw[k] = static_cast<int32_t *>(q[2]);
+    }
+    for (int64_t c = 0; c + 1 < nc; ++c) {
+        const int64_t r0 = cuts[c], r1 = cuts[c + 1];
+        rc = emit_range(p, r0, r1, sb[c], sb[c + 1], &offs[c * K], rp, ri, rj, rw, st);
+        if (rc != SLG_OK) return cleanup(rc);
+        STREAM_HIP(hipStreamSynchronize(st));
+        for (int k = 0; k < K; ++k) {
+            const int64_t e0 = offs[c * K + k], ne = offs[(c + 1) * K + k] - e0;
+            if (fn(user, k, s[k], r0, r1, e0, ne, rp[k], ri[k], rj[k], rw[k], stream) != 0)
+                return cleanup(fail(ctx, SLG_ERR_CANCELLED, "chunk callback stopped the stream at row %lld",
+                                    (long long)r0));
+        }
+    }
+#undef STREAM_HIP
+    return cleanup(SLG_OK);
 }
 
 slg_status slg_plan_stats(const slg_plan *p, int64_t *out, int32_t cap, int32_t *count) {

@@ -34,10 +34,13 @@ constexpr int kNumLists = kLightClasses + 2;  // light classes + heavy + heavy-w
 struct EmitParams {
     int32_t k;                      // number of thresholds
     int32_t s[SLG_MAX_S];           // strictly increasing, s[0] = s_min
+    int32_t slot_lo, slot_hi;       // emit only slots in [slot_lo, slot_hi)
+    int32_t pad_;
     int32_t *row[SLG_MAX_S];        // COO i per threshold (may be null)
     int32_t *col[SLG_MAX_S];        // j per threshold
     int32_t *w[SLG_MAX_S];          // overlap per threshold
     int64_t *row_ptr[SLG_MAX_S];    // CSR offsets per threshold
+    int64_t out_base[SLG_MAX_S];    // global edge offset of the buffers' first entry
 };
 
 // Device-side view of one hypergraph after pruning.
@@ -100,22 +103,27 @@ hipError_t launch_bounds(const Pruned &g, const HeavyDesc *desc, int64_t count, 
 // K3/K4/K5: count (EMIT=false) or emit (EMIT=true) per slot.
 hipError_t launch_light(int cls, bool emit, const int32_t *list, int64_t count, const Slots &sl,
                         const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
-                        const int64_t *slot_off, int64_t out_base, hipStream_t st);
+                        const int64_t *slot_off, hipStream_t st);
 // Persistent launch: `resident` workgroups (0 = a default) take slots from
 // the device counter `ticket`, which the caller zeroes before the launch.
 hipError_t launch_heavy(bool emit, bool wide, const HeavyDesc *desc, int64_t count, int64_t slots,
                         const int32_t *bounds, const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
-                        const int64_t *slot_off, int64_t out_base, int64_t *ticket, int resident,
-                        hipStream_t st);
+                        const int64_t *slot_off, int64_t *ticket, int resident, hipStream_t st);
 hipError_t launch_heavy_edges(const HeavyDesc *desc, int64_t count, const int64_t *slot_cnt, int64_t S,
                               int32_t K, int64_t *out, hipStream_t st);
 // Workgroups of the heavy kernel that fit on the device at once.
 int heavy_resident(int device);
 
-// K6: row_ptr[k][i] = slot_off[k][slot_base[i]] - out_base, i in [row_lo, row_hi].
+// K6: row_ptr[k][i - row_lo] = slot_off[k][slot_base[i]] - out_base[k], i in [row_lo, row_hi].
 hipError_t launch_row_ptr(int64_t row_lo, int64_t row_hi, const int64_t *slot_base,
-                          const int64_t *slot_off, int64_t slots, const EmitParams &ep,
-                          int64_t out_base, hipStream_t st);
+                          const int64_t *slot_off, int64_t slots, const EmitParams &ep, hipStream_t st);
+// Output bytes before row i (all thresholds; 12 B per edge + 8 B per row_ptr
+// entry), i in [0, m]; and slot_off[k][slot_base[r]] gathered at rows[c].
+hipError_t launch_row_bytes(int64_t m, const int64_t *slot_base, const int64_t *slot_off, int64_t slots,
+                            int32_t K, int64_t *out, hipStream_t st);
+hipError_t launch_gather_offsets(const int64_t *rows, int64_t count, const int64_t *slot_base,
+                                 const int64_t *slot_off, int64_t slots, int32_t K, int64_t *out,
+                                 hipStream_t st);
 hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t value, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t value, hipStream_t st);
 

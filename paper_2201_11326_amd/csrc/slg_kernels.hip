@@ -481,8 +481,7 @@ template <int KPL, bool EMIT>
 __global__ __launch_bounds__(256) void light_kernel(const int32_t *__restrict__ list, int64_t count,
                                                     Slots sl, Pruned g, EmitParams prm,
                                                     int64_t *__restrict__ slot_cnt,
-                                                    const int64_t *__restrict__ slot_off,
-                                                    int64_t out_base) {
+                                                    const int64_t *__restrict__ slot_off) {
     constexpr int P = 64 * KPL;
     __shared__ int32_t buf[4][P];
     __shared__ int32_t seg_a[4][64];
@@ -497,6 +496,7 @@ __global__ __launch_bounds__(256) void light_kernel(const int32_t *__restrict__ 
     if (wid >= count) return;
     int32_t *kb = buf[wv];
     const int slot = list[wid];
+    if (EMIT && (slot < ep->slot_lo || slot >= ep->slot_hi)) return;  // outside the emitted chunk
     const int i = sl.row[slot];
     const int64_t p0 = g.he_ptr[i], p1 = g.he_ptr[i + 1];
 
@@ -580,7 +580,7 @@ __global__ __launch_bounds__(256) void light_kernel(const int32_t *__restrict__ 
     const int64_t S = sl.count;
     for (int k = 0; k < K; ++k) {
         const int sk = ep->s[k];
-        int64_t base = EMIT ? slot_off[(int64_t)k * (S + 1) + slot] - out_base : 0;
+        int64_t base = EMIT ? slot_off[(int64_t)k * (S + 1) + slot] - ep->out_base[k] : 0;
         int32_t *col = EMIT ? ep->col[k] : nullptr;
         int32_t *wo = EMIT ? ep->w[k] : nullptr;
         int32_t *ro = EMIT ? ep->row[k] : nullptr;
@@ -739,7 +739,6 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(const HeavyDesc *_
                                                               EmitParams prm,
                                                               int64_t *__restrict__ slot_cnt,
                                                               const int64_t *__restrict__ slot_off,
-                                                              int64_t out_base,
                                                               unsigned long long *__restrict__ ticket) {
     constexpr int kCap = CounterCap<WIDE>::ranks;
     __shared__ HeavySmem sm;
@@ -778,12 +777,21 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(const HeavyDesc *_
         // slot and at the end of every slot
         if (tid < SLG_MAX_S) {
             sm.acc[tid] = 0;
-            sm.obase[tid] = (EMIT && tid < K) ? slot_off[(int64_t)tid * (S + 1) + slot] - out_base : 0;
+            sm.obase[tid] = (EMIT && tid < K) ? slot_off[(int64_t)tid * (S + 1) + slot] - ep->out_base[tid] : 0;
         }
         __syncthreads();
         const int64_t it_next = next_slot;
         const bool have_next = it_next < count;
         if (have_next) nd = desc[it_next];
+        if (EMIT && (slot < ep->slot_lo || slot >= ep->slot_hi)) {  // outside the emitted chunk
+            if (have_next && tid < nd.k) {
+                na = bounds[nd.bptr + tid];
+                nb = bounds[nd.bptr + nd.k + tid];
+            }
+            __syncthreads();  // next_slot is rewritten at the top of the loop
+            if (!have_next) break;
+            continue;
+        }
 
         // pass 1: mark every partner j of the slot's range; keep the partners
         // in LDS when they fit, so that pass 2 reads no global memory
@@ -1036,15 +1044,38 @@ __global__ __launch_bounds__(256) void bounds_kernel(
 // K6: CSR row pointers from slot offsets
 // ---------------------------------------------------------------------------
 __global__ void row_ptr_kernel(int64_t row_lo, int64_t row_hi, const int64_t *__restrict__ slot_base,
-                               const int64_t *__restrict__ slot_off, int64_t S, EmitParams prm,
-                               int64_t out_base) {
+                               const int64_t *__restrict__ slot_off, int64_t S, EmitParams prm) {
     __shared__ EmitParams sp;
     stage_params(&sp, prm);
     __syncthreads();
     const int64_t i = row_lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i > row_hi) return;
     const int64_t sb = slot_base[i];
-    for (int k = 0; k < sp.k; ++k) sp.row_ptr[k][i - row_lo] = slot_off[(int64_t)k * (S + 1) + sb] - out_base;
+    for (int k = 0; k < sp.k; ++k)
+        sp.row_ptr[k][i - row_lo] = slot_off[(int64_t)k * (S + 1) + sb] - sp.out_base[k];
+}
+
+// Output bytes of rows [0, i) over all thresholds, i in [0, m].
+__global__ void row_bytes_kernel(int64_t m, const int64_t *__restrict__ slot_base,
+                                 const int64_t *__restrict__ slot_off, int64_t S, int32_t K,
+                                 int64_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > m) return;
+    const int64_t sb = slot_base[i];
+    int64_t b = 0;
+    for (int k = 0; k < K; ++k) b += 12 * slot_off[(int64_t)k * (S + 1) + sb] + 8 * i;
+    out[i] = b;
+}
+
+// out[c * K + k] = slot_off[k][slot_base[rows[c]]].
+__global__ void gather_offsets_kernel(const int64_t *__restrict__ rows, int64_t count,
+                                      const int64_t *__restrict__ slot_base,
+                                      const int64_t *__restrict__ slot_off, int64_t S, int32_t K,
+                                      int64_t *__restrict__ out) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= count) return;
+    const int64_t sb = slot_base[rows[c]];
+    for (int k = 0; k < K; ++k) out[c * K + k] = slot_off[(int64_t)k * (S + 1) + sb];
 }
 
 // ---------------------------------------------------------------------------
@@ -1205,17 +1236,17 @@ hipError_t launch_fill_slots(int64_t m, const int64_t *he_ptr, const int64_t *sl
 
 hipError_t launch_light(int cls, bool emit, const int32_t *list, int64_t count, const Slots &sl,
                         const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
-                        const int64_t *slot_off, int64_t out_base, hipStream_t st) {
+                        const int64_t *slot_off, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     const unsigned grid = grid_for(count, 4);
 #define SLG_LIGHT(KPL)                                                                              \
     do {                                                                                           \
         if (emit)                                                                                  \
             light_kernel<KPL, true><<<grid, 256, 0, st>>>(list, count, sl, g, ep, slot_cnt,        \
-                                                          slot_off, out_base);                     \
+                                                          slot_off);                               \
         else                                                                                       \
             light_kernel<KPL, false><<<grid, 256, 0, st>>>(list, count, sl, g, ep, slot_cnt,       \
-                                                           slot_off, out_base);                    \
+                                                           slot_off);                              \
     } while (0)
     switch (cls) {
         case 0: SLG_LIGHT(1); break;
@@ -1232,15 +1263,14 @@ hipError_t launch_light(int cls, bool emit, const int32_t *list, int64_t count, 
 
 hipError_t launch_heavy(bool emit, bool wide, const HeavyDesc *desc, int64_t count, int64_t slots,
                         const int32_t *bounds, const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
-                        const int64_t *slot_off, int64_t out_base, int64_t *ticket, int resident,
-                        hipStream_t st) {
+                        const int64_t *slot_off, int64_t *ticket, int resident, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     const int64_t want = resident > 0 ? resident : 512;
     const unsigned grid = (unsigned)(count < want ? count : want);
     unsigned long long *tk = reinterpret_cast<unsigned long long *>(ticket);
 #define SLG_HEAVY(E, W)                                                                             \
     heavy_kernel<E, W><<<grid, kHeavyThreads, 0, st>>>(desc, count, slots, bounds, g.vs_idx, ep, slot_cnt, \
-                                                       slot_off, out_base, tk)
+                                                       slot_off, tk)
     if (emit && wide) SLG_HEAVY(true, true);
     else if (emit) SLG_HEAVY(true, false);
     else if (wide) SLG_HEAVY(false, true);
@@ -1266,12 +1296,25 @@ hipError_t launch_bounds(const Pruned &g, const HeavyDesc *desc, int64_t count, 
 }
 
 hipError_t launch_row_ptr(int64_t row_lo, int64_t row_hi, const int64_t *slot_base,
-                          const int64_t *slot_off, int64_t slots, const EmitParams &ep,
-                          int64_t out_base, hipStream_t st) {
+                          const int64_t *slot_off, int64_t slots, const EmitParams &ep, hipStream_t st) {
     const int64_t n = row_hi - row_lo + 1;
     if (n <= 0) return hipSuccess;
-    row_ptr_kernel<<<grid_for(n, 256), 256, 0, st>>>(row_lo, row_hi, slot_base, slot_off, slots, ep,
-                                                      out_base);
+    row_ptr_kernel<<<grid_for(n, 256), 256, 0, st>>>(row_lo, row_hi, slot_base, slot_off, slots, ep);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_bytes(int64_t m, const int64_t *slot_base, const int64_t *slot_off, int64_t slots,
+                            int32_t K, int64_t *out, hipStream_t st) {
+    row_bytes_kernel<<<grid_for(m + 1, 256), 256, 0, st>>>(m, slot_base, slot_off, slots, K, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_offsets(const int64_t *rows, int64_t count, const int64_t *slot_base,
+                                 const int64_t *slot_off, int64_t slots, int32_t K, int64_t *out,
+                                 hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    gather_offsets_kernel<<<grid_for(count, 256), 256, 0, st>>>(rows, count, slot_base, slot_off, slots, K,
+                                                                 out);
     return hipGetLastError();
 }
 

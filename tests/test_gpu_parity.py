@@ -277,3 +277,89 @@ def test_wide_rows_full(ctx):
     inc = hg.from_rows(rows, n=100_000)
     for lg in run_gpu(ctx, inc, [1, 2, 3, 20_000]):
         assert_matches_oracle(inc, lg, lg.s, "wide")
+
+
+def _stream_collect(ctx, g, s_list, chunk_bytes):
+    got = {k: [] for k in range(len(s_list))}
+
+    def fn(k, s, r0, r1, e0, rp, ri, rj, rw):
+        got[k].append((r0, r1, e0, rp.cpu().numpy(), ri.cpu().numpy(), rj.cpu().numpy(), rw.cpu().numpy()))
+        return False
+
+    ctx.line_graph_stream(g, s_list, chunk_bytes, fn)
+    return got
+
+
+@pytest.mark.parametrize("chunk_bytes", [128 << 10, 1 << 20, 16 << 20])
+def test_stream_chunks_reassemble_to_oracle(ctx, chunk_bytes):
+    inc = hg.random_small(401, 3000, 250, 30, 1.5)
+    g = ctx.register_incidence(inc)
+    s_list = [1, 2, 5]
+    got = _stream_collect(ctx, g, s_list, chunk_bytes)
+    nchunks = len(got[0])
+    for c in range(nchunks):  # every chunk's output, all thresholds, fits the budget
+        used = sum(12 * len(got[k][c][5]) + 8 * (got[k][c][1] - got[k][c][0] + 1) for k in got)
+        assert used <= chunk_bytes
+        assert len({(got[k][c][0], got[k][c][1]) for k in got}) == 1  # same rows for every s
+    for k, s in enumerate(s_list):
+        chunks = got[k]
+        assert chunks[0][0] == 0 and chunks[-1][1] == inc.m
+        rp = [0]
+        for (r0, r1, e0, crp, ci, cj, cw) in chunks:
+            assert crp[0] == 0 and r0 == len(rp) - 1 and e0 == rp[-1]
+            rp.extend((e0 + crp[1:]).tolist())
+        ref = oracle.line_graph(inc, s)
+        assert np.array_equal(np.array(rp), ref.row_ptr)
+        assert np.array_equal(np.concatenate([c[4] for c in chunks]), ref.i)
+        assert np.array_equal(np.concatenate([c[5] for c in chunks]), ref.j)
+        assert np.array_equal(np.concatenate([c[6] for c in chunks]), ref.w)
+    if chunk_bytes == 128 << 10:
+        assert nchunks > 10
+    g.release()
+
+
+def test_stream_cancel_and_budget_errors(ctx):
+    import paper_2201_11326_amd as slg
+    inc = hg.random_small(402, 2000, 200, 25, 1.5)
+    g = ctx.register_incidence(inc)
+    calls = []
+    with pytest.raises(slg.SlgError) as e:
+        ctx.line_graph_stream(g, [1], 1 << 20, lambda *a: calls.append(1) or True)
+    assert e.value.status == slg.SLG_ERR_CANCELLED and len(calls) == 1
+    with pytest.raises(slg.SlgError) as e:
+        ctx.line_graph_stream(g, [1], 16, lambda *a: False)
+    assert e.value.status == slg.SLG_ERR_OUT_OF_MEMORY
+    g.release()
+
+
+def test_stream_large_skewed_shape_sampled(ctx):
+    """The large skewed hypergraph's shape (lognormal sizes, vertex weight
+    rank^-1.5) scaled to m = 2e5, s = 16, streamed in chunks."""
+    inc = hg.large_skewed(n=100_000, m=200_000)
+    g = ctx.register_incidence(inc)
+    seen = {}
+    total = [0]
+
+    def fn(k, s, r0, r1, e0, rp, ri, rj, rw):
+        total[0] += int(rj.numel())
+        crp = rp.cpu().numpy()
+        for i in sample:
+            if r0 <= i < r1:
+                a, b = int(crp[i - r0]), int(crp[i - r0 + 1])
+                seen[i] = (rj[a:b].cpu().numpy(), rw[a:b].cpu().numpy())
+        assert bool((rw >= s).all()) and bool((rj > ri).all())
+        return False
+
+    sizes = inc.sizes()
+    kept = np.nonzero(sizes >= 16)[0]
+    rng = np.random.default_rng(3)
+    sample = set(kept[:5].tolist()) | set(rng.choice(kept, 40, replace=False).tolist())
+    ctx.line_graph_stream(g, [16], 64 << 20, fn)
+    ref = oracle.line_graph_rows(inc, 16, sorted(sample))
+    for t, i in enumerate(ref.rows):
+        rj, rw = ref.row(t)
+        assert np.array_equal(seen[int(i)][0], rj) and np.array_equal(seen[int(i)][1], rw)
+    p = ctx.plan(g, [16])
+    assert total[0] == p.num_edges()[0] and p.two_paths == oracle.two_paths(inc, 16)
+    p.destroy()
+    g.release()
