@@ -51,6 +51,7 @@ typedef struct slg_context slg_context;
 typedef struct slg_graph slg_graph;
 typedef struct slg_plan slg_plan;
 typedef struct slg_result slg_result;
+typedef struct slg_batch slg_batch;
 
 /*
  * The input: the incidence of H held as both CSR orientations
@@ -211,6 +212,40 @@ typedef int (*slg_chunk_fn)(void *user, int32_t k, int32_t s, int64_t row_begin,
                             const int32_t *row, const int32_t *col, const int32_t *w, void *stream);
 slg_status slg_line_graph_stream(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num_s,
                                  int64_t chunk_bytes, slg_chunk_fn fn, void *user, void *stream);
+
+/*
+ * Batched form: many independent hypergraphs, each with its own threshold
+ * s[g] (Algorithm 2 per graph). slg_batch_create builds their disjoint
+ * union on the device (ids offset per graph, a threshold per hyperedge),
+ * plans it once, allocates every buffer and computes the results (blocks
+ * until done). The registered graphs must stay valid until
+ * slg_batch_destroy. slg_batch_run repeats the whole device path (pruning,
+ * planning, counting, emitting) into the same buffers with no host
+ * synchronisation and no allocation; with use_graph != 0 the path is
+ * captured once into a HIP graph and replayed on `stream`.
+ * Results per graph g (DEVICE pointers, valid until destroy):
+ *   row_ptr: int64[m_g + 1], GLOBAL edge offsets (subtract *edge_begin);
+ *   row/col/w: int32[num_edges], ids local to graph g, sorted by (i, j).
+ * Errors: INVALID_ARG (n < 1 or > 65535, s[g] < 1), OVERFLOW (totals
+ * >= 2^31), and as slg_plan_create.
+ */
+slg_status slg_batch_create(slg_context *ctx, slg_graph *const *graphs, const int32_t *s, int32_t n,
+                            void *stream, slg_batch **out);
+slg_status slg_batch_run(slg_batch *b, int32_t use_graph, void *stream);
+slg_status slg_batch_info(const slg_batch *b, int64_t *num_edges, int64_t *two_paths, int64_t *rows);
+slg_status slg_batch_result(const slg_batch *b, int32_t g, int64_t *edge_begin, int64_t *num_edges,
+                            const int64_t **row_ptr, const int32_t **row, const int32_t **col,
+                            const int32_t **w);
+slg_status slg_batch_destroy(slg_batch *b);
+
+/*
+ * Tuning of the plan shape, used by the autotuner: light_max = largest row
+ * work (2-paths) sorted by one wavefront (<= 2048; 0 = default),
+ * slot_work = 2-paths per heavy slot before a row is split (0 = default),
+ * heavy_grid = persistent heavy workgroups (0 = as many as fit the GPU).
+ * Applies to plans and batches created afterwards on this context.
+ */
+slg_status slg_context_set_tuning(slg_context *ctx, int32_t light_max, int64_t slot_work, int32_t heavy_grid);
 
 /*
  * One-shot form of plan + emit: result buffers come from the context's

@@ -103,6 +103,13 @@ def lib() -> ctypes.CDLL:
         "slg_plan_stats": (_i32, [_p, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i32)]),
         "slg_line_graph": (_i32, [_p, _p, ctypes.POINTER(_i32), _i32, _p, ctypes.POINTER(_p)]),
         "slg_line_graph_stream": (_i32, [_p, _p, ctypes.POINTER(_i32), _i32, _i64, _CHUNK_FN, _p, _p]),
+        "slg_batch_create": (_i32, [_p, ctypes.POINTER(_p), ctypes.POINTER(_i32), _i32, _p, ctypes.POINTER(_p)]),
+        "slg_batch_run": (_i32, [_p, _i32, _p]),
+        "slg_batch_info": (_i32, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+        "slg_batch_result": (_i32, [_p, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_p),
+                                    ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
+        "slg_batch_destroy": (_i32, [_p]),
+        "slg_context_set_tuning": (_i32, [_p, _i32, _i64, _i32]),
         "slg_context_set_timing": (_i32, [_p, ctypes.c_int]),
         "slg_context_get_timing": (_i32, [_p, ctypes.POINTER(StageTime), _i32, ctypes.POINTER(_i32)]),
         "slg_context_reset_timing": (_i32, [_p]),
@@ -225,6 +232,48 @@ class Plan:
             pass
 
 
+class Batch:
+    """Many hypergraphs, each with its own s, planned as one disjoint union."""
+
+    def __init__(self, ctx: "Context", handle: int, graphs, s: List[int]):
+        self.ctx, self.handle, self.graphs, self.s = ctx, handle, list(graphs), list(s)
+
+    def run(self, use_graph: bool = True, stream=None):
+        """Repeat the whole device path (HIP-graph replay when use_graph)."""
+        self.ctx._check(lib().slg_batch_run(self.handle, 1 if use_graph else 0, _stream_handle(stream)))
+
+    def info(self):
+        e, w, r = _i64(), _i64(), _i64()
+        self.ctx._check(lib().slg_batch_info(self.handle, ctypes.byref(e), ctypes.byref(w), ctypes.byref(r)))
+        return {"edges": int(e.value), "two_paths": int(w.value), "rows": int(r.value)}
+
+    def result(self, g: int) -> LineGraph:
+        """Graph g's L_s as zero-copy views (row_ptr rebased to start at 0)."""
+        import torch
+        e0, ne = _i64(), _i64()
+        rp, ri, rj, rw = _p(), _p(), _p(), _p()
+        self.ctx._check(lib().slg_batch_result(self.handle, g, ctypes.byref(e0), ctypes.byref(ne),
+                                               ctypes.byref(rp), ctypes.byref(ri), ctypes.byref(rj),
+                                               ctypes.byref(rw)))
+        dev = f"cuda:{self.ctx.device}"
+        view = lambda ptr, n, ts: torch.as_tensor(_DeviceView(ptr, n, ts, self), device=dev)
+        m = self.graphs[g].m
+        n = int(ne.value)
+        return LineGraph(self.s[g], view(rp.value, m + 1, "<i8") - int(e0.value), view(ri.value, n, "<i4"),
+                         view(rj.value, n, "<i4"), view(rw.value, n, "<i4"), 0, owner=self)
+
+    def destroy(self):
+        if self.handle:
+            lib().slg_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
 class Context:
     def __init__(self, device: int = 0, mem_budget_bytes: int = 0, torch_allocator: bool = True):
         import torch
@@ -249,6 +298,18 @@ class Context:
         if st != SLG_OK:
             raise SlgError(st, "slg_context_create failed")
         self.handle = h.value
+
+    # -- batched form and tuning ---------------------------------------------
+    def batch(self, graphs: Sequence[Graph], s: Sequence[int], stream=None) -> Batch:
+        hs = (_p * len(graphs))(*[g.handle for g in graphs])
+        arr = (_i32 * len(s))(*[int(x) for x in s])
+        h = _p()
+        self._check(lib().slg_batch_create(self.handle, hs, arr, len(graphs), _stream_handle(stream),
+                                           ctypes.byref(h)))
+        return Batch(self, h.value, graphs, [int(x) for x in s])
+
+    def set_tuning(self, light_max: int = 0, slot_work: int = 0, heavy_grid: int = 0):
+        self._check(lib().slg_context_set_tuning(self.handle, light_max, slot_work, heavy_grid))
 
     # -- measurement ---------------------------------------------------------
     def set_timing(self, enable: bool = True):

@@ -38,6 +38,10 @@ struct slg_context {
     std::vector<hipEvent_t> event_pool;
     int64_t stage_launches[kNumStages] = {};
     double stage_ms[kNumStages] = {};
+    bool capturing = false;  // a hipGraph capture is recording: no event timing
+    int32_t light_max = kLightMax;
+    int64_t slot_work = kSlotWork;
+    int heavy_grid = 0;
     uint64_t budget = 0;
     bool has_alloc = false;
     slg_allocator alloc{};
@@ -117,7 +121,7 @@ struct StageTimer {
     hipStream_t st;
     hipEvent_t start = nullptr, stop = nullptr;
     StageTimer(slg_context *c, int sg, hipStream_t s) : ctx(c), stage(sg), st(s) {
-        if (!ctx || !ctx->timing) return;
+        if (!ctx || !ctx->timing || ctx->capturing) return;
         start = take();
         stop = take();
         if (start && stop) (void)hipEventRecord(start, st);
@@ -148,6 +152,17 @@ bool valid_s(const int32_t *s, int32_t k) {
 
 }  // namespace
 
+// Device buffers of a plan, kept so the planning launches can be replayed.
+struct PlanBufs {
+    uint8_t *flag = nullptr;
+    int64_t *pos = nullptr, *part_nnz = nullptr, *vs_ptr = nullptr;
+    int32_t *vs_idx = nullptr;
+    int32_t *tail_beg = nullptr, *jmax = nullptr, *nslots = nullptr, *slot_row = nullptr;
+    int64_t *work = nullptr, *work_pre = nullptr, *counters = nullptr, *part_m = nullptr;
+    int64_t *bsize = nullptr, *bbase = nullptr, *hat = nullptr, *part_s = nullptr;
+    uint8_t *rclass = nullptr;
+};
+
 struct slg_plan {
     slg_context *ctx = nullptr;
     slg_graph *g = nullptr;
@@ -155,6 +170,12 @@ struct slg_plan {
     EmitParams prm{};
     Pruned pr{};
     Scratch scratch;
+    PlanBufs b;
+    bool prune = false;            // vertex lists are compacted to E_{s_min}
+    int32_t s_min = 1;
+    int32_t light_max = kLightMax; // tuning: wavefront-sort tier bound
+    int64_t slot_work = kSlotWork; // tuning: 2-paths per heavy slot
+    int heavy_grid = 0;            // tuning: persistent heavy workgroups
     int64_t *slot_base = nullptr;  // [m+1]
     int64_t S = 0;                 // number of slots
     Slots slots{};
@@ -170,6 +191,23 @@ struct slg_plan {
     int64_t heavy_edges = 0;
     int64_t nbounds = 0;
     int64_t num_edges[SLG_MAX_S] = {};
+};
+
+struct slg_batch {
+    slg_context *ctx = nullptr;
+    hipStream_t st = nullptr;        // stream the batch was built on
+    int32_t n = 0;
+    std::vector<int64_t> m_off, m_g;  // per graph (m_off has n + 1 entries)
+    std::vector<int64_t> edge_off;    // n + 1 global edge offsets
+    slg_graph ug;                     // the disjoint union
+    slg_plan *p = nullptr;
+    int64_t *row_ptr = nullptr;
+    int32_t *row = nullptr, *col = nullptr, *w = nullptr;
+    int64_t edges = 0;
+    std::vector<void *> owned;        // union arrays and outputs (hipMallocAsync)
+    hipStream_t cap = nullptr;        // capture stream
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 struct slg_result {
@@ -297,6 +335,216 @@ slg_status slg_graph_release(slg_graph *g) {
     return SLG_OK;
 }
 
+namespace {
+
+// Planning launches up to the tier sizes: pruning, per-row plan, scans.
+hipError_t enqueue_rows(slg_plan *p, hipStream_t st) {
+    slg_context *ctx = p->ctx;
+    const slg_incidence &inc = p->g->inc;
+    const int64_t m = inc.num_hyperedges, n = inc.num_vertices, nnz = inc.nnz;
+    PlanBufs &b = p->b;
+    hipError_t e;
+    if ((e = launch_fill_i64(b.counters, 32, 0, st)) != hipSuccess) return e;
+    if (p->prune) {
+        StageTimer tm(ctx, kStPrune, st);
+        if ((e = launch_keep_incidence(nnz, inc.v_idx, inc.he_ptr, m, p->s_min, p->pr.row_s, b.flag, st)) !=
+            hipSuccess)
+            return e;
+        if ((e = launch_exclusive_scan_u8(b.flag, nnz, b.pos, b.part_nnz, st)) != hipSuccess) return e;
+        if ((e = launch_compact_vertex_lists(n, nnz, inc.v_ptr, inc.v_idx, b.flag, b.pos, b.vs_ptr, b.vs_idx,
+                                             st)) != hipSuccess)
+            return e;
+    }
+    {
+        StageTimer tm(ctx, kStRowPlan, st);
+        if ((e = launch_row_plan(p->pr, p->s_min, p->light_max, p->slot_work, b.tail_beg, b.work, b.jmax,
+                                 b.nslots, b.rclass, b.bsize,
+                                 reinterpret_cast<unsigned long long *>(b.counters + kCntClass),
+                                 reinterpret_cast<int *>(b.counters + kCntErr),
+                                 reinterpret_cast<unsigned long long *>(b.counters + kCntHeavyWork), st)) !=
+            hipSuccess)
+            return e;
+    }
+    StageTimer tm(ctx, kStPlanScans, st);
+    if ((e = launch_exclusive_scan_i32(b.nslots, m, p->slot_base, b.part_m, st)) != hipSuccess) return e;
+    if ((e = launch_exclusive_scan_i64(b.work, m, b.work_pre, b.part_m, st)) != hipSuccess) return e;
+    return launch_exclusive_scan_i64(b.bsize, m, b.bbase, b.part_m, st);
+}
+
+// Slot table, tier lists, boundary table, counting pass and its scans.
+hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
+    slg_context *ctx = p->ctx;
+    const int64_t m = p->pr.m;
+    PlanBufs &b = p->b;
+    hipError_t e;
+    // lists start zeroed: an entry the fill kernels refuse to write (list
+    // overflow, flagged in err) names slot 0 / an empty descriptor
+    for (int c = 0; c < kLightClasses; ++c)
+        if ((e = launch_fill_i32(p->lists[c], p->list_count[c], 0, st)) != hipSuccess) return e;
+    for (int h = 0; h < 2; ++h)
+        if ((e = launch_fill_i64(reinterpret_cast<int64_t *>(p->heavy[h]),
+                                 p->list_count[kLightClasses + h] * (int64_t)(sizeof(HeavyDesc) / 8), 0, st)) !=
+            hipSuccess)
+            return e;
+    {
+        StageTimer tm(ctx, kStSlots, st);
+        if ((e = launch_fill_slots(m, p->pr.he_ptr, p->slot_base, b.nslots, b.jmax, b.rclass, b.bbase, b.hat,
+                                   b.slot_row, p->lists, p->heavy, p->list_count,
+                                   reinterpret_cast<unsigned long long *>(b.counters + kCntFill),
+                                   reinterpret_cast<int *>(b.counters + kCntErr), st)) != hipSuccess)
+            return e;
+    }
+    {
+        StageTimer tm(ctx, kStBounds, st);
+        for (int h = 0; h < 2; ++h)
+            if ((e = launch_bounds(p->pr, p->heavy[h], p->list_count[kLightClasses + h], p->bounds, st)) !=
+                hipSuccess)
+                return e;
+    }
+    {
+        StageTimer tm(ctx, kStCountLight, st);
+        for (int c = 0; c < kLightClasses; ++c)
+            if ((e = launch_light(c, false, p->lists[c], p->list_count[c], p->slots, p->pr, p->prm, p->slot_cnt,
+                                  nullptr, st)) != hipSuccess)
+                return e;
+    }
+    if ((e = launch_fill_i64(p->tickets, 5, 0, st)) != hipSuccess) return e;
+    for (int wide = 0; wide < 2; ++wide) {
+        if (p->list_count[kLightClasses + wide] <= 0) continue;
+        StageTimer tm(ctx, wide ? kStCountHeavyWide : kStCountHeavy, st);
+        if ((e = launch_heavy(false, wide, p->heavy[wide], p->list_count[kLightClasses + wide], p->S, p->bounds,
+                              p->pr, p->prm, p->slot_cnt, nullptr, p->tickets + wide, p->heavy_grid, st)) !=
+            hipSuccess)
+            return e;
+    }
+    StageTimer tm(ctx, kStCountScans, st);
+    for (int k = 0; k < p->prm.k; ++k)
+        if ((e = launch_exclusive_scan_i64(p->slot_cnt + (size_t)k * p->S, p->S,
+                                           p->slot_off + (size_t)k * (p->S + 1), b.part_s, st)) != hipSuccess)
+            return e;
+    return hipSuccess;
+}
+
+// Builds a plan: allocations, the planning launches, and the two readbacks
+// that size the slot table and the outputs.
+slg_status plan_build(slg_plan *p) {
+    slg_context *ctx = p->ctx;
+    const slg_incidence &inc = p->g->inc;
+    const int64_t m = inc.num_hyperedges, n = inc.num_vertices, nnz = inc.nnz;
+    hipStream_t st = p->st;
+    Scratch &sc = p->scratch;
+    PlanBufs &b = p->b;
+#define BUILD_HIP(call)                                                                            \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? SLG_ERR_OUT_OF_MEMORY : SLG_ERR_DEVICE,     \
+                        "%s: %s", #call, hipGetErrorString(e_));                                   \
+    } while (0)
+    Pruned &pr = p->pr;
+    pr.m = m;
+    pr.n = n;
+    pr.nnz = nnz;
+    pr.he_ptr = inc.he_ptr;
+    pr.he_idx = inc.he_idx;
+    p->prune = (p->s_min > 1 || pr.row_s) && nnz > 0;
+    if (p->prune) {
+        BUILD_HIP(sc.get(&b.flag, nnz));
+        BUILD_HIP(sc.get(&b.pos, nnz + 1));
+        BUILD_HIP(sc.get(&b.part_nnz, scan_partials_size(nnz)));
+        BUILD_HIP(sc.get(&b.vs_ptr, n + 1));
+        BUILD_HIP(sc.get(&b.vs_idx, nnz));
+        pr.vs_ptr = b.vs_ptr;
+        pr.vs_idx = b.vs_idx;
+    } else {
+        pr.vs_ptr = inc.v_ptr;
+        pr.vs_idx = inc.v_idx;
+    }
+    BUILD_HIP(sc.get(&b.tail_beg, nnz));
+    BUILD_HIP(sc.get(&b.work, m));
+    BUILD_HIP(sc.get(&b.work_pre, m + 1));
+    BUILD_HIP(sc.get(&b.jmax, m));
+    BUILD_HIP(sc.get(&b.nslots, m));
+    BUILD_HIP(sc.get(&b.rclass, m));
+    BUILD_HIP(sc.get(&b.bsize, m));
+    BUILD_HIP(sc.get(&b.bbase, m + 1));
+    BUILD_HIP(sc.get(&b.hat, m));
+    BUILD_HIP(sc.get(&b.counters, 32));
+    BUILD_HIP(sc.get(&b.part_m, scan_partials_size(m)));
+    BUILD_HIP(sc.get(&p->slot_base, m + 1));
+    pr.tail_beg = b.tail_beg;
+    BUILD_HIP(enqueue_rows(p, st));
+    int64_t *hb = ctx->pinned;
+    BUILD_HIP(hipMemcpyAsync(hb, b.counters, kCntTotal * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    BUILD_HIP(hipMemcpyAsync(hb + kHbSlots, p->slot_base + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    BUILD_HIP(hipMemcpyAsync(hb + kHbSlots + 1, b.work_pre + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    BUILD_HIP(hipMemcpyAsync(hb + kHbSlots + 2, b.bbase + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    BUILD_HIP(hipStreamSynchronize(st));
+    if (hb[kCntErr] & 0xffffffff)
+        return fail(ctx, SLG_ERR_INVALID_GRAPH,
+                    "malformed incidence (bad pointer, id out of range, or vertex CSR not the transpose)");
+    for (int c = 0; c < kNumLists; ++c) p->list_count[c] = hb[kCntClass + c];
+    p->S = hb[kHbSlots];
+    if (p->S >= (int64_t(1) << 31)) return fail(ctx, SLG_ERR_OVERFLOW, "more than 2^31 output slots");
+    p->two_paths = hb[kHbSlots + 1];
+    p->nbounds = hb[kHbSlots + 2];
+    p->heavy_two_paths = hb[kCntHeavyWork];
+    if (p->nbounds >= (int64_t(1) << 40)) return fail(ctx, SLG_ERR_OVERFLOW, "boundary table too large");
+
+    const int K = p->prm.k;
+    BUILD_HIP(sc.get(&b.slot_row, p->S));
+    BUILD_HIP(sc.get(&p->bounds, p->nbounds));
+    BUILD_HIP(sc.get(&p->tickets, 5));
+    for (int c = 0; c < kLightClasses; ++c) BUILD_HIP(sc.get(&p->lists[c], p->list_count[c]));
+    for (int h = 0; h < 2; ++h) BUILD_HIP(sc.get(&p->heavy[h], p->list_count[kLightClasses + h]));
+    static_assert(sizeof(HeavyDesc) % 8 == 0, "HeavyDesc is filled as int64 words");
+    BUILD_HIP(sc.get(&p->slot_cnt, (size_t)K * p->S));
+    BUILD_HIP(sc.get(&p->slot_off, (size_t)K * (p->S + 1)));
+    BUILD_HIP(sc.get(&b.part_s, scan_partials_size(p->S)));
+    p->slots.count = p->S;
+    p->slots.row = b.slot_row;
+    BUILD_HIP(enqueue_slots_count(p, st));
+    for (int k = 0; k < K; ++k)
+        BUILD_HIP(hipMemcpyAsync(hb + kHbEdges + k, p->slot_off + (size_t)k * (p->S + 1) + p->S, sizeof(int64_t),
+                                 hipMemcpyDeviceToHost, st));
+    for (int h = 0; h < 2; ++h)
+        BUILD_HIP(launch_heavy_edges(p->heavy[h], p->list_count[kLightClasses + h], p->slot_cnt, p->S, K,
+                                     p->tickets + 4, st));
+    BUILD_HIP(hipMemcpyAsync(hb + kHbHeavyEdges, p->tickets + 4, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    BUILD_HIP(hipMemcpyAsync(hb + kHbHeavyEdges + 1, b.counters + kCntErr, sizeof(int64_t),
+                             hipMemcpyDeviceToHost, st));
+    BUILD_HIP(hipStreamSynchronize(st));
+#undef BUILD_HIP
+    if (hb[kHbHeavyEdges + 1] & 0xffffffff)
+        return fail(ctx, SLG_ERR_DEVICE, "internal error: a tier list overflowed its planned size");
+    for (int k = 0; k < K; ++k) p->num_edges[k] = hb[kHbEdges + k];
+    p->heavy_edges = hb[kHbHeavyEdges];
+    return SLG_OK;
+}
+
+slg_plan *plan_new(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num_s, hipStream_t st) {
+    slg_plan *p = new (std::nothrow) slg_plan();
+    if (!p) return nullptr;
+    p->ctx = ctx;
+    p->g = g;
+    p->st = st;
+    p->scratch.st = st;
+    p->prm.k = num_s;
+    for (int t = 0; t < num_s; ++t) p->prm.s[t] = s[t];
+    p->s_min = s[0];
+    p->light_max = ctx->light_max;
+    p->slot_work = ctx->slot_work;
+    p->heavy_grid = ctx->heavy_grid > 0 ? ctx->heavy_grid : ctx->heavy_resident;
+    return p;
+}
+
+void plan_free(slg_plan *p) {
+    p->scratch.release();
+    (void)hipStreamSynchronize(p->st);
+    delete p;
+}
+}  // namespace
+
 slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num_s,
                            void *stream, slg_plan **out) {
     if (!ctx || !g || !out) return fail(ctx, SLG_ERR_INVALID_ARG, "null argument");
@@ -305,188 +553,13 @@ slg_status slg_plan_create(slg_context *ctx, slg_graph *g, const int32_t *s, int
         return fail(ctx, SLG_ERR_INVALID_ARG, "s must be strictly increasing, s[0] >= 1, 1 <= num_s <= %d",
                     SLG_MAX_S);
     SLG_HIP(ctx, hipSetDevice(ctx->device));
-    slg_plan *p = new (std::nothrow) slg_plan();
+    slg_plan *p = plan_new(ctx, g, s, num_s, static_cast<hipStream_t>(stream));
     if (!p) return fail(ctx, SLG_ERR_OUT_OF_MEMORY, "host allocation failed");
-    p->ctx = ctx;
-    p->g = g;
-    p->st = static_cast<hipStream_t>(stream);
-    p->scratch.st = p->st;
-    p->prm.k = num_s;
-    for (int t = 0; t < num_s; ++t) p->prm.s[t] = s[t];
-    slg_status rc = SLG_OK;
-    auto bail = [&](slg_status code) {
-        p->scratch.release();
-        (void)hipStreamSynchronize(p->st);
-        delete p;
-        return code;
-    };
-#define PLAN_HIP(call)                                                                             \
-    do {                                                                                           \
-        hipError_t e_ = (call);                                                                    \
-        if (e_ != hipSuccess)                                                                      \
-            return bail(fail(ctx, e_ == hipErrorOutOfMemory ? SLG_ERR_OUT_OF_MEMORY : SLG_ERR_DEVICE, \
-                             "%s: %s", #call, hipGetErrorString(e_)));                              \
-    } while (0)
-
-    const slg_incidence &inc = g->inc;
-    const int64_t m = inc.num_hyperedges, n = inc.num_vertices, nnz = inc.nnz;
-    const int32_t s_min = s[0];
-    hipStream_t st = p->st;
-    Scratch &sc = p->scratch;
-
-    // K1: vertex lists restricted to E_{s_min}
-    Pruned &pr = p->pr;
-    pr.m = m;
-    pr.n = n;
-    pr.nnz = nnz;
-    pr.he_ptr = inc.he_ptr;
-    pr.he_idx = inc.he_idx;
-    if (s_min > 1 && nnz > 0) {
-        uint8_t *flag;
-        int64_t *pos, *part;
-        int64_t *vs_ptr;
-        int32_t *vs_idx;
-        PLAN_HIP(sc.get(&flag, nnz));
-        PLAN_HIP(sc.get(&pos, nnz + 1));
-        PLAN_HIP(sc.get(&part, scan_partials_size(nnz)));
-        PLAN_HIP(sc.get(&vs_ptr, n + 1));
-        PLAN_HIP(sc.get(&vs_idx, nnz));
-        StageTimer tm(ctx, kStPrune, st);
-        PLAN_HIP(launch_keep_incidence(nnz, inc.v_idx, inc.he_ptr, m, s_min, flag, st));
-        PLAN_HIP(launch_exclusive_scan_u8(flag, nnz, pos, part, st));
-        PLAN_HIP(launch_compact_vertex_lists(n, nnz, inc.v_ptr, inc.v_idx, flag, pos, vs_ptr, vs_idx, st));
-        pr.vs_ptr = vs_ptr;
-        pr.vs_idx = vs_idx;
-    } else {
-        pr.vs_ptr = inc.v_ptr;
-        pr.vs_idx = inc.v_idx;
+    slg_status rc = plan_build(p);
+    if (rc != SLG_OK) {
+        plan_free(p);
+        return rc;
     }
-
-    // K2: tails, 2-path work and slot counts per row
-    int32_t *tail_beg, *jmax, *nslots;
-    int64_t *work, *work_pre, *counters, *part_m, *bsize, *bbase;
-    uint8_t *rclass;
-    PLAN_HIP(sc.get(&tail_beg, nnz));
-    PLAN_HIP(sc.get(&work, m));
-    PLAN_HIP(sc.get(&work_pre, m + 1));
-    PLAN_HIP(sc.get(&jmax, m));
-    PLAN_HIP(sc.get(&nslots, m));
-    PLAN_HIP(sc.get(&rclass, m));
-    PLAN_HIP(sc.get(&bsize, m));
-    PLAN_HIP(sc.get(&bbase, m + 1));
-    PLAN_HIP(sc.get(&counters, 32));
-    PLAN_HIP(sc.get(&part_m, scan_partials_size(m)));
-    PLAN_HIP(sc.get(&p->slot_base, m + 1));
-    PLAN_HIP(launch_fill_i64(counters, 32, 0, st));
-    pr.tail_beg = tail_beg;
-    unsigned long long *class_count = reinterpret_cast<unsigned long long *>(counters + kCntClass);
-    int *err = reinterpret_cast<int *>(counters + kCntErr);
-    unsigned long long *list_fill = reinterpret_cast<unsigned long long *>(counters + kCntFill);
-    {
-        StageTimer tm(ctx, kStRowPlan, st);
-        PLAN_HIP(launch_row_plan(pr, s_min, tail_beg, work, jmax, nslots, rclass, bsize, class_count, err,
-                                 reinterpret_cast<unsigned long long *>(counters + kCntHeavyWork), st));
-    }
-    {
-        StageTimer tm(ctx, kStPlanScans, st);
-        PLAN_HIP(launch_exclusive_scan_i32(nslots, m, p->slot_base, part_m, st));
-        PLAN_HIP(launch_exclusive_scan_i64(work, m, work_pre, part_m, st));
-        PLAN_HIP(launch_exclusive_scan_i64(bsize, m, bbase, part_m, st));
-    }
-    int64_t *hb = ctx->pinned;
-    PLAN_HIP(hipMemcpyAsync(hb, counters, kCntTotal * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    PLAN_HIP(hipMemcpyAsync(hb + kHbSlots, p->slot_base + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    PLAN_HIP(hipMemcpyAsync(hb + kHbSlots + 1, work_pre + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    PLAN_HIP(hipMemcpyAsync(hb + kHbSlots + 2, bbase + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    PLAN_HIP(hipStreamSynchronize(st));
-    if (hb[kCntErr] & 0xffffffff)
-        return bail(fail(ctx, SLG_ERR_INVALID_GRAPH,
-                         "malformed incidence (bad pointer, id out of range, or vertex CSR not the transpose)"));
-    for (int c = 0; c < kNumLists; ++c) p->list_count[c] = hb[kCntClass + c];
-    p->S = hb[kHbSlots];
-    if (p->S >= (int64_t(1) << 31)) return bail(fail(ctx, SLG_ERR_OVERFLOW, "more than 2^31 output slots"));
-    p->two_paths = hb[kHbSlots + 1];
-    const int64_t nbounds = hb[kHbSlots + 2];
-    p->nbounds = nbounds;
-    p->heavy_two_paths = hb[kCntHeavyWork];
-    if (nbounds >= (int64_t(1) << 40))
-        return bail(fail(ctx, SLG_ERR_OVERFLOW, "boundary table too large"));
-
-    // slot table, tier lists and the heavy rows' boundary table
-    int32_t *slot_row;
-    PLAN_HIP(sc.get(&slot_row, p->S));
-    PLAN_HIP(sc.get(&p->bounds, nbounds));
-    PLAN_HIP(sc.get(&p->tickets, 5));
-    // lists start zeroed: an entry the fill kernels refuse to write (list
-    // overflow, flagged in err) names slot 0 / an empty descriptor
-    for (int c = 0; c < kLightClasses; ++c) {
-        PLAN_HIP(sc.get(&p->lists[c], p->list_count[c]));
-        PLAN_HIP(launch_fill_i32(p->lists[c], p->list_count[c], 0, st));
-    }
-    for (int h = 0; h < 2; ++h) {
-        PLAN_HIP(sc.get(&p->heavy[h], p->list_count[kLightClasses + h]));
-        PLAN_HIP(launch_fill_i64(reinterpret_cast<int64_t *>(p->heavy[h]),
-                                 p->list_count[kLightClasses + h] * (int64_t)(sizeof(HeavyDesc) / 8), 0, st));
-    }
-    static_assert(sizeof(HeavyDesc) % 8 == 0, "HeavyDesc is filled as int64 words");
-    int64_t *hat;  // first descriptor of each heavy row in its list
-    PLAN_HIP(sc.get(&hat, m));
-    {
-        StageTimer tm(ctx, kStSlots, st);
-        PLAN_HIP(launch_fill_slots(m, inc.he_ptr, p->slot_base, nslots, jmax, rclass, bbase, hat, slot_row,
-                                   p->lists, p->heavy, p->list_count, list_fill, err, st));
-    }
-    {
-        StageTimer tm(ctx, kStBounds, st);
-        for (int h = 0; h < 2; ++h)
-            PLAN_HIP(launch_bounds(pr, p->heavy[h], p->list_count[kLightClasses + h], p->bounds, st));
-    }
-    p->slots.count = p->S;
-    p->slots.row = slot_row;
-
-    // K3-K5 counting pass: per slot, per threshold, the number of edges
-    const int K = num_s;
-    PLAN_HIP(sc.get(&p->slot_cnt, (size_t)K * p->S));
-    PLAN_HIP(sc.get(&p->slot_off, (size_t)K * (p->S + 1)));
-    int64_t *part_s;
-    PLAN_HIP(sc.get(&part_s, scan_partials_size(p->S)));
-    {
-        StageTimer tm(ctx, kStCountLight, st);
-        for (int c = 0; c < kLightClasses; ++c)
-            PLAN_HIP(launch_light(c, false, p->lists[c], p->list_count[c], p->slots, pr, p->prm, p->slot_cnt,
-                                  nullptr, st));
-    }
-    PLAN_HIP(launch_fill_i64(p->tickets, 4, 0, st));
-    for (int wide = 0; wide < 2; ++wide) {
-        if (p->list_count[kLightClasses + wide] <= 0) continue;
-        StageTimer tm(ctx, wide ? kStCountHeavyWide : kStCountHeavy, st);
-        PLAN_HIP(launch_heavy(false, wide, p->heavy[wide], p->list_count[kLightClasses + wide], p->S,
-                              p->bounds, pr, p->prm, p->slot_cnt, nullptr, p->tickets + wide,
-                              ctx->heavy_resident, st));
-    }
-    {
-        StageTimer tm(ctx, kStCountScans, st);
-        for (int k = 0; k < K; ++k) {
-            PLAN_HIP(launch_exclusive_scan_i64(p->slot_cnt + (size_t)k * p->S, p->S,
-                                               p->slot_off + (size_t)k * (p->S + 1), part_s, st));
-            PLAN_HIP(hipMemcpyAsync(hb + kHbEdges + k, p->slot_off + (size_t)k * (p->S + 1) + p->S,
-                                    sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        }
-    }
-    PLAN_HIP(launch_fill_i64(p->tickets + 4, 1, 0, st));
-    for (int h = 0; h < 2; ++h)
-        PLAN_HIP(launch_heavy_edges(p->heavy[h], p->list_count[kLightClasses + h], p->slot_cnt, p->S, K,
-                                    p->tickets + 4, st));
-    PLAN_HIP(hipMemcpyAsync(hb + kHbHeavyEdges, p->tickets + 4, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    PLAN_HIP(hipMemcpyAsync(hb + kHbHeavyEdges + 1, counters + kCntErr, sizeof(int64_t), hipMemcpyDeviceToHost,
-                            st));
-    PLAN_HIP(hipStreamSynchronize(st));
-    if (hb[kHbHeavyEdges + 1] & 0xffffffff)
-        return bail(fail(ctx, SLG_ERR_DEVICE, "internal error: a tier list overflowed its planned size"));
-    for (int k = 0; k < K; ++k) p->num_edges[k] = hb[kHbEdges + k];
-    p->heavy_edges = hb[kHbHeavyEdges];
-#undef PLAN_HIP
-    (void)rc;
     *out = p;
     return SLG_OK;
 }
@@ -529,7 +602,7 @@ slg_status emit_range(slg_plan *p, int64_t r0, int64_t r1, int64_t s0, int64_t s
         StageTimer tm(ctx, wide ? kStEmitHeavyWide : kStEmitHeavy, st);
         SLG_HIP(ctx, launch_heavy(true, wide, p->heavy[wide], p->list_count[kLightClasses + wide], p->S,
                                   p->bounds, p->pr, prm, nullptr, p->slot_off, p->tickets + 2 + wide,
-                                  ctx->heavy_resident, st));
+                                  p->heavy_grid, st));
     }
     {
         StageTimer tm(ctx, kStRowPtr, st);
@@ -728,6 +801,204 @@ slg_status slg_plan_destroy(slg_plan *p) {
     if (!p) return SLG_ERR_INVALID_ARG;
     p->scratch.release();
     delete p;
+    return SLG_OK;
+}
+
+slg_status slg_context_set_tuning(slg_context *ctx, int32_t light_max, int64_t slot_work, int32_t heavy_grid) {
+    if (!ctx) return SLG_ERR_INVALID_ARG;
+    if (light_max < 0 || light_max > kLightMax || slot_work < 0 || heavy_grid < 0)
+        return fail(ctx, SLG_ERR_INVALID_ARG, "tuning out of range (light_max <= %d)", kLightMax);
+    ctx->light_max = light_max > 0 ? light_max : kLightMax;
+    ctx->slot_work = slot_work > 0 ? slot_work : kSlotWork;
+    ctx->heavy_grid = heavy_grid;
+    return SLG_OK;
+}
+
+
+namespace {
+slg_status batch_enqueue(slg_batch *b, hipStream_t st) {
+    slg_plan *p = b->p;
+    slg_context *ctx = b->ctx;
+    SLG_HIP(ctx, enqueue_rows(p, st));
+    SLG_HIP(ctx, enqueue_slots_count(p, st));
+    const int64_t zero[SLG_MAX_S] = {};
+    int64_t *rp[1] = {b->row_ptr};
+    int32_t *ri[1] = {b->row}, *rj[1] = {b->col}, *rw[1] = {b->w};
+    return emit_range(p, 0, p->pr.m, 0, p->S, zero, rp, ri, rj, rw, st);
+}
+
+void batch_free(slg_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->p) plan_free(b->p);
+    for (void *q : b->owned) (void)hipFreeAsync(q, b->st);
+    (void)hipStreamSynchronize(b->st);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+}
+}  // namespace
+
+slg_status slg_batch_create(slg_context *ctx, slg_graph *const *graphs, const int32_t *s, int32_t n,
+                            void *stream, slg_batch **out) {
+    if (!ctx || !graphs || !s || !out || n < 1 || n > 65535)
+        return fail(ctx, SLG_ERR_INVALID_ARG, "bad batch arguments (1 <= n <= 65535)");
+    *out = nullptr;
+    int32_t smin = INT32_MAX;
+    for (int32_t g = 0; g < n; ++g) {
+        if (!graphs[g] || s[g] < 1) return fail(ctx, SLG_ERR_INVALID_ARG, "graph %d: null or s < 1", g);
+        smin = std::min(smin, s[g]);
+    }
+    SLG_HIP(ctx, hipSetDevice(ctx->device));
+    slg_batch *b = new (std::nothrow) slg_batch();
+    if (!b) return fail(ctx, SLG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    b->ctx = ctx;
+    b->st = static_cast<hipStream_t>(stream);
+    b->n = n;
+    auto bail = [&](slg_status code) {
+        batch_free(b);
+        return code;
+    };
+#define BATCH_HIP(call)                                                                            \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return bail(fail(ctx, e_ == hipErrorOutOfMemory ? SLG_ERR_OUT_OF_MEMORY : SLG_ERR_DEVICE, \
+                             "%s: %s", #call, hipGetErrorString(e_)));                              \
+    } while (0)
+    hipStream_t st = b->st;
+    std::vector<UnionPart> parts(n);
+    int64_t M = 0, N = 0, NNZ = 0, max_elems = 0;
+    b->m_off.resize(n + 1);
+    b->m_g.resize(n);
+    for (int32_t g = 0; g < n; ++g) {
+        const slg_incidence &gi = graphs[g]->inc;
+        UnionPart &u = parts[g];
+        u.he_ptr = gi.he_ptr;
+        u.v_ptr = gi.v_ptr;
+        u.he_idx = gi.he_idx;
+        u.v_idx = gi.v_idx;
+        u.m = gi.num_hyperedges;
+        u.n = gi.num_vertices;
+        u.nnz = gi.nnz;
+        u.m_off = M;
+        u.n_off = N;
+        u.nnz_off = NNZ;
+        u.s = s[g];
+        u.pad_ = 0;
+        b->m_off[g] = M;
+        b->m_g[g] = u.m;
+        M += u.m;
+        N += u.n;
+        NNZ += u.nnz;
+        max_elems = std::max(max_elems, std::max(std::max(u.m + 1, u.n + 1), u.nnz));
+    }
+    b->m_off[n] = M;
+    if (M >= (int64_t(1) << 31) || N >= (int64_t(1) << 31) || NNZ >= (int64_t(1) << 31))
+        return bail(fail(ctx, SLG_ERR_OVERFLOW, "batch totals must stay below 2^31"));
+    auto get = [&](void **q, size_t bytes) -> hipError_t {
+        hipError_t e = hipMallocAsync(q, bytes ? bytes : 8, st);
+        if (e == hipSuccess) b->owned.push_back(*q);
+        return e;
+    };
+    int64_t *he_ptr, *v_ptr;
+    int32_t *he_idx, *v_idx, *row_s, *row_base;
+    UnionPart *dparts;
+    BATCH_HIP(get(reinterpret_cast<void **>(&he_ptr), (M + 1) * sizeof(int64_t)));
+    BATCH_HIP(get(reinterpret_cast<void **>(&v_ptr), (N + 1) * sizeof(int64_t)));
+    BATCH_HIP(get(reinterpret_cast<void **>(&he_idx), NNZ * sizeof(int32_t)));
+    BATCH_HIP(get(reinterpret_cast<void **>(&v_idx), NNZ * sizeof(int32_t)));
+    BATCH_HIP(get(reinterpret_cast<void **>(&row_s), M * sizeof(int32_t)));
+    BATCH_HIP(get(reinterpret_cast<void **>(&row_base), M * sizeof(int32_t)));
+    BATCH_HIP(get(reinterpret_cast<void **>(&dparts), n * sizeof(UnionPart)));
+    BATCH_HIP(hipMemcpyAsync(dparts, parts.data(), n * sizeof(UnionPart), hipMemcpyHostToDevice, st));
+    BATCH_HIP(launch_union(dparts, n, max_elems, he_ptr, he_idx, v_ptr, v_idx, row_s, row_base, st));
+    BATCH_HIP(hipStreamSynchronize(st));  // `parts` leaves scope; union ready
+    b->ug.ctx = ctx;
+    b->ug.inc = {N, M, NNZ, he_ptr, he_idx, v_ptr, v_idx};
+    b->p = plan_new(ctx, &b->ug, &smin, 1, st);
+    if (!b->p) return bail(fail(ctx, SLG_ERR_OUT_OF_MEMORY, "host allocation failed"));
+    b->p->pr.row_s = row_s;
+    b->p->prm.row_s = row_s;
+    b->p->prm.row_base = row_base;
+    slg_status rc = plan_build(b->p);
+    if (rc != SLG_OK) return bail(rc);
+    b->edges = b->p->num_edges[0];
+    BATCH_HIP(get(reinterpret_cast<void **>(&b->row_ptr), (M + 1) * sizeof(int64_t)));
+    BATCH_HIP(get(reinterpret_cast<void **>(&b->row), b->edges * sizeof(int32_t)));
+    BATCH_HIP(get(reinterpret_cast<void **>(&b->col), b->edges * sizeof(int32_t)));
+    BATCH_HIP(get(reinterpret_cast<void **>(&b->w), b->edges * sizeof(int32_t)));
+    const int64_t zero[SLG_MAX_S] = {};
+    int64_t *rp[1] = {b->row_ptr};
+    int32_t *ri[1] = {b->row}, *rj[1] = {b->col}, *rw[1] = {b->w};
+    rc = emit_range(b->p, 0, M, 0, b->p->S, zero, rp, ri, rj, rw, st);
+    if (rc != SLG_OK) return bail(rc);
+    // global edge offset of every graph's first row
+    int64_t *didx, *doff;
+    BATCH_HIP(get(reinterpret_cast<void **>(&didx), (n + 1) * sizeof(int64_t)));
+    BATCH_HIP(get(reinterpret_cast<void **>(&doff), (n + 1) * sizeof(int64_t)));
+    BATCH_HIP(hipMemcpyAsync(didx, b->m_off.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    BATCH_HIP(launch_gather_i64(b->row_ptr, didx, n + 1, doff, st));
+    b->edge_off.resize(n + 1);
+    BATCH_HIP(hipMemcpyAsync(b->edge_off.data(), doff, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    BATCH_HIP(hipStreamSynchronize(st));
+    BATCH_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+#undef BATCH_HIP
+    *out = b;
+    return SLG_OK;
+}
+
+slg_status slg_batch_run(slg_batch *b, int32_t use_graph, void *stream) {
+    if (!b) return SLG_ERR_INVALID_ARG;
+    slg_context *ctx = b->ctx;
+    SLG_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (!use_graph) return batch_enqueue(b, st);
+    if (!b->exec) {  // capture the whole device path once
+        slg_status rc = order_after(ctx, b->cap, b->st);
+        if (rc != SLG_OK) return rc;
+        SLG_HIP(ctx, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+        ctx->capturing = true;
+        rc = batch_enqueue(b, b->cap);
+        ctx->capturing = false;
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(b->cap, &graph);
+        if (rc != SLG_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(ctx, SLG_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        b->graph = graph;
+        SLG_HIP(ctx, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    SLG_HIP(ctx, hipGraphLaunch(b->exec, st));
+    return SLG_OK;
+}
+
+slg_status slg_batch_info(const slg_batch *b, int64_t *num_edges, int64_t *two_paths, int64_t *rows) {
+    if (!b) return SLG_ERR_INVALID_ARG;
+    if (num_edges) *num_edges = b->edges;
+    if (two_paths) *two_paths = b->p->two_paths;
+    if (rows) *rows = b->m_off[b->n];
+    return SLG_OK;
+}
+
+slg_status slg_batch_result(const slg_batch *b, int32_t g, int64_t *edge_begin, int64_t *num_edges,
+                            const int64_t **row_ptr, const int32_t **row, const int32_t **col,
+                            const int32_t **w) {
+    if (!b || g < 0 || g >= b->n) return SLG_ERR_INVALID_ARG;
+    const int64_t e0 = b->edge_off[g];
+    if (edge_begin) *edge_begin = e0;
+    if (num_edges) *num_edges = b->edge_off[g + 1] - e0;
+    if (row_ptr) *row_ptr = b->row_ptr + b->m_off[g];
+    if (row) *row = b->row + e0;
+    if (col) *col = b->col + e0;
+    if (w) *w = b->w + e0;
+    return SLG_OK;
+}
+
+slg_status slg_batch_destroy(slg_batch *b) {
+    if (!b) return SLG_ERR_INVALID_ARG;
+    batch_free(b);
     return SLG_OK;
 }
 

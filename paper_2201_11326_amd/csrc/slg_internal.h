@@ -41,6 +41,8 @@ struct EmitParams {
     int32_t *w[SLG_MAX_S];          // overlap per threshold
     int64_t *row_ptr[SLG_MAX_S];    // CSR offsets per threshold
     int64_t out_base[SLG_MAX_S];    // global edge offset of the buffers' first entry
+    const int32_t *row_s;           // per-row threshold (batched form, k = 1), or null
+    const int32_t *row_base;        // per-row id base subtracted on output, or null
 };
 
 // Device-side view of one hypergraph after pruning.
@@ -51,6 +53,7 @@ struct Pruned {
     const int64_t *vs_ptr;    // vertex lists restricted to E_{s_min}
     const int32_t *vs_idx;
     const int32_t *tail_beg;  // per incidence (i, v): first position in v's list after i
+    const int32_t *row_s;     // per-row threshold (batched form), or null for s_min
 };
 
 // Slot table: a slot is (row i, hyperedge-id range) with its own output
@@ -81,16 +84,16 @@ int64_t scan_partials_size(int64_t n);
 
 // K1: keep flags per incidence of the vertex CSR, then compaction.
 hipError_t launch_keep_incidence(int64_t nnz, const int32_t *v_idx, const int64_t *he_ptr, int64_t m,
-                                 int32_t s_min, uint8_t *flag, hipStream_t st);
+                                 int32_t s_min, const int32_t *row_s, uint8_t *flag, hipStream_t st);
 hipError_t launch_compact_vertex_lists(int64_t n, int64_t nnz, const int64_t *v_ptr,
                                        const int32_t *v_idx, const uint8_t *flag,
                                        const int64_t *pos, int64_t *vs_ptr, int32_t *vs_idx,
                                        hipStream_t st);
 
 // K1/K2: per kept row, tail offsets, 2-path work, last partner, slot count.
-hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t *tail_beg, int64_t *work,
-                           int32_t *jmax, int32_t *nslots, uint8_t *rclass, int64_t *bsize,
-                           unsigned long long *class_count, int *err,
+hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t light_max, int64_t slot_work,
+                           int32_t *tail_beg, int64_t *work, int32_t *jmax, int32_t *nslots, uint8_t *rclass,
+                           int64_t *bsize, unsigned long long *class_count, int *err,
                            unsigned long long *heavy_work, hipStream_t st);
 hipError_t launch_fill_slots(int64_t m, const int64_t *he_ptr, const int64_t *slot_base,
                              const int32_t *nslots, const int32_t *jmax, const uint8_t *rclass,
@@ -126,6 +129,22 @@ hipError_t launch_gather_offsets(const int64_t *rows, int64_t count, const int64
                                  hipStream_t st);
 hipError_t launch_fill_i64(int64_t *p, int64_t n, int64_t value, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t value, hipStream_t st);
+
+// Batched form: one graph of the disjoint union.
+struct UnionPart {
+    const int64_t *he_ptr, *v_ptr;
+    const int32_t *he_idx, *v_idx;
+    int64_t m, n, nnz, m_off, n_off, nnz_off;
+    int32_t s, pad_;
+};
+// Concatenate `count` graphs into the union arrays (ids offset per graph);
+// row_s/row_base get each row's threshold and first union row id.
+hipError_t launch_union(const UnionPart *parts, int32_t count, int64_t max_elems, int64_t *he_ptr,
+                        int32_t *he_idx, int64_t *v_ptr, int32_t *v_idx, int32_t *row_s, int32_t *row_base,
+                        hipStream_t st);
+// out[c] = src[idx[c]].
+hipError_t launch_gather_i64(const int64_t *src, const int64_t *idx, int64_t count, int64_t *out,
+                             hipStream_t st);
 
 // Validation kernels (SLG_VALIDATE).
 hipError_t launch_validate_ptr(const int64_t *ptr, int64_t rows, int64_t nnz, int *err,

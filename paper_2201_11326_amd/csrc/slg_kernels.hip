@@ -224,12 +224,12 @@ hipError_t exclusive_scan(const T *in, int64_t n, int64_t *out, int64_t *partial
 // ---------------------------------------------------------------------------
 __global__ void keep_incidence_kernel(int64_t nnz, const int32_t *__restrict__ v_idx,
                                       const int64_t *__restrict__ he_ptr, int64_t m, int32_t s_min,
-                                      uint8_t *__restrict__ flag) {
+                                      const int32_t *__restrict__ row_s, uint8_t *__restrict__ flag) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nnz) return;
     int32_t e = v_idx[p];
     uint8_t keep = 0;
-    if (e >= 0 && e < m) keep = (he_ptr[e + 1] - he_ptr[e]) >= s_min;
+    if (e >= 0 && e < m) keep = (he_ptr[e + 1] - he_ptr[e]) >= (row_s ? row_s[e] : s_min);
     flag[p] = keep;
 }
 
@@ -258,7 +258,8 @@ __device__ __forceinline__ int light_class(int64_t w) {
     return c;
 }
 
-__global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min,
+__global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min, int32_t light_max,
+                                                       int64_t slot_work,
                                                        int32_t *__restrict__ tail_beg,
                                                        int64_t *__restrict__ work,
                                                        int32_t *__restrict__ jmax_out,
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min,
         int bad = 0;
         if (p0 < 0 || p1 > g.nnz || p1 < p0) {
             bad = 1;
-        } else if (p1 - p0 >= s_min && p1 > p0) {
+        } else if (p1 - p0 >= (g.row_s ? g.row_s[i] : s_min) && p1 > p0) {
             for (int64_t p = p0 + lane; p < p1; p += 64) {
                 const int v = g.he_idx[p];
                 if (v < 0 || v >= g.n) {
@@ -314,14 +315,14 @@ __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min,
             if (bad) {
                 atomicOr(err, 1);
             } else if (w > 0) {
-                if (w <= kLightMax) {
+                if (w <= light_max) {
                     cls = kLight0 + light_class(w);
                     ns = 1;
                 } else {
                     cls = (p1 - p0 >= kWideMembers) ? kHeavyWide : kHeavy;
                     const int64_t range = (int64_t)jm - i;  // partners lie in [i+1, jm]
                     const int64_t by_range = (range + kRangeBits - 1) / kRangeBits;
-                    const int64_t by_work = (w + kSlotWork - 1) / kSlotWork;
+                    const int64_t by_work = (w + slot_work - 1) / slot_work;
                     ns = by_range > by_work ? by_range : by_work;
                     if (ns > range) ns = range;
                 }
@@ -578,8 +579,9 @@ __global__ __launch_bounds__(256) void light_kernel(const int32_t *__restrict__ 
 
     const int K = ep->k;
     const int64_t S = sl.count;
+    const int id0 = ep->row_base ? ep->row_base[i] : 0;  // caller's id of row i is i - id0
     for (int k = 0; k < K; ++k) {
-        const int sk = ep->s[k];
+        const int sk = ep->row_s ? ep->row_s[i] : ep->s[k];
         int64_t base = EMIT ? slot_off[(int64_t)k * (S + 1) + slot] - ep->out_base[k] : 0;
         int32_t *col = EMIT ? ep->col[k] : nullptr;
         int32_t *wo = EMIT ? ep->w[k] : nullptr;
@@ -590,9 +592,9 @@ __global__ __launch_bounds__(256) void light_kernel(const int32_t *__restrict__ 
             const unsigned long long mask = __ballot(surv);
             if (EMIT && surv) {
                 const int64_t pos = base + bits_below(mask);
-                col[pos] = x[r];
+                col[pos] = x[r] - id0;
                 wo[pos] = c[r];
-                if (ro) ro[pos] = i;
+                if (ro) ro[pos] = i - id0;
             }
             base += __popcll(mask);
         }
@@ -752,7 +754,6 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(const HeavyDesc *_
     __syncthreads();
     const EmitParams *ep = &sp;
     const int K = ep->k;
-    const bool only_presence = !EMIT && K == 1 && ep->s[0] <= 1;
     int64_t it = next_slot;
     if (it >= count) return;
 
@@ -771,6 +772,9 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(const HeavyDesc *_
         if (tid == 0) next_slot = (int64_t)atomicAdd(ticket, 1ull);
 
         const int i = d.row, ja = d.ja, jb = d.jb, k = d.k, slot = d.slot;
+        const int srow = ep->row_s ? ep->row_s[i] : 0;  // per-row threshold (batched form)
+        const int id0 = ep->row_base ? ep->row_base[i] : 0;
+        const bool only_presence = !EMIT && K == 1 && (ep->row_s ? srow : ep->s[0]) <= 1;
         const int nw = (jb - ja + 31) >> 5;
         const unsigned span = (unsigned)(jb - ja);
         // bitmap and counters are all-zero here: cleared before the first
@@ -934,7 +938,7 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(const HeavyDesc *_
                     const int c = r < rhi ? count_get<WIDE>(sm.cnt, r) : 0;
 #pragma unroll
                     for (int kk = 0; kk < SLG_MAX_S; ++kk)
-                        if (kk < K) tally[kk] += __popcll(__ballot(c >= ep->s[kk]));
+                        if (kk < K) tally[kk] += __popcll(__ballot(c >= (ep->row_s ? srow : ep->s[kk])));
                 }
                 if (EMIT) {
                     if (lane == 0)
@@ -957,14 +961,14 @@ __global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(const HeavyDesc *_
 #pragma unroll
                         for (int kk = 0; kk < SLG_MAX_S; ++kk) {
                             if (kk >= K) break;
-                            const bool surv = c >= ep->s[kk];
+                            const bool surv = c >= (ep->row_s ? srow : ep->s[kk]);
                             const unsigned long long mask = __ballot(surv);
                             if (surv) {
                                 const int64_t pos = base[kk] + bits_below(mask);
-                                ep->col[kk][pos] = key;
+                                ep->col[kk][pos] = key - id0;
                                 ep->w[kk][pos] = c;
                                 int32_t *ro = ep->row[kk];
-                                if (ro) ro[pos] = i;
+                                if (ro) ro[pos] = i - id0;
                             }
                             base[kk] += __popcll(mask);
                         }
@@ -1136,6 +1140,34 @@ __global__ __launch_bounds__(256) void validate_transpose_kernel(
     }
 }
 
+// Disjoint union of a batch of hypergraphs: graph g's hyperedges and
+// vertices get ids offset by the sizes of the graphs before it.
+__global__ __launch_bounds__(256) void union_kernel(const UnionPart *__restrict__ parts,
+                                                    int64_t *__restrict__ he_ptr, int32_t *__restrict__ he_idx,
+                                                    int64_t *__restrict__ v_ptr, int32_t *__restrict__ v_idx,
+                                                    int32_t *__restrict__ row_s, int32_t *__restrict__ row_base) {
+    const UnionPart u = parts[blockIdx.y];
+    const int64_t lim = max(max(u.m + 1, u.n + 1), u.nnz);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < lim; t += (int64_t)gridDim.x * blockDim.x) {
+        if (t <= u.m) he_ptr[u.m_off + t] = u.he_ptr[t] + u.nnz_off;  // the shared end entry agrees
+        if (t < u.m) {
+            row_s[u.m_off + t] = u.s;
+            row_base[u.m_off + t] = (int32_t)u.m_off;
+        }
+        if (t <= u.n) v_ptr[u.n_off + t] = u.v_ptr[t] + u.nnz_off;
+        if (t < u.nnz) {
+            he_idx[u.nnz_off + t] = u.he_idx[t] + (int32_t)u.n_off;
+            v_idx[u.nnz_off + t] = u.v_idx[t] + (int32_t)u.m_off;
+        }
+    }
+}
+
+__global__ void gather_i64_kernel(const int64_t *__restrict__ src, const int64_t *__restrict__ idx,
+                                  int64_t count, int64_t *__restrict__ out) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < count) out[c] = src[idx[c]];
+}
+
 inline unsigned grid_for(int64_t n, int threads) {
     int64_t b = (n + threads - 1) / threads;
     return (unsigned)(b < 1 ? 1 : b);
@@ -1191,9 +1223,9 @@ hipError_t launch_exclusive_scan_u8(const uint8_t *in, int64_t n, int64_t *out, 
 }
 
 hipError_t launch_keep_incidence(int64_t nnz, const int32_t *v_idx, const int64_t *he_ptr, int64_t m,
-                                 int32_t s_min, uint8_t *flag, hipStream_t st) {
+                                 int32_t s_min, const int32_t *row_s, uint8_t *flag, hipStream_t st) {
     if (nnz <= 0) return hipSuccess;
-    keep_incidence_kernel<<<grid_for(nnz, 256), 256, 0, st>>>(nnz, v_idx, he_ptr, m, s_min, flag);
+    keep_incidence_kernel<<<grid_for(nnz, 256), 256, 0, st>>>(nnz, v_idx, he_ptr, m, s_min, row_s, flag);
     return hipGetLastError();
 }
 
@@ -1206,13 +1238,16 @@ hipError_t launch_compact_vertex_lists(int64_t n, int64_t nnz, const int64_t *v_
     return hipGetLastError();
 }
 
-hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t *tail_beg, int64_t *work,
-                           int32_t *jmax, int32_t *nslots, uint8_t *rclass, int64_t *bsize,
-                           unsigned long long *class_count, int *err,
+hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t light_max, int64_t slot_work,
+                           int32_t *tail_beg, int64_t *work, int32_t *jmax, int32_t *nslots, uint8_t *rclass,
+                           int64_t *bsize, unsigned long long *class_count, int *err,
                            unsigned long long *heavy_work, hipStream_t st) {
     if (g.m <= 0) return hipSuccess;
-    row_plan_kernel<<<wave_grid(g.m, 4, 8192), 256, 0, st>>>(g, s_min, tail_beg, work, jmax, nslots,
-                                                              rclass, bsize, class_count, err, heavy_work);
+    if (light_max <= 0 || light_max > kLightMax) light_max = kLightMax;
+    if (slot_work <= 0) slot_work = kSlotWork;
+    row_plan_kernel<<<wave_grid(g.m, 4, 8192), 256, 0, st>>>(g, s_min, light_max, slot_work, tail_beg, work,
+                                                              jmax, nslots, rclass, bsize, class_count, err,
+                                                              heavy_work);
     return hipGetLastError();
 }
 
@@ -1315,6 +1350,25 @@ hipError_t launch_gather_offsets(const int64_t *rows, int64_t count, const int64
     if (count <= 0) return hipSuccess;
     gather_offsets_kernel<<<grid_for(count, 256), 256, 0, st>>>(rows, count, slot_base, slot_off, slots, K,
                                                                  out);
+    return hipGetLastError();
+}
+
+hipError_t launch_union(const UnionPart *parts, int32_t count, int64_t max_elems, int64_t *he_ptr,
+                        int32_t *he_idx, int64_t *v_ptr, int32_t *v_idx, int32_t *row_s, int32_t *row_base,
+                        hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    int64_t bx = (max_elems + 255) / 256;
+    if (bx > 256) bx = 256;
+    if (bx < 1) bx = 1;
+    union_kernel<<<dim3((unsigned)bx, (unsigned)count), 256, 0, st>>>(parts, he_ptr, he_idx, v_ptr, v_idx, row_s,
+                                                                       row_base);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_i64(const int64_t *src, const int64_t *idx, int64_t count, int64_t *out,
+                             hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    gather_i64_kernel<<<grid_for(count, 256), 256, 0, st>>>(src, idx, count, out);
     return hipGetLastError();
 }
 

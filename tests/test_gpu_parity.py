@@ -363,3 +363,61 @@ def test_stream_large_skewed_shape_sampled(ctx):
     assert total[0] == p.num_edges()[0] and p.two_paths == oracle.two_paths(inc, 16)
     p.destroy()
     g.release()
+
+
+def test_batch_matches_per_graph_oracle_and_replays(ctx):
+    import torch
+    fam = hg.batched_family(count=12, m_lo=200, m_hi=3000)
+    graphs = [ctx.register_incidence(mem.inc) for mem in fam]
+    s_list = [mem.s for mem in fam]
+    b = ctx.batch(graphs, s_list)
+    ref = [oracle.line_graph(mem.inc, mem.s) for mem in fam]
+
+    def check(tag):
+        for gidx, mem in enumerate(fam):
+            lg = b.result(gidx).cpu()
+            r = ref[gidx]
+            for got, want, f in ((lg.row_ptr, r.row_ptr, "row_ptr"), (lg.row, r.i, "i"), (lg.col, r.j, "j"),
+                                 (lg.w, r.w, "w")):
+                assert np.array_equal(got.numpy(), want), f"{tag} graph {gidx} {f}"
+
+    check("create")
+    assert b.info()["two_paths"] == sum(oracle.two_paths(m.inc, m.s) for m in fam)
+    b.run(use_graph=False)
+    torch.cuda.synchronize()
+    check("eager")
+    for rep in range(3):  # graph replays with eager work and syncs between
+        junk = torch.randint(0, 100, (1 << 20,), device="cuda").sum()
+        b.run(use_graph=True)
+        torch.cuda.synchronize()
+        check(f"replay {rep}")
+        del junk
+    b.destroy()
+    for g in graphs:
+        g.release()
+
+
+def test_batch_tuning_variants_agree(ctx):
+    fam = hg.batched_family(count=6, m_lo=2000, m_hi=20000)
+    graphs = [ctx.register_incidence(mem.inc) for mem in fam]
+    s_list = [mem.s for mem in fam]
+    outs = []
+    for tune in ((0, 0, 0), (512, 4096, 64), (2048, 16384, 0)):
+        ctx.set_tuning(*tune)
+        b = ctx.batch(graphs, s_list)
+        outs.append([b.result(g).cpu() for g in range(len(fam))])
+        b.destroy()
+    ctx.set_tuning()
+    for g in range(len(fam)):
+        for o in outs[1:]:
+            for f in ("row_ptr", "row", "col", "w"):
+                assert np.array_equal(getattr(outs[0][g], f).numpy(), getattr(o[g], f).numpy())
+        rows = np.linspace(0, fam[g].inc.m - 1, 25).astype(np.int64)
+        ref = oracle.line_graph_rows(fam[g].inc, s_list[g], rows)
+        rp = outs[0][g].row_ptr.numpy()
+        for t, i in enumerate(ref.rows):
+            rj, rw = ref.row(t)
+            assert np.array_equal(outs[0][g].col.numpy()[rp[i]:rp[i + 1]], rj)
+            assert np.array_equal(outs[0][g].w.numpy()[rp[i]:rp[i + 1]], rw)
+    for gr in graphs:
+        gr.release()
