@@ -89,6 +89,306 @@ def cpu_baseline(inc, seconds: float, seed: int = 7):
                       f"{work} 2-paths, {dt:.2f} s wall"}
 
 
+def batched_cpu_baseline(members, seconds: float, seed: int = 7):
+    """Oracle on whole member graphs, taken in a seeded random order until
+    about `seconds` of CPU time; rate = their 2-paths / oracle wall time."""
+    import numpy as np
+
+    import oracle
+    threads = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16)))
+    order = np.random.default_rng(seed).permutation(len(members))
+    work, dt, used = 0, 0.0, 0
+    for g in order:
+        inc, s = members[g].inc, members[g].s
+        t0 = time.perf_counter()
+        oracle.line_graph(inc, s, threads=threads)
+        dt += time.perf_counter() - t0
+        work += oracle.two_paths(inc, s)
+        used += 1
+        if dt >= seconds:
+            break
+    return {"value": work / dt, "unit": "2-paths/s", "cores": threads, "kind": "oracle",
+            "sample": f"{used} of {len(members)} member graphs (seeded order {seed}), each at its own s, "
+                      f"{work} 2-paths, {dt:.2f} s wall"}
+
+
+def bench_batched(args) -> int:
+    """256 hypergraphs of uneven size, each with its own s. Compares, in
+    aggregate 2-paths/s over the same member set: (a) per-instance one-shot
+    calls of the plain path, one graph after another; (b) building the batch
+    from scratch every step (disjoint union, one plan, one emit); (c) replays
+    of the captured HIP graph of the whole batched device path. `value` is
+    (c), the batched form; (a) and (b) ride along."""
+    import torch
+
+    import hypergen as hg
+    import paper_2201_11326_amd as slg
+    from paper_2201_11326_amd import autotune
+
+    t_gen = time.perf_counter()
+    members = hg.batched_family()
+    t_gen = time.perf_counter() - t_gen
+    ctx = slg.Context(0)
+    graphs = [ctx.register_incidence(mb.inc) for mb in members]
+    svals = [mb.s for mb in members]
+    torch.cuda.synchronize()
+    note = lambda msg: print(f"[bench batched] {msg}", file=sys.stderr, flush=True)
+    note(f"generated and registered {len(graphs)} graphs in {t_gen:.1f} s")
+
+    tuning, tune_times = (0, 0, 0), {}
+    if not args.no_tune:
+        tuning, tune_times = autotune.tune_batch(ctx, graphs, svals, use_cache=False)
+        note(f"tuned: {tuning}")
+
+    def per_instance():
+        outs = [ctx.line_graph(g, [s]) for g, s in zip(graphs, svals)]
+        torch.cuda.synchronize()
+        return outs
+
+    def timed(fn, steps, warm):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        lat = []
+        for _ in range(steps):
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t)
+        return lat
+
+    # (a) per-instance launches of the plain path
+    outs = per_instance()
+    work = sum(o[0].two_paths for o in outs)
+    edges = sum(o[0].num_edges for o in outs)
+    del outs
+    lat_a = timed(per_instance, args.steps, args.warmup)
+    note("per-instance timed")
+
+    # (b) batch built from scratch each step
+    def create_step():
+        b = ctx.batch(graphs, svals)
+        torch.cuda.synchronize()
+        b.destroy()
+    lat_b = timed(create_step, args.steps, args.warmup)
+    note("batch create timed")
+
+    # (c) HIP-graph replay of the whole batched device path
+    b = ctx.batch(graphs, svals)
+    info = b.info()
+    assert info["two_paths"] == work and info["edges"] == edges, (info, work, edges)
+    lat_c = timed(lambda: b.run(use_graph=True), args.steps, args.warmup)
+    lat_e = timed(lambda: b.run(use_graph=False), args.steps, args.warmup)
+    ctx.reset_timing()
+    ctx.set_timing(True)
+    for _ in range(args.steps):
+        b.run(use_graph=False)
+    torch.cuda.synchronize()
+    ctx.set_timing(False)
+    stages = ctx.timing()
+    note("replays timed")
+
+    # parity spot check of a few members against the oracle (untimed)
+    import numpy as np
+
+    import oracle
+    rng = np.random.default_rng(3)
+    checked = []
+    for gi in rng.choice(len(members), size=4, replace=False):
+        res = b.result(int(gi))
+        ref = oracle.line_graph(members[gi].inc, members[gi].s)
+        got = (res.row_ptr.cpu().numpy(), res.col.cpu().numpy(), res.w.cpu().numpy())
+        ok = (np.array_equal(got[0], ref.row_ptr) and np.array_equal(got[1], ref.j)
+              and np.array_equal(got[2], ref.w))
+        if not ok:
+            print(f"batched parity FAILED on member {gi}", file=sys.stderr)
+            return 1
+        checked.append(int(gi))
+    b.destroy()
+
+    total = lambda lat: sum(lat)
+    rate = lambda lat: work * len(lat) / total(lat)
+    ms_c = 1e3 * total(lat_c) / len(lat_c)
+    nnz = sum(mb.inc.nnz for mb in members)
+    rows = sum(mb.inc.m for mb in members)
+    nv = sum(mb.inc.n for mb in members)
+    step_bytes = 4 * work + 8 * nnz + 8 * (rows + nv) + 12 * edges + 8 * (rows + 1)
+    achieved = step_bytes / (ms_c / 1e3) / 1e9
+    cpu = None if args.no_cpu_baseline else batched_cpu_baseline(members, args.cpu_seconds)
+    line = {
+        "metric": METRIC, "value": rate(lat_c), "unit": "2-paths/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_c, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "batched: 256 hypergraphs, m log-uniform [1e3, 2e5], n=2m, "
+                               "|e|~min(Zipf(2.1), 1000), own s ~ U{1..8}",
+                   "graphs": len(members), "rows": rows, "nnz": nnz, "seed": hg.BASE_SEED + 4,
+                   "tuning": {"light_max": tuning[0], "slot_work": tuning[1], "heavy_grid": tuning[2]},
+                   "parallelism": "single GPU"},
+        "two_paths_per_step": work, "edges_per_step": edges,
+        "edges_per_s": edges * len(lat_c) / total(lat_c),
+        "p50_ms": 1e3 * percentile(lat_c, 0.5), "p99_ms": 1e3 * percentile(lat_c, 0.99),
+        "per_instance": {"value": rate(lat_a), "ms_per_step": 1e3 * total(lat_a) / len(lat_a),
+                         "p50_ms": 1e3 * percentile(lat_a, 0.5), "p99_ms": 1e3 * percentile(lat_a, 0.99)},
+        "batch_create": {"value": rate(lat_b), "ms_per_step": 1e3 * total(lat_b) / len(lat_b),
+                         "p50_ms": 1e3 * percentile(lat_b, 0.5), "p99_ms": 1e3 * percentile(lat_b, 0.99)},
+        "eager_replay": {"value": rate(lat_e), "ms_per_step": 1e3 * total(lat_e) / len(lat_e)},
+        "speedup_vs_per_instance": rate(lat_c) / rate(lat_a),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "whole batched step (HIP-graph replay)", "avg_launch_ms": ms_c,
+                     "algorithmic_bytes_per_launch": step_bytes},
+        "stage_ms_per_step": {k: v[1] / args.steps for k, v in stages.items()},
+        "tune_ms": {str(k): 1e3 * v for k, v in tune_times.items()},
+        "parity_checked_members": checked, "cpu_baseline": cpu, "generate_s": t_gen,
+    }
+    print(json.dumps(line), flush=True)
+    for g in graphs:
+        g.release()
+    ctx.close()
+    return 0
+
+
+def bench_served(args) -> int:
+    """Request loop over a device-resident pool (64 large-skewed-generator
+    graphs + 4 power-law-generator graphs) answering s-set queries drawn from
+    {1,2,3,4,5,8}. Three runs over the same request list: (a) per-instance
+    plain calls one after another (service times; FIFO latency under the
+    Poisson arrivals derived from them); (b) the server fed at the Poisson
+    arrival times (p50/p99 latency, achieved rate); (c) the server given every
+    request at once (capacity). `value` is (c) in 2-paths/s."""
+    import threading
+
+    import torch
+
+    import hypergen as hg
+    import paper_2201_11326_amd as slg
+
+    note = lambda msg: print(f"[bench served] {msg}", file=sys.stderr, flush=True)
+    t_gen = time.perf_counter()
+    pool = hg.served_pool()
+    reqs = hg.served_requests(len(pool), args.requests, rate=args.rate)
+    t_gen = time.perf_counter() - t_gen
+    ctx = slg.Context(0)
+    graphs = [ctx.register_incidence(x) for x in pool]
+    torch.cuda.synchronize()
+    note(f"pool of {len(pool)} graphs, {len(reqs)} requests generated in {t_gen:.1f} s")
+
+    # (a) per-instance plain calls, arrival order, back to back
+    for q in reqs[:32]:
+        outs = ctx.line_graph(graphs[q.graph], q.s)
+        torch.cuda.synchronize()
+        del outs
+    service, work_of = [], []
+    for q in reqs:
+        t = time.perf_counter()
+        outs = ctx.line_graph(graphs[q.graph], q.s)
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t)
+        work_of.append(outs[0].two_paths)
+        del outs
+    work = sum(work_of)
+    finish, lat_a = 0.0, []
+    for q, sv in zip(reqs, service):  # one FIFO server, same arrivals
+        finish = max(q.arrival, finish) + sv
+        lat_a.append(finish - q.arrival)
+    note(f"per-instance: {1e3 * sum(service):.1f} ms of service for {len(reqs)} requests")
+
+    def serve(paced: bool):
+        srv = ctx.server(workers=args.workers, mem_budget_bytes=int(args.budget_gb * (1 << 30)))
+        done = []
+
+        def collect():
+            for _ in range(len(reqs)):
+                r = srv.next(timeout_ms=120_000, keep=False)
+                done.append((time.perf_counter(), r))
+                if r is None:  # nothing ended for two minutes: give up
+                    break
+        th = threading.Thread(target=collect)
+        th.start()
+        t0 = time.perf_counter()
+        for q in reqs:
+            if paced:
+                dt = t0 + q.arrival - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+            srv.submit(graphs[q.graph], q.s)
+        th.join()
+        stats = srv.stats()
+        srv.close()
+        bad = [r for _, r in done if r is None or not r.ok]
+        if bad:
+            raise RuntimeError(f"{len(bad)} served queries failed: {bad[0] and bad[0].message}")
+        if len(done) != len(reqs):
+            raise RuntimeError(f"only {len(done)} of {len(reqs)} served queries ended")
+        span = max(t for t, _ in done) - t0
+        return span, [r.latency_ms for _, r in done], sum(r.two_paths for _, r in done), stats
+
+    span_b, lat_b, work_b, stats_b = serve(paced=True)
+    note(f"paced run: {span_b:.2f} s")
+    span_c, lat_c, work_c, stats_c = serve(paced=False)
+    note(f"burst run: {span_c:.2f} s")
+    assert work_b == work and work_c == work, (work, work_b, work_c)
+
+    # untimed parity spot check: a mix through the server against the same
+    # queries alone, and against the oracle where the graph is small
+    import numpy as np
+
+    import oracle
+    rng = np.random.default_rng(9)
+    pick = [reqs[int(i)] for i in rng.choice(len(reqs), size=16, replace=False)]
+    srv = ctx.server(workers=args.workers)
+    tick = {srv.submit(graphs[q.graph], q.s): q for q in pick}
+    checked = 0
+    for _ in pick:
+        r = srv.next(timeout_ms=300_000)
+        q = tick[r.ticket]
+        alone = ctx.line_graph(graphs[q.graph], q.s)
+        for a, b in zip(r.outs, alone):
+            for f in ("row_ptr", "col", "w"):
+                if not torch.equal(getattr(a, f), getattr(b, f)):
+                    print(f"served parity FAILED: graph {q.graph} s={q.s} {f}", file=sys.stderr)
+                    return 1
+            if pool[q.graph].m <= 10_000:
+                ref = oracle.line_graph(pool[q.graph], a.s)
+                if not (np.array_equal(a.row_ptr.cpu().numpy(), ref.row_ptr)
+                        and np.array_equal(a.col.cpu().numpy(), ref.j)
+                        and np.array_equal(a.w.cpu().numpy(), ref.w)):
+                    print(f"served oracle parity FAILED: graph {q.graph} s={a.s}", file=sys.stderr)
+                    return 1
+        checked += 1
+        del r, alone
+    srv.close()
+
+    pct = lambda xs, q: percentile(xs, q)
+    line = {
+        "metric": METRIC, "value": work / span_c, "unit": "2-paths/s", "n_gpus": 1, "steps": 1,
+        "warmup": 32, "ms_per_step": 1e3 * span_c, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"served: {len(pool)} resident graphs (64 large-skewed-generator, m log-uniform "
+                               f"[1e3, 1e4], n=m/2; 4 power-law-generator, m 1e4..8e4, n=2m), {len(reqs)} "
+                               f"Poisson requests at {args.rate:g}/s, s-sets of 1-3 from {{1,2,3,4,5,8}}",
+                   "workers": args.workers, "budget_gb": args.budget_gb, "seed": hg.BASE_SEED + 5,
+                   "parallelism": "single GPU"},
+        "two_paths_total": work,
+        "p50_ms": pct(lat_b, 0.5), "p99_ms": pct(lat_b, 0.99),
+        "paced": {"rate_2paths_per_s": work / span_b, "span_s": span_b, "p50_ms": pct(lat_b, 0.5),
+                  "p99_ms": pct(lat_b, 0.99), "yields": stats_b.get("yields"),
+                  "peak_bytes": stats_b.get("bytes_peak")},
+        "burst": {"rate_2paths_per_s": work / span_c, "span_s": span_c, "p50_ms": pct(lat_c, 0.5),
+                  "p99_ms": pct(lat_c, 0.99), "peak_bytes": stats_c.get("bytes_peak")},
+        "per_instance": {"rate_2paths_per_s": work / sum(service), "service_s": sum(service),
+                         "service_p50_ms": 1e3 * pct(service, 0.5), "service_p99_ms": 1e3 * pct(service, 0.99),
+                         "fifo_p50_ms": 1e3 * pct(lat_a, 0.5), "fifo_p99_ms": 1e3 * pct(lat_a, 0.99)},
+        "speedup_vs_per_instance": (work / span_c) / (work / sum(service)),
+        "parity_checked_requests": checked, "generate_s": t_gen, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+    for g in graphs:
+        g.release()
+    ctx.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +396,14 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("power_law", "batched", "served"), default="power_law",
+                    help="power_law: the single large hypergraph (default); batched: 256 small "
+                         "hypergraphs, each with its own s, as one disjoint-union batch")
+    ap.add_argument("--no-tune", action="store_true", help="batched: library-default plan shape")
+    ap.add_argument("--requests", type=int, default=4000, help="served: number of requests")
+    ap.add_argument("--rate", type=float, default=2000.0, help="served: Poisson arrivals per second")
+    ap.add_argument("--workers", type=int, default=4, help="served: queries in flight")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="served: device-memory budget")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the s-line graph path here runs on a single MI355X "
@@ -111,6 +419,10 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "served":
+        return bench_served(args)
     t_gen = time.perf_counter()
     inc = hg.power_law()
     t_gen = time.perf_counter() - t_gen

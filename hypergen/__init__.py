@@ -31,7 +31,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Optional, Sequence
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -218,6 +218,51 @@ def batched_family(seed: int = BASE_SEED + 4, count: int = 256, m_lo: int = 1000
         sizes = np.minimum(rng.zipf(alpha, size=m), kmax).astype(np.int64)
         s = int(rng.integers(1, s_max + 1))
         out.append(BatchMember(_build(rng, n, sizes, None), s))
+    return out
+
+
+def served_pool(seed: int = BASE_SEED + 5, skewed: int = 64, power: int = 4,
+                skewed_m: Tuple[int, int] = (1_000, 10_000),
+                power_m: Tuple[int, int] = (10_000, 80_000)) -> List[Incidence]:
+    """Device-resident pool of the served workload: `skewed` graphs from the
+    large-skewed generator (n = m/2, m log-uniform in skewed_m) followed by
+    `power` graphs from the power-law generator (n = 2m, m log-spaced over
+    power_m)."""
+    ss = np.random.SeedSequence(seed)
+    kids = ss.spawn(skewed + power)
+    out = []
+    for t in range(skewed):
+        rng = np.random.default_rng(kids[t])
+        m = int(math.floor(math.exp(rng.uniform(math.log(skewed_m[0]), math.log(skewed_m[1])))))
+        out.append(large_skewed(seed=int(rng.integers(1 << 62)), n=max(m // 2, 1), m=m))
+    for t in range(power):
+        rng = np.random.default_rng(kids[skewed + t])
+        frac = t / max(power - 1, 1)
+        m = int(round(math.exp(math.log(power_m[0]) + frac * (math.log(power_m[1]) - math.log(power_m[0])))))
+        out.append(power_law(seed=int(rng.integers(1 << 62)), n=2 * m, m=m))
+    return out
+
+
+@dataclasses.dataclass
+class Request:
+    arrival: float     # seconds from the start of the stream
+    graph: int         # index into the pool
+    s: List[int]       # increasing thresholds
+
+
+def served_requests(pool_size: int, count: int, rate: float = 2000.0, seed: int = BASE_SEED + 6,
+                    s_choices: Sequence[int] = (1, 2, 3, 4, 5, 8), max_set: int = 3) -> List[Request]:
+    """Poisson arrivals at `rate` per second; each request names a pool
+    graph uniformly and an s-set of 1..max_set distinct thresholds drawn
+    from s_choices."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    out = []
+    for a in t:
+        g = int(rng.integers(0, pool_size))
+        k = int(rng.integers(1, max_set + 1))
+        s = sorted(int(x) for x in rng.choice(np.asarray(s_choices), size=k, replace=False))
+        out.append(Request(float(a), g, s))
     return out
 
 

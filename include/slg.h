@@ -41,7 +41,8 @@ typedef enum {
     SLG_ERR_OUT_OF_MEMORY = 3, /* device allocation failed / budget exceeded */
     SLG_ERR_DEVICE = 4,        /* a HIP runtime call failed */
     SLG_ERR_OVERFLOW = 5,      /* m, n or nnz >= 2^31 */
-    SLG_ERR_CANCELLED = 6      /* a chunk callback asked to stop */
+    SLG_ERR_CANCELLED = 6,     /* a chunk callback asked to stop / server shut down */
+    SLG_ERR_TIMEOUT = 7        /* a server wait ran out of time (the request goes on) */
 } slg_status;
 
 /* Largest number of thresholds in one ensemble call. */
@@ -94,9 +95,11 @@ typedef struct {
 const char *slg_version(void);
 
 /*
- * Create a context on HIP device `device`. mem_budget_bytes bounds the
- * device memory a call may hold (0 = no bound; recorded for the batched and
- * served forms). `alloc` may be NULL.
+ * Create a context on HIP device `device`. Planning scratch (and the
+ * outputs of slg_line_graph when `alloc` is NULL) come from a block cache
+ * of the context: freed blocks are kept for reuse by later calls, up to
+ * mem_budget_bytes of them (0 = 16 GiB); beyond that the largest are given
+ * back to the device. `alloc` may be NULL.
  * Errors: INVALID_ARG (out == NULL), DEVICE (no such device).
  */
 slg_status slg_context_create(int device, uint64_t mem_budget_bytes, const slg_allocator *alloc,
@@ -261,6 +264,67 @@ slg_status slg_result_coo(const slg_result *r, int32_t k, const int32_t **i, con
 slg_status slg_result_csr(const slg_result *r, int32_t k, const int64_t **row_ptr,
                           const int32_t **col, const int32_t **w);
 slg_status slg_result_free(slg_result *r);
+
+/*
+ * Served form: a request loop over device-resident hypergraphs. Queries
+ * (a registered graph plus an s-set, each an ensemble pass of Algorithm 3)
+ * arrive at any time and are started in arrival order as soon as one of
+ * `workers` slots is free (1..16; each slot plans and emits on its own
+ * HIP stream, so several queries' kernels overlap on the device) and the
+ * device-memory budget allows. Every query asks the budget for its planning
+ * scratch (two phases, sized as the plan learns its shape) and then for its
+ * outputs; scratch is given back when the query ends, outputs when the
+ * caller frees the result (slg_result_free). When a query cannot get memory
+ * it waits, and no new query starts meanwhile; a second query that runs
+ * short while one already waits gives back what it holds and goes back to
+ * the head of the queue (it is planned again later; `attempts` counts
+ * this). A query whose own need exceeds the whole budget fails with
+ * SLG_ERR_OUT_OF_MEMORY. mem_budget_bytes = 0 means no limit.
+ *
+ * The server plans with its own contexts (one per slot, with ctx's device
+ * and plan-shape tuning); ctx itself is only read at creation. Graphs
+ * passed to submit must be registered on the same device and stay
+ * registered until their queries are done. submit, wait, next and stats may
+ * be called from any host threads. Results count against the budget until
+ * freed: a caller that keeps results while waiting for a query that needs
+ * their memory waits for ever (use a timeout, or `next`, which returns
+ * queries in completion order). A served result is complete when handed
+ * over; slg_result_free returns its buffers to the server's block cache
+ * after the work already queued on the null stream, so finish work on
+ * other streams that reads them first. Results may be freed after the
+ * server is destroyed. The slots share one block cache that keeps at most
+ * half the budget (16 GiB without a budget) of freed blocks for reuse.
+ */
+typedef struct slg_server slg_server;
+typedef struct {
+    uint64_t ticket;
+    slg_status status;   /* the query's own outcome */
+    int32_t attempts;    /* times the query was planned */
+    double queue_ms;     /* submit -> first start */
+    double latency_ms;   /* submit -> outputs complete */
+    int64_t two_paths;   /* 2-paths of the query's pass (at its smallest s) */
+    char message[192];   /* why it failed ("" when status is SLG_OK) */
+} slg_request_info;
+slg_status slg_server_create(slg_context *ctx, int32_t workers, uint64_t mem_budget_bytes, slg_server **out);
+/* Queue a query; *ticket names it. Errors: INVALID_ARG (null, bad s-set,
+ * graph on another device), CANCELLED (server shutting down). */
+slg_status slg_server_submit(slg_server *srv, slg_graph *g, const int32_t *s, int32_t num_s, uint64_t *ticket);
+/*
+ * Wait up to timeout_ms (< 0: no limit) for query `ticket`. Returns the
+ * query's status once it has ended (then *out is its result, or NULL when
+ * it failed, *info is filled, and the ticket is retired), TIMEOUT if it
+ * has not, INVALID_ARG for an unknown or retired ticket.
+ */
+slg_status slg_server_wait(slg_server *srv, uint64_t ticket, int32_t timeout_ms, slg_result **out,
+                           slg_request_info *info);
+/* As wait, for whichever query ended first among those not yet retired. */
+slg_status slg_server_next(slg_server *srv, int32_t timeout_ms, slg_result **out, slg_request_info *info);
+/* out[0..8]: submitted, completed, failed, yields, queued, running,
+ * bytes in use, peak bytes in use, bytes held by unfreed results. */
+slg_status slg_server_stats(slg_server *srv, int64_t *out, int32_t cap, int32_t *count);
+/* Cancels queued queries (CANCELLED), waits for running ones, frees the
+ * results nobody took. */
+slg_status slg_server_destroy(slg_server *srv);
 
 #ifdef __cplusplus
 }

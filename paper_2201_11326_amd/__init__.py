@@ -31,11 +31,12 @@ SLG_ERR_OUT_OF_MEMORY = 3
 SLG_ERR_DEVICE = 4
 SLG_ERR_OVERFLOW = 5
 SLG_ERR_CANCELLED = 6
+SLG_ERR_TIMEOUT = 7
 SLG_MAX_S = 16
 SLG_VALIDATE = 1
 
 _STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "INVALID_GRAPH", 3: "OUT_OF_MEMORY", 4: "DEVICE",
-                 5: "OVERFLOW", 6: "CANCELLED"}
+                 5: "OVERFLOW", 6: "CANCELLED", 7: "TIMEOUT"}
 
 _p = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -117,6 +118,12 @@ def lib() -> ctypes.CDLL:
         "slg_result_coo": (_i32, [_p, _i32, ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
         "slg_result_csr": (_i32, [_p, _i32, ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
         "slg_result_free": (_i32, [_p]),
+        "slg_server_create": (_i32, [_p, _i32, _u64, ctypes.POINTER(_p)]),
+        "slg_server_submit": (_i32, [_p, _p, ctypes.POINTER(_i32), _i32, ctypes.POINTER(_u64)]),
+        "slg_server_wait": (_i32, [_p, _u64, _i32, ctypes.POINTER(_p), ctypes.POINTER(RequestInfo)]),
+        "slg_server_next": (_i32, [_p, _i32, ctypes.POINTER(_p), ctypes.POINTER(RequestInfo)]),
+        "slg_server_stats": (_i32, [_p, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i32)]),
+        "slg_server_destroy": (_i32, [_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -420,26 +427,132 @@ class Context:
 
     def line_graph_result(self, g: Graph, s: Sequence[int], stream=None) -> List[LineGraph]:
         """The one-shot ABI call (slg_line_graph): library-owned result buffers."""
-        import torch
         arr, k = _s_array(s)
         h = _p()
         self._check(lib().slg_line_graph(self.handle, g.handle, arr, k, _stream_handle(stream),
                                          ctypes.byref(h)))
-        res = _Result(h.value)
-        outs = []
-        for kk, sk in enumerate(s):
-            e, wpaths = _i64(), _i64()
-            self._check(lib().slg_result_info(res.handle, kk, ctypes.byref(e), ctypes.byref(wpaths)))
-            ip, jp, wp, rp = _p(), _p(), _p(), _p()
-            self._check(lib().slg_result_coo(res.handle, kk, ctypes.byref(ip), ctypes.byref(jp),
-                                             ctypes.byref(wp)))
-            self._check(lib().slg_result_csr(res.handle, kk, ctypes.byref(rp), None, None))
-            view = lambda ptr, n, ts: torch.as_tensor(_DeviceView(ptr, n, ts, res), device=f"cuda:{self.device}")
-            ne = int(e.value)
-            outs.append(LineGraph(int(sk), view(rp.value, g.m + 1, "<i8"), view(ip.value, ne, "<i4"),
-                                  view(jp.value, ne, "<i4"), view(wp.value, ne, "<i4"), int(wpaths.value),
-                                  owner=res))
-        return outs
+        return _wrap_result(_Result(h.value), s, g.m, self.device)
+
+    def server(self, workers: int = 4, mem_budget_bytes: int = 0) -> "Server":
+        """The served form (slg_server_*): a request loop over registered graphs."""
+        return Server(self, workers, mem_budget_bytes)
+
+
+def _wrap_result(res: "_Result", s: Sequence[int], m: int, device: int) -> List[LineGraph]:
+    """Zero-copy torch views of an slg_result, one LineGraph per threshold."""
+    import torch
+
+    def check(st):
+        if st != SLG_OK:
+            raise SlgError(st, "result query failed")
+    outs = []
+    for kk, sk in enumerate(s):
+        e, wpaths = _i64(), _i64()
+        check(lib().slg_result_info(res.handle, kk, ctypes.byref(e), ctypes.byref(wpaths)))
+        ip, jp, wp, rp = _p(), _p(), _p(), _p()
+        check(lib().slg_result_coo(res.handle, kk, ctypes.byref(ip), ctypes.byref(jp), ctypes.byref(wp)))
+        check(lib().slg_result_csr(res.handle, kk, ctypes.byref(rp), None, None))
+        view = lambda ptr, n, ts: torch.as_tensor(_DeviceView(ptr, n, ts, res), device=f"cuda:{device}")
+        ne = int(e.value)
+        outs.append(LineGraph(int(sk), view(rp.value, m + 1, "<i8"), view(ip.value, ne, "<i4"),
+                              view(jp.value, ne, "<i4"), view(wp.value, ne, "<i4"), int(wpaths.value),
+                              owner=res))
+    return outs
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("ticket", _u64), ("status", ctypes.c_int), ("attempts", _i32), ("queue_ms", ctypes.c_double),
+                ("latency_ms", ctypes.c_double), ("two_paths", _i64), ("message", ctypes.c_char * 192)]
+
+
+class Served:
+    """One finished query of a Server: its outcome, timings and (on success)
+    one LineGraph per threshold. The outputs count against the server's
+    memory budget until every reference to them is dropped."""
+
+    def __init__(self, info: RequestInfo, s: List[int], graph: "Graph", outs):
+        self.ticket = int(info.ticket)
+        self.status = int(info.status)
+        self.attempts = int(info.attempts)
+        self.queue_ms = float(info.queue_ms)
+        self.latency_ms = float(info.latency_ms)
+        self.two_paths = int(info.two_paths)
+        self.message = info.message.decode(errors="replace")
+        self.s, self.graph, self.outs = s, graph, outs
+
+    @property
+    def ok(self) -> bool:
+        return self.status == SLG_OK
+
+
+class Server:
+    SERVER_STAT_NAMES = ("submitted", "completed", "failed", "yields", "queued", "running", "bytes_used",
+                         "bytes_peak", "bytes_in_results")
+
+    def __init__(self, ctx: Context, workers: int = 4, mem_budget_bytes: int = 0):
+        import threading
+        self.ctx = ctx
+        self._pending = {}  # ticket -> (graph, s)
+        self._lock = threading.Lock()  # a query may end before submit has recorded it
+        h = _p()
+        ctx._check(lib().slg_server_create(ctx.handle, int(workers), int(mem_budget_bytes), ctypes.byref(h)))
+        self.handle = h.value
+
+    def submit(self, g: Graph, s: Sequence[int]) -> int:
+        arr, k = _s_array(s)
+        t = _u64()
+        with self._lock:
+            st = lib().slg_server_submit(self.handle, g.handle, arr, k, ctypes.byref(t))
+            if st != SLG_OK:
+                raise SlgError(st, "slg_server_submit refused the query")
+            self._pending[int(t.value)] = (g, [int(x) for x in s])
+        return int(t.value)
+
+    def _finish(self, st: int, h, info: RequestInfo) -> Optional[Served]:
+        if st == SLG_ERR_TIMEOUT:
+            return None
+        ticket = int(info.ticket)
+        with self._lock:
+            if ticket not in self._pending:
+                raise SlgError(st, "unknown or retired ticket")
+            g, s = self._pending.pop(ticket)
+        outs = _wrap_result(_Result(h.value), s, g.m, self.ctx.device) if h.value else None
+        return Served(info, s, g, outs)
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> Optional[Served]:
+        """The query's outcome once it has ended; None on timeout."""
+        h, info = _p(), RequestInfo()
+        st = lib().slg_server_wait(self.handle, int(ticket), int(timeout_ms), ctypes.byref(h), ctypes.byref(info))
+        if st == SLG_ERR_INVALID_ARG and h.value is None and int(info.ticket) == 0:
+            raise SlgError(st, f"unknown or retired ticket {ticket}")
+        return self._finish(st, h, info)
+
+    def next(self, timeout_ms: int = -1, keep: bool = True) -> Optional[Served]:
+        """Whichever query ended first (completion order); None on timeout.
+        keep=False frees the outputs at once (outcome and timings only)."""
+        h, info = _p(), RequestInfo()
+        st = lib().slg_server_next(self.handle, int(timeout_ms), ctypes.byref(h) if keep else None,
+                                   ctypes.byref(info))
+        return self._finish(st, h, info)
+
+    def stats(self) -> dict:
+        out = (_i64 * 16)()
+        n = _i32()
+        st = lib().slg_server_stats(self.handle, out, 16, ctypes.byref(n))
+        if st != SLG_OK:
+            raise SlgError(st, "slg_server_stats failed")
+        return {self.SERVER_STAT_NAMES[t]: int(out[t]) for t in range(n.value)}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().slg_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class _Result:

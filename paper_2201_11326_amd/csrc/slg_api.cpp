@@ -7,11 +7,14 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "slg.h"
+#include "slg_arena.h"
+#include "slg_host.h"
 #include "slg_internal.h"
 
 using namespace slg;
@@ -47,6 +50,7 @@ struct slg_context {
     slg_allocator alloc{};
     std::string last_error;
     int64_t *pinned = nullptr;  // host staging for readbacks
+    std::shared_ptr<slg::Arena> arena;  // scratch and library-owned outputs
 };
 
 struct slg_graph {
@@ -70,6 +74,9 @@ constexpr int kHbSlots = kCntTotal;      // slot table size, then 2-paths, bound
 constexpr int kHbEdges = 40;             // SLG_MAX_S edge totals
 constexpr int kHbHeavyEdges = kHbEdges + SLG_MAX_S;
 static_assert(kHbSlots + 3 <= kHbEdges && kHbHeavyEdges + 1 < kPinnedSlots, "pinned staging layout");
+
+// Freed device blocks a context keeps for reuse unless told otherwise.
+constexpr uint64_t kDefaultCache = uint64_t(16) << 30;
 
 slg_status fail(slg_context *ctx, slg_status st, const char *fmt, ...) {
     if (ctx) {
@@ -95,11 +102,12 @@ slg_status fail(slg_context *ctx, slg_status st, const char *fmt, ...) {
 // Stream-ordered scratch owned by a plan.
 struct Scratch {
     hipStream_t st = nullptr;
+    slg::Arena *arena = nullptr;
     std::vector<void *> ptrs;
     hipError_t get(void **p, size_t bytes) {
         *p = nullptr;
         if (bytes == 0) bytes = 8;
-        hipError_t e = hipMallocAsync(p, bytes, st);
+        hipError_t e = arena->get(p, bytes, st);
         if (e == hipSuccess) ptrs.push_back(*p);
         return e;
     }
@@ -107,9 +115,22 @@ struct Scratch {
     hipError_t get(T **p, size_t count) {
         return get(reinterpret_cast<void **>(p), count * sizeof(T));
     }
-    void release() {
-        for (void *p : ptrs) (void)hipFreeAsync(p, st);
+    void release() {  // after the work already queued on st
+        if (arena) arena->put(ptrs, st);
         ptrs.clear();
+    }
+};
+
+// Allocations of one planning phase, summed before any is made so that a
+// budget can be asked for them at once.
+struct AllocList {
+    std::vector<std::pair<void **, size_t>> items;
+    uint64_t bytes = 0;
+    template <typename T>
+    void add(T **p, size_t count) {
+        const size_t b = std::max<size_t>(count * sizeof(T), 8);
+        items.push_back({reinterpret_cast<void **>(p), b});
+        bytes += b;
     }
 };
 
@@ -191,6 +212,8 @@ struct slg_plan {
     int64_t heavy_edges = 0;
     int64_t nbounds = 0;
     int64_t num_edges[SLG_MAX_S] = {};
+    const slg::ReserveFn *reserve = nullptr;  // asked before each planning allocation phase
+    uint64_t reserved = 0;                    // bytes granted by `reserve`
 };
 
 struct slg_batch {
@@ -222,6 +245,9 @@ struct slg_result {
     int32_t *col[SLG_MAX_S] = {};
     int32_t *w[SLG_MAX_S] = {};
     std::vector<void *> owned;
+    std::shared_ptr<slg::Arena> arena;     // owner of `owned` unless the context's allocator made them
+    std::shared_ptr<slg::ServeCore> core;  // served results: ledger the outputs are accounted to
+    uint64_t bytes = 0;                    // device bytes accounted to `core`
 };
 
 extern "C" {
@@ -250,6 +276,7 @@ slg_status slg_context_create(int device, uint64_t mem_budget_bytes, const slg_a
         return SLG_ERR_DEVICE;
     }
     ctx->heavy_resident = heavy_resident(device);
+    ctx->arena = std::make_shared<slg::Arena>(device, mem_budget_bytes ? mem_budget_bytes : kDefaultCache);
     // keep freed scratch in the stream-ordered pool between calls
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
@@ -293,6 +320,7 @@ slg_status slg_graph_register(slg_context *ctx, const slg_incidence *inc, uint32
     if (flags & SLG_VALIDATE) {
         Scratch sc;
         sc.st = st;
+        sc.arena = ctx->arena.get();
         int64_t *err = nullptr;
         SLG_HIP(ctx, sc.get(&err, 1));
         SLG_HIP(ctx, launch_fill_i64(err, 1, 0, st));
@@ -448,30 +476,38 @@ slg_status plan_build(slg_plan *p) {
     pr.he_ptr = inc.he_ptr;
     pr.he_idx = inc.he_idx;
     p->prune = (p->s_min > 1 || pr.row_s) && nnz > 0;
+    AllocList phase1;
     if (p->prune) {
-        BUILD_HIP(sc.get(&b.flag, nnz));
-        BUILD_HIP(sc.get(&b.pos, nnz + 1));
-        BUILD_HIP(sc.get(&b.part_nnz, scan_partials_size(nnz)));
-        BUILD_HIP(sc.get(&b.vs_ptr, n + 1));
-        BUILD_HIP(sc.get(&b.vs_idx, nnz));
+        phase1.add(&b.flag, nnz);
+        phase1.add(&b.pos, nnz + 1);
+        phase1.add(&b.part_nnz, scan_partials_size(nnz));
+        phase1.add(&b.vs_ptr, n + 1);
+        phase1.add(&b.vs_idx, nnz);
+    }
+    phase1.add(&b.tail_beg, nnz);
+    phase1.add(&b.work, m);
+    phase1.add(&b.work_pre, m + 1);
+    phase1.add(&b.jmax, m);
+    phase1.add(&b.nslots, m);
+    phase1.add(&b.rclass, m);
+    phase1.add(&b.bsize, m);
+    phase1.add(&b.bbase, m + 1);
+    phase1.add(&b.hat, m);
+    phase1.add(&b.counters, 32);
+    phase1.add(&b.part_m, scan_partials_size(m));
+    phase1.add(&p->slot_base, m + 1);
+    if (p->reserve) {
+        if (!(*p->reserve)(phase1.bytes)) return fail(ctx, SLG_ERR_OUT_OF_MEMORY, "device-memory budget refused");
+        p->reserved += phase1.bytes;
+    }
+    for (const auto &a : phase1.items) BUILD_HIP(sc.get(a.first, a.second));
+    if (p->prune) {
         pr.vs_ptr = b.vs_ptr;
         pr.vs_idx = b.vs_idx;
     } else {
         pr.vs_ptr = inc.v_ptr;
         pr.vs_idx = inc.v_idx;
     }
-    BUILD_HIP(sc.get(&b.tail_beg, nnz));
-    BUILD_HIP(sc.get(&b.work, m));
-    BUILD_HIP(sc.get(&b.work_pre, m + 1));
-    BUILD_HIP(sc.get(&b.jmax, m));
-    BUILD_HIP(sc.get(&b.nslots, m));
-    BUILD_HIP(sc.get(&b.rclass, m));
-    BUILD_HIP(sc.get(&b.bsize, m));
-    BUILD_HIP(sc.get(&b.bbase, m + 1));
-    BUILD_HIP(sc.get(&b.hat, m));
-    BUILD_HIP(sc.get(&b.counters, 32));
-    BUILD_HIP(sc.get(&b.part_m, scan_partials_size(m)));
-    BUILD_HIP(sc.get(&p->slot_base, m + 1));
     pr.tail_beg = b.tail_beg;
     BUILD_HIP(enqueue_rows(p, st));
     int64_t *hb = ctx->pinned;
@@ -492,15 +528,21 @@ slg_status plan_build(slg_plan *p) {
     if (p->nbounds >= (int64_t(1) << 40)) return fail(ctx, SLG_ERR_OVERFLOW, "boundary table too large");
 
     const int K = p->prm.k;
-    BUILD_HIP(sc.get(&b.slot_row, p->S));
-    BUILD_HIP(sc.get(&p->bounds, p->nbounds));
-    BUILD_HIP(sc.get(&p->tickets, 5));
-    for (int c = 0; c < kLightClasses; ++c) BUILD_HIP(sc.get(&p->lists[c], p->list_count[c]));
-    for (int h = 0; h < 2; ++h) BUILD_HIP(sc.get(&p->heavy[h], p->list_count[kLightClasses + h]));
+    AllocList phase2;
+    phase2.add(&b.slot_row, p->S);
+    phase2.add(&p->bounds, p->nbounds);
+    phase2.add(&p->tickets, 5);
+    for (int c = 0; c < kLightClasses; ++c) phase2.add(&p->lists[c], p->list_count[c]);
+    for (int h = 0; h < 2; ++h) phase2.add(&p->heavy[h], p->list_count[kLightClasses + h]);
     static_assert(sizeof(HeavyDesc) % 8 == 0, "HeavyDesc is filled as int64 words");
-    BUILD_HIP(sc.get(&p->slot_cnt, (size_t)K * p->S));
-    BUILD_HIP(sc.get(&p->slot_off, (size_t)K * (p->S + 1)));
-    BUILD_HIP(sc.get(&b.part_s, scan_partials_size(p->S)));
+    phase2.add(&p->slot_cnt, (size_t)K * p->S);
+    phase2.add(&p->slot_off, (size_t)K * (p->S + 1));
+    phase2.add(&b.part_s, scan_partials_size(p->S));
+    if (p->reserve) {
+        if (!(*p->reserve)(phase2.bytes)) return fail(ctx, SLG_ERR_OUT_OF_MEMORY, "device-memory budget refused");
+        p->reserved += phase2.bytes;
+    }
+    for (const auto &a : phase2.items) BUILD_HIP(sc.get(a.first, a.second));
     p->slots.count = p->S;
     p->slots.row = b.slot_row;
     BUILD_HIP(enqueue_slots_count(p, st));
@@ -529,6 +571,7 @@ slg_plan *plan_new(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num
     p->g = g;
     p->st = st;
     p->scratch.st = st;
+    p->scratch.arena = ctx->arena.get();
     p->prm.k = num_s;
     for (int t = 0; t < num_s; ++t) p->prm.s[t] = s[t];
     p->s_min = s[0];
@@ -651,10 +694,12 @@ slg_status slg_line_graph_stream(slg_context *ctx, slg_graph *g, const int32_t *
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int K = num_s;
     const int64_t m = p->pr.m;
-    std::vector<void *> bufs;
+    Scratch bufs;
+    bufs.st = st;
+    bufs.arena = ctx->arena.get();
     auto cleanup = [&](slg_status code) {
         (void)hipStreamSynchronize(st);
-        for (void *b : bufs) (void)hipFreeAsync(b, st);
+        bufs.release();
         slg_plan_destroy(p);
         (void)hipStreamSynchronize(st);
         return code;
@@ -668,8 +713,7 @@ slg_status slg_line_graph_stream(slg_context *ctx, slg_graph *g, const int32_t *
     } while (0)
     // output bytes before every row; chunks are greedy row ranges
     int64_t *dbytes;
-    STREAM_HIP(hipMallocAsync(reinterpret_cast<void **>(&dbytes), (m + 1) * sizeof(int64_t), st));
-    bufs.push_back(dbytes);
+    STREAM_HIP(bufs.get(&dbytes, m + 1));
     STREAM_HIP(launch_row_bytes(m, p->slot_base, p->slot_off, p->S, K, dbytes, st));
     std::vector<int64_t> rbytes(m + 1);
     STREAM_HIP(hipMemcpyAsync(rbytes.data(), dbytes, (m + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -689,10 +733,8 @@ slg_status slg_line_graph_stream(slg_context *ctx, slg_graph *g, const int32_t *
     // slot offsets of every threshold at every cut
     const int64_t nc = (int64_t)cuts.size();
     int64_t *dcuts, *doffs;
-    STREAM_HIP(hipMallocAsync(reinterpret_cast<void **>(&dcuts), nc * sizeof(int64_t), st));
-    bufs.push_back(dcuts);
-    STREAM_HIP(hipMallocAsync(reinterpret_cast<void **>(&doffs), nc * K * sizeof(int64_t), st));
-    bufs.push_back(doffs);
+    STREAM_HIP(bufs.get(&dcuts, nc));
+    STREAM_HIP(bufs.get(&doffs, nc * K));
     STREAM_HIP(hipMemcpyAsync(dcuts, cuts.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice, st));
     STREAM_HIP(launch_gather_offsets(dcuts, nc, p->slot_base, p->slot_off, p->S, K, doffs, st));
     std::vector<int64_t> offs(nc * K), sb(nc);
@@ -709,13 +751,9 @@ slg_status slg_line_graph_stream(slg_context *ctx, slg_graph *g, const int32_t *
     int64_t *rp[SLG_MAX_S];
     int32_t *ri[SLG_MAX_S], *rj[SLG_MAX_S], *rw[SLG_MAX_S];
     for (int k = 0; k < K; ++k) {
-        STREAM_HIP(hipMallocAsync(reinterpret_cast<void **>(&rp[k]), (max_rows + 1) * sizeof(int64_t), st));
-        bufs.push_back(rp[k]);
+        STREAM_HIP(bufs.get(&rp[k], max_rows + 1));
         void *q[3];
-        for (int t = 0; t < 3; ++t) {
-            STREAM_HIP(hipMallocAsync(&q[t], std::max<int64_t>(max_e[k], 1) * sizeof(int32_t), st));
-            bufs.push_back(q[t]);
-        }
+        for (int t = 0; t < 3; ++t) STREAM_HIP(bufs.get(&q[t], std::max<int64_t>(max_e[k], 1) * sizeof(int32_t)));
         ri[k] = static_cast<int32_t *>(q[0]);
         rj[k] = static_cast<int32_t *>(q[1]);
         rw[k] = static_cast<int32_t *>(q[2]);
@@ -1016,6 +1054,7 @@ slg_status slg_line_graph(slg_context *ctx, slg_graph *g, const int32_t *s, int3
     }
     r->ctx = ctx;
     r->st = static_cast<hipStream_t>(stream);
+    if (!ctx->has_alloc) r->arena = ctx->arena;
     r->k = num_s;
     r->m = g->inc.num_hyperedges;
     r->two_paths = p->two_paths;
@@ -1023,7 +1062,7 @@ slg_status slg_line_graph(slg_context *ctx, slg_graph *g, const int32_t *s, int3
         if (bytes == 0) bytes = 8;
         if (ctx->has_alloc) {
             *ptr = ctx->alloc.alloc(ctx->alloc.user, bytes, stream);
-        } else if (hipMallocAsync(ptr, bytes, r->st) != hipSuccess) {
+        } else if (ctx->arena->get(ptr, bytes, r->st) != hipSuccess) {
             *ptr = nullptr;
         }
         if (*ptr) r->owned.push_back(*ptr);
@@ -1047,6 +1086,85 @@ slg_status slg_line_graph(slg_context *ctx, slg_graph *g, const int32_t *s, int3
     *out = r;
     return SLG_OK;
 }
+
+}  // extern "C"
+
+namespace slg {
+
+int context_device(const slg_context *ctx) { return ctx->device; }
+const slg_context *graph_context(const slg_graph *g) { return g->ctx; }
+slg_status set_error(slg_context *ctx, slg_status code, const char *msg) { return fail(ctx, code, "%s", msg); }
+
+void share_arena(slg_context *ctx, const std::shared_ptr<Arena> &arena) { ctx->arena = arena; }
+
+void copy_tuning(slg_context *dst, const slg_context *src) {
+    dst->light_max = src->light_max;
+    dst->slot_work = src->slot_work;
+    dst->heavy_grid = src->heavy_grid;
+}
+
+slg_status serve_query(slg_context *wctx, slg_graph *g, const int32_t *s, int32_t num_s, hipStream_t st,
+                       const ReserveFn &reserve, const std::shared_ptr<ServeCore> &core, slg_result **out,
+                       uint64_t *scratch_bytes, uint64_t *output_bytes) {
+    *out = nullptr;
+    *scratch_bytes = 0;
+    *output_bytes = 0;
+    if (!g || !valid_s(s, num_s)) return fail(wctx, SLG_ERR_INVALID_ARG, "bad graph or s-set");
+    SLG_HIP(wctx, hipSetDevice(wctx->device));
+    slg_plan *p = plan_new(wctx, g, s, num_s, st);
+    if (!p) return fail(wctx, SLG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    p->reserve = &reserve;
+    slg_status rc = plan_build(p);
+    *scratch_bytes = p->reserved;
+    if (rc != SLG_OK) {
+        plan_free(p);
+        return rc;
+    }
+    slg_result *r = new (std::nothrow) slg_result();
+    if (!r) {
+        plan_free(p);
+        return fail(wctx, SLG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+    r->st = st;
+    r->k = num_s;
+    r->m = g->inc.num_hyperedges;
+    r->two_paths = p->two_paths;
+    AllocList outs;
+    for (int k = 0; k < num_s; ++k) {
+        r->num_edges[k] = p->num_edges[k];
+        outs.add(&r->row_ptr[k], r->m + 1);
+        outs.add(&r->row[k], p->num_edges[k]);
+        outs.add(&r->col[k], p->num_edges[k]);
+        outs.add(&r->w[k], p->num_edges[k]);
+    }
+    auto drop = [&](slg_status code) {
+        wctx->arena->put(r->owned, st);
+        delete r;
+        plan_free(p);  // also waits for the stream
+        return code;
+    };
+    if (!reserve(outs.bytes)) return drop(fail(wctx, SLG_ERR_OUT_OF_MEMORY, "device-memory budget refused"));
+    *output_bytes = outs.bytes;
+    for (const auto &a : outs.items) {
+        hipError_t e = wctx->arena->get(a.first, a.second, st);
+        if (e != hipSuccess)
+            return drop(fail(wctx, e == hipErrorOutOfMemory ? SLG_ERR_OUT_OF_MEMORY : SLG_ERR_DEVICE,
+                             "output allocation: %s", hipGetErrorString(e)));
+        r->owned.push_back(*a.first);
+    }
+    rc = slg_plan_emit(p, r->row_ptr, r->row, r->col, r->w, st);
+    if (rc != SLG_OK) return drop(rc);
+    plan_free(p);  // frees the scratch on `st` and waits for the stream: outputs are complete
+    r->arena = wctx->arena;
+    r->core = core;
+    r->bytes = outs.bytes;
+    *out = r;
+    return SLG_OK;
+}
+
+}  // namespace slg
+
+extern "C" {
 
 slg_status slg_result_info(const slg_result *r, int32_t k, int64_t *num_edges, int64_t *two_paths) {
     if (!r || k < 0 || k >= r->k) return SLG_ERR_INVALID_ARG;
@@ -1075,12 +1193,17 @@ slg_status slg_result_csr(const slg_result *r, int32_t k, const int64_t **row_pt
 
 slg_status slg_result_free(slg_result *r) {
     if (!r) return SLG_ERR_INVALID_ARG;
-    slg_context *ctx = r->ctx;
-    for (void *ptr : r->owned) {
-        if (ctx && ctx->has_alloc)
-            ctx->alloc.release(ctx->alloc.user, ptr, r->st);
-        else
-            (void)hipFreeAsync(ptr, r->st);
+    if (r->core) {  // a served result: reusable after the work queued on the null stream
+        r->arena->put(r->owned, nullptr);
+        r->core->release(r->bytes, true);
+        delete r;
+        return SLG_OK;
+    }
+    if (r->arena) {
+        r->arena->put(r->owned, r->st);
+    } else {
+        slg_context *ctx = r->ctx;
+        for (void *ptr : r->owned) ctx->alloc.release(ctx->alloc.user, ptr, r->st);
     }
     delete r;
     return SLG_OK;

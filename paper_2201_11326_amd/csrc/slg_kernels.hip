@@ -733,8 +733,10 @@ __device__ __forceinline__ int count_get(const uint32_t *cnt, int r) {
     return (int)((cnt[r >> 1] >> ((r & 1) << 4)) & 0xFFFFu);
 }
 
+// Two workgroups per CU (4 waves per SIMD) is what the LDS footprint allows;
+// the register budget is held to match (<= 128 VGPRs).
 template <bool EMIT, bool WIDE>
-__global__ __launch_bounds__(kHeavyThreads) void heavy_kernel(const HeavyDesc *__restrict__ desc,
+__global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4))) void heavy_kernel(const HeavyDesc *__restrict__ desc,
                                                               int64_t count, int64_t S,
                                                               const int32_t *__restrict__ bounds,
                                                               const int32_t *__restrict__ vs_idx,
@@ -1189,9 +1191,16 @@ int64_t scan_partials_size(int64_t n) { return (n + kScanTile - 1) / kScanTile +
 int heavy_resident(int device) {
     int cus = 0, per = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, heavy_kernel<true, false>, kHeavyThreads, 0) !=
-        hipSuccess)
-        per = 0;
+    // the grid is shared by every variant: take the least resident one
+    const void *variants[4] = {reinterpret_cast<const void *>(heavy_kernel<false, false>),
+                               reinterpret_cast<const void *>(heavy_kernel<false, true>),
+                               reinterpret_cast<const void *>(heavy_kernel<true, false>),
+                               reinterpret_cast<const void *>(heavy_kernel<true, true>)};
+    for (const void *f : variants) {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, f, kHeavyThreads, 0) != hipSuccess) v = 0;
+        per = (per == 0 || (v > 0 && v < per)) ? v : per;
+    }
     if (cus <= 0) cus = 256;
     if (per <= 0) per = 1;
     return cus * per;
