@@ -35,6 +35,14 @@ namespace {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Pointers that reach a kernel through LDS or a struct in memory lose their
+// address space; naming it keeps their accesses global_* (flat accesses also
+// count against the LDS wait counter, so every LDS wait would wait for them).
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *as_global(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 __device__ __forceinline__ int bits_below(unsigned long long mask) {
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
                                      __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
@@ -579,13 +587,14 @@ __global__ __launch_bounds__(256) void light_kernel(const int32_t *__restrict__ 
 
     const int K = ep->k;
     const int64_t S = sl.count;
-    const int id0 = ep->row_base ? ep->row_base[i] : 0;  // caller's id of row i is i - id0
+    const int id0 = ep->row_base ? as_global(ep->row_base)[i] : 0;  // caller's id of row i is i - id0
+    const int srow = ep->row_s ? as_global(ep->row_s)[i] : 0;
     for (int k = 0; k < K; ++k) {
-        const int sk = ep->row_s ? ep->row_s[i] : ep->s[k];
+        const int sk = ep->row_s ? srow : ep->s[k];
         int64_t base = EMIT ? slot_off[(int64_t)k * (S + 1) + slot] - ep->out_base[k] : 0;
-        int32_t *col = EMIT ? ep->col[k] : nullptr;
-        int32_t *wo = EMIT ? ep->w[k] : nullptr;
-        int32_t *ro = EMIT ? ep->row[k] : nullptr;
+        auto col = as_global(EMIT ? ep->col[k] : nullptr);
+        auto wo = as_global(EMIT ? ep->w[k] : nullptr);
+        auto ro = as_global(EMIT ? ep->row[k] : nullptr);
 #pragma unroll
         for (int r = 0; r < KPL; ++r) {
             const bool surv = c[r] >= sk;  // sk >= 1, so only run heads
@@ -623,6 +632,7 @@ struct HeavySmem {
     int32_t seg_a[kHeavyThreads];        // segment start per member of the batch
     int32_t seg_pre[kHeavyThreads + 1];  // flattened start per member of the batch
     int32_t wsum[kHW];
+    int32_t nrep;                        // pass-1 repeats (partners already marked)
     int32_t wtot[SLG_MAX_S][kHW];
     unsigned long long acc[SLG_MAX_S];
     long long obase[SLG_MAX_S];
@@ -680,8 +690,9 @@ __device__ __forceinline__ int segment_of(const int32_t *seg_pre, int lo, int hi
     return lo;
 }
 
-// Calls f(f_idx, j) for every partner of the laid-out segments, f_idx being
-// the position in the batch's flattened 2-path list. Each wavefront takes
+// Calls f(f_idx, j, valid) with every lane of the wavefront for every piece
+// of the laid-out segments (valid marks the lanes that hold a partner j,
+// f_idx being its position in the batch's flattened 2-path list). Each wavefront takes
 // an equal share of the list (so a heavy vertex's tail is shared by all
 // wavefronts) and walks it in pieces of 64*kWalkUnroll positions: every
 // lane finds the segment of each of its positions by binary search between
@@ -703,28 +714,118 @@ __device__ __forceinline__ void walk_segments(const int32_t *__restrict__ vs_idx
     for (int pb = c0; pb < c1; pb += 64 * kWalkUnroll) {
         const int plast = min(c1, pb + 64 * kWalkUnroll) - 1;
         const int ulast = segment_of(sm.seg_pre, ufirst, useg, plast);
-        int jr[kWalkUnroll];
+        // the lane's positions search [ufirst, ulast] in lockstep, with a
+        // fixed step count, so that their LDS reads overlap
+        int fq[kWalkUnroll], u[kWalkUnroll];
 #pragma unroll
         for (int r = 0; r < kWalkUnroll; ++r) {
-            const int fq = min(pb + lane + 64 * r, plast);
-            const int u = segment_of(sm.seg_pre, ufirst, ulast, fq);
-            jr[r] = vs_idx[sm.seg_a[u] + (fq - sm.seg_pre[u])];
+            fq[r] = min(pb + lane + 64 * r, plast);
+            u[r] = ufirst;
         }
+        for (int len = ulast - ufirst + 1; len > 1;) {
+            const int half = len >> 1;
+#pragma unroll
+            for (int r = 0; r < kWalkUnroll; ++r)
+                u[r] = sm.seg_pre[u[r] + half] <= fq[r] ? u[r] + half : u[r];
+            len -= half;
+        }
+        int jr[kWalkUnroll];
+#pragma unroll
+        for (int r = 0; r < kWalkUnroll; ++r) jr[r] = vs_idx[sm.seg_a[u[r]] + (fq[r] - sm.seg_pre[u[r]])];
 #pragma unroll
         for (int r = 0; r < kWalkUnroll; ++r) {
             const int fr = pb + lane + 64 * r;
-            if (fr <= plast) f(fr, jr[r]);
+            f(fr, jr[r], fr <= plast);
         }
         ufirst = ulast;
     }
 }
 
+// Pass 1 of a heavy slot: marks partner j of every laid-out 2-path in the
+// bitmap over [ja, ja + span). With RECORD, a 2-path whose partner was
+// already marked (a repeat) is appended to buf (up to cap entries; nrep
+// counts them all). The walk is that of walk_segments, with each piece's
+// atomics issued together and one list reservation per piece.
+template <bool RECORD>
+__device__ __forceinline__ void walk_mark(const int32_t *__restrict__ vs_idx, int total, int nseg, HeavySmem &sm,
+                                          int ja, unsigned span, int cap) {
+    if (total <= 0) return;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const int per = (total + kHW - 1) / kHW;
+    const int c0 = wave * per;
+    const int c1 = min(total, c0 + per);
+    if (c0 >= c1) return;
+    const int useg = min(nseg, kHeavyThreads) - 1;
+    int ufirst = segment_of(sm.seg_pre, 0, useg, c0);
+    for (int pb = c0; pb < c1; pb += 64 * kWalkUnroll) {
+        const int plast = min(c1, pb + 64 * kWalkUnroll) - 1;
+        const int ulast = segment_of(sm.seg_pre, ufirst, useg, plast);
+        int fq[kWalkUnroll], u[kWalkUnroll];
+#pragma unroll
+        for (int r = 0; r < kWalkUnroll; ++r) {
+            fq[r] = min(pb + lane + 64 * r, plast);
+            u[r] = ufirst;
+        }
+        for (int len = ulast - ufirst + 1; len > 1;) {
+            const int half = len >> 1;
+#pragma unroll
+            for (int r = 0; r < kWalkUnroll; ++r)
+                u[r] = sm.seg_pre[u[r] + half] <= fq[r] ? u[r] + half : u[r];
+            len -= half;
+        }
+        int jr[kWalkUnroll];
+#pragma unroll
+        for (int r = 0; r < kWalkUnroll; ++r) jr[r] = vs_idx[sm.seg_a[u[r]] + (fq[r] - sm.seg_pre[u[r]])];
+        // rows of the piece past its end are skipped; lanes past it OR
+        // nothing into a word of their own bank
+        unsigned bit[kWalkUnroll], old[kWalkUnroll];
+#pragma unroll
+        for (int r = 0; r < kWalkUnroll; ++r) {
+            bit[r] = 0u;
+            old[r] = 0u;
+            if (pb + 64 * r <= plast) {  // wave-uniform
+                const unsigned off = (unsigned)(jr[r] - ja);
+                const bool ok = pb + lane + 64 * r <= plast && off < span;
+                bit[r] = ok ? 1u << (off & 31) : 0u;
+                const unsigned word = ok ? off >> 5 : (unsigned)(lane & 31);
+                if (RECORD)
+                    old[r] = atomicOr(&sm.bitmap[word], bit[r]);
+                else
+                    atomicOr(&sm.bitmap[word], bit[r]);
+            }
+        }
+        if (RECORD) {
+            unsigned long long m[kWalkUnroll];
+            int tot = 0;
+#pragma unroll
+            for (int r = 0; r < kWalkUnroll; ++r) {
+                m[r] = __ballot((old[r] & bit[r]) != 0u);
+                tot += __popcll(m[r]);
+            }
+            if (tot) {  // wave-uniform
+                int at = 0;
+                if (lane == 0) at = atomicAdd(&sm.nrep, tot);
+                at = __builtin_amdgcn_readfirstlane(at);
+#pragma unroll
+                for (int r = 0; r < kWalkUnroll; ++r) {
+                    if ((old[r] & bit[r]) != 0u) {
+                        const int pos = at + bits_below(m[r]);
+                        if (pos < cap) sm.buf[pos] = jr[r];
+                    }
+                    at += __popcll(m[r]);
+                }
+            }
+        }
+        ufirst = ulast;
+    }
+}
+
+// Adds one to rank r's counter and returns the count it held before.
 template <bool WIDE>
-__device__ __forceinline__ void count_add(uint32_t *cnt, uint32_t r) {
-    if (WIDE)
-        atomicAdd(&cnt[r], 1u);
-    else
-        atomicAdd(&cnt[r >> 1], 1u << ((r & 1u) << 4));
+__device__ __forceinline__ int count_add_rtn(uint32_t *cnt, uint32_t r) {
+    if (WIDE) return (int)atomicAdd(&cnt[r], 1u);
+    const unsigned sh = (r & 1u) << 4;
+    return (int)((atomicAdd(&cnt[r >> 1], 1u << sh) >> sh) & 0xFFFFu);
 }
 
 template <bool WIDE>
@@ -747,120 +848,123 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
     constexpr int kCap = CounterCap<WIDE>::ranks;
     __shared__ HeavySmem sm;
     __shared__ EmitParams sp;  // thresholds and outputs, indexed by a uniform k
-    __shared__ int64_t next_slot;
+    __shared__ int64_t next_pair;  // first slot of the pair claimed to follow the current one
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     stage_params(&sp, prm);
-    if (tid == 0) next_slot = (int64_t)atomicAdd(ticket, 1ull);
+    if (tid == 0) next_pair = (int64_t)atomicAdd(ticket, 2ull);
     for (int x = tid; x < kRangeWords; x += kHeavyThreads) sm.bitmap[x] = 0u;
     for (int x = tid; x < kRankCap / 2; x += kHeavyThreads) sm.cnt[x] = 0u;
+    if (tid < SLG_MAX_S * kHW) sm.wtot[tid / kHW][tid % kHW] = 0;
     __syncthreads();
     const EmitParams *ep = &sp;
-    const int K = ep->k;
-    int64_t it = next_slot;
+    const int K = prm.k;
+    const bool row_thr = prm.row_s != nullptr;  // batched form: one threshold per row
+    int64_t pair = next_pair;  // first slot of the current pair
+    int64_t it = pair;         // the current slot
     if (it >= count) return;
 
-    // Persistent workgroups take slots from a ticket counter. Software
-    // pipeline: the next slot's descriptor and this thread's member segment
-    // are loaded while the current slot is processed.
+    // Persistent workgroups claim slots two at a time from a ticket counter.
+    // Software pipeline: the claim of the next pair is made during the
+    // first slot of the current pair and read one slot later; the next
+    // slot's descriptor, output bases, per-row values and this thread's
+    // member segment are loaded while the current slot is processed.
     HeavyDesc nd = desc[it];
-    int na = 0, nb = 0;
-    if (tid < nd.k) {
-        na = bounds[nd.bptr + tid];
-        nb = bounds[nd.bptr + nd.k + tid];
-    }
+    int na = 0, nb = 0, nsrow = 0, nid0 = 0;
+    int64_t nob = 0;
+    auto prefetch = [&](const HeavyDesc &n) {
+        if (tid < n.k) {
+            na = bounds[n.bptr + tid];
+            nb = bounds[n.bptr + n.k + tid];
+        }
+        if (EMIT && tid < K) nob = slot_off[(int64_t)tid * (S + 1) + n.slot] - ep->out_base[tid];
+        if (ep->row_s) nsrow = as_global(ep->row_s)[n.row];  // per-row threshold (batched form)
+        if (ep->row_base) nid0 = as_global(ep->row_base)[n.row];
+    };
+    prefetch(nd);
+    unsigned long long claim = 0;  // tid 0's claim of the next pair
     while (true) {
         const HeavyDesc d = nd;
-        const int ra = na, rb = nb;
-        if (tid == 0) next_slot = (int64_t)atomicAdd(ticket, 1ull);
+        const int ra = na, rb = nb, srow = nsrow, id0 = nid0;
+        const bool first = it == pair;
+        if (first && tid == 0) claim = atomicAdd(ticket, 2ull);  // read at the end of this slot
 
         const int i = d.row, ja = d.ja, jb = d.jb, k = d.k, slot = d.slot;
-        const int srow = ep->row_s ? ep->row_s[i] : 0;  // per-row threshold (batched form)
-        const int id0 = ep->row_base ? ep->row_base[i] : 0;
-        const bool only_presence = !EMIT && K == 1 && (ep->row_s ? srow : ep->s[0]) <= 1;
+        const int s_bottom = row_thr ? srow : ep->s[0];   // smallest and largest threshold
+        const int s_top = row_thr ? srow : ep->s[K - 1];
+        const bool only_presence = !EMIT && K == 1 && s_bottom <= 1;
         const int nw = (jb - ja + 31) >> 5;
         const unsigned span = (unsigned)(jb - ja);
         // bitmap and counters are all-zero here: cleared before the first
         // slot and at the end of every slot
         if (tid < SLG_MAX_S) {
             sm.acc[tid] = 0;
-            sm.obase[tid] = (EMIT && tid < K) ? slot_off[(int64_t)tid * (S + 1) + slot] - ep->out_base[tid] : 0;
+            sm.obase[tid] = (EMIT && tid < K) ? nob : 0;
         }
+        if (tid == 0) sm.nrep = 0;
         __syncthreads();
-        const int64_t it_next = next_slot;
+        // the pair's second slot, else the first of the claimed pair (published
+        // at the end of the current pair's first slot)
+        const int64_t it_next = first ? (it + 1 < count ? it + 1 : count) : next_pair;
         const bool have_next = it_next < count;
         if (have_next) nd = desc[it_next];
+        bool acc_out = !EMIT;  // slot_cnt takes the per-threshold tallies
+        do {
         if (EMIT && (slot < ep->slot_lo || slot >= ep->slot_hi)) {  // outside the emitted chunk
-            if (have_next && tid < nd.k) {
-                na = bounds[nd.bptr + tid];
-                nb = bounds[nd.bptr + nd.k + tid];
-            }
-            __syncthreads();  // next_slot is rewritten at the top of the loop
-            if (!have_next) break;
-            continue;
+            if (have_next) prefetch(nd);
+            break;
         }
 
-        // pass 1: mark every partner j of the slot's range; keep the partners
-        // in LDS when they fit, so that pass 2 reads no global memory
+        // pass 1: mark every partner j of the slot's range. A 2-path whose
+        // partner was already marked is a repeat; repeats are listed in LDS
+        // (while they fit), so that pass 2 only has to count them: a
+        // partner's overlap is 1 + its number of repeats.
         const bool one_batch = k <= kHeavyThreads;
         int total1 = 0;
-        bool cached = false;
-        auto mark = [&](int, int j) {
-            const unsigned off = (unsigned)(j - ja);
-            if (off < span) atomicOr(&sm.bitmap[off >> 5], 1u << (off & 31));
-        };
         if (one_batch) {
             const int len = (tid < k && rb > ra) ? rb - ra : 0;
             total1 = layout_segments(ra, len, sm);
-            cached = total1 <= kRankCap;
-            if (cached)
-                walk_segments(vs_idx, total1, k, sm, [&](int f, int j) {
-                    sm.buf[f] = j;
-                    mark(f, j);
-                });
-            else
-                walk_segments(vs_idx, total1, k, sm, mark);
+            walk_mark<true>(vs_idx, total1, k, sm, ja, span, kRankCap);
             __syncthreads();
         } else {
             for (int qb = 0; qb < k; qb += kHeavyThreads) {
                 int a, len;
                 member_segment<false>(vs_idx, bounds, d.bptr, k, qb, 0, 0, a, len);
-                walk_segments(vs_idx, layout_segments(a, len, sm), k - qb, sm, mark);
+                walk_mark<false>(vs_idx, layout_segments(a, len, sm), k - qb, sm, ja, span, 0);
                 __syncthreads();
             }
         }
-        if (have_next && tid < nd.k) {  // prefetch the next slot's segments
-            na = bounds[nd.bptr + tid];
-            nb = bounds[nd.bptr + nd.k + tid];
-        }
+        if (have_next) prefetch(nd);
 
-        // rank of a partner = number of marked partners below it
-        constexpr int kWPT = kRangeWords / kHeavyThreads;
-        int loc[kWPT];
+        // rank of a partner = number of marked partners below it. Each thread
+        // owns 8 consecutive bitmap words, read and written 16 bytes at a time
+        // (words past the slot's range are zero).
+        static_assert(kRangeWords == 8 * kHeavyThreads, "8 bitmap words per thread");
+        const uint4 q0 = reinterpret_cast<const uint4 *>(sm.bitmap)[2 * tid];
+        const uint4 q1 = reinterpret_cast<const uint4 *>(sm.bitmap)[2 * tid + 1];
+        const int loc[8] = {(int)__popc(q0.x), (int)__popc(q0.y), (int)__popc(q0.z), (int)__popc(q0.w),
+                            (int)__popc(q1.x), (int)__popc(q1.y), (int)__popc(q1.z), (int)__popc(q1.w)};
         int mine = 0;
 #pragma unroll
-        for (int r = 0; r < kWPT; ++r) {
-            const int x = tid * kWPT + r;
-            loc[r] = x < nw ? __popc(sm.bitmap[x]) : 0;
-            mine += loc[r];
-        }
+        for (int r = 0; r < 8; ++r) mine += loc[r];
         int distinct;
         int run = block_excl_scan_open<kHeavyThreads>(mine, sm.wsum, distinct);
+        if ((tid * 8) % kSuperWords == 0) sm.sup[tid * 8 / kSuperWords] = (uint32_t)run;
+        uint32_t pk[4];
 #pragma unroll
-        for (int r = 0; r < kWPT; ++r) {
-            const int x = tid * kWPT + r;
-            sm.wpre[x] = (uint16_t)run;
-            if ((x % kSuperWords) == 0) sm.sup[x / kSuperWords] = (uint32_t)run;
-            run += loc[r];
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t lo = (uint32_t)run & 0xFFFFu;
+            run += loc[2 * r];
+            pk[r] = lo | (((uint32_t)run & 0xFFFFu) << 16);
+            run += loc[2 * r + 1];
         }
+        reinterpret_cast<uint4 *>(sm.wpre)[tid] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
         if (tid == 0) sm.sup[kSupers] = (uint32_t)distinct;
         __syncthreads();
 
         if (only_presence) {  // L_1 alone: every marked partner is an edge
             if (tid == 0) slot_cnt[slot] = distinct;
-            for (int x = tid; x < nw; x += kHeavyThreads) sm.bitmap[x] = 0u;
-            __syncthreads();
-            if (!have_next) break;
-            continue;
+            acc_out = false;
+            break;
         }
 
         // windows of at most kCap ranks, cut at word boundaries
@@ -880,26 +984,54 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
             const int nr = (int)((w1 == nw ? (uint32_t)distinct : word_rank(sm, w1)) - r0);
             if (nr > 0) {
                 const int nwords = WIDE ? nr : (nr + 1) >> 1;
-                // pass 2: count every 2-path into its partner's rank
-                auto add = [&](int, int j) {
+                // every wavefront owns a contiguous range of ranks
+                const int per = (((nr + kHW - 1) / kHW) + 63) & ~63;
+                const int rlo = wave * per;
+                const int rhi = min(nr, rlo + per);
+                const bool whole = w0 == 0 && w1 == nw;
+                // the repeat list serves every window of the counting pass, and
+                // the single window of the emit pass (whose rank-to-partner map
+                // reuses the list's storage afterwards)
+                const int nrep = sm.nrep;
+                const bool by_repeats = one_batch && nrep <= kRankCap && (whole || !EMIT);
+                const int c_add = by_repeats ? 1 : 0;  // partners start at overlap 1
+                // pass 2: count 2-paths into their partner's rank. The overlap of
+                // a partner passes every value up to its final one exactly once,
+                // so the 2-path that takes it to s_k makes it a survivor of
+                // threshold k: one tally for the wavefront that owns its rank.
+                auto add = [&](int, int j, bool valid) {
                     const unsigned off = (unsigned)(j - ja);
-                    if (off >= span) return;
+                    if (!valid || off >= span) return;
                     const int x = (int)(off >> 5);
                     const uint32_t r = word_rank(sm, x) + __popc(sm.bitmap[x] & ((1u << (off & 31)) - 1u)) - r0;
-                    if (r < (uint32_t)nr) count_add<WIDE>(sm.cnt, r);
+                    if (r >= (uint32_t)nr) return;
+                    const int reached = count_add_rtn<WIDE>(sm.cnt, r) + 1 + c_add;
+                    if (reached > s_top) return;
+                    int hit = -1;
+                    if (row_thr) {
+                        hit = reached == srow ? 0 : -1;
+                    } else {
+                        for (int kk = 0; kk < K; ++kk) {
+                            const int s = ep->s[kk];
+                            if (s >= reached) {
+                                hit = s == reached ? kk : -1;
+                                break;
+                            }
+                        }
+                    }
+                    if (hit >= 0) atomicAdd(&sm.wtot[hit][r / per], 1);
                 };
-                const bool whole = w0 == 0 && w1 == nw;
-                if (cached && (whole || !EMIT)) {
+                if (by_repeats) {
                     int f = tid;
-                    for (; f + 3 * kHeavyThreads < total1; f += 4 * kHeavyThreads) {
+                    for (; f + 3 * kHeavyThreads < nrep; f += 4 * kHeavyThreads) {
                         const int j0 = sm.buf[f], j1 = sm.buf[f + kHeavyThreads];
                         const int j2 = sm.buf[f + 2 * kHeavyThreads], j3 = sm.buf[f + 3 * kHeavyThreads];
-                        add(f, j0);
-                        add(f, j1);
-                        add(f, j2);
-                        add(f, j3);
+                        add(f, j0, true);
+                        add(f, j1, true);
+                        add(f, j2, true);
+                        add(f, j3, true);
                     }
-                    for (; f < total1; f += kHeavyThreads) add(f, sm.buf[f]);
+                    for (; f < nrep; f += kHeavyThreads) add(f, sm.buf[f], true);
                     __syncthreads();
                 } else if (one_batch && whole) {
                     walk_segments(vs_idx, total1, k, sm, add);  // segments of pass 1 still laid out
@@ -914,7 +1046,9 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
                         __syncthreads();
                     }
                 }
-                if (EMIT) {
+                // threshold 1 over the repeat list: every rank survives
+                if (c_add && lane == 0 && s_bottom == 1) sm.wtot[0][wave] = rhi > rlo ? rhi - rlo : 0;
+                if (EMIT) {  // partner of every rank
                     for (int x = w0 + tid; x < w1; x += kHeavyThreads) {
                         unsigned bits = sm.bitmap[x];
                         int r = (int)(word_rank(sm, x) - r0);
@@ -924,77 +1058,60 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
                             bits &= bits - 1u;
                         }
                     }
-                    __syncthreads();
                 }
-                // threshold per s_k over this wavefront's contiguous ranks:
-                // every counter is read once and tested against all of S;
-                // the per-threshold tallies are wave-uniform
-                const int per = (((nr + kHW - 1) / kHW) + 63) & ~63;
-                const int rlo = wave * per;
-                const int rhi = min(nr, rlo + per);
-                int tally[SLG_MAX_S];
-#pragma unroll
-                for (int kk = 0; kk < SLG_MAX_S; ++kk) tally[kk] = 0;
-                for (int rbase = rlo; rbase < rhi; rbase += 64) {
-                    const int r = rbase + lane;
-                    const int c = r < rhi ? count_get<WIDE>(sm.cnt, r) : 0;
-#pragma unroll
-                    for (int kk = 0; kk < SLG_MAX_S; ++kk)
-                        if (kk < K) tally[kk] += __popcll(__ballot(c >= (ep->row_s ? srow : ep->s[kk])));
-                }
+                __syncthreads();
                 if (EMIT) {
-                    if (lane == 0)
-                        for (int kk = 0; kk < K; ++kk) sm.wtot[kk][wave] = tally[kk];
-                    __syncthreads();
-                    int64_t base[SLG_MAX_S];
-#pragma unroll
-                    for (int kk = 0; kk < SLG_MAX_S; ++kk) {
-                        base[kk] = 0;
-                        if (kk < K) {
-                            base[kk] = sm.obase[kk];
-                            for (int w = 0; w < wave; ++w) base[kk] += sm.wtot[kk][w];
-                        }
-                    }
-                    for (int rbase = rlo; rbase < rhi; rbase += 64) {
-                        const int r = rbase + lane;
-                        const bool valid = r < rhi;
-                        const int c = valid ? count_get<WIDE>(sm.cnt, r) : 0;
-                        const int key = valid ? sm.buf[r] : 0;
-#pragma unroll
-                        for (int kk = 0; kk < SLG_MAX_S; ++kk) {
-                            if (kk >= K) break;
-                            const bool surv = c >= (ep->row_s ? srow : ep->s[kk]);
+                    // per threshold, this wavefront's survivors in rank order,
+                    // compacted with ballots into consecutive positions
+                    for (int kk = 0; kk < K; ++kk) {
+                        int left = sm.wtot[kk][wave];
+                        if (left == 0) continue;
+                        const int sk = row_thr ? srow : ep->s[kk];
+                        int64_t base = sm.obase[kk];
+                        for (int w = 0; w < wave; ++w) base += sm.wtot[kk][w];
+                        const auto colp = as_global(ep->col[kk]);
+                        const auto wp = as_global(ep->w[kk]);
+                        const auto rowp = as_global(ep->row[kk]);
+                        for (int rbase = rlo; rbase < rhi && left > 0; rbase += 64) {
+                            const int r = rbase + lane;
+                            const int c = r < rhi ? count_get<WIDE>(sm.cnt, r) + c_add : 0;
+                            const bool surv = c >= sk;
                             const unsigned long long mask = __ballot(surv);
                             if (surv) {
-                                const int64_t pos = base[kk] + bits_below(mask);
-                                ep->col[kk][pos] = key - id0;
-                                ep->w[kk][pos] = c;
-                                int32_t *ro = ep->row[kk];
-                                if (ro) ro[pos] = i - id0;
+                                const int64_t pos = base + bits_below(mask);
+                                colp[pos] = sm.buf[r] - id0;
+                                wp[pos] = c;
+                                if (rowp) rowp[pos] = i - id0;
                             }
-                            base[kk] += __popcll(mask);
+                            base += __popcll(mask);
+                            left -= __popcll(mask);
                         }
                     }
                     __syncthreads();
-                    if (tid < K) {
-                        int tot = 0;
-                        for (int w = 0; w < kHW; ++w) tot += sm.wtot[tid][w];
+                }
+                if (tid < K) {  // each threshold's total is kept by one thread
+                    int tot = 0;
+                    for (int w = 0; w < kHW; ++w) tot += sm.wtot[tid][w];
+                    if (EMIT)
                         sm.obase[tid] += tot;
-                    }
-                } else if (lane == 0) {
-                    for (int kk = 0; kk < K; ++kk)
-                        if (tally[kk]) atomicAdd(&sm.acc[kk], (unsigned long long)tally[kk]);
+                    else
+                        sm.acc[tid] += (unsigned long long)tot;
                 }
                 __syncthreads();
                 for (int x = tid; x < nwords; x += kHeavyThreads) sm.cnt[x] = 0u;
+                if (tid < SLG_MAX_S * kHW) sm.wtot[tid / kHW][tid % kHW] = 0;
                 if (w1 < nw) __syncthreads();  // the next window counts into cleared counters
             }
             w0 = w1;
         }
+        } while (false);
         for (int x = tid; x < nw; x += kHeavyThreads) sm.bitmap[x] = 0u;
+        if (first && tid == 0) next_pair = (int64_t)claim;
         __syncthreads();
-        if (!EMIT && tid < K) slot_cnt[(int64_t)tid * S + slot] = (int64_t)sm.acc[tid];
+        if (acc_out && tid < K) slot_cnt[(int64_t)tid * S + slot] = (int64_t)sm.acc[tid];
         if (!have_next) break;
+        if (!first) pair = it_next;
+        it = it_next;
     }
 }
 
@@ -1058,7 +1175,7 @@ __global__ void row_ptr_kernel(int64_t row_lo, int64_t row_hi, const int64_t *__
     if (i > row_hi) return;
     const int64_t sb = slot_base[i];
     for (int k = 0; k < sp.k; ++k)
-        sp.row_ptr[k][i - row_lo] = slot_off[(int64_t)k * (S + 1) + sb] - sp.out_base[k];
+        as_global(sp.row_ptr[k])[i - row_lo] = slot_off[(int64_t)k * (S + 1) + sb] - sp.out_base[k];
 }
 
 // Output bytes of rows [0, i) over all thresholds, i in [0, m].
@@ -1151,15 +1268,15 @@ __global__ __launch_bounds__(256) void union_kernel(const UnionPart *__restrict_
     const UnionPart u = parts[blockIdx.y];
     const int64_t lim = max(max(u.m + 1, u.n + 1), u.nnz);
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < lim; t += (int64_t)gridDim.x * blockDim.x) {
-        if (t <= u.m) he_ptr[u.m_off + t] = u.he_ptr[t] + u.nnz_off;  // the shared end entry agrees
+        if (t <= u.m) he_ptr[u.m_off + t] = as_global(u.he_ptr)[t] + u.nnz_off;  // the shared end entry agrees
         if (t < u.m) {
             row_s[u.m_off + t] = u.s;
             row_base[u.m_off + t] = (int32_t)u.m_off;
         }
-        if (t <= u.n) v_ptr[u.n_off + t] = u.v_ptr[t] + u.nnz_off;
+        if (t <= u.n) v_ptr[u.n_off + t] = as_global(u.v_ptr)[t] + u.nnz_off;
         if (t < u.nnz) {
-            he_idx[u.nnz_off + t] = u.he_idx[t] + (int32_t)u.n_off;
-            v_idx[u.nnz_off + t] = u.v_idx[t] + (int32_t)u.m_off;
+            he_idx[u.nnz_off + t] = as_global(u.he_idx)[t] + (int32_t)u.n_off;
+            v_idx[u.nnz_off + t] = as_global(u.v_idx)[t] + (int32_t)u.m_off;
         }
     }
 }

@@ -110,6 +110,31 @@ def test_heavy_work_split_sampled(ctx):
     assert outs[1].num_edges == 4000 * 3999 // 2  # the planted clique, overlap 20
 
 
+@pytest.mark.parametrize("tune", [(0, 1 << 24, 0), (256, 1 << 24, 8), (0, 1024, 0)])
+def test_heavy_repeat_list_and_windows_under_tuning(ctx, tune):
+    # slot_work 2^24 leaves each heavy row in one slot (split by id range
+    # only): a shared 30-vertex core makes > 8,192 repeated 2-paths per slot
+    # (the repeat list overflows) over > 8,192 partners (several rank
+    # windows); 20 random members over 300 vertices give the first rows
+    # ~8,800 distinct partners and ~7,200 repeats (the list serves the
+    # counting windows, the emit pass re-walks)
+    core = planted(9000, 3000, [(list(range(30)), 1, 0)], 5, seed=31)
+    spread = hg.random_small(32, m=12000, n=300, kmax=20, kmin=20)
+    ctx.set_tuning(*tune)
+    try:
+        for inc, s_list, what in ((core, [1, 30, 31], "core"), (spread, [1, 2, 3], "spread")):
+            outs = run_gpu(ctx, inc, s_list)
+            rows = np.unique(np.concatenate([np.arange(0, 48), np.arange(0, inc.m, inc.m // 40),
+                                             [inc.m - 2, inc.m - 1]]))
+            for lg in outs:
+                assert_well_formed(inc, lg, lg.s)
+                assert_rows_match_oracle(inc, lg, lg.s, rows, f"{what} tune={tune}")
+                if what == "core" and lg.s == 30:
+                    assert lg.num_edges == 9000 * 8999 // 2  # the core alone gives overlap >= 30
+    finally:
+        ctx.set_tuning()
+
+
 def test_edge_cases(ctx):
     empty = hg.from_rows([], n=0)
     (lg,) = run_gpu(ctx, empty, [1])
