@@ -636,6 +636,8 @@ struct HeavySmem {
     int32_t wtot[SLG_MAX_S][kHW];
     unsigned long long acc[SLG_MAX_S];
     long long obase[SLG_MAX_S];
+    long long wbase[SLG_MAX_S][kHW];     // output position of each wavefront's first survivor
+    uint8_t thr_of[256];                 // threshold index of an overlap value (0xFF: none)
 };
 
 // Rank of the first bit of word x (x < number of words in use).
@@ -855,6 +857,9 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
     for (int x = tid; x < kRangeWords; x += kHeavyThreads) sm.bitmap[x] = 0u;
     for (int x = tid; x < kRankCap / 2; x += kHeavyThreads) sm.cnt[x] = 0u;
     if (tid < SLG_MAX_S * kHW) sm.wtot[tid / kHW][tid % kHW] = 0;
+    if (tid < 256) sm.thr_of[tid] = 0xFF;
+    __syncthreads();
+    if (tid < prm.k && prm.s[tid] < 256) sm.thr_of[prm.s[tid]] = (uint8_t)tid;
     __syncthreads();
     const EmitParams *ep = &sp;
     const int K = prm.k;
@@ -948,6 +953,7 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
         for (int r = 0; r < 8; ++r) mine += loc[r];
         int distinct;
         int run = block_excl_scan_open<kHeavyThreads>(mine, sm.wsum, distinct);
+        const int run0 = run;  // rank of this thread's first marked partner
         if ((tid * 8) % kSuperWords == 0) sm.sup[tid * 8 / kSuperWords] = (uint32_t)run;
         uint32_t pk[4];
 #pragma unroll
@@ -1010,6 +1016,9 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
                     int hit = -1;
                     if (row_thr) {
                         hit = reached == srow ? 0 : -1;
+                    } else if (reached < 256) {
+                        const int t = sm.thr_of[reached];
+                        hit = t == 0xFF ? -1 : t;
                     } else {
                         for (int kk = 0; kk < K; ++kk) {
                             const int s = ep->s[kk];
@@ -1048,54 +1057,75 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
                 }
                 // threshold 1 over the repeat list: every rank survives
                 if (c_add && lane == 0 && s_bottom == 1) sm.wtot[0][wave] = rhi > rlo ? rhi - rlo : 0;
-                if (EMIT) {  // partner of every rank
-                    for (int x = w0 + tid; x < w1; x += kHeavyThreads) {
-                        unsigned bits = sm.bitmap[x];
-                        int r = (int)(word_rank(sm, x) - r0);
-                        const int jbase = ja + 32 * x;
-                        while (bits) {
-                            sm.buf[r++] = jbase + __ffs(bits) - 1;
-                            bits &= bits - 1u;
+                if (EMIT) {  // partner of every rank, from this thread's own 8 words
+                    const uint32_t wd[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+                    int r = run0 - (int)r0;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int x = tid * 8 + q;
+                        unsigned bits = wd[q];
+                        if (x >= w0 && x < w1) {
+                            const int jbase = ja + 32 * x;
+                            int rr = r;
+                            while (bits) {
+                                sm.buf[rr++] = jbase + __ffs(bits) - 1;
+                                bits &= bits - 1u;
+                            }
                         }
+                        r += loc[q];
                     }
                 }
                 __syncthreads();
+                if (tid < K) {  // each threshold's wavefront offsets and total, by one thread
+                    long long b = EMIT ? sm.obase[tid] : 0;
+#pragma unroll
+                    for (int w = 0; w < kHW; ++w) {
+                        if (EMIT) sm.wbase[tid][w] = b;
+                        b += sm.wtot[tid][w];
+                    }
+                    if (EMIT)
+                        sm.obase[tid] = b;
+                    else
+                        sm.acc[tid] += (unsigned long long)b;
+                }
                 if (EMIT) {
+                    __syncthreads();
                     // per threshold, this wavefront's survivors in rank order,
                     // compacted with ballots into consecutive positions
                     for (int kk = 0; kk < K; ++kk) {
                         int left = sm.wtot[kk][wave];
                         if (left == 0) continue;
                         const int sk = row_thr ? srow : ep->s[kk];
-                        int64_t base = sm.obase[kk];
-                        for (int w = 0; w < wave; ++w) base += sm.wtot[kk][w];
+                        int64_t base = sm.wbase[kk][wave];
                         const auto colp = as_global(ep->col[kk]);
                         const auto wp = as_global(ep->w[kk]);
                         const auto rowp = as_global(ep->row[kk]);
-                        for (int rbase = rlo; rbase < rhi && left > 0; rbase += 64) {
-                            const int r = rbase + lane;
-                            const int c = r < rhi ? count_get<WIDE>(sm.cnt, r) + c_add : 0;
-                            const bool surv = c >= sk;
-                            const unsigned long long mask = __ballot(surv);
-                            if (surv) {
-                                const int64_t pos = base + bits_below(mask);
-                                colp[pos] = sm.buf[r] - id0;
-                                wp[pos] = c;
+                        // two groups of 64 ranks per step: their LDS reads overlap
+                        for (int rbase = rlo; rbase < rhi && left > 0; rbase += 128) {
+                            const int ra_ = rbase + lane, rb_ = rbase + 64 + lane;
+                            const int ca = ra_ < rhi ? count_get<WIDE>(sm.cnt, ra_) + c_add : 0;
+                            const int cb = rb_ < rhi ? count_get<WIDE>(sm.cnt, rb_) + c_add : 0;
+                            const bool sa = ca >= sk, sb = cb >= sk;
+                            const int ka_ = sa ? sm.buf[ra_] : 0;
+                            const int kb_ = sb ? sm.buf[rb_] : 0;
+                            const unsigned long long ma = __ballot(sa), mb = __ballot(sb);
+                            const int na_ = __popcll(ma);
+                            if (sa) {
+                                const int64_t pos = base + bits_below(ma);
+                                colp[pos] = ka_ - id0;
+                                wp[pos] = ca;
                                 if (rowp) rowp[pos] = i - id0;
                             }
-                            base += __popcll(mask);
-                            left -= __popcll(mask);
+                            if (sb) {
+                                const int64_t pos = base + na_ + bits_below(mb);
+                                colp[pos] = kb_ - id0;
+                                wp[pos] = cb;
+                                if (rowp) rowp[pos] = i - id0;
+                            }
+                            base += na_ + __popcll(mb);
+                            left -= na_ + __popcll(mb);
                         }
                     }
-                    __syncthreads();
-                }
-                if (tid < K) {  // each threshold's total is kept by one thread
-                    int tot = 0;
-                    for (int w = 0; w < kHW; ++w) tot += sm.wtot[tid][w];
-                    if (EMIT)
-                        sm.obase[tid] += tot;
-                    else
-                        sm.acc[tid] += (unsigned long long)tot;
                 }
                 __syncthreads();
                 for (int x = tid; x < nwords; x += kHeavyThreads) sm.cnt[x] = 0u;
