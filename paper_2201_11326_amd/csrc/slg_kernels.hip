@@ -743,11 +743,30 @@ __device__ __forceinline__ void walk_segments(const int32_t *__restrict__ vs_idx
     }
 }
 
+// Largest u in [lo, hi] with seg_pre[u] <= f, for wave-uniform lo, hi and f
+// (seg_pre[lo] <= f): every lane tests one of 64 evenly spaced candidates,
+// so 512 segments take two LDS round trips.
+__device__ __forceinline__ int wave_segment_of(const int32_t *seg_pre, int lo, int hi, int f) {
+    const int lane = lane_id();
+    while (hi > lo) {
+        const int step = (hi - lo + 64) / 64;
+        const int cand = lo + lane * step;
+        const bool ok = cand <= hi && seg_pre[cand] <= f;
+        lo += (__popcll(__ballot(ok)) - 1) * step;  // the candidates that pass form a prefix
+        hi = min(hi, lo + step - 1);
+    }
+    return lo;
+}
+
 // Pass 1 of a heavy slot: marks partner j of every laid-out 2-path in the
 // bitmap over [ja, ja + span). With RECORD, a 2-path whose partner was
 // already marked (a repeat) is appended to buf (up to cap entries; nrep
 // counts them all). The walk is that of walk_segments, with each piece's
 // atomics issued together and one list reservation per piece.
+// Pass 1 takes twice the positions per lane of the other walks: its
+// registers are not live together with the emit loop's.
+constexpr int kMarkUnroll = 8;
+
 template <bool RECORD>
 __device__ __forceinline__ void walk_mark(const int32_t *__restrict__ vs_idx, int total, int nseg, HeavySmem &sm,
                                           int ja, unsigned span, int cap) {
@@ -758,31 +777,31 @@ __device__ __forceinline__ void walk_mark(const int32_t *__restrict__ vs_idx, in
     const int c1 = min(total, c0 + per);
     if (c0 >= c1) return;
     const int useg = min(nseg, kHeavyThreads) - 1;
-    int ufirst = segment_of(sm.seg_pre, 0, useg, c0);
-    for (int pb = c0; pb < c1; pb += 64 * kWalkUnroll) {
-        const int plast = min(c1, pb + 64 * kWalkUnroll) - 1;
-        const int ulast = segment_of(sm.seg_pre, ufirst, useg, plast);
-        int fq[kWalkUnroll], u[kWalkUnroll];
+    int ufirst = wave_segment_of(sm.seg_pre, 0, useg, c0);
+    for (int pb = c0; pb < c1; pb += 64 * kMarkUnroll) {
+        const int plast = min(c1, pb + 64 * kMarkUnroll) - 1;
+        const int ulast = wave_segment_of(sm.seg_pre, ufirst, useg, plast);
+        int fq[kMarkUnroll], u[kMarkUnroll];
 #pragma unroll
-        for (int r = 0; r < kWalkUnroll; ++r) {
+        for (int r = 0; r < kMarkUnroll; ++r) {
             fq[r] = min(pb + lane + 64 * r, plast);
             u[r] = ufirst;
         }
         for (int len = ulast - ufirst + 1; len > 1;) {
             const int half = len >> 1;
 #pragma unroll
-            for (int r = 0; r < kWalkUnroll; ++r)
+            for (int r = 0; r < kMarkUnroll; ++r)
                 u[r] = sm.seg_pre[u[r] + half] <= fq[r] ? u[r] + half : u[r];
             len -= half;
         }
-        int jr[kWalkUnroll];
+        int jr[kMarkUnroll];
 #pragma unroll
-        for (int r = 0; r < kWalkUnroll; ++r) jr[r] = vs_idx[sm.seg_a[u[r]] + (fq[r] - sm.seg_pre[u[r]])];
+        for (int r = 0; r < kMarkUnroll; ++r) jr[r] = vs_idx[sm.seg_a[u[r]] + (fq[r] - sm.seg_pre[u[r]])];
         // rows of the piece past its end are skipped; lanes past it OR
         // nothing into a word of their own bank
-        unsigned bit[kWalkUnroll], old[kWalkUnroll];
+        unsigned bit[kMarkUnroll], old[kMarkUnroll];
 #pragma unroll
-        for (int r = 0; r < kWalkUnroll; ++r) {
+        for (int r = 0; r < kMarkUnroll; ++r) {
             bit[r] = 0u;
             old[r] = 0u;
             if (pb + 64 * r <= plast) {  // wave-uniform
@@ -797,10 +816,10 @@ __device__ __forceinline__ void walk_mark(const int32_t *__restrict__ vs_idx, in
             }
         }
         if (RECORD) {
-            unsigned long long m[kWalkUnroll];
+            unsigned long long m[kMarkUnroll];
             int tot = 0;
 #pragma unroll
-            for (int r = 0; r < kWalkUnroll; ++r) {
+            for (int r = 0; r < kMarkUnroll; ++r) {
                 m[r] = __ballot((old[r] & bit[r]) != 0u);
                 tot += __popcll(m[r]);
             }
@@ -809,7 +828,7 @@ __device__ __forceinline__ void walk_mark(const int32_t *__restrict__ vs_idx, in
                 if (lane == 0) at = atomicAdd(&sm.nrep, tot);
                 at = __builtin_amdgcn_readfirstlane(at);
 #pragma unroll
-                for (int r = 0; r < kWalkUnroll; ++r) {
+                for (int r = 0; r < kMarkUnroll; ++r) {
                     if ((old[r] & bit[r]) != 0u) {
                         const int pos = at + bits_below(m[r]);
                         if (pos < cap) sm.buf[pos] = jr[r];
