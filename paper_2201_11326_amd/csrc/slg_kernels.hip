@@ -266,14 +266,77 @@ __device__ __forceinline__ int light_class(int64_t w) {
     return c;
 }
 
+// Per-row work estimate (Section III-E's cost: the 2-paths of row i) and
+// tier, one lane per row for rows of at most kSmallRow members (their
+// members are walked serially), one wavefront per larger row. For every
+// incidence (i, v) of a kept row: tail_beg = first position after i in v's
+// (pruned) list; w_i = sum of the tails; jm = largest partner id.
+constexpr int kSmallRow = 16;
+
+struct RowPlanOut {
+    int32_t *tail_beg;
+    int64_t *work;
+    int32_t *jmax;
+    int32_t *nslots;
+    uint8_t *rclass;
+    int64_t *bsize;
+};
+
+// One member of row i: its tail in v's list; returns false when the
+// incidence is malformed.
+__device__ __forceinline__ bool plan_member(const Pruned &g, int64_t i, int64_t p, int32_t *tail_beg, int64_t &w,
+                                            int &jm) {
+    const int v = g.he_idx[p];
+    if (v < 0 || v >= g.n) {
+        tail_beg[p] = 0;
+        return false;
+    }
+    const int64_t lo = g.vs_ptr[v], hi = g.vs_ptr[v + 1];
+    if (lo < 0 || hi < lo || hi > g.nnz) {
+        tail_beg[p] = 0;
+        return false;
+    }
+    const int a = lower_bound_i32(g.vs_idx, (int)lo, (int)hi, (int)i);
+    const bool found = a < hi && g.vs_idx[a] == (int)i;  // the vertex CSR must be the transpose
+    const int beg = found ? a + 1 : a;
+    tail_beg[p] = beg;
+    w += hi - beg;
+    if (beg < hi) jm = max(jm, g.vs_idx[hi - 1]);
+    return found;
+}
+
+// Tier, slot count and boundary-table size of row i from its totals.
+__device__ __forceinline__ void plan_finish(int64_t i, int64_t p0, int64_t p1, int64_t w, int jm, bool bad,
+                                            int32_t light_max, int64_t slot_work, const RowPlanOut &o,
+                                            unsigned long long *ccount, unsigned long long *hwork, int *err) {
+    int cls = kNone;
+    int64_t ns = 0;
+    if (bad) {
+        atomicOr(err, 1);
+    } else if (w > 0) {
+        if (w <= light_max) {
+            cls = kLight0 + light_class(w);
+            ns = 1;
+        } else {
+            cls = (p1 - p0 >= kWideMembers) ? kHeavyWide : kHeavy;
+            const int64_t range = (int64_t)jm - i;  // partners lie in [i+1, jm]
+            const int64_t by_range = (range + kRangeBits - 1) / kRangeBits;
+            const int64_t by_work = (w + slot_work - 1) / slot_work;
+            ns = by_range > by_work ? by_range : by_work;
+            if (ns > range) ns = range;
+        }
+    }
+    o.work[i] = w;
+    o.jmax[i] = jm;
+    o.nslots[i] = (int32_t)ns;
+    o.rclass[i] = (uint8_t)cls;
+    o.bsize[i] = cls >= kHeavy ? (ns + 1) * (p1 - p0) : 0;
+    if (cls != kNone) atomicAdd(&ccount[cls - 1], (unsigned long long)ns);
+    if (cls >= kHeavy) atomicAdd(hwork, (unsigned long long)w);
+}
+
 __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min, int32_t light_max,
-                                                       int64_t slot_work,
-                                                       int32_t *__restrict__ tail_beg,
-                                                       int64_t *__restrict__ work,
-                                                       int32_t *__restrict__ jmax_out,
-                                                       int32_t *__restrict__ nslots,
-                                                       uint8_t *__restrict__ rclass,
-                                                       int64_t *__restrict__ bsize,
+                                                       int64_t slot_work, RowPlanOut o,
                                                        unsigned long long *__restrict__ class_count,
                                                        int *__restrict__ err,
                                                        unsigned long long *__restrict__ heavy_work) {
@@ -284,64 +347,42 @@ __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min, 
     __syncthreads();
     const int lane = lane_id();
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
-    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; i < g.m; i += nwaves) {
-        const int64_t p0 = g.he_ptr[i], p1 = g.he_ptr[i + 1];
-        int64_t w = 0;
-        int jm = -1;
-        int bad = 0;
-        if (p0 < 0 || p1 > g.nnz || p1 < p0) {
-            bad = 1;
-        } else if (p1 - p0 >= (g.row_s ? g.row_s[i] : s_min) && p1 > p0) {
-            for (int64_t p = p0 + lane; p < p1; p += 64) {
-                const int v = g.he_idx[p];
-                if (v < 0 || v >= g.n) {
-                    bad = 1;
-                    tail_beg[p] = 0;
-                    continue;
+    for (int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64 * 64; i0 < g.m; i0 += nwaves * 64) {
+        const int64_t i = i0 + lane;
+        bool big = false;
+        if (i < g.m) {
+            const int64_t p0 = g.he_ptr[i], p1 = g.he_ptr[i + 1];
+            if (p0 < 0 || p1 > g.nnz || p1 < p0) {  // malformed pointers
+                plan_finish(i, p0, p1, 0, -1, true, light_max, slot_work, o, ccount, &hwork, err);
+            } else {
+                const int64_t size = p1 - p0;
+                const bool kept = size > 0 && size >= (g.row_s ? g.row_s[i] : s_min);
+                big = kept && size > kSmallRow;
+                if (!big) {  // a small (or pruned) row, walked by its own lane
+                    int64_t w = 0;
+                    int jm = -1;
+                    bool rbad = false;
+                    if (kept)
+                        for (int64_t p = p0; p < p1; ++p) rbad |= !plan_member(g, i, p, o.tail_beg, w, jm);
+                    plan_finish(i, p0, p1, w, jm, rbad, light_max, slot_work, o, ccount, &hwork, err);
                 }
-                const int64_t lo = g.vs_ptr[v], hi = g.vs_ptr[v + 1];
-                if (lo < 0 || hi < lo || hi > g.nnz) {
-                    bad = 1;
-                    tail_beg[p] = 0;
-                    continue;
-                }
-                int a = lower_bound_i32(g.vs_idx, (int)lo, (int)hi, (int)i);
-                const bool found = a < hi && g.vs_idx[a] == (int)i;
-                bad |= !found;  // the vertex CSR must be the transpose
-                const int beg = found ? a + 1 : a;
-                tail_beg[p] = beg;
-                w += hi - beg;
-                if (beg < hi) jm = max(jm, g.vs_idx[hi - 1]);
             }
         }
-        w = wave_sum(w);
-        jm = wave_max(jm);
-        bad = wave_max(bad);
-        if (lane == 0) {
-            int cls = kNone;
-            int64_t ns = 0;
-            if (bad) {
-                atomicOr(err, 1);
-            } else if (w > 0) {
-                if (w <= light_max) {
-                    cls = kLight0 + light_class(w);
-                    ns = 1;
-                } else {
-                    cls = (p1 - p0 >= kWideMembers) ? kHeavyWide : kHeavy;
-                    const int64_t range = (int64_t)jm - i;  // partners lie in [i+1, jm]
-                    const int64_t by_range = (range + kRangeBits - 1) / kRangeBits;
-                    const int64_t by_work = (w + slot_work - 1) / slot_work;
-                    ns = by_range > by_work ? by_range : by_work;
-                    if (ns > range) ns = range;
-                }
-            }
-            work[i] = w;
-            jmax_out[i] = jm;
-            nslots[i] = (int32_t)ns;
-            rclass[i] = (uint8_t)cls;
-            bsize[i] = cls >= kHeavy ? (ns + 1) * (p1 - p0) : 0;
-            if (cls != kNone) atomicAdd(&ccount[cls - 1], (unsigned long long)ns);
-            if (cls >= kHeavy) atomicAdd(&hwork, (unsigned long long)w);
+        // the large rows of this group, one after another by the whole wavefront
+        unsigned long long todo = __ballot(big);
+        while (todo) {
+            const int l = __ffsll((long long)todo) - 1;
+            todo &= todo - 1;
+            const int64_t r = i0 + l;
+            const int64_t q0 = g.he_ptr[r], q1 = g.he_ptr[r + 1];
+            int64_t w = 0;
+            int jm = -1;
+            int rbad = 0;
+            for (int64_t p = q0 + lane; p < q1; p += 64) rbad |= !plan_member(g, r, p, o.tail_beg, w, jm);
+            w = wave_sum(w);
+            jm = wave_max(jm);
+            rbad = wave_max(rbad);
+            if (lane == 0) plan_finish(r, q0, q1, w, jm, rbad != 0, light_max, slot_work, o, ccount, &hwork, err);
         }
     }
     __syncthreads();
@@ -350,64 +391,81 @@ __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min, 
     if (threadIdx.x == 0 && hwork) atomicAdd(heavy_work, hwork);
 }
 
+// Tier lists filled by fill_slots_kernel.
 struct LightLists {
     int32_t *l[kLightClasses];
     int64_t cap[kNumLists];  // capacity of every tier list (light, heavy, heavy-wide)
     int *err;                // set when an append would overflow a list
 };
 
-// One thread per row: write the row's slots and append them to the tier
-// lists (light: slot ids; heavy: slot descriptors).
+// Writes every light row's slot and appends it to its tier list, and
+// reserves each heavy row's slot descriptors in the heavy lists. Rows are
+// appended in blocks: a workgroup takes 256 * kFillRows rows, counts them per
+// list with wavefront sums into LDS,
+// reserves each list's share with one global atomic, then places its rows
+// through LDS cursors (global atomics on the few list counters would
+// serialise).
+constexpr int kFillRows = 4;
+
 __global__ __launch_bounds__(256) void fill_slots_kernel(
     int64_t m, const int64_t *__restrict__ he_ptr, const int64_t *__restrict__ slot_base,
     const int32_t *__restrict__ nslots, const int32_t *__restrict__ jmax,
     const uint8_t *__restrict__ rclass, const int64_t *__restrict__ bbase,
     int32_t *__restrict__ slot_row, LightLists ll, int64_t *__restrict__ hat,
     unsigned long long *__restrict__ list_fill) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = lane_id();
-    int cls = kNone;
-    int ns = 0;
-    int64_t base = 0;
-    int jm = 0;
-    if (i < m) {
-        cls = rclass[i];
-        ns = nslots[i];
-        base = slot_base[i];
-        jm = jmax[i];
-    }
-    // light classes: wavefront-aggregated append, one slot per row
+    __shared__ unsigned long long cursor[kNumLists];
+    const int tid = threadIdx.x, lane = lane_id();
+    const int64_t i0 = (int64_t)blockIdx.x * (256 * kFillRows);
+    int cls[kFillRows], ns[kFillRows];
+    int64_t base[kFillRows];
 #pragma unroll
-    for (int c = 0; c < kLightClasses; ++c) {
-        const bool mine = (cls == kLight0 + c);
-        const unsigned long long mask = __ballot(mine);
-        if (!mask) continue;
-        const int leader = __ffsll((long long)mask) - 1;
-        unsigned long long at = 0;
-        if (lane == leader) at = atomicAdd(&list_fill[c], (unsigned long long)__popcll(mask));
-        at = __shfl(at, leader);
-        if (mine) {
-            const unsigned long long pos = at + bits_below(mask);
-            if (pos < (unsigned long long)ll.cap[c]) {
-                ll.l[c][pos] = (int32_t)base;
-                slot_row[base] = (int32_t)i;
+    for (int r = 0; r < kFillRows; ++r) {
+        const int64_t i = i0 + r * 256 + tid;
+        cls[r] = kNone;
+        ns[r] = 0;
+        base[r] = 0;
+        if (i < m) {
+            cls[r] = rclass[i];
+            ns[r] = nslots[i];
+            base[r] = slot_base[i];
+        }
+    }
+    if (tid < kNumLists) cursor[tid] = 0;
+    __syncthreads();
+    // entries per list: one per light row, one descriptor per heavy slot
+    for (int c = kLight0; c < kLight0 + kNumLists; ++c) {
+        int mine = 0;
+#pragma unroll
+        for (int r = 0; r < kFillRows; ++r)
+            if (cls[r] == c) mine += c >= kHeavy ? ns[r] : 1;
+        const int tot = wave_sum(mine);
+        if (lane == 0 && tot) atomicAdd(&cursor[c - 1], (unsigned long long)tot);
+    }
+    __syncthreads();
+    if (tid < kNumLists && cursor[tid]) cursor[tid] = atomicAdd(&list_fill[tid], cursor[tid]);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kFillRows; ++r) {
+        const int64_t i = i0 + r * 256 + tid;
+        for (int c = kLight0; c < kLight0 + kNumLists; ++c) {
+            const int w = (cls[r] == c) ? (c >= kHeavy ? ns[r] : 1) : 0;
+            const int incl = wave_incl_scan(w);
+            const int tot = __shfl(incl, 63);
+            if (!tot) continue;
+            unsigned long long at = 0;
+            if (lane == 63) at = atomicAdd(&cursor[c - 1], (unsigned long long)tot);
+            at = __shfl(at, 63);
+            if (!w) continue;
+            const unsigned long long pos = at + incl - w;
+            if (c >= kHeavy) {
+                hat[i] = (int64_t)pos;  // the row's descriptors, written by heavy_desc_kernel
+            } else if (pos < (unsigned long long)ll.cap[c - 1]) {
+                ll.l[c - 1][pos] = (int32_t)base[r];
+                slot_row[base[r]] = (int32_t)i;
             } else {
                 atomicOr(ll.err, 16);
             }
         }
-    }
-    // heavy rows: reserve the row's descriptors (written by heavy_desc_kernel),
-    // one atomic per wavefront and class
-#pragma unroll
-    for (int c = kHeavy; c <= kHeavyWide; ++c) {
-        const int mine = (cls == c) ? ns : 0;
-        const int incl = wave_incl_scan(mine);
-        const int tot = __shfl(incl, 63);
-        if (!tot) continue;
-        unsigned long long at = 0;
-        if (lane == 63) at = atomicAdd(&list_fill[c - 1], (unsigned long long)tot);
-        at = __shfl(at, 63);
-        if (mine) hat[i] = (int64_t)(at + incl - mine);
     }
 }
 
@@ -1420,9 +1478,9 @@ hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t light_max, in
     if (g.m <= 0) return hipSuccess;
     if (light_max <= 0 || light_max > kLightMax) light_max = kLightMax;
     if (slot_work <= 0) slot_work = kSlotWork;
-    row_plan_kernel<<<wave_grid(g.m, 4, 8192), 256, 0, st>>>(g, s_min, light_max, slot_work, tail_beg, work,
-                                                              jmax, nslots, rclass, bsize, class_count, err,
-                                                              heavy_work);
+    const RowPlanOut o{tail_beg, work, jmax, nslots, rclass, bsize};
+    row_plan_kernel<<<wave_grid((g.m + 63) / 64, 4, 8192), 256, 0, st>>>(g, s_min, light_max, slot_work, o,
+                                                                          class_count, err, heavy_work);
     return hipGetLastError();
 }
 
@@ -1436,8 +1494,8 @@ hipError_t launch_fill_slots(int64_t m, const int64_t *he_ptr, const int64_t *sl
     for (int c = 0; c < kLightClasses; ++c) ll.l[c] = lists[c];
     for (int c = 0; c < kNumLists; ++c) ll.cap[c] = caps[c];
     ll.err = err;
-    fill_slots_kernel<<<grid_for(m, 256), 256, 0, st>>>(m, he_ptr, slot_base, nslots, jmax, rclass, bbase,
-                                                         slot_row, ll, hat, list_fill);
+    fill_slots_kernel<<<grid_for(m, 256 * kFillRows), 256, 0, st>>>(m, he_ptr, slot_base, nslots, jmax, rclass,
+                                                                     bbase, slot_row, ll, hat, list_fill);
     heavy_desc_kernel<<<wave_grid(m, 4, 8192), 256, 0, st>>>(m, he_ptr, slot_base, nslots, jmax, rclass,
                                                               bbase, hat, slot_row, heavy[0], heavy[1],
                                                               caps[kLightClasses], caps[kLightClasses + 1], err);
