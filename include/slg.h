@@ -162,12 +162,13 @@ slg_status slg_plan_emit(slg_plan *p, int64_t *const *row_ptr, int32_t *const *r
  * Shape of a plan, for measurement and tuning: fills up to `cap` entries of
  * out[] (host array) with, in order:
  *   [0] slots (output segments);
- *   [1..6] rows in the six wavefront-sort classes (<= 64, 128, 256, 512,
+ *   [1] rows of at most 8 2-paths (one lane per row);
+ *   [2..7] rows in the six wavefront-sort classes (<= 64, 128, 256, 512,
  *          1024, 2048 2-paths);
- *   [7] heavy slots; [8] heavy slots of rows with >= 65535 members;
- *   [9] 2-paths (as slg_plan_info); [10] 2-paths in heavy slots;
- *   [11] entries of the heavy boundary table;
- *   [12] edges written by heavy slots, summed over all thresholds.
+ *   [8] heavy slots; [9] heavy slots of rows with >= 65535 members;
+ *   [10] 2-paths (as slg_plan_info); [11] 2-paths in heavy slots;
+ *   [12] entries of the heavy boundary table;
+ *   [13] edges written by heavy slots, summed over all thresholds.
  * Returns the number of entries written in *count (may be NULL).
  */
 slg_status slg_plan_stats(const slg_plan *p, int64_t *out, int32_t cap, int32_t *count);

@@ -211,7 +211,7 @@ class Plan:
     def num_edges(self) -> List[int]:
         return [self.info(k)[0] for k in range(len(self.s))]
 
-    STAT_NAMES = ("slots", "light64", "light128", "light256", "light512", "light1024", "light2048",
+    STAT_NAMES = ("slots", "tiny8", "light64", "light128", "light256", "light512", "light1024", "light2048",
                   "heavy_slots", "heavy_wide_slots", "two_paths", "heavy_two_paths", "bound_entries",
                   "heavy_edges")
 

@@ -776,17 +776,17 @@ slg_status slg_line_graph_stream(slg_context *ctx, slg_graph *g, const int32_t *
 
 slg_status slg_plan_stats(const slg_plan *p, int64_t *out, int32_t cap, int32_t *count) {
     if (!p || (!out && cap > 0) || cap < 0) return SLG_ERR_INVALID_ARG;
-    int64_t vals[13];
+    int64_t vals[14];
     vals[0] = p->S;
     for (int c = 0; c < kLightClasses; ++c) vals[1 + c] = p->list_count[c];
-    vals[7] = p->list_count[kLightClasses];
-    vals[8] = p->list_count[kLightClasses + 1];
-    vals[9] = p->two_paths;
-    vals[10] = p->heavy_two_paths;
-    vals[11] = p->nbounds;
-    vals[12] = p->heavy_edges;
-    static_assert(kLightClasses == 6, "plan stats layout");
-    int32_t n = cap < 13 ? cap : 13;
+    vals[8] = p->list_count[kLightClasses];
+    vals[9] = p->list_count[kLightClasses + 1];
+    vals[10] = p->two_paths;
+    vals[11] = p->heavy_two_paths;
+    vals[12] = p->nbounds;
+    vals[13] = p->heavy_edges;
+    static_assert(kLightClasses == 7, "plan stats layout");
+    int32_t n = cap < 14 ? cap : 14;
     for (int32_t t = 0; t < n; ++t) out[t] = vals[t];
     if (count) *count = n;
     return SLG_OK;

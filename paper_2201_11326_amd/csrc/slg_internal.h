@@ -12,7 +12,8 @@ namespace slg {
 // ---- tuning constants of the hot path ------------------------------------
 constexpr int kWave = 64;              // CDNA wavefront width
 constexpr int kLightMax = 2048;        // rows with <= this many 2-paths: wave-sort tier
-constexpr int kLightClasses = 6;       // 64, 128, 256, 512, 1024, 2048 keys per wave
+constexpr int kTinyMax = 8;            // rows with <= this many 2-paths: one lane each
+constexpr int kLightClasses = 7;       // tiny (lane per row), then 64 ... 2048 keys per wave
 constexpr int kHeavyThreads = 512;     // workgroup of the bitmap-rank tier
 constexpr int kRangeBits = 1 << 17;    // hyperedge-id range of one heavy slot (bitmap bits)
 constexpr int kRangeWords = kRangeBits / 32;

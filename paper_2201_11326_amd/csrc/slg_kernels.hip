@@ -261,8 +261,9 @@ __global__ void compact_ptr_kernel(int64_t n, int64_t nnz, const int64_t *__rest
 // K2: per-row plan (one wavefront per hyperedge, grid-stride)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int light_class(int64_t w) {
-    int c = 0;
-    while (c < kLightClasses - 1 && w > (int64_t(64) << c)) ++c;
+    if (w <= kTinyMax) return 0;
+    int c = 1;
+    while (c < kLightClasses - 1 && w > (int64_t(64) << (c - 1))) ++c;
     return c;
 }
 
@@ -541,6 +542,85 @@ __device__ __forceinline__ void wave_bitonic(int (&key)[KPL], int lane) {
                 }
             }
         }
+    }
+}
+
+// Rows with at most kTinyMax 2-paths: one lane per row. The lane collects
+// its row's partners (the tails of its members' vertex lists), sorts them
+// with a fixed 8-key network in registers, and writes the runs that reach
+// each threshold to its own slot's place in the output.
+template <bool EMIT>
+__global__ __launch_bounds__(256) void tiny_kernel(const int32_t *__restrict__ list, int64_t count, Slots sl,
+                                                   Pruned g, EmitParams prm, int64_t *__restrict__ slot_cnt,
+                                                   const int64_t *__restrict__ slot_off) {
+    static_assert(kTinyMax == 8, "8-key sorting network");
+    __shared__ int32_t keys[kTinyMax][256];  // column per thread: conflict-free
+    __shared__ EmitParams sp;
+    stage_params(&sp, prm);
+    __syncthreads();
+    const EmitParams *ep = &sp;
+    const int tid = threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * 256 + tid;
+    if (t >= count) return;
+    const int slot = list[t];
+    if (EMIT && (slot < ep->slot_lo || slot >= ep->slot_hi)) return;  // outside the emitted chunk
+    const int i = sl.row[slot];
+    const int64_t p0 = g.he_ptr[i], p1 = g.he_ptr[i + 1];
+    int n = 0;
+    for (int64_t p = p0; p < p1 && n < kTinyMax; ++p) {
+        const int v = g.he_idx[p];
+        const int64_t end = g.vs_ptr[v + 1];
+        for (int64_t q = g.tail_beg[p]; q < end && n < kTinyMax; ++q) keys[n++][tid] = g.vs_idx[q];
+    }
+    int k[kTinyMax];
+#pragma unroll
+    for (int r = 0; r < kTinyMax; ++r) k[r] = r < n ? keys[r][tid] : INT_MAX;
+    // Batcher's odd-even merge sort network for 8 keys (19 compare-exchanges)
+    auto cx = [&](int a, int b) {
+        const int lo = min(k[a], k[b]), hi = max(k[a], k[b]);
+        k[a] = lo;
+        k[b] = hi;
+    };
+    cx(0, 1); cx(2, 3); cx(4, 5); cx(6, 7);
+    cx(0, 2); cx(1, 3); cx(4, 6); cx(5, 7);
+    cx(1, 2); cx(5, 6);
+    cx(0, 4); cx(1, 5); cx(2, 6); cx(3, 7);
+    cx(2, 4); cx(3, 5);
+    cx(1, 2); cx(3, 4); cx(5, 6);
+    // the head of each run of equal partners holds the overlap
+    int c[kTinyMax];
+#pragma unroll
+    for (int r = 0; r < kTinyMax; ++r) {
+        int run = 0;
+        if (r < n && (r == 0 || k[r] != k[r - 1])) {
+#pragma unroll
+            for (int q = r; q < kTinyMax; ++q) run += (q < n && k[q] == k[r]) ? 1 : 0;
+        }
+        c[r] = run;  // 0 for non-heads
+    }
+    const int K = ep->k;
+    const int64_t S = sl.count;
+    const int id0 = ep->row_base ? as_global(ep->row_base)[i] : 0;  // caller's id of row i is i - id0
+    const int srow = ep->row_s ? as_global(ep->row_s)[i] : 0;
+    for (int kk = 0; kk < K; ++kk) {
+        const int sk = ep->row_s ? srow : ep->s[kk];
+        int64_t pos = EMIT ? slot_off[(int64_t)kk * (S + 1) + slot] - ep->out_base[kk] : 0;
+        const int64_t start = pos;
+        const auto col = as_global(EMIT ? ep->col[kk] : nullptr);
+        const auto wo = as_global(EMIT ? ep->w[kk] : nullptr);
+        const auto ro = as_global(EMIT ? ep->row[kk] : nullptr);
+#pragma unroll
+        for (int r = 0; r < kTinyMax; ++r) {
+            if (c[r] >= sk) {  // sk >= 1, so only run heads
+                if (EMIT) {
+                    col[pos] = k[r] - id0;
+                    wo[pos] = c[r];
+                    if (ro) ro[pos] = i - id0;
+                }
+                ++pos;
+            }
+        }
+        if (!EMIT) slot_cnt[(int64_t)kk * S + slot] = pos - start;
     }
 }
 
@@ -1506,6 +1586,13 @@ hipError_t launch_light(int cls, bool emit, const int32_t *list, int64_t count, 
                         const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
                         const int64_t *slot_off, hipStream_t st) {
     if (count <= 0) return hipSuccess;
+    if (cls == 0) {  // one lane per row
+        if (emit)
+            tiny_kernel<true><<<grid_for(count, 256), 256, 0, st>>>(list, count, sl, g, ep, slot_cnt, slot_off);
+        else
+            tiny_kernel<false><<<grid_for(count, 256), 256, 0, st>>>(list, count, sl, g, ep, slot_cnt, slot_off);
+        return hipGetLastError();
+    }
     const unsigned grid = grid_for(count, 4);
 #define SLG_LIGHT(KPL)                                                                              \
     do {                                                                                           \
@@ -1517,12 +1604,12 @@ hipError_t launch_light(int cls, bool emit, const int32_t *list, int64_t count, 
                                                            slot_off);                              \
     } while (0)
     switch (cls) {
-        case 0: SLG_LIGHT(1); break;
-        case 1: SLG_LIGHT(2); break;
-        case 2: SLG_LIGHT(4); break;
-        case 3: SLG_LIGHT(8); break;
-        case 4: SLG_LIGHT(16); break;
-        case 5: SLG_LIGHT(32); break;
+        case 1: SLG_LIGHT(1); break;
+        case 2: SLG_LIGHT(2); break;
+        case 3: SLG_LIGHT(4); break;
+        case 4: SLG_LIGHT(8); break;
+        case 5: SLG_LIGHT(16); break;
+        case 6: SLG_LIGHT(32); break;
         default: return hipErrorInvalidValue;
     }
 #undef SLG_LIGHT
