@@ -366,7 +366,7 @@ def bench_served(args) -> int:
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": f"served: {len(pool)} resident graphs (64 large-skewed-generator, m log-uniform "
                                f"[1e3, 1e4], n=m/2; 4 power-law-generator, m 1e4..8e4, n=2m), {len(reqs)} "
-                               f"Poisson requests at {args.rate:g}/s, s-sets of 1-3 from {{1,2,3,4,5,8}}",
+                               f"Poisson requests at {args.rate:g}/s, s-sets of 1-6 from {{1,2,3,4,5,8}}",
                    "workers": args.workers, "budget_gb": args.budget_gb, "seed": hg.BASE_SEED + 5,
                    "parallelism": "single GPU"},
         "two_paths_total": work,

@@ -251,7 +251,7 @@ class Request:
 
 
 def served_requests(pool_size: int, count: int, rate: float = 2000.0, seed: int = BASE_SEED + 6,
-                    s_choices: Sequence[int] = (1, 2, 3, 4, 5, 8), max_set: int = 3) -> List[Request]:
+                    s_choices: Sequence[int] = (1, 2, 3, 4, 5, 8), max_set: int = 6) -> List[Request]:
     """Poisson arrivals at `rate` per second; each request names a pool
     graph uniformly and an s-set of 1..max_set distinct thresholds drawn
     from s_choices."""
