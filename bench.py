@@ -402,7 +402,7 @@ def main() -> int:
     ap.add_argument("--no-tune", action="store_true", help="batched: library-default plan shape")
     ap.add_argument("--requests", type=int, default=4000, help="served: number of requests")
     ap.add_argument("--rate", type=float, default=2000.0, help="served: Poisson arrivals per second")
-    ap.add_argument("--workers", type=int, default=4, help="served: queries in flight")
+    ap.add_argument("--workers", type=int, default=8, help="served: queries in flight")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="served: device-memory budget")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
