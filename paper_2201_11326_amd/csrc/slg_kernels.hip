@@ -43,6 +43,18 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *as_global(T *p) 
     return (__attribute__((address_space(1))) T *)p;
 }
 
+// Wavefront-uniform values moved to scalar registers.
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ long long uniform(long long x) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(x & 0xFFFFFFFFll));
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)x >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ T *uniform(T *p) {
+    return reinterpret_cast<T *>(uniform((long long)reinterpret_cast<uintptr_t>(p)));
+}
+
 __device__ __forceinline__ int bits_below(unsigned long long mask) {
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
                                      __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
@@ -1215,12 +1227,15 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
                 // threshold 1 over the repeat list: every rank survives
                 if (c_add && lane == 0 && s_bottom == 1) sm.wtot[0][wave] = rhi > rlo ? rhi - rlo : 0;
                 if (EMIT) {  // partner of every rank, from this thread's own 8 words
-                    const uint32_t wd[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+                    const uint4 e0 = reinterpret_cast<const uint4 *>(sm.bitmap)[2 * tid];
+                    const uint4 e1 = reinterpret_cast<const uint4 *>(sm.bitmap)[2 * tid + 1];
+                    const uint32_t wd[8] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
                     int r = run0 - (int)r0;
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
                         const int x = tid * 8 + q;
                         unsigned bits = wd[q];
+                        const int nb = __popc(bits);
                         if (x >= w0 && x < w1) {
                             const int jbase = ja + 32 * x;
                             int rr = r;
@@ -1229,7 +1244,7 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
                                 bits &= bits - 1u;
                             }
                         }
-                        r += loc[q];
+                        r += nb;
                     }
                 }
                 __syncthreads();
@@ -1245,7 +1260,44 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
                     else
                         sm.acc[tid] += (unsigned long long)b;
                 }
-                if (EMIT) {
+                if (EMIT && K <= 4) {
+                    __syncthreads();
+                    // up to four thresholds in one sweep over this wavefront's
+                    // ranks: each count and partner is read once, thresholds
+                    // and output positions stay in scalar registers
+                    int sk4[4], left[4];
+                    long long b4[4];
+                    int32_t *col4[4], *w4[4], *row4[4];
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        sk4[kk] = uniform(kk < K ? (row_thr ? srow : ep->s[kk]) : INT_MAX);
+                        left[kk] = uniform(kk < K ? sm.wtot[kk][wave] : 0);
+                        b4[kk] = uniform(kk < K ? sm.wbase[kk][wave] : 0ll);
+                        col4[kk] = uniform(kk < K ? ep->col[kk] : nullptr);
+                        w4[kk] = uniform(kk < K ? ep->w[kk] : nullptr);
+                        row4[kk] = uniform(kk < K ? ep->row[kk] : nullptr);
+                    }
+                    for (int rbase = rlo; rbase < rhi && left[0] + left[1] + left[2] + left[3] > 0; rbase += 64) {
+                        const int r = rbase + lane;
+                        const int c = r < rhi ? count_get<WIDE>(sm.cnt, r) + c_add : 0;
+                        const bool any = c >= sk4[0];  // thresholds increase
+                        const int key = any ? sm.buf[r] - id0 : 0;
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk) {
+                            if (left[kk] == 0) continue;  // wave-uniform
+                            const bool surv = c >= sk4[kk];
+                            const unsigned long long mask = __ballot(surv);
+                            if (surv) {
+                                const int64_t pos = b4[kk] + bits_below(mask);
+                                as_global(col4[kk])[pos] = key;
+                                as_global(w4[kk])[pos] = c;
+                                if (row4[kk]) as_global(row4[kk])[pos] = i - id0;
+                            }
+                            b4[kk] += __popcll(mask);
+                            left[kk] -= __popcll(mask);
+                        }
+                    }
+                } else if (EMIT) {
                     __syncthreads();
                     // per threshold, this wavefront's survivors in rank order,
                     // compacted with ballots into consecutive positions
