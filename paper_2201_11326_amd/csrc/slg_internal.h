@@ -14,11 +14,11 @@ constexpr int kWave = 64;              // CDNA wavefront width
 constexpr int kLightMax = 2048;        // rows with <= this many 2-paths: wave-sort tier
 constexpr int kTinyMax = 8;            // rows with <= this many 2-paths: one lane each
 constexpr int kLightClasses = 7;       // tiny (lane per row), then 64 ... 2048 keys per wave
-constexpr int kHeavyThreads = 512;     // workgroup of the bitmap-rank tier
-constexpr int kRangeBits = 1 << 17;    // hyperedge-id range of one heavy slot (bitmap bits)
+constexpr int kHeavyThreads = 256;     // workgroup of the bitmap-rank tier (4 per CU)
+constexpr int kRangeBits = 1 << 16;    // hyperedge-id range of one heavy slot (bitmap bits)
 constexpr int kRangeWords = kRangeBits / 32;
-constexpr int kRankCap = 8192;         // overlap counters per rank window (LDS, u16)
-constexpr int64_t kSlotWork = 8192;    // 2-paths per heavy slot before a row is split
+constexpr int kRankCap = 4096;         // overlap counters per rank window (LDS, u16)
+constexpr int64_t kSlotWork = 4096;    // 2-paths per heavy slot before a row is split
 constexpr int kWideMembers = 65535;    // rows this large need u32 overlap counters
 
 // Row classes written by the planning kernel.

@@ -773,6 +773,8 @@ struct CounterCap {  // u16 counters packed in pairs, or u32 counters
     static constexpr int ranks = WIDE ? kRankCap / 2 : kRankCap;
 };
 
+constexpr int kThrTable = 128;  // overlaps below this find their threshold by table
+
 struct HeavySmem {
     uint32_t bitmap[kRangeWords];        // partner j of the slot range present
     uint16_t wpre[kRangeWords];          // low 16 bits of the word's exclusive popcount prefix
@@ -787,7 +789,7 @@ struct HeavySmem {
     unsigned long long acc[SLG_MAX_S];
     long long obase[SLG_MAX_S];
     long long wbase[SLG_MAX_S][kHW];     // output position of each wavefront's first survivor
-    uint8_t thr_of[256];                 // threshold index of an overlap value (0xFF: none)
+    uint8_t thr_of[kThrTable];           // threshold index of an overlap value (0xFF: none)
 };
 
 // Rank of the first bit of word x (x < number of words in use).
@@ -1005,8 +1007,9 @@ __device__ __forceinline__ int count_get(const uint32_t *cnt, int r) {
     return (int)((cnt[r >> 1] >> ((r & 1) << 4)) & 0xFFFFu);
 }
 
-// Two workgroups per CU (4 waves per SIMD) is what the LDS footprint allows;
-// the register budget is held to match (<= 128 VGPRs).
+// Four 256-thread workgroups per CU (4 waves per SIMD) is what the LDS
+// footprint allows; the register budget is held to match (<= 128 VGPRs).
+// Four slots in flight per CU hide the latency of each slot's phases.
 template <bool EMIT, bool WIDE>
 __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4))) void heavy_kernel(const HeavyDesc *__restrict__ desc,
                                                               int64_t count, int64_t S,
@@ -1026,9 +1029,9 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
     for (int x = tid; x < kRangeWords; x += kHeavyThreads) sm.bitmap[x] = 0u;
     for (int x = tid; x < kRankCap / 2; x += kHeavyThreads) sm.cnt[x] = 0u;
     if (tid < SLG_MAX_S * kHW) sm.wtot[tid / kHW][tid % kHW] = 0;
-    if (tid < 256) sm.thr_of[tid] = 0xFF;
+    if (tid < kThrTable) sm.thr_of[tid] = 0xFF;
     __syncthreads();
-    if (tid < prm.k && prm.s[tid] < 256) sm.thr_of[prm.s[tid]] = (uint8_t)tid;
+    if (tid < prm.k && prm.s[tid] < kThrTable) sm.thr_of[prm.s[tid]] = (uint8_t)tid;
     __syncthreads();
     const EmitParams *ep = &sp;
     const int K = prm.k;
@@ -1103,7 +1106,7 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
             for (int qb = 0; qb < k; qb += kHeavyThreads) {
                 int a, len;
                 member_segment<false>(vs_idx, bounds, d.bptr, k, qb, 0, 0, a, len);
-                walk_mark<false>(vs_idx, layout_segments(a, len, sm), k - qb, sm, ja, span, 0);
+                walk_mark<true>(vs_idx, layout_segments(a, len, sm), k - qb, sm, ja, span, kRankCap);
                 __syncthreads();
             }
         }
@@ -1168,7 +1171,7 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
                 // the single window of the emit pass (whose rank-to-partner map
                 // reuses the list's storage afterwards)
                 const int nrep = sm.nrep;
-                const bool by_repeats = one_batch && nrep <= kRankCap && (whole || !EMIT);
+                const bool by_repeats = nrep <= kRankCap && (whole || !EMIT);
                 const int c_add = by_repeats ? 1 : 0;  // partners start at overlap 1
                 // pass 2: count 2-paths into their partner's rank. The overlap of
                 // a partner passes every value up to its final one exactly once,
@@ -1185,7 +1188,7 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
                     int hit = -1;
                     if (row_thr) {
                         hit = reached == srow ? 0 : -1;
-                    } else if (reached < 256) {
+                    } else if (reached < kThrTable) {
                         const int t = sm.thr_of[reached];
                         hit = t == 0xFF ? -1 : t;
                     } else {
