@@ -267,6 +267,33 @@ slg_status slg_result_csr(const slg_result *r, int32_t k, const int64_t **row_pt
 slg_status slg_result_free(slg_result *r);
 
 /*
+ * s-connected components (Section II-B): the maximal subsets of E_s in
+ * which every two hyperedges are joined by an s-walk, i.e. the connected
+ * components of L_s. row/col: DEVICE int32[num_edges], the edges of L_s
+ * (as emitted, or any order; every id in [0, m) and in E_s). labels:
+ * DEVICE int32[m], written: the smallest hyperedge id of e_i's component,
+ * or -1 when |e_i| < s (a hyperedge of E_s with no edge is its own
+ * component). *num_components (may be NULL): their number. Ordered on
+ * `stream`; returns after the stream has reached the end of the call.
+ * Errors: INVALID_ARG (null, s < 1, an id outside [0, m), an edge end
+ * outside E_s).
+ */
+slg_status slg_components(slg_context *ctx, slg_graph *g, int32_t s, const int32_t *row, const int32_t *col,
+                          int64_t num_edges, int32_t *labels, int64_t *num_components, void *stream);
+
+/*
+ * ID squeezing (Stage 4 of the paper's pipeline, Section III): hyperedges
+ * that are an end of at least one edge keep their order and are renumbered
+ * 0, 1, ...: new_id DEVICE int32[m] gets the new id or -1; *num_kept (may
+ * be NULL) their number. With remap != 0, row/col (DEVICE int32[num_edges])
+ * are rewritten in place to the new ids (a sorted edge list stays sorted).
+ * Ordered on `stream`; returns after the stream has reached the end of the
+ * call. Errors: INVALID_ARG (null, m out of range, an id outside [0, m)).
+ */
+slg_status slg_squeeze(slg_context *ctx, int64_t m, int32_t *row, int32_t *col, int64_t num_edges, int32_t remap,
+                       int32_t *new_id, int64_t *num_kept, void *stream);
+
+/*
  * Served form: a request loop over device-resident hypergraphs. Queries
  * (a registered graph plus an s-set, each an ensemble pass of Algorithm 3)
  * arrive at any time and are started in arrival order as soon as one of

@@ -56,6 +56,10 @@ def _load():
         lib.slgo_two_paths.restype = _i64
         lib.slgo_row_two_paths.argtypes = [_i64, _i64, _p, _p, _i64, _p, _i64, _p, ctypes.c_int]
         lib.slgo_row_two_paths.restype = ctypes.c_int
+        lib.slgo_components_brute.argtypes = [_i64, _i64, _p, _p, _i64, _p]
+        lib.slgo_components_brute.restype = _i64
+        lib.slgo_components_edges.argtypes = [_i64, _p, _i64, _i64, _p, _p, _p]
+        lib.slgo_components_edges.restype = _i64
         _lib = lib
     return _lib
 
@@ -158,3 +162,40 @@ def row_two_paths(inc, size_min: int, rows: Sequence[int], threads: int = 0) -> 
                                   rows_a.shape[0], _ptr(out), threads):
         raise MemoryError("oracle: allocation failed")
     return out[:rows_a.shape[0]]
+
+
+def components(inc, s: int, row: Optional[np.ndarray] = None, col: Optional[np.ndarray] = None):
+    """s-connected components (Section II-B): (labels int32[m], count). The
+    label of e_i is the smallest id of its component, -1 when |e_i| < s.
+    Without an edge list, s-incidence is tested by brute force for every
+    pair met by the search (small inputs); with one (the edges of L_s), the
+    search follows those edges."""
+    he_ptr, he_idx = _csr(inc)
+    label = np.empty(max(inc.m, 1), np.int32)
+    lib = _load()
+    if row is None:
+        count = lib.slgo_components_brute(inc.m, inc.n, _ptr(he_ptr), _ptr(he_idx), int(s), _ptr(label))
+    else:
+        r = np.ascontiguousarray(row, dtype=np.int32)
+        c = np.ascontiguousarray(col, dtype=np.int32)
+        if r.size == 0:
+            r = c = np.zeros(1, np.int32)
+        count = lib.slgo_components_edges(inc.m, _ptr(he_ptr), int(s), int(np.asarray(row).size), _ptr(r),
+                                          _ptr(c), _ptr(label))
+    if count == -1:
+        raise MemoryError("oracle: allocation failed")
+    if count == -2:
+        raise ValueError("an edge names an id outside [0, m) or a hyperedge outside E_s")
+    return label[: inc.m], int(count)
+
+
+def squeeze(m: int, row: np.ndarray, col: np.ndarray):
+    """ID squeezing (Stage 4 of Section III): hyperedges that end at least one
+    edge keep their order and are numbered 0, 1, ...; (new_id int32[m] with
+    -1 for the others, number kept)."""
+    present = np.zeros(m, dtype=bool)
+    present[np.asarray(row, dtype=np.int64)] = True
+    present[np.asarray(col, dtype=np.int64)] = True
+    new_id = np.full(m, -1, dtype=np.int32)
+    new_id[present] = np.arange(int(present.sum()), dtype=np.int32)
+    return new_id, int(present.sum())

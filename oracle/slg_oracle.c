@@ -192,3 +192,110 @@ int slgo_row_two_paths(int64_t m, int64_t n, const int64_t *he_ptr, const int32_
     }
     return bad;
 }
+
+/* s-connected components (Section II-B): the maximal subsets of E_s whose
+ * members are pairwise joined by s-walks (sequences of s-incident
+ * hyperedges). Breadth-first search from every unlabelled hyperedge of E_s
+ * in increasing id order; the neighbours of e are found by counting
+ * |e n f| for every unlabelled f of E_s. label[i] = the first (smallest) id
+ * of its component, -1 when |e_i| < s. Returns the number of components,
+ * or -1 when memory runs out. O(m^2 |e|): small inputs only. */
+int64_t slgo_components_brute(int64_t m, int64_t n, const int64_t *he_ptr, const int32_t *he_idx,
+                              int64_t s, int32_t *label)
+{
+    unsigned char *flag = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+    if (!flag || !queue) {
+        free(flag);
+        free(queue);
+        return -1;
+    }
+    for (int64_t i = 0; i < m; ++i) label[i] = (he_ptr[i + 1] - he_ptr[i] >= s) ? -2 : -1;
+    int64_t count = 0;
+    for (int64_t r = 0; r < m; ++r) {
+        if (label[r] != -2) continue;
+        ++count;
+        label[r] = (int32_t)r;
+        int64_t head = 0, tail = 0;
+        queue[tail++] = r;
+        while (head < tail) {
+            const int64_t e = queue[head++];
+            for (int64_t p = he_ptr[e]; p < he_ptr[e + 1]; ++p) flag[he_idx[p]] = 1;
+            for (int64_t f = 0; f < m; ++f) {
+                if (label[f] != -2) continue;
+                if (overlap_with_flagged(he_ptr, he_idx, f, flag) >= s) {
+                    label[f] = (int32_t)r;
+                    queue[tail++] = f;
+                }
+            }
+            for (int64_t p = he_ptr[e]; p < he_ptr[e + 1]; ++p) flag[he_idx[p]] = 0;
+        }
+    }
+    free(flag);
+    free(queue);
+    return count;
+}
+
+/* The same components from a given edge list of L_s (both ends in E_s):
+ * breadth-first search over the undirected adjacency of the edges. Returns
+ * the number of components, -1 when memory runs out, -2 when an edge names
+ * an id outside [0, m) or a hyperedge with fewer than s vertices. */
+int64_t slgo_components_edges(int64_t m, const int64_t *he_ptr, int64_t s, int64_t num_edges,
+                              const int32_t *row, const int32_t *col, int32_t *label)
+{
+    for (int64_t e = 0; e < num_edges; ++e) {
+        const int64_t a = row[e], b = col[e];
+        if (a < 0 || a >= m || b < 0 || b >= m) return -2;
+        if (he_ptr[a + 1] - he_ptr[a] < s || he_ptr[b + 1] - he_ptr[b] < s) return -2;
+    }
+    int64_t *ptr = (int64_t *)calloc((size_t)(m + 1), sizeof(int64_t));
+    int32_t *adj = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * num_edges > 0 ? 2 * num_edges : 1));
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+    if (!ptr || !adj || !queue) {
+        free(ptr);
+        free(adj);
+        free(queue);
+        return -1;
+    }
+    for (int64_t e = 0; e < num_edges; ++e) {
+        ++ptr[row[e] + 1];
+        ++ptr[col[e] + 1];
+    }
+    for (int64_t i = 0; i < m; ++i) ptr[i + 1] += ptr[i];
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+    if (!fill) {
+        free(ptr);
+        free(adj);
+        free(queue);
+        return -1;
+    }
+    for (int64_t i = 0; i < m; ++i) fill[i] = ptr[i];
+    for (int64_t e = 0; e < num_edges; ++e) {
+        adj[fill[row[e]]++] = col[e];
+        adj[fill[col[e]]++] = row[e];
+    }
+    free(fill);
+    for (int64_t i = 0; i < m; ++i) label[i] = (he_ptr[i + 1] - he_ptr[i] >= s) ? -2 : -1;
+    int64_t count = 0;
+    for (int64_t r = 0; r < m; ++r) {
+        if (label[r] != -2) continue;
+        ++count;
+        label[r] = (int32_t)r;
+        int64_t head = 0, tail = 0;
+        queue[tail++] = r;
+        while (head < tail) {
+            const int64_t e = queue[head++];
+            for (int64_t q = ptr[e]; q < ptr[e + 1]; ++q) {
+                const int64_t f = adj[q];
+                if (label[f] == -2) {
+                    label[f] = (int32_t)r;
+                    queue[tail++] = f;
+                }
+            }
+        }
+    }
+    free(ptr);
+    free(adj);
+    free(queue);
+    return count;
+}

@@ -118,6 +118,8 @@ def lib() -> ctypes.CDLL:
         "slg_result_coo": (_i32, [_p, _i32, ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
         "slg_result_csr": (_i32, [_p, _i32, ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
         "slg_result_free": (_i32, [_p]),
+        "slg_components": (_i32, [_p, _p, _i32, _p, _p, _i64, _p, ctypes.POINTER(_i64), _p]),
+        "slg_squeeze": (_i32, [_p, _i64, _p, _p, _i64, _i32, _p, ctypes.POINTER(_i64), _p]),
         "slg_server_create": (_i32, [_p, _i32, _u64, ctypes.POINTER(_p)]),
         "slg_server_submit": (_i32, [_p, _p, ctypes.POINTER(_i32), _i32, ctypes.POINTER(_u64)]),
         "slg_server_wait": (_i32, [_p, _u64, _i32, ctypes.POINTER(_p), ctypes.POINTER(RequestInfo)]),
@@ -433,9 +435,39 @@ class Context:
                                          ctypes.byref(h)))
         return _wrap_result(_Result(h.value), s, g.m, self.device)
 
+    def components(self, g: Graph, s: int, lg: "LineGraph", stream=None):
+        """s-connected components of L_s given its edges: (labels int32[m] on the
+        device, smallest id of each component or -1 off E_s; number of components)."""
+        import torch
+        labels = torch.empty(max(g.m, 1), dtype=torch.int32, device=f"cuda:{self.device}")[: g.m]
+        nc = _i64()
+        row = _need_rows(lg)
+        self._check(lib().slg_components(self.handle, g.handle, int(s), row.data_ptr(), lg.col.data_ptr(),
+                                         int(lg.num_edges), labels.data_ptr(), ctypes.byref(nc),
+                                         _stream_handle(stream)))
+        return labels, int(nc.value)
+
+    def squeeze(self, m: int, lg: "LineGraph", remap: bool = False, stream=None):
+        """ID squeezing: (new_id int32[m], -1 for hyperedges without an edge;
+        number kept). remap=True rewrites lg.row/lg.col in place."""
+        import torch
+        new_id = torch.empty(max(m, 1), dtype=torch.int32, device=f"cuda:{self.device}")[:m]
+        nk = _i64()
+        row = _need_rows(lg)
+        self._check(lib().slg_squeeze(self.handle, int(m), row.data_ptr(), lg.col.data_ptr(), int(lg.num_edges),
+                                      1 if remap else 0, new_id.data_ptr(), ctypes.byref(nk),
+                                      _stream_handle(stream)))
+        return new_id, int(nk.value)
+
     def server(self, workers: int = 4, mem_budget_bytes: int = 0) -> "Server":
         """The served form (slg_server_*): a request loop over registered graphs."""
         return Server(self, workers, mem_budget_bytes)
+
+
+def _need_rows(lg: "LineGraph"):
+    if lg.row is None:
+        raise ValueError("this call needs the COO rows of the line graph (line_graph(..., coo=True))")
+    return lg.row
 
 
 def _wrap_result(res: "_Result", s: Sequence[int], m: int, device: int) -> List[LineGraph]:

@@ -1166,6 +1166,68 @@ slg_status serve_query(slg_context *wctx, slg_graph *g, const int32_t *s, int32_
 
 extern "C" {
 
+slg_status slg_components(slg_context *ctx, slg_graph *g, int32_t s, const int32_t *row, const int32_t *col,
+                          int64_t num_edges, int32_t *labels, int64_t *num_components, void *stream) {
+    if (!ctx || !g || !labels || s < 1 || num_edges < 0 || (num_edges > 0 && (!row || !col)))
+        return fail(ctx, SLG_ERR_INVALID_ARG, "bad components arguments");
+    SLG_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t m = g->inc.num_hyperedges;
+    Scratch sc;
+    sc.st = st;
+    sc.arena = ctx->arena.get();
+    int64_t *dev = nullptr;  // [0] roots, [1] error flags
+    int32_t *parent = nullptr;
+    SLG_HIP(ctx, sc.get(&dev, 2));
+    SLG_HIP(ctx, sc.get(&parent, m));
+    SLG_HIP(ctx, launch_fill_i64(dev, 2, 0, st));
+    SLG_HIP(ctx, launch_cc_init(g->inc.he_ptr, m, s, parent, st));
+    SLG_HIP(ctx, launch_cc_hook(row, col, num_edges, m, parent, reinterpret_cast<int *>(dev + 1), st));
+    SLG_HIP(ctx, launch_cc_finish(m, parent, labels, reinterpret_cast<unsigned long long *>(dev), st));
+    SLG_HIP(ctx, hipMemcpyAsync(ctx->pinned, dev, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SLG_HIP(ctx, hipStreamSynchronize(st));
+    sc.release();
+    const int64_t err = ctx->pinned[1];
+    if (err & 4) return fail(ctx, SLG_ERR_INVALID_ARG, "an edge names a hyperedge id outside [0, m)");
+    if (err & 2) return fail(ctx, SLG_ERR_INVALID_ARG, "an edge joins a hyperedge with fewer than s vertices");
+    if (err & 1) return fail(ctx, SLG_ERR_DEVICE, "internal error: a union step did not settle");
+    if (num_components) *num_components = ctx->pinned[0];
+    return SLG_OK;
+}
+
+slg_status slg_squeeze(slg_context *ctx, int64_t m, int32_t *row, int32_t *col, int64_t num_edges, int32_t remap,
+                       int32_t *new_id, int64_t *num_kept, void *stream) {
+    if (!ctx || !new_id || m < 0 || m >= (int64_t(1) << 31) || num_edges < 0 || (num_edges > 0 && (!row || !col)))
+        return fail(ctx, SLG_ERR_INVALID_ARG, "bad squeeze arguments");
+    SLG_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Scratch sc;
+    sc.st = st;
+    sc.arena = ctx->arena.get();
+    int32_t *flag = nullptr;
+    int64_t *pre = nullptr, *part = nullptr, *err = nullptr;
+    SLG_HIP(ctx, sc.get(&flag, m));
+    SLG_HIP(ctx, sc.get(&pre, m + 1));
+    SLG_HIP(ctx, sc.get(&part, scan_partials_size(m)));
+    SLG_HIP(ctx, sc.get(&err, 1));
+    SLG_HIP(ctx, launch_fill_i32(flag, m, 0, st));
+    SLG_HIP(ctx, launch_fill_i64(err, 1, 0, st));
+    SLG_HIP(ctx, launch_mark_ends(row, col, num_edges, m, flag, reinterpret_cast<int *>(err), st));
+    SLG_HIP(ctx, launch_exclusive_scan_i32(flag, m, pre, part, st));
+    SLG_HIP(ctx, launch_squeeze_ids(m, flag, pre, new_id, st));
+    SLG_HIP(ctx, hipMemcpyAsync(ctx->pinned, err, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SLG_HIP(ctx, hipMemcpyAsync(ctx->pinned + 1, pre + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SLG_HIP(ctx, hipStreamSynchronize(st));
+    if (ctx->pinned[0] & 4) {
+        sc.release();
+        return fail(ctx, SLG_ERR_INVALID_ARG, "an edge names a hyperedge id outside [0, m)");
+    }
+    if (remap) SLG_HIP(ctx, launch_remap_edges(row, col, num_edges, new_id, st));
+    sc.release();
+    if (num_kept) *num_kept = ctx->pinned[1];
+    return SLG_OK;
+}
+
 slg_status slg_result_info(const slg_result *r, int32_t k, int64_t *num_edges, int64_t *two_paths) {
     if (!r || k < 0 || k >= r->k) return SLG_ERR_INVALID_ARG;
     if (num_edges) *num_edges = r->num_edges[k];

@@ -147,6 +147,26 @@ hipError_t launch_union(const UnionPart *parts, int32_t count, int64_t max_elems
 hipError_t launch_gather_i64(const int64_t *src, const int64_t *idx, int64_t count, int64_t *out,
                              hipStream_t st);
 
+// s-connected components of L_s (hooking union-find over the edge list):
+// label[i] = i for |e_i| >= s, else -1; then every edge (row, col) joins the
+// trees of its ends (the larger root under the smaller); finally out[i] is
+// the root of i, the smallest id of its component (or -1). count gets the
+// number of roots; err is set if a bounded loop ran out (never expected).
+hipError_t launch_cc_init(const int64_t *he_ptr, int64_t m, int32_t s, int32_t *label, hipStream_t st);
+hipError_t launch_cc_hook(const int32_t *row, const int32_t *col, int64_t num_edges, int64_t m, int32_t *label,
+                          int *err, hipStream_t st);
+hipError_t launch_cc_finish(int64_t m, const int32_t *label, int32_t *out, unsigned long long *count,
+                            hipStream_t st);
+// ID squeezing: flag[i] = 1 for every end of an edge (ids outside [0, m):
+// err |= 4, also in the hook).
+hipError_t launch_mark_ends(const int32_t *row, const int32_t *col, int64_t num_edges, int64_t m, int32_t *flag,
+                            int *err, hipStream_t st);
+// new_id[i] = pre[i] when flag[i], else -1 (pre: exclusive scan of flag).
+hipError_t launch_squeeze_ids(int64_t m, const int32_t *flag, const int64_t *pre, int32_t *new_id, hipStream_t st);
+// row[e] = new_id[row[e]], col[e] = new_id[col[e]].
+hipError_t launch_remap_edges(int32_t *row, int32_t *col, int64_t num_edges, const int32_t *new_id,
+                              hipStream_t st);
+
 // Validation kernels (SLG_VALIDATE).
 hipError_t launch_validate_ptr(const int64_t *ptr, int64_t rows, int64_t nnz, int *err,
                                hipStream_t st);

@@ -1529,6 +1529,127 @@ __global__ void gather_i64_kernel(const int64_t *__restrict__ src, const int64_t
     if (c < count) out[c] = src[idx[c]];
 }
 
+// ---------------------------------------------------------------------------
+// s-connected components (Section II-B: maximal sets of E_s joined by
+// s-walks) and ID squeezing, on the emitted edge list
+// ---------------------------------------------------------------------------
+// label[] doubles as the union-find parent array: label[x] <= x for kept x,
+// and a root is its own label. Loads and stores go to the device-coherent
+// level so that concurrent hooks see each other; values only decrease, so a
+// stale read still names an ancestor.
+__device__ __forceinline__ int cc_load(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void cc_store(int32_t *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of x's tree, halving the path on the way (each step strictly
+// decreases, so the walk ends within x steps).
+__device__ __forceinline__ int cc_root(int32_t *label, int x) {
+    int cur = cc_load(&label[x]);
+    if (cur == x) return x;
+    int prev = x;
+    while (true) {
+        const int next = cc_load(&label[cur]);
+        if (next >= cur) return cur;  // a root (next == cur)
+        cc_store(&label[prev], next);
+        prev = cur;
+        cur = next;
+    }
+}
+
+__global__ void cc_init_kernel(const int64_t *__restrict__ he_ptr, int64_t m, int32_t s, int32_t *__restrict__ label) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) label[i] = (he_ptr[i + 1] - he_ptr[i] >= s) ? (int32_t)i : -1;
+}
+
+constexpr int kHookTries = 1 << 20;  // far above any real retry count
+
+__global__ void cc_hook_kernel(const int32_t *__restrict__ row, const int32_t *__restrict__ col, int64_t num_edges,
+                               int64_t m, int32_t *label, int *err) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < num_edges; e += stride) {
+        const int u = row[e], v = col[e];
+        if (u < 0 || u >= m || v < 0 || v >= m) {  // not a hyperedge id
+            atomicOr(err, 4);
+            continue;
+        }
+        if (cc_load(&label[u]) < 0 || cc_load(&label[v]) < 0) {  // an end outside E_s: not an edge of L_s
+            atomicOr(err, 2);
+            continue;
+        }
+        int ru = cc_root(label, u), rv = cc_root(label, v);
+        int tries = 0;
+        while (ru != rv) {
+            const int lo = min(ru, rv), hi = max(ru, rv);
+            const int old = atomicCAS(&label[hi], hi, lo);  // hang the larger root under the smaller
+            if (old == hi) break;
+            // hi stopped being a root meanwhile: start again from the current roots
+            ru = cc_root(label, lo);
+            rv = cc_root(label, old);
+            if (++tries >= kHookTries) {
+                atomicOr(err, 1);
+                break;
+            }
+        }
+    }
+}
+
+// Roots into a separate array: the trees are read, never written, here (a
+// path-halving walk racing with the final stores could leave a label at an
+// ancestor that is not the root).
+__global__ __launch_bounds__(256) void cc_finish_kernel(int64_t m, const int32_t *__restrict__ label,
+                                                        int32_t *__restrict__ out, unsigned long long *count) {
+    __shared__ unsigned long long blk;
+    if (threadIdx.x == 0) blk = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int root = 0;
+    if (i < m) {
+        int cur = label[i];
+        if (cur >= 0) {
+            int next;
+            while ((next = label[cur]) < cur) cur = next;
+            root = cur == (int)i;
+        }
+        out[i] = cur;
+    }
+    const unsigned long long b = __ballot(root);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&blk, (unsigned long long)__popcll(b));
+    __syncthreads();
+    if (threadIdx.x == 0 && blk) atomicAdd(count, blk);
+}
+
+__global__ void mark_ends_kernel(const int32_t *__restrict__ row, const int32_t *__restrict__ col, int64_t num_edges,
+                                 int64_t m, int32_t *__restrict__ flag, int *err) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < num_edges; e += stride) {
+        const int u = row[e], v = col[e];
+        if (u < 0 || u >= m || v < 0 || v >= m) {
+            atomicOr(err, 4);
+            continue;
+        }
+        flag[u] = 1;
+        flag[v] = 1;
+    }
+}
+
+__global__ void squeeze_ids_kernel(int64_t m, const int32_t *__restrict__ flag, const int64_t *__restrict__ pre,
+                                   int32_t *__restrict__ new_id) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < m) new_id[i] = flag[i] ? (int32_t)pre[i] : -1;
+}
+
+__global__ void remap_edges_kernel(int32_t *__restrict__ row, int32_t *__restrict__ col, int64_t num_edges,
+                                   const int32_t *__restrict__ new_id) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < num_edges; e += stride) {
+        row[e] = new_id[row[e]];
+        col[e] = new_id[col[e]];
+    }
+}
+
 inline unsigned grid_for(int64_t n, int threads) {
     int64_t b = (n + threads - 1) / threads;
     return (unsigned)(b < 1 ? 1 : b);
@@ -1737,6 +1858,52 @@ hipError_t launch_union(const UnionPart *parts, int32_t count, int64_t max_elems
     if (bx < 1) bx = 1;
     union_kernel<<<dim3((unsigned)bx, (unsigned)count), 256, 0, st>>>(parts, he_ptr, he_idx, v_ptr, v_idx, row_s,
                                                                        row_base);
+    return hipGetLastError();
+}
+
+inline unsigned stride_grid(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 16384) b = 16384;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
+hipError_t launch_cc_init(const int64_t *he_ptr, int64_t m, int32_t s, int32_t *label, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    cc_init_kernel<<<grid_for(m, 256), 256, 0, st>>>(he_ptr, m, s, label);
+    return hipGetLastError();
+}
+
+hipError_t launch_cc_hook(const int32_t *row, const int32_t *col, int64_t num_edges, int64_t m, int32_t *label,
+                          int *err, hipStream_t st) {
+    if (num_edges <= 0) return hipSuccess;
+    cc_hook_kernel<<<stride_grid(num_edges), 256, 0, st>>>(row, col, num_edges, m, label, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_cc_finish(int64_t m, const int32_t *label, int32_t *out, unsigned long long *count,
+                            hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    cc_finish_kernel<<<grid_for(m, 256), 256, 0, st>>>(m, label, out, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_ends(const int32_t *row, const int32_t *col, int64_t num_edges, int64_t m, int32_t *flag,
+                            int *err, hipStream_t st) {
+    if (num_edges <= 0) return hipSuccess;
+    mark_ends_kernel<<<stride_grid(num_edges), 256, 0, st>>>(row, col, num_edges, m, flag, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_squeeze_ids(int64_t m, const int32_t *flag, const int64_t *pre, int32_t *new_id, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    squeeze_ids_kernel<<<grid_for(m, 256), 256, 0, st>>>(m, flag, pre, new_id);
+    return hipGetLastError();
+}
+
+hipError_t launch_remap_edges(int32_t *row, int32_t *col, int64_t num_edges, const int32_t *new_id,
+                              hipStream_t st) {
+    if (num_edges <= 0) return hipSuccess;
+    remap_edges_kernel<<<stride_grid(num_edges), 256, 0, st>>>(row, col, num_edges, new_id);
     return hipGetLastError();
 }
 

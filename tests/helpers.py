@@ -71,3 +71,17 @@ def assert_same_graph(a_rowptr, a_i, a_j, a_w, b_rowptr, b_i, b_j, b_w, what="")
     np.testing.assert_array_equal(np.asarray(a_i), np.asarray(b_i), err_msg=f"{what}: i")
     np.testing.assert_array_equal(np.asarray(a_j), np.asarray(b_j), err_msg=f"{what}: j")
     np.testing.assert_array_equal(np.asarray(a_w), np.asarray(b_w), err_msg=f"{what}: w")
+
+
+def load_toy_components(path: str = os.path.join(GOLDEN, "toy_components.txt")):
+    """Parse the components/squeeze fixture -> ({s: labels}, {s: new ids})."""
+    cc, sq = {}, {}
+    with open(path) as f:
+        for raw in f:
+            line = raw.split("#", 1)[0].strip()
+            if not line:
+                continue
+            tok = line.split()
+            vals = [int(x) for x in tok[2:]]
+            (cc if tok[0] == "cc" else sq)[int(tok[1])] = vals
+    return cc, sq

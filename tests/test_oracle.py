@@ -13,7 +13,7 @@ from hypothesis import given, settings, strategies as st
 
 import hypergen as hg
 import oracle
-from helpers import brute_force_sets, edges_of, load_toy, rows_of
+from helpers import brute_force_sets, edges_of, load_toy, rows_of, load_toy_components
 
 
 # --- the worked example of Section I (hand-enumerated fixture) -------------
@@ -222,3 +222,83 @@ def test_sampled_rows_match_full_graph():
         j, w = r.row(k)
         a, b = full.row_ptr[i], full.row_ptr[i + 1]
         assert np.array_equal(j, full.j[a:b]) and np.array_equal(w, full.w[a:b])
+
+
+# --- s-connected components and ID squeezing -------------------------------
+
+def _canonical(labels):
+    """Component labels as the smallest member id (-1 stays -1)."""
+    labels = np.asarray(labels)
+    out = np.full(labels.shape, -1, dtype=np.int64)
+    first = {}
+    for i, l in enumerate(labels):
+        if l < 0:
+            continue
+        first.setdefault(int(l), i)
+        out[i] = first[int(l)]
+    return out
+
+
+def test_components_and_squeeze_of_the_worked_example():
+    inc, _, _, _ = load_toy()
+    cc, sq = load_toy_components()
+    for s, want in cc.items():
+        lab, count = oracle.components(inc, s)
+        assert lab.tolist() == want
+        assert count == len({l for l in want if l >= 0})
+        lg = oracle.line_graph(inc, s)
+        lab2, count2 = oracle.components(inc, s, lg.i, lg.j)
+        assert lab2.tolist() == want and count2 == count
+        new_id, kept = oracle.squeeze(inc.m, lg.i, lg.j)
+        assert new_id.tolist() == sq[s] and kept == sum(1 for x in sq[s] if x >= 0)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_components_match_scipy_on_the_thresholded_product(seed):
+    from scipy.sparse.csgraph import connected_components
+    inc = hg.random_small(seed + 40, m=70, n=30, kmax=9, exponent=1.0)
+    H = sp.csr_matrix((np.ones(inc.nnz), inc.he_idx, inc.he_ptr), shape=(inc.m, inc.n))
+    G = (H @ H.T).tocsr()  # (H^T H) in hyperedge x hyperedge orientation
+    sizes = inc.sizes()
+    for s in (1, 2, 3):
+        keep = np.flatnonzero(sizes >= s)
+        A = G[keep][:, keep].tolil()
+        A.setdiag(0)
+        A = (A.tocsr() >= s).astype(np.int8)
+        _, comp = connected_components(A, directed=False)
+        ref = np.full(inc.m, -1)
+        for c in np.unique(comp):
+            members = keep[comp == c]
+            ref[members] = members.min()
+        lab, count = oracle.components(inc, s)
+        np.testing.assert_array_equal(lab, ref)
+        assert count == len(np.unique(comp)) if keep.size else count == 0
+        lg = oracle.line_graph(inc, s)
+        lab2, _ = oracle.components(inc, s, lg.i, lg.j)
+        np.testing.assert_array_equal(lab2, ref)
+
+
+def test_components_refine_as_s_grows():
+    inc = hg.random_small(77, m=120, n=40, kmax=12, exponent=1.1)
+    prev = None
+    for s in range(1, 6):
+        lab, _ = oracle.components(inc, s)
+        if prev is not None:
+            kept = np.flatnonzero(lab >= 0)
+            assert np.all(prev[kept] >= 0)  # E_{s+1} is inside E_s
+            for a in kept:  # same component at s+1 => same component at s
+                same = kept[lab[kept] == lab[a]]
+                assert np.all(prev[same] == prev[a])
+        prev = lab
+
+
+def test_squeeze_is_the_order_preserving_rank_of_the_edge_ends():
+    rng = np.random.default_rng(5)
+    m = 50
+    row = rng.integers(0, m, 40).astype(np.int32)
+    col = rng.integers(0, m, 40).astype(np.int32)
+    new_id, kept = oracle.squeeze(m, row, col)
+    ends = sorted(set(row.tolist()) | set(col.tolist()))
+    assert kept == len(ends)
+    assert [int(new_id[e]) for e in ends] == list(range(kept))
+    assert all(new_id[i] == -1 for i in range(m) if i not in set(ends))
