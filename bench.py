@@ -389,6 +389,60 @@ def bench_served(args) -> int:
     return 0
 
 
+def bench_components(args) -> int:
+    """s-connected components and ID squeezing (the pipeline's stages after
+    construction, Section III) on the power-law instance's L_s for every s of
+    S = {1,2,4,8}. value = s-line edges consumed per second by the component
+    search; the squeeze rate rides along. Inputs (the emitted L_s) are on the
+    device before timing starts."""
+    import torch
+
+    import hypergen as hg
+    import paper_2201_11326_amd as slg
+
+    inc = hg.power_law()
+    ctx = slg.Context(0)
+    g = ctx.register_incidence(inc)
+    outs = ctx.line_graph(g, S_SET)
+    torch.cuda.synchronize()
+    edges = [lg.num_edges for lg in outs]
+    res = {}
+    for _ in range(args.warmup):
+        for lg in outs:
+            ctx.components(g, lg.s, lg)
+            ctx.squeeze(inc.m, lg)
+    torch.cuda.synchronize()
+    t_cc = t_sq = 0.0
+    counts = {}
+    for _ in range(args.steps):
+        for lg in outs:
+            t0 = time.perf_counter()
+            _, nc = ctx.components(g, lg.s, lg)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, nk = ctx.squeeze(inc.m, lg)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            t_cc += t1 - t0
+            t_sq += t2 - t1
+            counts[lg.s] = {"components": nc, "squeezed": nk}
+    total = sum(edges) * args.steps
+    line = {
+        "metric": METRIC, "value": total / t_cc, "unit": "s-line edges/s (components)", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t_cc / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "s-connected components + ID squeezing of the power-law instance's L_s, "
+                               "S={1,2,4,8}", "s": S_SET, "edges": edges, "parallelism": "single GPU"},
+        "squeeze_edges_per_s": total / t_sq, "squeeze_ms_per_step": 1e3 * t_sq / args.steps,
+        "per_s": counts, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+    del outs
+    g.release()
+    ctx.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -396,7 +450,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("power_law", "batched", "served"), default="power_law",
+    ap.add_argument("--workload", choices=("power_law", "batched", "served", "components"), default="power_law",
                     help="power_law: the single large hypergraph (default); batched: 256 small "
                          "hypergraphs, each with its own s, as one disjoint-union batch")
     ap.add_argument("--no-tune", action="store_true", help="batched: library-default plan shape")
@@ -423,6 +477,8 @@ def main() -> int:
         return bench_batched(args)
     if args.workload == "served":
         return bench_served(args)
+    if args.workload == "components":
+        return bench_components(args)
     t_gen = time.perf_counter()
     inc = hg.power_law()
     t_gen = time.perf_counter() - t_gen
