@@ -67,7 +67,8 @@ constexpr int kCntClass = 0;                    // kNumLists: rows / slots per t
 constexpr int kCntErr = kCntClass + kNumLists;  // malformed-input flag (low 32 bits)
 constexpr int kCntFill = kCntErr + 1;           // kNumLists: append cursors of the tier lists
 constexpr int kCntHeavyWork = kCntFill + kNumLists;  // 2-paths in heavy rows
-constexpr int kCntTotal = kCntHeavyWork + 1;
+constexpr int kCntPieces = kCntHeavyWork + 1;     // large-row pieces of row planning
+constexpr int kCntTotal = kCntPieces + 1;
 static_assert(kCntTotal <= 32, "counter block");
 // Host staging slots for readbacks.
 constexpr int kHbSlots = kCntTotal;      // slot table size, then 2-paths, boundary entries
@@ -181,6 +182,7 @@ struct PlanBufs {
     int32_t *tail_beg = nullptr, *jmax = nullptr, *nslots = nullptr, *slot_row = nullptr;
     int64_t *work = nullptr, *work_pre = nullptr, *counters = nullptr, *part_m = nullptr;
     int64_t *bsize = nullptr, *bbase = nullptr, *hat = nullptr, *part_s = nullptr;
+    int64_t *pieces = nullptr;
     uint8_t *rclass = nullptr;
 };
 
@@ -389,7 +391,8 @@ hipError_t enqueue_rows(slg_plan *p, hipStream_t st) {
                                  b.nslots, b.rclass, b.bsize,
                                  reinterpret_cast<unsigned long long *>(b.counters + kCntClass),
                                  reinterpret_cast<int *>(b.counters + kCntErr),
-                                 reinterpret_cast<unsigned long long *>(b.counters + kCntHeavyWork), st)) !=
+                                 reinterpret_cast<unsigned long long *>(b.counters + kCntHeavyWork), b.pieces,
+                                 reinterpret_cast<unsigned long long *>(b.counters + kCntPieces), st)) !=
             hipSuccess)
             return e;
     }
@@ -494,6 +497,7 @@ slg_status plan_build(slg_plan *p) {
     phase1.add(&b.bbase, m + 1);
     phase1.add(&b.hat, m);
     phase1.add(&b.counters, 32);
+    phase1.add(&b.pieces, 3 * plan_pieces_cap(nnz));
     phase1.add(&b.part_m, scan_partials_size(m));
     phase1.add(&p->slot_base, m + 1);
     if (p->reserve) {

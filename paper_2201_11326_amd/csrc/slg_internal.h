@@ -82,6 +82,8 @@ hipError_t launch_exclusive_scan_i32(const int32_t *in, int64_t n, int64_t *out,
 hipError_t launch_exclusive_scan_u8(const uint8_t *in, int64_t n, int64_t *out, int64_t *partials,
                                     hipStream_t st);
 int64_t scan_partials_size(int64_t n);
+// Capacity of the large-row piece list of row planning.
+int64_t plan_pieces_cap(int64_t nnz);
 
 // K1: keep flags per incidence of the vertex CSR, then compaction.
 hipError_t launch_keep_incidence(int64_t nnz, const int32_t *v_idx, const int64_t *he_ptr, int64_t m,
@@ -95,7 +97,8 @@ hipError_t launch_compact_vertex_lists(int64_t n, int64_t nnz, const int64_t *v_
 hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t light_max, int64_t slot_work,
                            int32_t *tail_beg, int64_t *work, int32_t *jmax, int32_t *nslots, uint8_t *rclass,
                            int64_t *bsize, unsigned long long *class_count, int *err,
-                           unsigned long long *heavy_work, hipStream_t st);
+                           unsigned long long *heavy_work, int64_t *pieces, unsigned long long *num_pieces,
+                           hipStream_t st);
 hipError_t launch_fill_slots(int64_t m, const int64_t *he_ptr, const int64_t *slot_base,
                              const int32_t *nslots, const int32_t *jmax, const uint8_t *rclass,
                              const int64_t *bbase, int64_t *hat, int32_t *slot_row, int32_t *const *lists,

@@ -280,11 +280,14 @@ __device__ __forceinline__ int light_class(int64_t w) {
 }
 
 // Per-row work estimate (Section III-E's cost: the 2-paths of row i) and
-// tier, one lane per row for rows of at most kSmallRow members (their
-// members are walked serially), one wavefront per larger row. For every
-// incidence (i, v) of a kept row: tail_beg = first position after i in v's
-// (pruned) list; w_i = sum of the tails; jm = largest partner id.
+// tier. Rows of at most kSmallRow members are walked by one lane each; larger
+// rows are cut into pieces of kPlanPiece members, one wavefront per piece,
+// so that a run of large rows (an input sorted by size) spreads over the
+// whole grid. For every incidence (i, v) of a kept row: tail_beg = first
+// position after i in v's (pruned) list; w_i = sum of the tails; jm =
+// largest partner id.
 constexpr int kSmallRow = 16;
+constexpr int kPlanPiece = 256;
 
 struct RowPlanOut {
     int32_t *tail_beg;
@@ -348,11 +351,16 @@ __device__ __forceinline__ void plan_finish(int64_t i, int64_t p0, int64_t p1, i
     if (cls >= kHeavy) atomicAdd(hwork, (unsigned long long)w);
 }
 
+// Small rows, and the piece list of the large ones: a large row appends
+// ceil(size / kPlanPiece) entries (row | piece << 32), one row's pieces
+// side by side.
 __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min, int32_t light_max,
                                                        int64_t slot_work, RowPlanOut o,
                                                        unsigned long long *__restrict__ class_count,
                                                        int *__restrict__ err,
-                                                       unsigned long long *__restrict__ heavy_work) {
+                                                       unsigned long long *__restrict__ heavy_work,
+                                                       int64_t *__restrict__ pieces, int64_t pieces_cap,
+                                                       unsigned long long *__restrict__ num_pieces) {
     __shared__ unsigned long long ccount[kNumLists];
     __shared__ unsigned long long hwork;
     if (threadIdx.x < kNumLists) ccount[threadIdx.x] = 0;
@@ -362,7 +370,7 @@ __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min, 
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
     for (int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64 * 64; i0 < g.m; i0 += nwaves * 64) {
         const int64_t i = i0 + lane;
-        bool big = false;
+        unsigned long long np = 0;  // pieces of a large row
         if (i < g.m) {
             const int64_t p0 = g.he_ptr[i], p1 = g.he_ptr[i + 1];
             if (p0 < 0 || p1 > g.nnz || p1 < p0) {  // malformed pointers
@@ -370,8 +378,9 @@ __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min, 
             } else {
                 const int64_t size = p1 - p0;
                 const bool kept = size > 0 && size >= (g.row_s ? g.row_s[i] : s_min);
-                big = kept && size > kSmallRow;
-                if (!big) {  // a small (or pruned) row, walked by its own lane
+                if (kept && size > kSmallRow) {
+                    np = (unsigned long long)((size + kPlanPiece - 1) / kPlanPiece);
+                } else {  // a small (or pruned) row, walked by its own lane
                     int64_t w = 0;
                     int jm = -1;
                     bool rbad = false;
@@ -381,22 +390,90 @@ __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min, 
                 }
             }
         }
-        // the large rows of this group, one after another by the whole wavefront
-        unsigned long long todo = __ballot(big);
-        while (todo) {
-            const int l = __ffsll((long long)todo) - 1;
-            todo &= todo - 1;
-            const int64_t r = i0 + l;
-            const int64_t q0 = g.he_ptr[r], q1 = g.he_ptr[r + 1];
-            int64_t w = 0;
-            int jm = -1;
-            int rbad = 0;
-            for (int64_t p = q0 + lane; p < q1; p += 64) rbad |= !plan_member(g, r, p, o.tail_beg, w, jm);
-            w = wave_sum(w);
-            jm = wave_max(jm);
-            rbad = wave_max(rbad);
-            if (lane == 0) plan_finish(r, q0, q1, w, jm, rbad != 0, light_max, slot_work, o, ccount, &hwork, err);
+        // one reservation per wavefront for the pieces of its large rows
+        const unsigned long long incl = wave_incl_scan(np);
+        const unsigned long long total = __shfl(incl, 63);
+        if (total) {
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(num_pieces, total);
+            base = __shfl(base, 0) + incl - np;
+            // within the capacity unless the row pointers overlap (malformed)
+            for (unsigned long long k = 0; k < np; ++k) {
+                if (base + k < (unsigned long long)pieces_cap)
+                    pieces[base + k] = (int64_t)((unsigned long long)i | (k << 32));
+                else
+                    atomicOr(err, 1);
+            }
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumLists && ccount[threadIdx.x])
+        atomicAdd(&class_count[threadIdx.x], ccount[threadIdx.x]);
+    if (threadIdx.x == 0 && hwork) atomicAdd(heavy_work, hwork);
+}
+
+// One wavefront per piece of a large row: the piece's tails and its largest
+// partner id, into the piece's own partial slots.
+__global__ __launch_bounds__(256) void row_piece_kernel(Pruned g, int32_t *__restrict__ tail_beg,
+                                                        const int64_t *__restrict__ pieces, int64_t pieces_cap,
+                                                        const unsigned long long *__restrict__ num_pieces,
+                                                        int64_t *__restrict__ piece_w,
+                                                        int32_t *__restrict__ piece_jm, int *__restrict__ err) {
+    const int lane = lane_id();
+    const int64_t count = min((int64_t)*num_pieces, pieces_cap);
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; t < count; t += nwaves) {
+        const unsigned long long e = (unsigned long long)pieces[t];
+        const int64_t r = (int64_t)(e & 0xFFFFFFFFull), k = (int64_t)(e >> 32);
+        const int64_t q0 = g.he_ptr[r], q1 = g.he_ptr[r + 1];
+        const int64_t a = q0 + k * kPlanPiece, b = min(q1, a + kPlanPiece);
+        int64_t w = 0;
+        int jm = -1, rbad = 0;
+        for (int64_t p = a + lane; p < b; p += 64) rbad |= !plan_member(g, r, p, tail_beg, w, jm);
+        w = wave_sum(w);
+        jm = wave_max(jm);
+        rbad = wave_max(rbad);
+        if (lane == 0) {
+            piece_w[t] = w;
+            piece_jm[t] = jm;
+            if (rbad) atomicOr(err, 1);
+        }
+    }
+}
+
+// One lane per row's first piece: the row's totals from its pieces, then the
+// tier decision.
+__global__ __launch_bounds__(256) void row_piece_finish_kernel(Pruned g, int32_t light_max, int64_t slot_work,
+                                                               RowPlanOut o,
+                                                               unsigned long long *__restrict__ class_count,
+                                                               int *__restrict__ err,
+                                                               unsigned long long *__restrict__ heavy_work,
+                                                               const int64_t *__restrict__ pieces,
+                                                               int64_t pieces_cap,
+                                                               const unsigned long long *__restrict__ num_pieces,
+                                                               const int64_t *__restrict__ piece_w,
+                                                               const int32_t *__restrict__ piece_jm) {
+    __shared__ unsigned long long ccount[kNumLists];
+    __shared__ unsigned long long hwork;
+    if (threadIdx.x < kNumLists) ccount[threadIdx.x] = 0;
+    if (threadIdx.x == 0) hwork = 0;
+    __syncthreads();
+    const int64_t count = min((int64_t)*num_pieces, pieces_cap);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long e = (unsigned long long)pieces[t];
+        if (e >> 32) continue;  // not the row's first piece
+        const int64_t r = (int64_t)(e & 0xFFFFFFFFull);
+        const int64_t q0 = g.he_ptr[r], q1 = g.he_ptr[r + 1];
+        const int64_t np = min((q1 - q0 + kPlanPiece - 1) / kPlanPiece, count - t);
+        int64_t w = 0;
+        int jm = -1;
+        for (int64_t k = 0; k < np; ++k) {
+            w += piece_w[t + k];
+            jm = max(jm, piece_jm[t + k]);
+        }
+        // a malformed member has already set err
+        plan_finish(r, q0, q1, w, jm, false, light_max, slot_work, o, ccount, &hwork, err);
     }
     __syncthreads();
     if (threadIdx.x < kNumLists && ccount[threadIdx.x])
@@ -1668,6 +1745,13 @@ inline unsigned wave_grid(int64_t rows, int waves_per_block, int64_t cap) {
 // ---------------------------------------------------------------------------
 int64_t scan_partials_size(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
+// A large row of S > kSmallRow members has ceil(S / 256) <= (S + 255) / 256
+// <= S / 16 pieces (S >= 17): at most nnz / 16 in all when the rows do not
+// overlap. The piece list holds, per piece, its entry, its 2-paths (int64)
+// and its largest partner (int32): 3 * cap int64 in all.
+static_assert(kPlanPiece == 256 && kSmallRow >= 16, "piece bound");
+int64_t plan_pieces_cap(int64_t nnz) { return nnz / 16 + 1; }
+
 int heavy_resident(int device) {
     int cus = 0, per = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 0;
@@ -1730,13 +1814,24 @@ hipError_t launch_compact_vertex_lists(int64_t n, int64_t nnz, const int64_t *v_
 hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t light_max, int64_t slot_work,
                            int32_t *tail_beg, int64_t *work, int32_t *jmax, int32_t *nslots, uint8_t *rclass,
                            int64_t *bsize, unsigned long long *class_count, int *err,
-                           unsigned long long *heavy_work, hipStream_t st) {
+                           unsigned long long *heavy_work, int64_t *pieces, unsigned long long *num_pieces,
+                           hipStream_t st) {
     if (g.m <= 0) return hipSuccess;
     if (light_max <= 0 || light_max > kLightMax) light_max = kLightMax;
     if (slot_work <= 0) slot_work = kSlotWork;
     const RowPlanOut o{tail_beg, work, jmax, nslots, rclass, bsize};
     row_plan_kernel<<<wave_grid((g.m + 63) / 64, 4, 8192), 256, 0, st>>>(g, s_min, light_max, slot_work, o,
-                                                                          class_count, err, heavy_work);
+                                                                          class_count, err, heavy_work, pieces,
+                                                                          plan_pieces_cap(g.nnz), num_pieces);
+    // the piece count is known on the device only: grids for the bound
+    const int64_t cap = plan_pieces_cap(g.nnz);
+    int64_t *piece_w = pieces + cap;
+    int32_t *piece_jm = reinterpret_cast<int32_t *>(pieces + 2 * cap);
+    row_piece_kernel<<<wave_grid(cap, 4, 4096), 256, 0, st>>>(g, tail_beg, pieces, cap, num_pieces, piece_w,
+                                                              piece_jm, err);
+    row_piece_finish_kernel<<<grid_for(cap, 256), 256, 0, st>>>(g, light_max, slot_work, o, class_count, err,
+                                                                heavy_work, pieces, cap, num_pieces, piece_w,
+                                                                piece_jm);
     return hipGetLastError();
 }
 

@@ -77,6 +77,29 @@ def test_random_skewed_full(ctx, seed, m, n, kmax, expo, s_list):
     assert outs[0].two_paths == oracle.two_paths(inc, s_list[0])
 
 
+def _rows_in_order(inc, order):
+    """The same hypergraph with hyperedge k holding the old row order[k]."""
+    sizes = np.diff(inc.he_ptr)[order]
+    he_ptr = np.zeros(inc.m + 1, np.int64)
+    np.cumsum(sizes, out=he_ptr[1:])
+    src = np.repeat(inc.he_ptr[order] - he_ptr[:-1], sizes) + np.arange(he_ptr[-1])
+    return hg.from_csr(inc.m, inc.n, he_ptr, inc.he_idx[src])
+
+
+@pytest.mark.parametrize("direction", ["ascending", "descending"])
+def test_rows_sorted_by_size_full(ctx, direction):
+    # runs of large rows side by side (up to 600 members: several planning
+    # pieces per row), as in an input relabelled by degree
+    inc = hg.random_small(111, 1500, 3000, 600, 0.8)
+    sizes = np.diff(inc.he_ptr)
+    order = np.argsort(sizes if direction == "ascending" else -sizes, kind="stable")
+    inc = _rows_in_order(inc, order)
+    outs = run_gpu(ctx, inc, [1, 2, 40])
+    for lg in outs:
+        assert_matches_oracle(inc, lg, lg.s, direction)
+    assert outs[0].two_paths == oracle.two_paths(inc, 1)
+
+
 def test_heavy_rank_windows_full(ctx):
     # half of the rows share vertex 0: partner sets of several thousand per
     # row, more than one LDS rank window per slot
