@@ -280,6 +280,27 @@ def toy_paper_example() -> Incidence:
     return from_rows([[0, 1, 2], [1, 2, 3], [0, 1, 2, 3, 4], [4, 5]], n=6)
 
 
+def random_upper_edges(seed: int, m: int, count: int, exponent: float = 1.0, wmax: int = 50):
+    """A seeded edge list shaped like the upper triangle of an s-line graph,
+    for tests of the edge-list operations: about `count` distinct pairs i < j
+    over m ids, the ends drawn with weight ~ rank^-exponent (a few hub ids,
+    permuted over the id space), sorted by (i, j), with weights in
+    [1, wmax]. Returns (row_ptr int64[m+1], row, col, w int32)."""
+    rng = np.random.default_rng(seed)
+    cdf = _rank_cdf(m, exponent)
+    perm = rng.permutation(m)
+    a = perm[np.searchsorted(cdf, rng.random(count) * cdf[-1], side="right").clip(0, m - 1)]
+    b = perm[np.searchsorted(cdf, rng.random(count) * cdf[-1], side="right").clip(0, m - 1)]
+    lo, hi = np.minimum(a, b), np.maximum(a, b)
+    key = np.unique(lo[lo < hi].astype(np.int64) * m + hi[lo < hi])
+    row = (key // m).astype(np.int32)
+    col = (key % m).astype(np.int32)
+    w = rng.integers(1, wmax + 1, size=key.size).astype(np.int32)
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(np.bincount(row, minlength=m), out=row_ptr[1:])
+    return row_ptr, row, col, w
+
+
 def stats(inc: Incidence) -> dict:
     sz = inc.sizes()
     dv = np.diff(inc.v_ptr)

@@ -282,7 +282,7 @@ slg_status slg_components(slg_context *ctx, slg_graph *g, int32_t s, const int32
                           int64_t num_edges, int32_t *labels, int64_t *num_components, void *stream);
 
 /*
- * ID squeezing (Stage 4 of the paper's pipeline, Section III): hyperedges
+ * ID squeezing (Stage 4 of the paper's framework, Section IV): hyperedges
  * that are an end of at least one edge keep their order and are renumbered
  * 0, 1, ...: new_id DEVICE int32[m] gets the new id or -1; *num_kept (may
  * be NULL) their number. With remap != 0, row/col (DEVICE int32[num_edges])
@@ -292,6 +292,26 @@ slg_status slg_components(slg_context *ctx, slg_graph *g, int32_t s, const int32
  */
 slg_status slg_squeeze(slg_context *ctx, int64_t m, int32_t *row, int32_t *col, int64_t num_edges, int32_t remap,
                        int32_t *new_id, int64_t *num_kept, void *stream);
+
+/*
+ * Symmetric CSR of one s-line graph (Stage 4 of the paper's framework,
+ * Section IV: the edge list becomes the graph's adjacency; L_s is the
+ * symmetric matrix of Section II-B). Input: the upper triangle of L_s as
+ * emitted (slg_plan_emit, slg_result_csr/coo): row_ptr DEVICE int64[m+1],
+ * row/col/w DEVICE int32[num_edges], sorted by (row, col), row < col.
+ * Output, caller-allocated DEVICE buffers: sym_ptr int64[m+1], sym_col and
+ * sym_w int32[2 * num_edges]; row r lists every partner of r in ascending
+ * order with its overlap. w and sym_w may both be NULL (structure only).
+ * Ordered on `stream`; returns after the stream has reached the end of the
+ * call. Device scratch: 12 (8 without weights) bytes per edge for one
+ * 8-bit radix pass, twice that for m > 256.
+ * Errors: INVALID_ARG (null arrays, m outside [0, 2^31), w without sym_w,
+ * or an input that is not such an upper triangle; the outputs are then
+ * unspecified), OUT_OF_MEMORY.
+ */
+slg_status slg_symmetrize(slg_context *ctx, int64_t m, const int64_t *row_ptr, const int32_t *row,
+                          const int32_t *col, const int32_t *w, int64_t num_edges, int64_t *sym_ptr,
+                          int32_t *sym_col, int32_t *sym_w, void *stream);
 
 /*
  * Served form: a request loop over device-resident hypergraphs. Queries

@@ -190,7 +190,7 @@ def components(inc, s: int, row: Optional[np.ndarray] = None, col: Optional[np.n
 
 
 def squeeze(m: int, row: np.ndarray, col: np.ndarray):
-    """ID squeezing (Stage 4 of Section III): hyperedges that end at least one
+    """ID squeezing (Stage 4 of the framework, Section IV): hyperedges that end at least one
     edge keep their order and are numbered 0, 1, ...; (new_id int32[m] with
     -1 for the others, number kept)."""
     present = np.zeros(m, dtype=bool)
@@ -199,3 +199,22 @@ def squeeze(m: int, row: np.ndarray, col: np.ndarray):
     new_id = np.full(m, -1, dtype=np.int32)
     new_id[present] = np.arange(int(present.sum()), dtype=np.int32)
     return new_id, int(present.sum())
+
+
+def symmetric(m: int, row: np.ndarray, col: np.ndarray, w: Optional[np.ndarray] = None):
+    """Symmetric CSR of L_s (Stage 4 of the framework, Section IV; the
+    adjacency of L_s is the symmetric matrix of Section II-B): every edge
+    {i, j} appears in row i and in row j, each row in ascending order.
+    Returns (ptr int64[m+1], col int32[2E], w int32[2E] or None)."""
+    row = np.asarray(row, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    r = np.concatenate([row, col])
+    c = np.concatenate([col, row])
+    order = np.lexsort((c, r))  # by row, then column
+    ptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r, minlength=m)[:m], out=ptr[1:])
+    ww = None
+    if w is not None:
+        w = np.asarray(w, dtype=np.int32)
+        ww = np.concatenate([w, w])[order]
+    return ptr, c[order].astype(np.int32), ww

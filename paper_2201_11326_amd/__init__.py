@@ -120,6 +120,7 @@ def lib() -> ctypes.CDLL:
         "slg_result_free": (_i32, [_p]),
         "slg_components": (_i32, [_p, _p, _i32, _p, _p, _i64, _p, ctypes.POINTER(_i64), _p]),
         "slg_squeeze": (_i32, [_p, _i64, _p, _p, _i64, _i32, _p, ctypes.POINTER(_i64), _p]),
+        "slg_symmetrize": (_i32, [_p, _i64, _p, _p, _p, _p, _i64, _p, _p, _p, _p]),
         "slg_server_create": (_i32, [_p, _i32, _u64, ctypes.POINTER(_p)]),
         "slg_server_submit": (_i32, [_p, _p, ctypes.POINTER(_i32), _i32, ctypes.POINTER(_u64)]),
         "slg_server_wait": (_i32, [_p, _u64, _i32, ctypes.POINTER(_p), ctypes.POINTER(RequestInfo)]),
@@ -458,6 +459,24 @@ class Context:
                                       1 if remap else 0, new_id.data_ptr(), ctypes.byref(nk),
                                       _stream_handle(stream)))
         return new_id, int(nk.value)
+
+    def symmetrize(self, lg: "LineGraph", weights: bool = True, stream=None):
+        """Symmetric CSR of L_s from its upper triangle: (sym_ptr int64[m+1],
+        sym_col int32[2E], sym_w int32[2E] or None) on the device; row r holds
+        every partner of r, ascending."""
+        import torch
+        dev = f"cuda:{self.device}"
+        m = int(lg.row_ptr.shape[0]) - 1
+        e = int(lg.num_edges)
+        row = _need_rows(lg)
+        sym_ptr = torch.empty(m + 1, dtype=torch.int64, device=dev)
+        sym_col = torch.empty(max(2 * e, 1), dtype=torch.int32, device=dev)[: 2 * e]
+        sym_w = torch.empty(max(2 * e, 1), dtype=torch.int32, device=dev)[: 2 * e] if weights else None
+        self._check(lib().slg_symmetrize(self.handle, m, lg.row_ptr.data_ptr(), row.data_ptr(), lg.col.data_ptr(),
+                                         lg.w.data_ptr() if weights else None, e, sym_ptr.data_ptr(),
+                                         sym_col.data_ptr(), sym_w.data_ptr() if weights else None,
+                                         _stream_handle(stream)))
+        return sym_ptr, sym_col, sym_w
 
     def server(self, workers: int = 4, mem_budget_bytes: int = 0) -> "Server":
         """The served form (slg_server_*): a request loop over registered graphs."""

@@ -10,8 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libslg.so")
-SOURCES = [os.path.join(CSRC, "slg_kernels.hip"), os.path.join(CSRC, "slg_api.cpp"),
-           os.path.join(CSRC, "slg_server.cpp"), os.path.join(CSRC, "slg_arena.cpp")]
+SOURCES = [os.path.join(CSRC, name) for name in
+           ("slg_kernels.hip", "slg_sort.hip", "slg_api.cpp", "slg_server.cpp", "slg_arena.cpp")]
 ARCH = "gfx950"
 
 

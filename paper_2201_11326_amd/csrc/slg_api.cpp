@@ -105,6 +105,10 @@ struct Scratch {
     hipStream_t st = nullptr;
     slg::Arena *arena = nullptr;
     std::vector<void *> ptrs;
+    Scratch() = default;
+    Scratch(const Scratch &) = delete;
+    Scratch &operator=(const Scratch &) = delete;
+    ~Scratch() { release(); }  // an early error return gives the blocks back too
     hipError_t get(void **p, size_t bytes) {
         *p = nullptr;
         if (bytes == 0) bytes = 8;
@@ -1229,6 +1233,58 @@ slg_status slg_squeeze(slg_context *ctx, int64_t m, int32_t *row, int32_t *col, 
     if (remap) SLG_HIP(ctx, launch_remap_edges(row, col, num_edges, new_id, st));
     sc.release();
     if (num_kept) *num_kept = ctx->pinned[1];
+    return SLG_OK;
+}
+
+slg_status slg_symmetrize(slg_context *ctx, int64_t m, const int64_t *row_ptr, const int32_t *row,
+                          const int32_t *col, const int32_t *w, int64_t num_edges, int64_t *sym_ptr,
+                          int32_t *sym_col, int32_t *sym_w, void *stream) {
+    if (!ctx || m < 0 || m >= (int64_t(1) << 31) || num_edges < 0 || !row_ptr || !sym_ptr ||
+        (num_edges > 0 && (!row || !col || !sym_col)) || (!w) != (!sym_w))
+        return fail(ctx, SLG_ERR_INVALID_ARG, "bad symmetrize arguments");
+    SLG_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = num_edges;
+    int key_bits = 0;  // columns lie in [0, m)
+    while ((int64_t(1) << key_bits) < m) ++key_bits;
+    const int passes = sort_passes(key_bits);
+    const int digit = passes ? (key_bits + passes - 1) / passes : 0;
+    const int64_t hist_n = passes ? (int64_t(1) << digit) * sort_chunks(n) : 0;
+    Scratch sc;
+    sc.st = st;
+    sc.arena = ctx->arena.get();
+    int64_t *err = nullptr, *lower_ptr = nullptr, *off = nullptr, *part = nullptr;
+    int32_t *hist = nullptr, *buf[2][3] = {};
+    SLG_HIP(ctx, sc.get(&err, 1));
+    SLG_HIP(ctx, sc.get(&lower_ptr, m + 1));
+    if (passes && n > 0) {
+        SLG_HIP(ctx, sc.get(&hist, hist_n));
+        SLG_HIP(ctx, sc.get(&off, hist_n + 1));  // the scan also writes the total
+        SLG_HIP(ctx, sc.get(&part, scan_partials_size(hist_n)));
+        for (int h = 0; h < (passes > 1 ? 2 : 1); ++h)
+            for (int a = 0; a < (w ? 3 : 2); ++a) SLG_HIP(ctx, sc.get(&buf[h][a], n));
+    }
+    SLG_HIP(ctx, launch_fill_i64(err, 1, 0, st));
+    SLG_HIP(ctx, launch_check_upper(row_ptr, row, col, n, m, reinterpret_cast<int *>(err), st));
+    // the upper triangle sorted by column (stable: rows stay ascending)
+    const int32_t *k_in = col, *a_in = row, *b_in = w;
+    for (int p = 0; p < passes && n > 0; ++p) {
+        int32_t *const *out = buf[p & 1];
+        const int shift = p * digit;
+        const int bits = std::min(digit, key_bits - shift);
+        SLG_HIP(ctx, launch_sort_pass(k_in, a_in, b_in, n, shift, bits, hist, off, part, out[0], out[1], out[2],
+                                      st));
+        k_in = out[0];
+        a_in = out[1];
+        b_in = out[2];
+    }
+    SLG_HIP(ctx, launch_symmetric(k_in, a_in, b_in, row_ptr, row, col, w, n, m, lower_ptr, sym_ptr, sym_col, sym_w,
+                                  st));
+    SLG_HIP(ctx, hipMemcpyAsync(ctx->pinned, err, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SLG_HIP(ctx, hipStreamSynchronize(st));
+    sc.release();
+    if (ctx->pinned[0] & 1)
+        return fail(ctx, SLG_ERR_INVALID_ARG, "input is not an upper triangle sorted by (row, col)");
     return SLG_OK;
 }
 

@@ -170,6 +170,28 @@ hipError_t launch_squeeze_ids(int64_t m, const int32_t *flag, const int64_t *pre
 hipError_t launch_remap_edges(int32_t *row, int32_t *col, int64_t num_edges, const int32_t *new_id,
                               hipStream_t st);
 
+// Stable LSD radix sort (slg_sort.hip): one pass orders items by the digit
+// (key >> shift) & (2^bits - 1), bits <= kSortDigitBits, keeping the order of
+// equal digits; a, b: optional int32 payloads (b only with a). hist:
+// int32[2^bits * sort_chunks(n)], off: int64 of that count + 1, partials:
+// scan_partials_size of that count.
+constexpr int kSortDigitBits = 8;
+int64_t sort_chunks(int64_t n);
+int sort_passes(int key_bits);
+hipError_t launch_sort_pass(const int32_t *key_in, const int32_t *a_in, const int32_t *b_in, int64_t n, int shift,
+                            int bits, int32_t *hist, int64_t *off, int64_t *partials, int32_t *key_out,
+                            int32_t *a_out, int32_t *b_out, hipStream_t st);
+// err |= 1 unless (row_ptr, row, col) is an upper triangle in CSR order.
+hipError_t launch_check_upper(const int64_t *row_ptr, const int32_t *row, const int32_t *col, int64_t n, int64_t m,
+                              int *err, hipStream_t st);
+// Symmetric CSR from the upper triangle (row_ptr, row, col, w) and the same
+// edges sorted by column (skey = column, srow, sw); w / sw / sym_w may be
+// null together. lower_ptr: int64[m+1] scratch.
+hipError_t launch_symmetric(const int32_t *skey, const int32_t *srow, const int32_t *sw, const int64_t *row_ptr,
+                            const int32_t *row, const int32_t *col, const int32_t *w, int64_t n, int64_t m,
+                            int64_t *lower_ptr, int64_t *sym_ptr, int32_t *sym_col, int32_t *sym_w,
+                            hipStream_t st);
+
 // Validation kernels (SLG_VALIDATE).
 hipError_t launch_validate_ptr(const int64_t *ptr, int64_t rows, int64_t nnz, int *err,
                                hipStream_t st);

@@ -85,3 +85,20 @@ def load_toy_components(path: str = os.path.join(GOLDEN, "toy_components.txt")):
             vals = [int(x) for x in tok[2:]]
             (cc if tok[0] == "cc" else sq)[int(tok[1])] = vals
     return cc, sq
+
+
+def load_toy_symmetric(path: str = os.path.join(GOLDEN, "toy_symmetric.txt")):
+    """Parse the symmetric-adjacency fixture -> {s: [[(partner, overlap), ...] per row]}."""
+    out = {}
+    with open(path) as f:
+        for raw in f:
+            line = raw.split("#", 1)[0].strip()
+            if not line:
+                continue
+            tok = line.split()
+            s, r = int(tok[1]), int(tok[2])
+            rows = out.setdefault(s, [])
+            while len(rows) <= r:
+                rows.append([])
+            rows[r] = [tuple(int(x) for x in t.split(":")) for t in tok[3:]]
+    return out

@@ -1,5 +1,5 @@
-"""s-connected components and ID squeezing on the device, through the C
-ABI, against the oracle (labels and new ids bit for bit)."""
+"""s-connected components, ID squeezing and the symmetric CSR on the
+device, through the C ABI, against the oracle (bit for bit)."""
 from __future__ import annotations
 
 import numpy as np
@@ -8,7 +8,7 @@ import pytest
 import hypergen as hg
 import oracle
 from gpu_util import planted
-from helpers import load_toy, load_toy_components
+from helpers import load_toy, load_toy_components, load_toy_symmetric
 
 pytestmark = pytest.mark.gpu
 
@@ -35,6 +35,11 @@ def check(ctx, inc, s_list, what):
         ref, ref_count = oracle.components(inc, lg.s, ref_lg.i, ref_lg.j)
         np.testing.assert_array_equal(labels.cpu().numpy(), ref, err_msg=f"{what} s={lg.s} labels")
         assert count == ref_count, (what, lg.s)
+        sym_ptr, sym_col, sym_w = ctx.symmetrize(lg)
+        ref_ptr, ref_col, ref_w = oracle.symmetric(inc.m, ref_lg.i, ref_lg.j, ref_lg.w)
+        np.testing.assert_array_equal(sym_ptr.cpu().numpy(), ref_ptr, err_msg=f"{what} s={lg.s} sym_ptr")
+        np.testing.assert_array_equal(sym_col.cpu().numpy(), ref_col, err_msg=f"{what} s={lg.s} sym_col")
+        np.testing.assert_array_equal(sym_w.cpu().numpy(), ref_w, err_msg=f"{what} s={lg.s} sym_w")
         new_id, kept = ctx.squeeze(inc.m, lg)
         ref_id, ref_kept = oracle.squeeze(inc.m, ref_lg.i, ref_lg.j)
         np.testing.assert_array_equal(new_id.cpu().numpy(), ref_id, err_msg=f"{what} s={lg.s} squeeze")
@@ -57,6 +62,10 @@ def test_worked_example(ctx):
         assert count == len({l for l in cc[s] if l >= 0})
         new_id, kept = ctx.squeeze(inc.m, lg)
         assert new_id.cpu().tolist() == sq[s]
+        sym_ptr, sym_col, sym_w = ctx.symmetrize(lg)
+        ptr, col, w = sym_ptr.cpu().numpy(), sym_col.cpu().numpy(), sym_w.cpu().numpy()
+        rows = [list(zip(col[ptr[r]:ptr[r + 1]].tolist(), w[ptr[r]:ptr[r + 1]].tolist())) for r in range(inc.m)]
+        assert rows == load_toy_symmetric()[s], f"s={s}"
     g.release()
 
 

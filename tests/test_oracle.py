@@ -13,7 +13,7 @@ from hypothesis import given, settings, strategies as st
 
 import hypergen as hg
 import oracle
-from helpers import brute_force_sets, edges_of, load_toy, rows_of, load_toy_components
+from helpers import brute_force_sets, edges_of, load_toy, rows_of, load_toy_components, load_toy_symmetric
 
 
 # --- the worked example of Section I (hand-enumerated fixture) -------------
@@ -302,3 +302,54 @@ def test_squeeze_is_the_order_preserving_rank_of_the_edge_ends():
     assert kept == len(ends)
     assert [int(new_id[e]) for e in ends] == list(range(kept))
     assert all(new_id[i] == -1 for i in range(m) if i not in set(ends))
+
+
+# --- symmetric CSR (Stage 4) ----------------------------------------------
+
+def _sym_rows(ptr, col, w):
+    return [list(zip(col[ptr[r]:ptr[r + 1]].tolist(), w[ptr[r]:ptr[r + 1]].tolist()))
+            for r in range(len(ptr) - 1)]
+
+
+def test_symmetric_of_the_worked_example():
+    inc, _, _, _ = load_toy()
+    want = load_toy_symmetric()
+    for s in (1, 2, 3, 4):
+        lg = oracle.line_graph(inc, s)
+        ptr, col, w = oracle.symmetric(inc.m, lg.i, lg.j, lg.w)
+        assert _sym_rows(ptr, col, w) == want[s], f"s={s}"
+
+
+@pytest.mark.parametrize("seed,m,n,kmax,expo", [(11, 300, 90, 14, 1.0), (12, 200, 400, 9, None)])
+def test_symmetric_matches_scipy_thresholded_product(seed, m, n, kmax, expo):
+    # off the diagonal, the thresholded H^T H on E_s is the symmetric
+    # adjacency of L_s; scipy's CSR with sorted indices is its row form
+    inc = hg.random_small(seed, m, n, kmax, expo)
+    H = sp.csr_matrix((np.ones(inc.nnz, np.int64), inc.he_idx, inc.he_ptr), shape=(inc.m, inc.n))
+    G = (H @ H.T).tocsr()
+    sizes = inc.sizes()
+    for s in (1, 2, 4):
+        off = sizes < s
+        A = G.tolil()
+        A.setdiag(0)
+        A = A.tocsr()
+        A = sp.diags((~off).astype(np.int64)) @ A @ sp.diags((~off).astype(np.int64))
+        A.data[A.data < s] = 0
+        A.eliminate_zeros()
+        A.sort_indices()
+        lg = oracle.line_graph(inc, s)
+        ptr, col, w = oracle.symmetric(inc.m, lg.i, lg.j, lg.w)
+        np.testing.assert_array_equal(ptr, A.indptr)
+        np.testing.assert_array_equal(col, A.indices)
+        np.testing.assert_array_equal(w, A.data)
+
+
+def test_symmetric_is_its_own_transpose_and_doubles_the_edges():
+    inc = hg.random_small(13, 400, 150, 12, 0.9)
+    lg = oracle.line_graph(inc, 2)
+    ptr, col, w = oracle.symmetric(inc.m, lg.i, lg.j, lg.w)
+    assert ptr[-1] == 2 * len(lg.j)
+    rows = np.repeat(np.arange(inc.m), np.diff(ptr))
+    fwd = set(zip(rows.tolist(), col.tolist(), w.tolist()))
+    assert fwd == set(zip(col.tolist(), rows.tolist(), w.tolist()))
+    assert all(np.all(np.diff(col[ptr[r]:ptr[r + 1]]) > 0) for r in range(inc.m))
