@@ -46,70 +46,144 @@ __global__ __launch_bounds__(kSortThreads) void sort_hist_kernel(const int32_t *
     }
 }
 
-// Stable scatter of every chunk. A round holds kSortThreads consecutive
-// items, one per thread; an item's place among the equal digits of its round
-// is the count of such items in lower wavefronts (LDS counts) plus those in
-// lower lanes of its own wavefront (ballots on the digit bits), so items keep
-// their order. `run` holds the next output position of every digit.
+// Stable scatter of every chunk, a tile of kSortTile items at a time. An
+// item's rank among the equal digits of its tile counts such items in
+// earlier rounds (LDS running counts), in lower wavefronts of its round (LDS
+// counts) and in lower lanes of its wavefront (ballots on the digit bits),
+// so items keep their order. The tile is then reordered by digit in LDS and
+// written out in runs, which keeps the HBM writes of a digit contiguous.
+// `run` holds the next output position of every digit.
+constexpr int kTileRounds = 16;
+constexpr int kSortTile = kSortThreads * kTileRounds;
+static_assert(kSortRounds % kTileRounds == 0, "a chunk is whole tiles");
+
 template <int NP>
 __global__ __launch_bounds__(kSortThreads) void sort_scatter_kernel(
     const int32_t *__restrict__ key_in, const int32_t *__restrict__ a_in, const int32_t *__restrict__ b_in,
     int64_t n, int shift, int bits, int64_t nchunks, const int64_t *__restrict__ off,
     int32_t *__restrict__ key_out, int32_t *__restrict__ a_out, int32_t *__restrict__ b_out) {
     __shared__ int64_t run[kSortBins];
+    __shared__ int cnt[kSortBins];          // tile counts so far, then the tile's digit starts
     __shared__ int wcnt[kSortWaves][kSortBins];
+    __shared__ int wsum[kSortWaves];
+    __shared__ int32_t tk[kSortTile];
+    __shared__ int32_t ta[NP > 0 ? kSortTile : 1];
+    __shared__ int32_t tb[NP > 1 ? kSortTile : 1];
     const int nb = 1 << bits;
     const unsigned mask = (unsigned)nb - 1u;
-    const int wave = threadIdx.x >> 6;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int t = threadIdx.x; t < kSortWaves * kSortBins; t += kSortThreads) (&wcnt[0][0])[t] = 0;
+    for (int t = threadIdx.x; t < kSortBins; t += kSortThreads) cnt[t] = 0;
     for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
         for (int d = threadIdx.x; d < nb; d += kSortThreads) run[d] = off[(int64_t)d * nchunks + c];
         __syncthreads();
-        const int64_t base = c * kSortChunk;
-        for (int r = 0; r < kSortRounds; ++r) {
-            const int64_t r0 = base + (int64_t)r * kSortThreads;  // the same for the whole workgroup
-            if (r0 >= n) break;
-            const int64_t q = r0 + threadIdx.x;
-            const bool valid = q < n;
-            unsigned k = 0;
-            int32_t a = 0, b = 0;
-            if (valid) {
-                k = (unsigned)key_in[q];
-                if (NP > 0) a = a_in[q];
-                if (NP > 1) b = b_in[q];
+        for (int64_t t0 = c * kSortChunk; t0 < min(n, (c + 1) * kSortChunk); t0 += kSortTile) {
+            const int tn = (int)min((int64_t)kSortTile, n - t0);  // items in this tile
+            unsigned key[kTileRounds];
+            int32_t pa[kTileRounds], pb[kTileRounds];
+            int rk[kTileRounds];
+#pragma unroll
+            for (int r = 0; r < kTileRounds; ++r) {
+                const int i = r * kSortThreads + threadIdx.x;
+                key[r] = i < tn ? (unsigned)key_in[t0 + i] : 0u;
+                if (NP > 0) pa[r] = i < tn ? a_in[t0 + i] : 0;
+                if (NP > 1) pb[r] = i < tn ? b_in[t0 + i] : 0;
             }
-            const unsigned d = (k >> shift) & mask;
-            unsigned long long peers = __ballot(valid);
-            for (int i = 0; i < bits; ++i) {
-                const bool bit = (d >> i) & 1u;
-                const unsigned long long bb = __ballot(bit);
-                peers &= bit ? bb : ~bb;
-            }
-            const int rank = lanes_below(peers);
-            if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
-            __syncthreads();
-            if (valid) {
+#pragma unroll
+            for (int r = 0; r < kTileRounds; ++r) {
+                const bool valid = r * kSortThreads + (int)threadIdx.x < tn;
+                const unsigned d = (key[r] >> shift) & mask;
+                unsigned long long peers = __ballot(valid);
+                for (int i = 0; i < bits; ++i) {
+                    const bool bit = (d >> i) & 1u;
+                    const unsigned long long bb = __ballot(bit);
+                    peers &= bit ? bb : ~bb;
+                }
+                const int rank = lanes_below(peers);
+                if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
+                __syncthreads();
                 int pre = 0;
                 for (int w = 0; w < wave; ++w) pre += wcnt[w][d];
-                const int64_t pos = run[d] + pre + rank;
-                key_out[pos] = (int32_t)k;
-                if (NP > 0) a_out[pos] = a;
-                if (NP > 1) b_out[pos] = b;
+                rk[r] = cnt[d] + pre + rank;  // rank within the tile's digit d
+                __syncthreads();
+                for (int dd = threadIdx.x; dd < nb; dd += kSortThreads) {
+                    int tot = 0;
+#pragma unroll
+                    for (int w = 0; w < kSortWaves; ++w) {
+                        tot += wcnt[w][dd];
+                        wcnt[w][dd] = 0;
+                    }
+                    cnt[dd] += tot;
+                }
+                __syncthreads();
+            }
+            // digit starts within the tile (exclusive scan of cnt)
+            {
+                int v[kSortBins / kSortThreads > 0 ? kSortBins / kSortThreads : 1];
+                int mine = 0;
+                constexpr int per = kSortBins / kSortThreads > 0 ? kSortBins / kSortThreads : 1;
+#pragma unroll
+                for (int j = 0; j < per; ++j) {
+                    const int d = threadIdx.x * per + j;
+                    v[j] = d < nb ? cnt[d] : 0;
+                    mine += v[j];
+                }
+                int incl = mine;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int y = __shfl_up(incl, o);
+                    if (lane >= o) incl += y;
+                }
+                if (lane == 63) wsum[wave] = incl;
+                __syncthreads();
+                int base = incl - mine;
+                for (int w = 0; w < wave; ++w) base += wsum[w];
+#pragma unroll
+                for (int j = 0; j < per; ++j) {
+                    const int d = threadIdx.x * per + j;
+                    if (d < nb) cnt[d] = base;  // start of digit d in the tile
+                    base += v[j];
+                }
+                __syncthreads();
+            }
+            // reorder by digit in LDS
+#pragma unroll
+            for (int r = 0; r < kTileRounds; ++r) {
+                if (r * kSortThreads + (int)threadIdx.x < tn) {
+                    const unsigned d = (key[r] >> shift) & mask;
+                    const int q = cnt[d] + rk[r];
+                    tk[q] = (int32_t)key[r];
+                    if (NP > 0) ta[q] = pa[r];
+                    if (NP > 1) tb[q] = pb[r];
+                }
             }
             __syncthreads();
-            for (int dd = threadIdx.x; dd < nb; dd += kSortThreads) {
-                int tot = 0;
-#pragma unroll
-                for (int w = 0; w < kSortWaves; ++w) {
-                    tot += wcnt[w][dd];
-                    wcnt[w][dd] = 0;
-                }
-                run[dd] += tot;
+            // runs of equal digits to their places
+            for (int q = threadIdx.x; q < tn; q += kSortThreads) {
+                const int32_t k = tk[q];
+                const unsigned d = ((unsigned)k >> shift) & mask;
+                const int64_t pos = run[d] + (q - cnt[d]);
+                key_out[pos] = k;
+                if (NP > 0) a_out[pos] = ta[q];
+                if (NP > 1) b_out[pos] = tb[q];
             }
+            __syncthreads();
+            // next tile: advance the digit positions, clear the counts
+            for (int d = threadIdx.x; d < nb; d += kSortThreads) {
+                const int end = d + 1 < nb ? cnt[d + 1] : tn;
+                run[d] += end - cnt[d];
+            }
+            __syncthreads();
+            for (int d = threadIdx.x; d < kSortBins; d += kSortThreads) cnt[d] = 0;
             __syncthreads();
         }
     }
 }
+
+// The flat kernels below give every thread kFlat items per grid step, loaded
+// before any is used, so that enough loads are in flight to cover HBM
+// latency.
+constexpr int kFlat = 4;
 
 // Checks that (row_ptr, row, col) is the upper triangle of a graph on m
 // vertices in CSR order: row[e] = r for e in [row_ptr[r], row_ptr[r+1]),
@@ -117,14 +191,29 @@ __global__ __launch_bounds__(kSortThreads) void sort_scatter_kernel(
 __global__ void check_upper_kernel(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ row,
                                    const int32_t *__restrict__ col, int64_t n, int64_t m, int *__restrict__ err) {
     bool bad = false;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t r = row[e], c = col[e];
-        if (r < 0 || r >= m || c <= r || c >= m) {
-            bad = true;
-            continue;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * kFlat;
+    for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x * kFlat + threadIdx.x; e0 < n; e0 += step) {
+        int32_t r[kFlat], c[kFlat], rp[kFlat], cp[kFlat];
+#pragma unroll
+        for (int j = 0; j < kFlat; ++j) {
+            const int64_t e = e0 + (int64_t)j * blockDim.x;
+            const bool in = e < n;
+            r[j] = in ? row[e] : 0;
+            c[j] = in ? col[e] : 1;
+            rp[j] = (in && e > 0) ? row[e - 1] : -1;
+            cp[j] = (in && e > 0) ? col[e - 1] : -1;
         }
-        if (e < row_ptr[r] || e >= row_ptr[r + 1]) bad = true;
-        if (e > 0 && row[e - 1] == r && col[e - 1] >= c) bad = true;
+#pragma unroll
+        for (int j = 0; j < kFlat; ++j) {
+            const int64_t e = e0 + (int64_t)j * blockDim.x;
+            if (e >= n) continue;
+            if (r[j] < 0 || r[j] >= m || c[j] <= r[j] || c[j] >= m) {
+                bad = true;
+                continue;
+            }
+            if (e < row_ptr[r[j]] || e >= row_ptr[r[j] + 1]) bad = true;
+            if (rp[j] == r[j] && cp[j] >= c[j]) bad = true;
+        }
     }
     if (bad) atomicOr(err, 1);
 }
@@ -169,13 +258,26 @@ __global__ void sym_lower_kernel(const int32_t *__restrict__ skey, const int32_t
                                  const int32_t *__restrict__ sw, int64_t n, int64_t m,
                                  const int64_t *__restrict__ row_ptr, int32_t *__restrict__ sym_col,
                                  int32_t *__restrict__ sym_w) {
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t c = skey[p];
-        if (c < 0 || c >= m) continue;  // the input check has failed already
-        const int64_t q = p + row_ptr[c];
-        if (q < 0 || q >= 2 * n) continue;
-        sym_col[q] = srow[p];
-        if (sw) sym_w[q] = sw[p];
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * kFlat;
+    for (int64_t p0 = (int64_t)blockIdx.x * blockDim.x * kFlat + threadIdx.x; p0 < n; p0 += step) {
+        int32_t c[kFlat], r[kFlat], w[kFlat];
+#pragma unroll
+        for (int j = 0; j < kFlat; ++j) {
+            const int64_t p = p0 + (int64_t)j * blockDim.x;
+            const bool in = p < n;
+            c[j] = in ? skey[p] : -1;
+            r[j] = in ? srow[p] : 0;
+            w[j] = (in && sw) ? sw[p] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kFlat; ++j) {
+            const int64_t p = p0 + (int64_t)j * blockDim.x;
+            if (c[j] < 0 || c[j] >= m) continue;  // past the end, or the input check has failed
+            const int64_t q = p + row_ptr[c[j]];
+            if (q < 0 || q >= 2 * n) continue;
+            sym_col[q] = r[j];
+            if (sw) sym_w[q] = w[j];
+        }
     }
 }
 
@@ -184,13 +286,26 @@ __global__ void sym_upper_kernel(const int32_t *__restrict__ row, const int32_t 
                                  const int32_t *__restrict__ w, int64_t n, int64_t m,
                                  const int64_t *__restrict__ lower_ptr, int32_t *__restrict__ sym_col,
                                  int32_t *__restrict__ sym_w) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t r = row[e];
-        if (r < 0 || r >= m) continue;
-        const int64_t q = e + lower_ptr[r + 1];
-        if (q < 0 || q >= 2 * n) continue;
-        sym_col[q] = col[e];
-        if (w) sym_w[q] = w[e];
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * kFlat;
+    for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x * kFlat + threadIdx.x; e0 < n; e0 += step) {
+        int32_t r[kFlat], c[kFlat], ww[kFlat];
+#pragma unroll
+        for (int j = 0; j < kFlat; ++j) {
+            const int64_t e = e0 + (int64_t)j * blockDim.x;
+            const bool in = e < n;
+            r[j] = in ? row[e] : -1;
+            c[j] = in ? col[e] : 0;
+            ww[j] = (in && w) ? w[e] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kFlat; ++j) {
+            const int64_t e = e0 + (int64_t)j * blockDim.x;
+            if (r[j] < 0 || r[j] >= m) continue;
+            const int64_t q = e + lower_ptr[r[j] + 1];
+            if (q < 0 || q >= 2 * n) continue;
+            sym_col[q] = c[j];
+            if (w) sym_w[q] = ww[j];
+        }
     }
 }
 
@@ -231,7 +346,7 @@ hipError_t launch_sort_pass(const int32_t *key_in, const int32_t *a_in, const in
 hipError_t launch_check_upper(const int64_t *row_ptr, const int32_t *row, const int32_t *col, int64_t n, int64_t m,
                               int *err, hipStream_t st) {
     check_ptr_kernel<<<sort_grid(m > 0 ? m : 1, 256, 4096), 256, 0, st>>>(row_ptr, m, n, err);
-    if (n > 0) check_upper_kernel<<<sort_grid(n, 256, 16384), 256, 0, st>>>(row_ptr, row, col, n, m, err);
+    if (n > 0) check_upper_kernel<<<sort_grid(n, 256 * kFlat, 16384), 256, 0, st>>>(row_ptr, row, col, n, m, err);
     return hipGetLastError();
 }
 
@@ -242,8 +357,8 @@ hipError_t launch_symmetric(const int32_t *skey, const int32_t *srow, const int3
     key_bounds_kernel<<<sort_grid(m + 1, 256, 4096), 256, 0, st>>>(skey, n, m, lower_ptr);
     sym_ptr_kernel<<<sort_grid(m + 1, 256, 4096), 256, 0, st>>>(lower_ptr, row_ptr, m, sym_ptr);
     if (n > 0) {
-        sym_lower_kernel<<<sort_grid(n, 256, 16384), 256, 0, st>>>(skey, srow, sw, n, m, row_ptr, sym_col, sym_w);
-        sym_upper_kernel<<<sort_grid(n, 256, 16384), 256, 0, st>>>(row, col, w, n, m, lower_ptr, sym_col, sym_w);
+        sym_lower_kernel<<<sort_grid(n, 256 * kFlat, 16384), 256, 0, st>>>(skey, srow, sw, n, m, row_ptr, sym_col, sym_w);
+        sym_upper_kernel<<<sort_grid(n, 256 * kFlat, 16384), 256, 0, st>>>(row, col, w, n, m, lower_ptr, sym_col, sym_w);
     }
     return hipGetLastError();
 }
