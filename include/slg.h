@@ -314,6 +314,47 @@ slg_status slg_symmetrize(slg_context *ctx, int64_t m, const int64_t *row_ptr, c
                           int32_t *sym_col, int32_t *sym_w, void *stream);
 
 /*
+ * Relabel-by-degree (Stage 1 of the paper's framework, Section IV): the
+ * order of hyperedge ids by size, ascending (descending = 0) or descending;
+ * hyperedges of equal size keep their id order. order: DEVICE int32[m],
+ * written: order[k] = the old id that becomes id k. Build the relabelled
+ * hypergraph with slg_select(order, m); its line graphs are in the new ids
+ * (old id = order[new id]). Ordered on `stream`; returns after the stream
+ * has reached the end of the call. Errors: INVALID_ARG (null).
+ */
+slg_status slg_relabel_order(slg_context *ctx, slg_graph *g, int32_t descending, int32_t *order, void *stream);
+
+/*
+ * Toplexes (Stage 2 of the paper's framework, Section IV): the hyperedges
+ * that no other hyperedge contains. Computed from the edges of L_1 of g
+ * (row/col/w DEVICE int32[num_edges], as emitted for s = 1, or in any order
+ * or orientation): e_i lies inside e_j exactly when their overlap equals
+ * |e_i|. Of several identical maximal hyperedges the smallest id is kept;
+ * empty hyperedges are never toplexes. toplexes: DEVICE int32[m], written:
+ * the toplex ids in ascending order; *num_toplexes (may be NULL): their
+ * number. slg_select(toplexes, count) builds the simplified hypergraph.
+ * Ordered on `stream`; returns after the stream has reached the end of the
+ * call. Errors: INVALID_ARG (null, an id outside [0, m), a loop, an overlap
+ * above a hyperedge's size).
+ */
+slg_status slg_toplexes(slg_context *ctx, slg_graph *g, const int32_t *row, const int32_t *col, const int32_t *w,
+                        int64_t num_edges, int32_t *toplexes, int64_t *num_toplexes, void *stream);
+
+/*
+ * The sub-hypergraph of g made of the hyperedges order[0..count) (distinct
+ * ids), hyperedge k being order[k]; vertex ids are unchanged. Outputs,
+ * caller-allocated DEVICE buffers: he_ptr int64[count+1], v_ptr
+ * int64[n+1], he_idx and v_idx int32 with room for g's nnz; *nnz (may be
+ * NULL) gets the number written. Both CSRs come out well formed (rows
+ * ascending, the vertex CSR the exact transpose), ready for
+ * slg_graph_register. Ordered on `stream`; returns after the stream has
+ * reached the end of the call. Errors: INVALID_ARG (null, count > m, an id
+ * outside [0, m) or named twice), OUT_OF_MEMORY.
+ */
+slg_status slg_select(slg_context *ctx, slg_graph *g, const int32_t *order, int64_t count, int64_t *he_ptr,
+                      int32_t *he_idx, int64_t *v_ptr, int32_t *v_idx, int64_t *nnz, void *stream);
+
+/*
  * Served form: a request loop over device-resident hypergraphs. Queries
  * (a registered graph plus an s-set, each an ensemble pass of Algorithm 3)
  * arrive at any time and are started in arrival order as soon as one of

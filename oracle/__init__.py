@@ -218,3 +218,60 @@ def symmetric(m: int, row: np.ndarray, col: np.ndarray, w: Optional[np.ndarray] 
         w = np.asarray(w, dtype=np.int32)
         ww = np.concatenate([w, w])[order]
     return ptr, c[order].astype(np.int32), ww
+
+
+def relabel_order(inc, descending: bool = False) -> np.ndarray:
+    """Relabel-by-degree (Stage 1 of the framework, Section IV): hyperedge
+    ids ordered by size, ascending or descending, equal sizes in id order;
+    order[k] = the old id that becomes id k."""
+    sizes = np.diff(np.asarray(inc.he_ptr, dtype=np.int64))
+    return np.argsort(-sizes if descending else sizes, kind="stable").astype(np.int32)
+
+
+def select(inc, order):
+    """The sub-hypergraph of hyperedges order[0..count): hyperedge k is
+    order[k], vertex ids unchanged. Returns (he_ptr, he_idx, v_ptr, v_idx)
+    with every vertex list ascending."""
+    he_ptr = np.asarray(inc.he_ptr, dtype=np.int64)
+    he_idx = np.asarray(inc.he_idx, dtype=np.int32)
+    order = np.asarray(order, dtype=np.int64)
+    rows = [he_idx[he_ptr[i]:he_ptr[i + 1]] for i in order]
+    new_ptr = np.zeros(order.size + 1, dtype=np.int64)
+    np.cumsum([r.size for r in rows], out=new_ptr[1:])
+    new_idx = np.concatenate(rows).astype(np.int32) if rows and new_ptr[-1] else np.zeros(0, np.int32)
+    # the vertex lists: incidences (k, v) ordered by vertex, then by k
+    k_of = np.repeat(np.arange(order.size, dtype=np.int64), np.diff(new_ptr))
+    by_v = np.lexsort((k_of, new_idx))
+    v_ptr = np.zeros(inc.n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(new_idx, minlength=inc.n)[: inc.n], out=v_ptr[1:])
+    return new_ptr, new_idx, v_ptr, k_of[by_v].astype(np.int32)
+
+
+def toplexes(inc) -> np.ndarray:
+    """Toplexes (Stage 2 of the framework, Section IV), by subset tests on
+    every pair of hyperedges: e is kept unless some other hyperedge is a
+    strict superset, or an identical set with a smaller id; empty
+    hyperedges are not kept. Small inputs only."""
+    sets = [frozenset(inc.row(i).tolist()) for i in range(inc.m)]
+    keep = []
+    for i, e in enumerate(sets):
+        if not e:
+            continue
+        if any((j != i and e < f) or (j < i and e == f) for j, f in enumerate(sets)):
+            continue
+        keep.append(i)
+    return np.asarray(keep, dtype=np.int32)
+
+
+def toplexes_from_edges(inc, row, col, w) -> np.ndarray:
+    """Toplexes from the edges of L_1: e_i lies inside e_j exactly when
+    their overlap is |e_i| (same keep rule as toplexes())."""
+    sizes = np.diff(np.asarray(inc.he_ptr, dtype=np.int64))
+    drop = sizes == 0
+    a = np.asarray(row, dtype=np.int64)
+    b = np.asarray(col, dtype=np.int64)
+    x = np.asarray(w, dtype=np.int64)
+    sa, sb = sizes[a], sizes[b]
+    drop[a[(x == sa) & ((sb > sa) | ((sb == sa) & (b < a)))]] = True
+    drop[b[(x == sb) & ((sa > sb) | ((sa == sb) & (a < b)))]] = True
+    return np.flatnonzero(~drop).astype(np.int32)

@@ -121,6 +121,9 @@ def lib() -> ctypes.CDLL:
         "slg_components": (_i32, [_p, _p, _i32, _p, _p, _i64, _p, ctypes.POINTER(_i64), _p]),
         "slg_squeeze": (_i32, [_p, _i64, _p, _p, _i64, _i32, _p, ctypes.POINTER(_i64), _p]),
         "slg_symmetrize": (_i32, [_p, _i64, _p, _p, _p, _p, _i64, _p, _p, _p, _p]),
+        "slg_relabel_order": (_i32, [_p, _p, _i32, _p, _p]),
+        "slg_toplexes": (_i32, [_p, _p, _p, _p, _p, _i64, _p, ctypes.POINTER(_i64), _p]),
+        "slg_select": (_i32, [_p, _p, _p, _i64, _p, _p, _p, _p, ctypes.POINTER(_i64), _p]),
         "slg_server_create": (_i32, [_p, _i32, _u64, ctypes.POINTER(_p)]),
         "slg_server_submit": (_i32, [_p, _p, ctypes.POINTER(_i32), _i32, ctypes.POINTER(_u64)]),
         "slg_server_wait": (_i32, [_p, _u64, _i32, ctypes.POINTER(_p), ctypes.POINTER(RequestInfo)]),
@@ -477,6 +480,56 @@ class Context:
                                          sym_col.data_ptr(), sym_w.data_ptr() if weights else None,
                                          _stream_handle(stream)))
         return sym_ptr, sym_col, sym_w
+
+    # -- preprocessing (relabel-by-degree, toplexes) ------------------------
+    def relabel_order(self, g: Graph, descending: bool = False, stream=None):
+        """Hyperedge ids ordered by size: int32[m] on the device, order[k] =
+        the old id that becomes id k (equal sizes keep their id order)."""
+        import torch
+        order = torch.empty(max(g.m, 1), dtype=torch.int32, device=f"cuda:{self.device}")[: g.m]
+        self._check(lib().slg_relabel_order(self.handle, g.handle, 1 if descending else 0, order.data_ptr(),
+                                            _stream_handle(stream)))
+        return order
+
+    def select(self, g: Graph, order, stream=None) -> Graph:
+        """The sub-hypergraph of the hyperedges order[0..count), registered."""
+        import torch
+        dev = f"cuda:{self.device}"
+        order = order.to(device=dev, dtype=torch.int32).contiguous()
+        count = int(order.numel())
+        nnz_cap = int(g._tensors[1].numel())
+        he_ptr = torch.empty(count + 1, dtype=torch.int64, device=dev)
+        v_ptr = torch.empty(g.n + 1, dtype=torch.int64, device=dev)
+        he_idx = torch.empty(max(nnz_cap, 1), dtype=torch.int32, device=dev)
+        v_idx = torch.empty(max(nnz_cap, 1), dtype=torch.int32, device=dev)
+        nz = _i64()
+        self._check(lib().slg_select(self.handle, g.handle, order.data_ptr() if count else None, count,
+                                     he_ptr.data_ptr(), he_idx.data_ptr(), v_ptr.data_ptr(), v_idx.data_ptr(),
+                                     ctypes.byref(nz), _stream_handle(stream)))
+        k = int(nz.value)
+        return self.register(count, g.n, he_ptr, he_idx[:k], v_ptr, v_idx[:k], stream=stream)
+
+    def relabel(self, g: Graph, descending: bool = False, stream=None):
+        """Relabel-by-degree: (the relabelled graph, order) with old id =
+        order[new id]."""
+        order = self.relabel_order(g, descending, stream)
+        return self.select(g, order, stream), order
+
+    def toplexes(self, g: Graph, l1: "LineGraph", stream=None):
+        """Toplex ids (ascending, int32 on the device) from the edges of L_1."""
+        import torch
+        ids = torch.empty(max(g.m, 1), dtype=torch.int32, device=f"cuda:{self.device}")
+        cnt = _i64()
+        row = _need_rows(l1)
+        self._check(lib().slg_toplexes(self.handle, g.handle, row.data_ptr(), l1.col.data_ptr(), l1.w.data_ptr(),
+                                       int(l1.num_edges), ids.data_ptr(), ctypes.byref(cnt), _stream_handle(stream)))
+        return ids[: int(cnt.value)]
+
+    def simplify(self, g: Graph, l1: "LineGraph", stream=None):
+        """The simplification (toplexes only): (graph, toplex ids), hyperedge
+        k of the graph being toplex ids[k]."""
+        ids = self.toplexes(g, l1, stream)
+        return self.select(g, ids, stream), ids
 
     def server(self, workers: int = 4, mem_budget_bytes: int = 0) -> "Server":
         """The served form (slg_server_*): a request loop over registered graphs."""

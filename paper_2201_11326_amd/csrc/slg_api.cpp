@@ -1236,6 +1236,63 @@ slg_status slg_squeeze(slg_context *ctx, int64_t m, int32_t *row, int32_t *col, 
     return SLG_OK;
 }
 
+namespace {
+
+// Stable sort of n int32 keys in [0, 2^key_bits) with up to two payloads
+// (b only with a), from the *_in arrays into the *_out arrays (which may be
+// caller memory), through scratch from `sc` when more than one digit pass is
+// needed. With key_bits = 0 the inputs are copied.
+hipError_t sort_pairs(Scratch &sc, const int32_t *key_in, const int32_t *a_in, const int32_t *b_in, int64_t n,
+                      int key_bits, int32_t *key_out, int32_t *a_out, int32_t *b_out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int passes = sort_passes(key_bits);
+    hipError_t e;
+    if (passes == 0) {
+        const int32_t *src[3] = {key_in, a_in, b_in};
+        int32_t *dst[3] = {key_out, a_out, b_out};
+        for (int t = 0; t < 3; ++t)
+            if (src[t] && dst[t] && src[t] != dst[t] &&
+                (e = hipMemcpyAsync(dst[t], src[t], n * sizeof(int32_t), hipMemcpyDeviceToDevice, st)) != hipSuccess)
+                return e;
+        return hipSuccess;
+    }
+    const int digit = (key_bits + passes - 1) / passes;
+    const int64_t hist_n = (int64_t(1) << digit) * sort_chunks(n);
+    int32_t *hist = nullptr, *tmp[2][3] = {};
+    int64_t *off = nullptr, *part = nullptr;
+    if ((e = sc.get(&hist, hist_n)) != hipSuccess || (e = sc.get(&off, hist_n + 1)) != hipSuccess ||
+        (e = sc.get(&part, scan_partials_size(hist_n))) != hipSuccess)
+        return e;
+    const int arrays = b_in ? 3 : (a_in ? 2 : 1);
+    // pass p writes tmp[p & 1] except the last, which writes the outputs
+    for (int h = 0; h < (passes > 2 ? 2 : passes - 1); ++h)
+        for (int t = 0; t < arrays; ++t)
+            if ((e = sc.get(&tmp[h][t], n)) != hipSuccess) return e;
+    const int32_t *k = key_in, *a = a_in, *b = b_in;
+    for (int p = 0; p < passes; ++p) {
+        const bool last = p + 1 == passes;
+        int32_t *ko = last ? key_out : tmp[p & 1][0];
+        int32_t *ao = a_in ? (last ? a_out : tmp[p & 1][1]) : nullptr;
+        int32_t *bo = b_in ? (last ? b_out : tmp[p & 1][2]) : nullptr;
+        const int shift = p * digit;
+        if ((e = launch_sort_pass(k, a, b, n, shift, std::min(digit, key_bits - shift), hist, off, part, ko, ao, bo,
+                                  st)) != hipSuccess)
+            return e;
+        k = ko;
+        a = ao;
+        b = bo;
+    }
+    return hipSuccess;
+}
+
+int bits_for(int64_t values) {  // bits of the largest value below `values`
+    int b = 0;
+    while ((int64_t(1) << b) < values) ++b;
+    return b;
+}
+
+}  // namespace
+
 slg_status slg_symmetrize(slg_context *ctx, int64_t m, const int64_t *row_ptr, const int32_t *row,
                           const int32_t *col, const int32_t *w, int64_t num_edges, int64_t *sym_ptr,
                           int32_t *sym_col, int32_t *sym_w, void *stream) {
@@ -1245,46 +1302,123 @@ slg_status slg_symmetrize(slg_context *ctx, int64_t m, const int64_t *row_ptr, c
     SLG_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t n = num_edges;
-    int key_bits = 0;  // columns lie in [0, m)
-    while ((int64_t(1) << key_bits) < m) ++key_bits;
-    const int passes = sort_passes(key_bits);
-    const int digit = passes ? (key_bits + passes - 1) / passes : 0;
-    const int64_t hist_n = passes ? (int64_t(1) << digit) * sort_chunks(n) : 0;
     Scratch sc;
     sc.st = st;
     sc.arena = ctx->arena.get();
-    int64_t *err = nullptr, *lower_ptr = nullptr, *off = nullptr, *part = nullptr;
-    int32_t *hist = nullptr, *buf[2][3] = {};
+    int64_t *err = nullptr, *lower_ptr = nullptr;
+    int32_t *sorted[3] = {};
     SLG_HIP(ctx, sc.get(&err, 1));
     SLG_HIP(ctx, sc.get(&lower_ptr, m + 1));
-    if (passes && n > 0) {
-        SLG_HIP(ctx, sc.get(&hist, hist_n));
-        SLG_HIP(ctx, sc.get(&off, hist_n + 1));  // the scan also writes the total
-        SLG_HIP(ctx, sc.get(&part, scan_partials_size(hist_n)));
-        for (int h = 0; h < (passes > 1 ? 2 : 1); ++h)
-            for (int a = 0; a < (w ? 3 : 2); ++a) SLG_HIP(ctx, sc.get(&buf[h][a], n));
-    }
+    if (n > 0)
+        for (int t = 0; t < (w ? 3 : 2); ++t) SLG_HIP(ctx, sc.get(&sorted[t], n));
     SLG_HIP(ctx, launch_fill_i64(err, 1, 0, st));
     SLG_HIP(ctx, launch_check_upper(row_ptr, row, col, n, m, reinterpret_cast<int *>(err), st));
     // the upper triangle sorted by column (stable: rows stay ascending)
-    const int32_t *k_in = col, *a_in = row, *b_in = w;
-    for (int p = 0; p < passes && n > 0; ++p) {
-        int32_t *const *out = buf[p & 1];
-        const int shift = p * digit;
-        const int bits = std::min(digit, key_bits - shift);
-        SLG_HIP(ctx, launch_sort_pass(k_in, a_in, b_in, n, shift, bits, hist, off, part, out[0], out[1], out[2],
-                                      st));
-        k_in = out[0];
-        a_in = out[1];
-        b_in = out[2];
-    }
-    SLG_HIP(ctx, launch_symmetric(k_in, a_in, b_in, row_ptr, row, col, w, n, m, lower_ptr, sym_ptr, sym_col, sym_w,
-                                  st));
+    SLG_HIP(ctx, sort_pairs(sc, col, row, w, n, bits_for(m), sorted[0], sorted[1], sorted[2], st));
+    SLG_HIP(ctx, launch_symmetric(sorted[0], sorted[1], sorted[2], row_ptr, row, col, w, n, m, lower_ptr, sym_ptr,
+                                  sym_col, sym_w, st));
     SLG_HIP(ctx, hipMemcpyAsync(ctx->pinned, err, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     SLG_HIP(ctx, hipStreamSynchronize(st));
     sc.release();
     if (ctx->pinned[0] & 1)
         return fail(ctx, SLG_ERR_INVALID_ARG, "input is not an upper triangle sorted by (row, col)");
+    return SLG_OK;
+}
+
+slg_status slg_relabel_order(slg_context *ctx, slg_graph *g, int32_t descending, int32_t *order, void *stream) {
+    if (!ctx || !g || !order) return fail(ctx, SLG_ERR_INVALID_ARG, "bad relabel arguments");
+    SLG_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t m = g->inc.num_hyperedges, n = g->inc.num_vertices;
+    Scratch sc;
+    sc.st = st;
+    sc.arena = ctx->arena.get();
+    int32_t *key = nullptr, *id = nullptr, *skey = nullptr;
+    SLG_HIP(ctx, sc.get(&key, m));
+    SLG_HIP(ctx, sc.get(&id, m));
+    SLG_HIP(ctx, sc.get(&skey, m));
+    SLG_HIP(ctx, launch_size_keys(g->inc.he_ptr, m, n, descending ? 1 : 0, key, id, st));
+    // sizes lie in [0, n]: stable, so equal sizes keep their id order
+    SLG_HIP(ctx, sort_pairs(sc, key, id, nullptr, m, bits_for(n + 1), skey, order, nullptr, st));
+    SLG_HIP(ctx, hipStreamSynchronize(st));
+    return SLG_OK;
+}
+
+slg_status slg_toplexes(slg_context *ctx, slg_graph *g, const int32_t *row, const int32_t *col, const int32_t *w,
+                        int64_t num_edges, int32_t *toplexes, int64_t *num_toplexes, void *stream) {
+    if (!ctx || !g || !toplexes || num_edges < 0 || (num_edges > 0 && (!row || !col || !w)))
+        return fail(ctx, SLG_ERR_INVALID_ARG, "bad toplex arguments");
+    SLG_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t m = g->inc.num_hyperedges;
+    Scratch sc;
+    sc.st = st;
+    sc.arena = ctx->arena.get();
+    int32_t *drop = nullptr, *keep = nullptr;
+    int64_t *pre = nullptr, *part = nullptr, *err = nullptr;
+    SLG_HIP(ctx, sc.get(&drop, m));
+    SLG_HIP(ctx, sc.get(&keep, m));
+    SLG_HIP(ctx, sc.get(&pre, m + 1));
+    SLG_HIP(ctx, sc.get(&part, scan_partials_size(m)));
+    SLG_HIP(ctx, sc.get(&err, 1));
+    SLG_HIP(ctx, launch_fill_i64(err, 1, 0, st));
+    SLG_HIP(ctx, launch_fill_i64(pre + m, 1, 0, st));  // m = 0: the count
+    SLG_HIP(ctx, launch_toplex_flags(row, col, w, num_edges, g->inc.he_ptr, m, drop, keep,
+                                     reinterpret_cast<int *>(err), st));
+    SLG_HIP(ctx, launch_exclusive_scan_i32(keep, m, pre, part, st));
+    SLG_HIP(ctx, launch_compact_ids(keep, pre, m, toplexes, st));
+    SLG_HIP(ctx, hipMemcpyAsync(ctx->pinned, err, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SLG_HIP(ctx, hipMemcpyAsync(ctx->pinned + 1, pre + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SLG_HIP(ctx, hipStreamSynchronize(st));
+    sc.release();
+    if (ctx->pinned[0] & 1) return fail(ctx, SLG_ERR_INVALID_ARG, "an edge names an id outside [0, m) or a loop");
+    if (ctx->pinned[0] & 2)
+        return fail(ctx, SLG_ERR_INVALID_ARG, "an overlap exceeds a hyperedge size: not the edges of L_1");
+    if (num_toplexes) *num_toplexes = ctx->pinned[1];
+    return SLG_OK;
+}
+
+slg_status slg_select(slg_context *ctx, slg_graph *g, const int32_t *order, int64_t count, int64_t *he_ptr,
+                      int32_t *he_idx, int64_t *v_ptr, int32_t *v_idx, int64_t *nnz, void *stream) {
+    if (!ctx || !g || count < 0 || !he_ptr || !v_ptr || (count > 0 && !order) ||
+        (g->inc.nnz > 0 && (!he_idx || !v_idx)))
+        return fail(ctx, SLG_ERR_INVALID_ARG, "bad select arguments");
+    SLG_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const slg_incidence &inc = g->inc;
+    const int64_t m = inc.num_hyperedges, n = inc.num_vertices;
+    if (count > m) return fail(ctx, SLG_ERR_INVALID_ARG, "more hyperedges selected than the graph has");
+    Scratch sc;
+    sc.st = st;
+    sc.arena = ctx->arena.get();
+    int32_t *seen = nullptr, *row_of = nullptr, *skey = nullptr;
+    int64_t *sizes = nullptr, *part = nullptr, *err = nullptr;
+    SLG_HIP(ctx, sc.get(&seen, m));
+    SLG_HIP(ctx, sc.get(&sizes, count));
+    SLG_HIP(ctx, sc.get(&part, scan_partials_size(count)));
+    SLG_HIP(ctx, sc.get(&err, 1));
+    SLG_HIP(ctx, launch_fill_i64(err, 1, 0, st));
+    SLG_HIP(ctx, launch_fill_i32(seen, m, 0, st));
+    SLG_HIP(ctx, launch_fill_i64(he_ptr + count, 1, 0, st));  // count = 0: an empty graph
+    SLG_HIP(ctx, launch_select_sizes(order, count, inc.he_ptr, m, seen, sizes, reinterpret_cast<int *>(err), st));
+    SLG_HIP(ctx, launch_exclusive_scan_i64(sizes, count, he_ptr, part, st));
+    SLG_HIP(ctx, hipMemcpyAsync(ctx->pinned, err, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SLG_HIP(ctx, hipMemcpyAsync(ctx->pinned + 1, he_ptr + count, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SLG_HIP(ctx, hipStreamSynchronize(st));
+    const int64_t bad = ctx->pinned[0], nz = ctx->pinned[1];
+    if (bad & 1) return fail(ctx, SLG_ERR_INVALID_ARG, "order names an id outside [0, m)");
+    if (bad & 2) return fail(ctx, SLG_ERR_INVALID_ARG, "order names a hyperedge twice");
+    if (nz > 0) {
+        SLG_HIP(ctx, sc.get(&row_of, nz));
+        SLG_HIP(ctx, sc.get(&skey, nz));
+    }
+    SLG_HIP(ctx, launch_select_rows(order, count, inc.he_ptr, inc.he_idx, m, he_ptr, he_idx, row_of, st));
+    // vertex lists: the new incidences sorted by vertex, rows ascending
+    SLG_HIP(ctx, sort_pairs(sc, he_idx, row_of, nullptr, nz, bits_for(n), skey, v_idx, nullptr, st));
+    SLG_HIP(ctx, launch_key_bounds(skey, nz, n, v_ptr, st));
+    SLG_HIP(ctx, hipStreamSynchronize(st));
+    sc.release();
+    if (nnz) *nnz = nz;
     return SLG_OK;
 }
 

@@ -181,6 +181,8 @@ int sort_passes(int key_bits);
 hipError_t launch_sort_pass(const int32_t *key_in, const int32_t *a_in, const int32_t *b_in, int64_t n, int shift,
                             int bits, int32_t *hist, int64_t *off, int64_t *partials, int32_t *key_out,
                             int32_t *a_out, int32_t *b_out, hipStream_t st);
+// lower_ptr[c] = number of ascending keys skey[0..n) below c, c in [0, m].
+hipError_t launch_key_bounds(const int32_t *skey, int64_t n, int64_t m, int64_t *lower_ptr, hipStream_t st);
 // err |= 1 unless (row_ptr, row, col) is an upper triangle in CSR order.
 hipError_t launch_check_upper(const int64_t *row_ptr, const int32_t *row, const int32_t *col, int64_t n, int64_t m,
                               int *err, hipStream_t st);
@@ -191,6 +193,24 @@ hipError_t launch_symmetric(const int32_t *skey, const int32_t *srow, const int3
                             const int32_t *row, const int32_t *col, const int32_t *w, int64_t n, int64_t m,
                             int64_t *lower_ptr, int64_t *sym_ptr, int32_t *sym_col, int32_t *sym_w,
                             hipStream_t st);
+
+// Preprocessing (slg_prep.hip). key[i] = |e_i| or n - |e_i|, id[i] = i.
+hipError_t launch_size_keys(const int64_t *he_ptr, int64_t m, int64_t n, int descending, int32_t *key, int32_t *id,
+                            hipStream_t st);
+// size_out[k] = |e_order[k]|; err |= 1 for an id outside [0, m), 2 for a
+// repeated id (seen: int32[m], zeroed).
+hipError_t launch_select_sizes(const int32_t *order, int64_t count, const int64_t *he_ptr, int64_t m, int32_t *seen,
+                               int64_t *size_out, int *err, hipStream_t st);
+// Rows of the selection at new_ptr, with the new row id of every incidence.
+hipError_t launch_select_rows(const int32_t *order, int64_t count, const int64_t *he_ptr, const int32_t *he_idx,
+                              int64_t m, const int64_t *new_ptr, int32_t *new_idx, int32_t *row_of, hipStream_t st);
+// keep[i] = 1 for a toplex, from the edges of L_1 (drop: int32[m] scratch);
+// err |= 1 for an id outside [0, m) or a loop, 2 for an impossible overlap.
+hipError_t launch_toplex_flags(const int32_t *row, const int32_t *col, const int32_t *w, int64_t num_edges,
+                               const int64_t *he_ptr, int64_t m, int32_t *drop, int32_t *keep, int *err,
+                               hipStream_t st);
+// out[pre[i]] = i for every i with keep[i].
+hipError_t launch_compact_ids(const int32_t *keep, const int64_t *pre, int64_t m, int32_t *out, hipStream_t st);
 
 // Validation kernels (SLG_VALIDATE).
 hipError_t launch_validate_ptr(const int64_t *ptr, int64_t rows, int64_t nnz, int *err,

@@ -343,6 +343,11 @@ hipError_t launch_sort_pass(const int32_t *key_in, const int32_t *a_in, const in
     return hipGetLastError();
 }
 
+hipError_t launch_key_bounds(const int32_t *skey, int64_t n, int64_t m, int64_t *lower_ptr, hipStream_t st) {
+    key_bounds_kernel<<<sort_grid(m + 1, 256, 4096), 256, 0, st>>>(skey, n, m, lower_ptr);
+    return hipGetLastError();
+}
+
 hipError_t launch_check_upper(const int64_t *row_ptr, const int32_t *row, const int32_t *col, int64_t n, int64_t m,
                               int *err, hipStream_t st) {
     check_ptr_kernel<<<sort_grid(m > 0 ? m : 1, 256, 4096), 256, 0, st>>>(row_ptr, m, n, err);

@@ -102,3 +102,31 @@ def load_toy_symmetric(path: str = os.path.join(GOLDEN, "toy_symmetric.txt")):
                 rows.append([])
             rows[r] = [tuple(int(x) for x in t.split(":")) for t in tok[3:]]
     return out
+
+
+def load_toy_preprocess(path: str = os.path.join(GOLDEN, "toy_preprocess.txt")):
+    """Parse the preprocessing fixture -> {"asc": [...], "desc": [...], "top": [...]}."""
+    out = {}
+    with open(path) as f:
+        for raw in f:
+            line = raw.split("#", 1)[0].strip()
+            if line:
+                tok = line.split()
+                out[tok[0]] = [int(x) for x in tok[1:]]
+    return out
+
+
+def with_subsets(seed: int, m: int, n: int, kmax: int, extra: int):
+    """Input construction for toplex tests: random hyperedges, then `extra`
+    more that are random subsets (some empty, some whole copies) of earlier
+    ones, all shuffled together."""
+    import hypergen as hg
+    rng = np.random.default_rng(seed)
+    base = hg.random_small(seed, m, n, kmax, 0.9)
+    rows = [base.row(i).tolist() for i in range(base.m)]
+    for _ in range(extra):
+        src = rows[int(rng.integers(0, len(rows)))]
+        pick = rng.random(len(src)) < rng.choice([0.0, 0.5, 0.9, 1.0])
+        rows.append([v for v, p in zip(src, pick) if p])
+    perm = rng.permutation(len(rows))
+    return hg.from_rows([rows[i] for i in perm], n=n)

@@ -13,7 +13,8 @@ from hypothesis import given, settings, strategies as st
 
 import hypergen as hg
 import oracle
-from helpers import brute_force_sets, edges_of, load_toy, rows_of, load_toy_components, load_toy_symmetric
+from helpers import (brute_force_sets, edges_of, load_toy, rows_of, load_toy_components, load_toy_symmetric,
+                     load_toy_preprocess, with_subsets)
 
 
 # --- the worked example of Section I (hand-enumerated fixture) -------------
@@ -353,3 +354,67 @@ def test_symmetric_is_its_own_transpose_and_doubles_the_edges():
     fwd = set(zip(rows.tolist(), col.tolist(), w.tolist()))
     assert fwd == set(zip(col.tolist(), rows.tolist(), w.tolist()))
     assert all(np.all(np.diff(col[ptr[r]:ptr[r + 1]]) > 0) for r in range(inc.m))
+
+
+# --- relabel-by-degree, selection, toplexes (Stages 1-2) --------------------
+
+def _as_incidence(inc, arrays):
+    he_ptr, he_idx, v_ptr, v_idx = arrays
+    return hg.Incidence(len(he_ptr) - 1, inc.n, he_ptr, he_idx, v_ptr, v_idx)
+
+
+def test_preprocessing_of_the_worked_example():
+    inc, _, _, _ = load_toy()
+    want = load_toy_preprocess()
+    assert oracle.relabel_order(inc).tolist() == want["asc"]
+    assert oracle.relabel_order(inc, descending=True).tolist() == want["desc"]
+    assert oracle.toplexes(inc).tolist() == want["top"]
+    lg = oracle.line_graph(inc, 1)
+    assert oracle.toplexes_from_edges(inc, lg.i, lg.j, lg.w).tolist() == want["top"]
+
+
+@pytest.mark.parametrize("seed,descending", [(21, False), (22, True), (23, False)])
+def test_relabelled_line_graph_maps_back_to_the_original(seed, descending):
+    inc = hg.random_small(seed, 300, 100, 14, 1.0)
+    order = oracle.relabel_order(inc, descending)
+    sizes = inc.sizes()[order]
+    assert sorted(order.tolist()) == list(range(inc.m))
+    assert np.all(np.diff(sizes) <= 0) if descending else np.all(np.diff(sizes) >= 0)
+    sub = _as_incidence(inc, oracle.select(inc, order))
+    # the vertex CSR is the exact transpose (an independent stable transpose)
+    ptr_t, idx_t = hg.transpose_csr(sub.m, sub.n, sub.he_ptr, sub.he_idx)
+    np.testing.assert_array_equal(sub.v_ptr, ptr_t)
+    np.testing.assert_array_equal(sub.v_idx, idx_t)
+    for s in (1, 2, 3):
+        a = oracle.line_graph(sub, s)
+        i, j = order[a.i], order[a.j]
+        got = sorted(zip(np.minimum(i, j).tolist(), np.maximum(i, j).tolist(), a.w.tolist()))
+        assert got == edges_of(oracle.line_graph(inc, s)), f"s={s}"
+
+
+@pytest.mark.parametrize("seed", [31, 32, 33])
+def test_toplexes_brute_force_and_from_edges_agree(seed):
+    inc = with_subsets(seed, 120, 40, 10, 60)
+    top = oracle.toplexes(inc)
+    lg = oracle.line_graph(inc, 1)
+    np.testing.assert_array_equal(oracle.toplexes_from_edges(inc, lg.i, lg.j, lg.w), top)
+    # no kept hyperedge inside another kept one; every dropped non-empty one
+    # lies inside a kept one
+    sets = [frozenset(inc.row(i).tolist()) for i in range(inc.m)]
+    kept = set(top.tolist())
+    for a in kept:
+        assert not any(b != a and sets[a] <= sets[b] for b in kept)
+    for a in range(inc.m):
+        if a not in kept and sets[a]:
+            assert any(sets[a] <= sets[b] for b in kept)
+
+
+def test_select_of_a_subset():
+    inc = hg.random_small(41, 200, 60, 9, None)
+    order = np.array([150, 3, 77, 4, 199], dtype=np.int32)
+    he_ptr, he_idx, v_ptr, v_idx = oracle.select(inc, order)
+    for k, i in enumerate(order):
+        assert he_idx[he_ptr[k]:he_ptr[k + 1]].tolist() == inc.row(int(i)).tolist()
+    ptr_t, idx_t = hg.transpose_csr(len(order), inc.n, he_ptr, he_idx)
+    np.testing.assert_array_equal(v_ptr, ptr_t)
+    np.testing.assert_array_equal(v_idx, idx_t)
