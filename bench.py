@@ -453,6 +453,75 @@ def bench_components(args) -> int:
     return 0
 
 
+def bench_preprocess(args) -> int:
+    """The framework's optional preprocessing (Section IV, Stages 1-2) on the
+    power-law instance: relabel-by-degree (ascending, descending) and the
+    simplification to toplexes, and what relabelling does to the ensemble
+    construction S = {1,2,4,8} on the GPU (the paper relabels to balance CPU
+    threads). value = 2-paths/s of the construction on the ascending
+    relabelling; the original order's rate rides along."""
+    import torch
+
+    import hypergen as hg
+    import paper_2201_11326_amd as slg
+
+    inc = hg.power_law()
+    ctx = slg.Context(0)
+    g = ctx.register_incidence(inc)
+    torch.cuda.synchronize()
+
+    def timed(fn, reps):
+        ts = []
+        out = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[len(ts) // 2] * 1e3, out
+
+    def construction(graph):
+        for _ in range(args.warmup):
+            outs = ctx.line_graph(graph, S_SET)
+            del outs
+        ms, outs = timed(lambda: ctx.line_graph(graph, S_SET), args.steps)
+        two_paths = outs[0].two_paths
+        del outs
+        return ms, two_paths
+
+    res = {}
+    res["original_ms"], W = construction(g)
+    for desc in (False, True):
+        name = "descending" if desc else "ascending"
+        timed(lambda: ctx.relabel(g, desc), args.warmup)
+        rl_ms, (sub, _) = timed(lambda: ctx.relabel(g, desc), args.steps)
+        res[f"relabel_{name}_ms"] = rl_ms
+        res[f"{name}_ms"], _ = construction(sub)
+        sub.release()
+    l1 = ctx.line_graph(g, [1])[0]
+    timed(lambda: ctx.simplify(g, l1), args.warmup)
+    sim_ms, (simple, ids) = timed(lambda: ctx.simplify(g, l1), args.steps)
+    res["simplify_ms"] = sim_ms
+    res["toplexes"] = int(ids.numel())
+    simple.release()
+    del l1
+    line = {
+        "metric": METRIC, "value": W / (res["ascending_ms"] * 1e-3), "unit": "2-paths/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ascending_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "relabel-by-degree and toplex simplification of the power-law hypergraph "
+                               "n=1e6 m=5e5; ensemble S={1,2,4,8} on each order", "s": S_SET,
+                   "parallelism": "single GPU"},
+        "original_two_paths_per_s": W / (res["original_ms"] * 1e-3), "stages_ms": res,
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+    g.release()
+    ctx.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -460,9 +529,12 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("power_law", "batched", "served", "components"), default="power_law",
+    ap.add_argument("--workload", choices=("power_law", "batched", "served", "components", "preprocess"),
+                    default="power_law",
                     help="power_law: the single large hypergraph (default); batched: 256 small "
-                         "hypergraphs, each with its own s, as one disjoint-union batch")
+                         "hypergraphs, each with its own s, as one disjoint-union batch; served: a request "
+                         "loop; components: components, squeezing and symmetric CSR of the power-law L_s; "
+                         "preprocess: relabel-by-degree and toplexes of the power-law hypergraph")
     ap.add_argument("--no-tune", action="store_true", help="batched: library-default plan shape")
     ap.add_argument("--requests", type=int, default=4000, help="served: number of requests")
     ap.add_argument("--rate", type=float, default=2000.0, help="served: Poisson arrivals per second")
@@ -489,6 +561,8 @@ def main() -> int:
         return bench_served(args)
     if args.workload == "components":
         return bench_components(args)
+    if args.workload == "preprocess":
+        return bench_preprocess(args)
     t_gen = time.perf_counter()
     inc = hg.power_law()
     t_gen = time.perf_counter() - t_gen
