@@ -243,6 +243,19 @@ slg_status slg_batch_result(const slg_batch *b, int32_t g, int64_t *edge_begin, 
 slg_status slg_batch_destroy(slg_batch *b);
 
 /*
+ * Count store (a memory-for-time trade of this implementation, not in the
+ * paper): the counting pass of a plan keeps every heavy slot's partners and
+ * overlaps (4 bytes per 2-path of the heavy rows, plus 20 bytes per heavy
+ * slot) so that the emit pass reads them instead of walking the 2-paths
+ * again, whenever that takes at most max_bytes and the heavy rows hold at
+ * least min_two_paths 2-paths (below that, the store's extra launches cost
+ * more than they save). max_bytes = 0 turns it off. Defaults: 32 GiB and
+ * 2^24. Results are identical either way. Applies to plans created
+ * afterwards (and to a server's slots when set before slg_server_create).
+ */
+slg_status slg_context_set_count_store(slg_context *ctx, int64_t max_bytes, int64_t min_two_paths);
+
+/*
  * Tuning of the plan shape, used by the autotuner: light_max = largest row
  * work (2-paths) sorted by one wavefront (<= 2048; 0 = default),
  * slot_work = 2-paths per heavy slot before a row is split (0 = default),

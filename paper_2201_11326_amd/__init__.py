@@ -122,6 +122,7 @@ def lib() -> ctypes.CDLL:
         "slg_squeeze": (_i32, [_p, _i64, _p, _p, _i64, _i32, _p, ctypes.POINTER(_i64), _p]),
         "slg_symmetrize": (_i32, [_p, _i64, _p, _p, _p, _p, _i64, _p, _p, _p, _p]),
         "slg_relabel_order": (_i32, [_p, _p, _i32, _p, _p]),
+        "slg_context_set_count_store": (_i32, [_p, _i64, _i64]),
         "slg_toplexes": (_i32, [_p, _p, _p, _p, _p, _i64, _p, ctypes.POINTER(_i64), _p]),
         "slg_select": (_i32, [_p, _p, _p, _i64, _p, _p, _p, _p, ctypes.POINTER(_i64), _p]),
         "slg_server_create": (_i32, [_p, _i32, _u64, ctypes.POINTER(_p)]),
@@ -219,7 +220,7 @@ class Plan:
 
     STAT_NAMES = ("slots", "tiny8", "light64", "light128", "light256", "light512", "light1024", "light2048",
                   "heavy_slots", "heavy_wide_slots", "two_paths", "heavy_two_paths", "bound_entries",
-                  "heavy_edges")
+                  "heavy_edges", "stored_ranks")
 
     def stats(self) -> dict:
         out = (_i64 * 16)()
@@ -325,6 +326,12 @@ class Context:
         self._check(lib().slg_context_set_tuning(self.handle, light_max, slot_work, heavy_grid))
 
     # -- measurement ---------------------------------------------------------
+    def set_count_store(self, max_bytes: int, min_two_paths: int = 1 << 24):
+        """Largest count store a plan may keep (0: the emit pass walks the
+        2-paths again) and the fewest heavy 2-paths that make one worth it;
+        results are identical either way."""
+        self._check(lib().slg_context_set_count_store(self.handle, int(max_bytes), int(min_two_paths)))
+
     def set_timing(self, enable: bool = True):
         self._check(lib().slg_context_set_timing(self.handle, 1 if enable else 0))
 

@@ -45,6 +45,8 @@ struct slg_context {
     int32_t light_max = kLightMax;
     int64_t slot_work = kSlotWork;
     int heavy_grid = 0;
+    int64_t store_limit = int64_t(32) << 30;  // largest count store a plan keeps (0: none)
+    int64_t store_min = int64_t(1) << 24;     // fewest heavy 2-paths for which a plan keeps one
     uint64_t budget = 0;
     bool has_alloc = false;
     slg_allocator alloc{};
@@ -74,7 +76,7 @@ static_assert(kCntTotal <= 32, "counter block");
 constexpr int kHbSlots = kCntTotal;      // slot table size, then 2-paths, boundary entries
 constexpr int kHbEdges = 40;             // SLG_MAX_S edge totals
 constexpr int kHbHeavyEdges = kHbEdges + SLG_MAX_S;
-static_assert(kHbSlots + 3 <= kHbEdges && kHbHeavyEdges + 1 < kPinnedSlots, "pinned staging layout");
+static_assert(kHbSlots + 3 <= kHbEdges && kHbHeavyEdges + 2 < kPinnedSlots, "pinned staging layout");
 
 // Freed device blocks a context keeps for reuse unless told otherwise.
 constexpr uint64_t kDefaultCache = uint64_t(16) << 30;
@@ -213,6 +215,12 @@ struct slg_plan {
     int64_t list_count[kNumLists] = {};
     int64_t *slot_cnt = nullptr;   // [K][S]
     int64_t *slot_off = nullptr;   // [K][S+1]
+    bool use_store = false;        // the counting pass keeps the heavy overlaps for the emit pass
+    CountStore store{};
+    int64_t *store_work = nullptr; // [heavy slots]: 2-paths per slot
+    int64_t store_limit = 0;
+    int64_t store_min = 0;
+    int64_t stored_ranks = 0;
     int64_t two_paths = 0;
     int64_t heavy_two_paths = 0;
     int64_t heavy_edges = 0;
@@ -436,6 +444,12 @@ hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
                 hipSuccess)
                 return e;
     }
+    if (p->use_store) {  // the store's layout: each heavy slot's 2-paths bound its partners
+        StageTimer tm(ctx, kStBounds, st);
+        const int64_t nh = p->list_count[kLightClasses];
+        if ((e = launch_slot_work(p->heavy[0], nh, p->bounds, p->store_work, st)) != hipSuccess) return e;
+        if ((e = launch_exclusive_scan_i64(p->store_work, nh, p->store.off, b.part_s, st)) != hipSuccess) return e;
+    }
     {
         StageTimer tm(ctx, kStCountLight, st);
         for (int c = 0; c < kLightClasses; ++c)
@@ -443,13 +457,13 @@ hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
                                   nullptr, st)) != hipSuccess)
                 return e;
     }
-    if ((e = launch_fill_i64(p->tickets, 5, 0, st)) != hipSuccess) return e;
+    if ((e = launch_fill_i64(p->tickets, 6, 0, st)) != hipSuccess) return e;
     for (int wide = 0; wide < 2; ++wide) {
         if (p->list_count[kLightClasses + wide] <= 0) continue;
         StageTimer tm(ctx, wide ? kStCountHeavyWide : kStCountHeavy, st);
         if ((e = launch_heavy(false, wide, p->heavy[wide], p->list_count[kLightClasses + wide], p->S, p->bounds,
-                              p->pr, p->prm, p->slot_cnt, nullptr, p->tickets + wide, p->heavy_grid, st)) !=
-            hipSuccess)
+                              p->pr, p->prm, p->slot_cnt, nullptr, p->tickets + wide, p->heavy_grid,
+                              (p->use_store && !wide) ? &p->store : nullptr, st)) != hipSuccess)
             return e;
     }
     StageTimer tm(ctx, kStCountScans, st);
@@ -539,13 +553,27 @@ slg_status plan_build(slg_plan *p) {
     AllocList phase2;
     phase2.add(&b.slot_row, p->S);
     phase2.add(&p->bounds, p->nbounds);
-    phase2.add(&p->tickets, 5);
+    phase2.add(&p->tickets, 6);
     for (int c = 0; c < kLightClasses; ++c) phase2.add(&p->lists[c], p->list_count[c]);
     for (int h = 0; h < 2; ++h) phase2.add(&p->heavy[h], p->list_count[kLightClasses + h]);
     static_assert(sizeof(HeavyDesc) % 8 == 0, "HeavyDesc is filled as int64 words");
     phase2.add(&p->slot_cnt, (size_t)K * p->S);
     phase2.add(&p->slot_off, (size_t)K * (p->S + 1));
     phase2.add(&b.part_s, scan_partials_size(p->S));
+    {  // the count store, when it fits the context's limit
+        const int64_t nh = p->list_count[kLightClasses];
+        // below store_min (a batch of small graphs) the store's extra
+        // launches cost more than the walk they save
+        const int64_t bytes = p->heavy_two_paths * 4 + nh * 20 + 16;
+        p->use_store = nh > 0 && p->store_limit > 0 && bytes <= p->store_limit &&
+                       p->heavy_two_paths >= p->store_min;
+        if (p->use_store) {
+            phase2.add(&p->store.ent, p->heavy_two_paths);
+            phase2.add(&p->store.off, nh + 1);
+            phase2.add(&p->store.n, nh);
+            phase2.add(&p->store_work, nh);
+        }
+    }
     if (p->reserve) {
         if (!(*p->reserve)(phase2.bytes)) return fail(ctx, SLG_ERR_OUT_OF_MEMORY, "device-memory budget refused");
         p->reserved += phase2.bytes;
@@ -561,6 +589,9 @@ slg_status plan_build(slg_plan *p) {
         BUILD_HIP(launch_heavy_edges(p->heavy[h], p->list_count[kLightClasses + h], p->slot_cnt, p->S, K,
                                      p->tickets + 4, st));
     BUILD_HIP(hipMemcpyAsync(hb + kHbHeavyEdges, p->tickets + 4, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    if (p->use_store)
+        BUILD_HIP(launch_sum_i32(p->store.n, p->list_count[kLightClasses], p->tickets + 5, st));
+    BUILD_HIP(hipMemcpyAsync(hb + kHbHeavyEdges + 2, p->tickets + 5, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     BUILD_HIP(hipMemcpyAsync(hb + kHbHeavyEdges + 1, b.counters + kCntErr, sizeof(int64_t),
                              hipMemcpyDeviceToHost, st));
     BUILD_HIP(hipStreamSynchronize(st));
@@ -569,6 +600,7 @@ slg_status plan_build(slg_plan *p) {
         return fail(ctx, SLG_ERR_DEVICE, "internal error: a tier list overflowed its planned size");
     for (int k = 0; k < K; ++k) p->num_edges[k] = hb[kHbEdges + k];
     p->heavy_edges = hb[kHbHeavyEdges];
+    p->stored_ranks = hb[kHbHeavyEdges + 2];
     return SLG_OK;
 }
 
@@ -586,6 +618,8 @@ slg_plan *plan_new(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num
     p->light_max = ctx->light_max;
     p->slot_work = ctx->slot_work;
     p->heavy_grid = ctx->heavy_grid > 0 ? ctx->heavy_grid : ctx->heavy_resident;
+    p->store_limit = ctx->store_limit;
+    p->store_min = ctx->store_min;
     return p;
 }
 
@@ -651,9 +685,13 @@ slg_status emit_range(slg_plan *p, int64_t r0, int64_t r1, int64_t s0, int64_t s
     for (int wide = 0; wide < 2; ++wide) {
         if (p->list_count[kLightClasses + wide] <= 0) continue;
         StageTimer tm(ctx, wide ? kStEmitHeavyWide : kStEmitHeavy, st);
-        SLG_HIP(ctx, launch_heavy(true, wide, p->heavy[wide], p->list_count[kLightClasses + wide], p->S,
-                                  p->bounds, p->pr, prm, nullptr, p->slot_off, p->tickets + 2 + wide,
-                                  p->heavy_grid, st));
+        if (p->use_store && !wide)
+            SLG_HIP(ctx, launch_heavy_store_emit(p->heavy[0], p->list_count[kLightClasses], p->S, p->store, prm,
+                                                 p->slot_off, st));
+        else
+            SLG_HIP(ctx, launch_heavy(true, wide, p->heavy[wide], p->list_count[kLightClasses + wide], p->S,
+                                      p->bounds, p->pr, prm, nullptr, p->slot_off, p->tickets + 2 + wide,
+                                      p->heavy_grid, nullptr, st));
     }
     {
         StageTimer tm(ctx, kStRowPtr, st);
@@ -784,7 +822,7 @@ slg_status slg_line_graph_stream(slg_context *ctx, slg_graph *g, const int32_t *
 
 slg_status slg_plan_stats(const slg_plan *p, int64_t *out, int32_t cap, int32_t *count) {
     if (!p || (!out && cap > 0) || cap < 0) return SLG_ERR_INVALID_ARG;
-    int64_t vals[14];
+    int64_t vals[15];
     vals[0] = p->S;
     for (int c = 0; c < kLightClasses; ++c) vals[1 + c] = p->list_count[c];
     vals[8] = p->list_count[kLightClasses];
@@ -793,8 +831,9 @@ slg_status slg_plan_stats(const slg_plan *p, int64_t *out, int32_t cap, int32_t 
     vals[11] = p->heavy_two_paths;
     vals[12] = p->nbounds;
     vals[13] = p->heavy_edges;
+    vals[14] = p->stored_ranks;
     static_assert(kLightClasses == 7, "plan stats layout");
-    int32_t n = cap < 14 ? cap : 14;
+    int32_t n = cap < 15 ? cap : 15;
     for (int32_t t = 0; t < n; ++t) out[t] = vals[t];
     if (count) *count = n;
     return SLG_OK;
@@ -847,6 +886,15 @@ slg_status slg_plan_destroy(slg_plan *p) {
     if (!p) return SLG_ERR_INVALID_ARG;
     p->scratch.release();
     delete p;
+    return SLG_OK;
+}
+
+slg_status slg_context_set_count_store(slg_context *ctx, int64_t max_bytes, int64_t min_two_paths) {
+    if (!ctx) return SLG_ERR_INVALID_ARG;
+    if (max_bytes < 0 || min_two_paths < 0)
+        return fail(ctx, SLG_ERR_INVALID_ARG, "max_bytes and min_two_paths must be >= 0");
+    ctx->store_limit = max_bytes;
+    ctx->store_min = min_two_paths;
     return SLG_OK;
 }
 
@@ -1109,6 +1157,8 @@ void copy_tuning(slg_context *dst, const slg_context *src) {
     dst->light_max = src->light_max;
     dst->slot_work = src->slot_work;
     dst->heavy_grid = src->heavy_grid;
+    dst->store_limit = src->store_limit;
+    dst->store_min = src->store_min;
 }
 
 slg_status serve_query(slg_context *wctx, slg_graph *g, const int32_t *s, int32_t num_s, hipStream_t st,

@@ -74,6 +74,17 @@ struct HeavyDesc {
     int64_t bptr;
 };
 
+// Overlaps kept by the counting pass for the emit pass: heavy slot t (its
+// index in the heavy list) holds n[t] entries in rank order at off[t], each
+// (partner - ja) | overlap << 16 (a slot spans at most 2^16 ids, and a
+// non-wide row has fewer than 2^16 members); off is the exclusive prefix of
+// the slots' 2-path counts, which bound their distinct partners.
+struct CountStore {
+    uint32_t *ent;
+    int64_t *off;
+    int32_t *n;
+};
+
 // ---- launchers (all enqueue on `st`, return hipError_t) -------------------
 hipError_t launch_exclusive_scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *partials,
                                      hipStream_t st);
@@ -113,9 +124,19 @@ hipError_t launch_light(int cls, bool emit, const int32_t *list, int64_t count, 
                         const int64_t *slot_off, hipStream_t st);
 // Persistent launch: `resident` workgroups (0 = a default) take slots from
 // the device counter `ticket`, which the caller zeroes before the launch.
+// store (counting pass of non-wide slots only, or null): keep the overlaps.
 hipError_t launch_heavy(bool emit, bool wide, const HeavyDesc *desc, int64_t count, int64_t slots,
                         const int32_t *bounds, const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
-                        const int64_t *slot_off, int64_t *ticket, int resident, hipStream_t st);
+                        const int64_t *slot_off, int64_t *ticket, int resident, const CountStore *store,
+                        hipStream_t st);
+// work[t] = 2-paths of heavy slot t (from the boundary table).
+hipError_t launch_slot_work(const HeavyDesc *desc, int64_t count, const int32_t *bounds, int64_t *work,
+                            hipStream_t st);
+// Emit pass of the heavy slots from the counting pass's store.
+hipError_t launch_heavy_store_emit(const HeavyDesc *desc, int64_t count, int64_t slots, const CountStore &store,
+                                   const EmitParams &ep, const int64_t *slot_off, hipStream_t st);
+// *out += sum of n[0..count) (int32).
+hipError_t launch_sum_i32(const int32_t *n, int64_t count, int64_t *out, hipStream_t st);
 hipError_t launch_heavy_edges(const HeavyDesc *desc, int64_t count, const int64_t *slot_cnt, int64_t S,
                               int32_t K, int64_t *out, hipStream_t st);
 // Workgroups of the heavy kernel that fit on the device at once.

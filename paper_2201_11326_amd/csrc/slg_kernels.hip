@@ -280,13 +280,14 @@ __device__ __forceinline__ int light_class(int64_t w) {
 }
 
 // Per-row work estimate (Section III-E's cost: the 2-paths of row i) and
-// tier. Rows of at most kSmallRow members are walked by one lane each; larger
-// rows are cut into pieces of kPlanPiece members, one wavefront per piece,
-// so that a run of large rows (an input sorted by size) spreads over the
-// whole grid. For every incidence (i, v) of a kept row: tail_beg = first
+// tier. Rows of at most kSmallRow members are walked by one lane each, rows
+// of at most kWaveRow by the wavefront of their row group; larger rows are
+// cut into pieces of kPlanPiece members, one wavefront per piece, so that a
+// run of large rows (an input sorted by size) spreads over the whole grid. For every incidence (i, v) of a kept row: tail_beg = first
 // position after i in v's (pruned) list; w_i = sum of the tails; jm =
 // largest partner id.
 constexpr int kSmallRow = 16;
+constexpr int kWaveRow = 64;
 constexpr int kPlanPiece = 256;
 
 struct RowPlanOut {
@@ -351,9 +352,9 @@ __device__ __forceinline__ void plan_finish(int64_t i, int64_t p0, int64_t p1, i
     if (cls >= kHeavy) atomicAdd(hwork, (unsigned long long)w);
 }
 
-// Small rows, and the piece list of the large ones: a large row appends
-// ceil(size / kPlanPiece) entries (row | piece << 32), one row's pieces
-// side by side.
+// Small and middle rows, and the piece list of the large ones: a large row
+// appends ceil(size / kPlanPiece) entries (row | piece << 32), one row's
+// pieces side by side.
 __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min, int32_t light_max,
                                                        int64_t slot_work, RowPlanOut o,
                                                        unsigned long long *__restrict__ class_count,
@@ -371,6 +372,7 @@ __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min, 
     for (int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64 * 64; i0 < g.m; i0 += nwaves * 64) {
         const int64_t i = i0 + lane;
         unsigned long long np = 0;  // pieces of a large row
+        bool mid = false;           // a middle row, walked by the wavefront below
         if (i < g.m) {
             const int64_t p0 = g.he_ptr[i], p1 = g.he_ptr[i + 1];
             if (p0 < 0 || p1 > g.nnz || p1 < p0) {  // malformed pointers
@@ -378,8 +380,10 @@ __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min, 
             } else {
                 const int64_t size = p1 - p0;
                 const bool kept = size > 0 && size >= (g.row_s ? g.row_s[i] : s_min);
-                if (kept && size > kSmallRow) {
+                if (kept && size > kWaveRow) {
                     np = (unsigned long long)((size + kPlanPiece - 1) / kPlanPiece);
+                } else if (kept && size > kSmallRow) {
+                    mid = true;
                 } else {  // a small (or pruned) row, walked by its own lane
                     int64_t w = 0;
                     int jm = -1;
@@ -389,6 +393,23 @@ __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min, 
                     plan_finish(i, p0, p1, w, jm, rbad, light_max, slot_work, o, ccount, &hwork, err);
                 }
             }
+        }
+        // the middle rows of this group, one after another by the whole
+        // wavefront (one member per lane)
+        unsigned long long todo = __ballot(mid);
+        while (todo) {
+            const int l = __ffsll((long long)todo) - 1;
+            todo &= todo - 1;
+            const int64_t r = i0 + l;
+            const int64_t q0 = g.he_ptr[r], q1 = g.he_ptr[r + 1];
+            int64_t w = 0;
+            int jm = -1;
+            int rbad = 0;
+            if (q0 + lane < q1) rbad = !plan_member(g, r, q0 + lane, o.tail_beg, w, jm);
+            w = wave_sum(w);
+            jm = wave_max(jm);
+            rbad = wave_max(rbad);
+            if (lane == 0) plan_finish(r, q0, q1, w, jm, rbad != 0, light_max, slot_work, o, ccount, &hwork, err);
         }
         // one reservation per wavefront for the pieces of its large rows
         const unsigned long long incl = wave_incl_scan(np);
@@ -1087,7 +1108,10 @@ __device__ __forceinline__ int count_get(const uint32_t *cnt, int r) {
 // Four 256-thread workgroups per CU (4 waves per SIMD) is what the LDS
 // footprint allows; the register budget is held to match (<= 128 VGPRs).
 // Four slots in flight per CU hide the latency of each slot's phases.
-template <bool EMIT, bool WIDE>
+// STORE (counting pass of non-wide slots): the pass also writes every
+// slot's partners and overlaps in rank order, so that the emit pass reads
+// them instead of walking the 2-paths again.
+template <bool EMIT, bool WIDE, bool STORE>
 __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4))) void heavy_kernel(const HeavyDesc *__restrict__ desc,
                                                               int64_t count, int64_t S,
                                                               const int32_t *__restrict__ bounds,
@@ -1095,7 +1119,9 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
                                                               EmitParams prm,
                                                               int64_t *__restrict__ slot_cnt,
                                                               const int64_t *__restrict__ slot_off,
-                                                              unsigned long long *__restrict__ ticket) {
+                                                              unsigned long long *__restrict__ ticket,
+                                                              CountStore cs) {
+    static_assert(!STORE || (!EMIT && !WIDE), "the store is written by the non-wide counting pass");
     constexpr int kCap = CounterCap<WIDE>::ranks;
     __shared__ HeavySmem sm;
     __shared__ EmitParams sp;  // thresholds and outputs, indexed by a uniform k
@@ -1145,7 +1171,7 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
         const int i = d.row, ja = d.ja, jb = d.jb, k = d.k, slot = d.slot;
         const int s_bottom = row_thr ? srow : ep->s[0];   // smallest and largest threshold
         const int s_top = row_thr ? srow : ep->s[K - 1];
-        const bool only_presence = !EMIT && K == 1 && s_bottom <= 1;
+        const bool only_presence = !EMIT && !STORE && K == 1 && s_bottom <= 1;
         const int nw = (jb - ja + 31) >> 5;
         const unsigned span = (unsigned)(jb - ja);
         // bitmap and counters are all-zero here: cleared before the first
@@ -1214,6 +1240,7 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
         }
         reinterpret_cast<uint4 *>(sm.wpre)[tid] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
         if (tid == 0) sm.sup[kSupers] = (uint32_t)distinct;
+        if (STORE && tid == 0) as_global(cs.n)[it] = distinct;
         __syncthreads();
 
         if (only_presence) {  // L_1 alone: every marked partner is an edge
@@ -1248,7 +1275,7 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
                 // the single window of the emit pass (whose rank-to-partner map
                 // reuses the list's storage afterwards)
                 const int nrep = sm.nrep;
-                const bool by_repeats = nrep <= kRankCap && (whole || !EMIT);
+                const bool by_repeats = nrep <= kRankCap && (whole || !(EMIT || STORE));
                 const int c_add = by_repeats ? 1 : 0;  // partners start at overlap 1
                 // pass 2: count 2-paths into their partner's rank. The overlap of
                 // a partner passes every value up to its final one exactly once,
@@ -1306,7 +1333,7 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
                 }
                 // threshold 1 over the repeat list: every rank survives
                 if (c_add && lane == 0 && s_bottom == 1) sm.wtot[0][wave] = rhi > rlo ? rhi - rlo : 0;
-                if (EMIT) {  // partner of every rank, from this thread's own 8 words
+                if (EMIT || STORE) {  // partner of every rank, from this thread's own 8 words
                     const uint4 e0 = reinterpret_cast<const uint4 *>(sm.bitmap)[2 * tid];
                     const uint4 e1 = reinterpret_cast<const uint4 *>(sm.bitmap)[2 * tid + 1];
                     const uint32_t wd[8] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
@@ -1328,6 +1355,14 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
                     }
                 }
                 __syncthreads();
+                if (STORE) {  // the window's partners and overlaps, coalesced
+                    static_assert(kRangeBits <= (1 << 16) && kWideMembers <= (1 << 16), "16-bit store fields");
+                    const int64_t base = as_global(cs.off)[it] + r0;
+                    for (int r = tid; r < nr; r += kHeavyThreads)  // whole lines, read much later
+                        __builtin_nontemporal_store(
+                            (uint32_t)(sm.buf[r] - ja) | ((uint32_t)(count_get<WIDE>(sm.cnt, r) + c_add) << 16),
+                            &as_global(cs.ent)[base + r]);
+                }
                 if (tid < K) {  // each threshold's wavefront offsets and total, by one thread
                     long long b = EMIT ? sm.obase[tid] : 0;
 #pragma unroll
@@ -1432,6 +1467,100 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
         if (!first) pair = it_next;
         it = it_next;
     }
+}
+
+// 2-paths of every heavy slot: the lengths of its members' segments in the
+// boundary table, one wavefront per slot.
+__global__ __launch_bounds__(256) void slot_work_kernel(const HeavyDesc *__restrict__ desc, int64_t count,
+                                                        const int32_t *__restrict__ bounds,
+                                                        int64_t *__restrict__ work) {
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; t < count; t += nwaves) {
+        const HeavyDesc d = desc[t];
+        int64_t w = 0;
+        for (int q = lane; q < d.k; q += 64) w += bounds[d.bptr + d.k + q] - bounds[d.bptr + q];
+        w = wave_sum(w);
+        if (lane == 0) work[t] = w;
+    }
+}
+
+// Emit pass of the heavy slots from the counting pass's store: one
+// wavefront per slot reads its partners and overlaps in rank (partner id)
+// order, four groups of 64 ranks per step (all loads issued before any is
+// used), and compacts the survivors of every threshold with ballots into the
+// slot's output segment. Thresholds increase, so a group with no survivor of
+// s_k has none of the larger ones either. MAXK: 4 for ensembles of up to
+// four thresholds (fewer registers), else SLG_MAX_S.
+constexpr int kStoreGroups = 8;
+
+template <int MAXK>
+__global__ __launch_bounds__(256) void heavy_store_emit_kernel(const HeavyDesc *__restrict__ desc, int64_t count,
+                                                               int64_t S, CountStore cs, EmitParams prm,
+                                                               const int64_t *__restrict__ slot_off) {
+    __shared__ EmitParams sp;
+    stage_params(&sp, prm);
+    __syncthreads();
+    const int lane = lane_id();
+    const int K = prm.k;
+    const bool row_thr = prm.row_s != nullptr;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; t < count; t += nwaves) {
+        const HeavyDesc d = desc[t];
+        if (d.slot < prm.slot_lo || d.slot >= prm.slot_hi) continue;  // outside the emitted chunk
+        const int n = as_global(cs.n)[t];
+        const int64_t off = as_global(cs.off)[t];
+        const int i = d.row;
+        const int id0 = prm.row_base ? as_global(prm.row_base)[i] : 0;
+        const int srow = row_thr ? as_global(prm.row_s)[i] : 0;
+        long long b[MAXK];
+        int sk[MAXK];
+#pragma unroll
+        for (int kk = 0; kk < MAXK; ++kk) {
+            b[kk] = kk < K ? slot_off[(int64_t)kk * (S + 1) + d.slot] - sp.out_base[kk] : 0;
+            sk[kk] = kk < K ? (row_thr ? srow : sp.s[kk]) : INT_MAX;
+        }
+        for (int r0 = 0; r0 < n; r0 += 64 * kStoreGroups) {
+            uint32_t e[kStoreGroups];
+#pragma unroll
+            for (int q = 0; q < kStoreGroups; ++q) {
+                const int r = r0 + 64 * q + lane;
+                e[q] = r < n ? as_global(cs.ent)[off + r] : 0u;
+            }
+            int key[kStoreGroups], c[kStoreGroups];
+#pragma unroll
+            for (int q = 0; q < kStoreGroups; ++q) {
+                key[q] = d.ja + (int)(e[q] & 0xFFFFu);
+                c[q] = (int)(e[q] >> 16);
+            }
+#pragma unroll
+            for (int q = 0; q < kStoreGroups; ++q) {
+                if (r0 + 64 * q >= n) break;  // wave-uniform
+#pragma unroll
+                for (int kk = 0; kk < MAXK; ++kk) {
+                    if (kk >= K) break;
+                    const bool surv = c[q] >= sk[kk];
+                    const unsigned long long mask = __ballot(surv);
+                    if (mask == 0ull) break;
+                    if (surv) {
+                        const int64_t pos = b[kk] + bits_below(mask);
+                        as_global(sp.col[kk])[pos] = key[q] - id0;
+                        as_global(sp.w[kk])[pos] = c[q];
+                        if (sp.row[kk]) as_global(sp.row[kk])[pos] = i - id0;
+                    }
+                    b[kk] += __popcll(mask);
+                }
+            }
+        }
+    }
+}
+
+__global__ void sum_i32_kernel(const int32_t *__restrict__ n, int64_t count, unsigned long long *__restrict__ out) {
+    unsigned long long acc = 0;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
+        acc += (unsigned long long)n[t];
+    acc = wave_sum(acc);
+    if (lane_id() == 0 && acc) atomicAdd(out, acc);
 }
 
 // Edges of every threshold emitted by heavy slots (for measurement).
@@ -1745,21 +1874,22 @@ inline unsigned wave_grid(int64_t rows, int waves_per_block, int64_t cap) {
 // ---------------------------------------------------------------------------
 int64_t scan_partials_size(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
-// A large row of S > kSmallRow members has ceil(S / 256) <= (S + 255) / 256
-// <= S / 16 pieces (S >= 17): at most nnz / 16 in all when the rows do not
-// overlap. The piece list holds, per piece, its entry, its 2-paths (int64)
+// A large row of S > kWaveRow >= kSmallRow members has ceil(S / 256) <=
+// (S + 255) / 256 <= S / 16 pieces (S >= 17): at most nnz / 16 in all when
+// the rows do not overlap. The piece list holds, per piece, its entry, its 2-paths (int64)
 // and its largest partner (int32): 3 * cap int64 in all.
-static_assert(kPlanPiece == 256 && kSmallRow >= 16, "piece bound");
+static_assert(kPlanPiece == 256 && kWaveRow >= kSmallRow && kSmallRow >= 16 && kWaveRow <= 64, "piece bound");
 int64_t plan_pieces_cap(int64_t nnz) { return nnz / 16 + 1; }
 
 int heavy_resident(int device) {
     int cus = 0, per = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 0;
     // the grid is shared by every variant: take the least resident one
-    const void *variants[4] = {reinterpret_cast<const void *>(heavy_kernel<false, false>),
-                               reinterpret_cast<const void *>(heavy_kernel<false, true>),
-                               reinterpret_cast<const void *>(heavy_kernel<true, false>),
-                               reinterpret_cast<const void *>(heavy_kernel<true, true>)};
+    const void *variants[5] = {reinterpret_cast<const void *>(heavy_kernel<false, false, false>),
+                               reinterpret_cast<const void *>(heavy_kernel<false, true, false>),
+                               reinterpret_cast<const void *>(heavy_kernel<true, false, false>),
+                               reinterpret_cast<const void *>(heavy_kernel<true, true, false>),
+                               reinterpret_cast<const void *>(heavy_kernel<false, false, true>)};
     for (const void *f : variants) {
         int v = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, f, kHeavyThreads, 0) != hipSuccess) v = 0;
@@ -1889,19 +2019,49 @@ hipError_t launch_light(int cls, bool emit, const int32_t *list, int64_t count, 
 
 hipError_t launch_heavy(bool emit, bool wide, const HeavyDesc *desc, int64_t count, int64_t slots,
                         const int32_t *bounds, const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
-                        const int64_t *slot_off, int64_t *ticket, int resident, hipStream_t st) {
+                        const int64_t *slot_off, int64_t *ticket, int resident, const CountStore *store,
+                        hipStream_t st) {
     if (count <= 0) return hipSuccess;
+    if (store && (emit || wide)) return hipErrorInvalidValue;
     const int64_t want = resident > 0 ? resident : 512;
     const unsigned grid = (unsigned)(count < want ? count : want);
     unsigned long long *tk = reinterpret_cast<unsigned long long *>(ticket);
-#define SLG_HEAVY(E, W)                                                                             \
-    heavy_kernel<E, W><<<grid, kHeavyThreads, 0, st>>>(desc, count, slots, bounds, g.vs_idx, ep, slot_cnt, \
-                                                       slot_off, tk)
-    if (emit && wide) SLG_HEAVY(true, true);
-    else if (emit) SLG_HEAVY(true, false);
-    else if (wide) SLG_HEAVY(false, true);
-    else SLG_HEAVY(false, false);
+    const CountStore cs = store ? *store : CountStore{};
+#define SLG_HEAVY(E, W, ST)                                                                          \
+    heavy_kernel<E, W, ST><<<grid, kHeavyThreads, 0, st>>>(desc, count, slots, bounds, g.vs_idx, ep, slot_cnt, \
+                                                           slot_off, tk, cs)
+    if (emit && wide) SLG_HEAVY(true, true, false);
+    else if (emit) SLG_HEAVY(true, false, false);
+    else if (wide) SLG_HEAVY(false, true, false);
+    else if (store) SLG_HEAVY(false, false, true);
+    else SLG_HEAVY(false, false, false);
 #undef SLG_HEAVY
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_work(const HeavyDesc *desc, int64_t count, const int32_t *bounds, int64_t *work,
+                            hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    slot_work_kernel<<<wave_grid(count, 4, 8192), 256, 0, st>>>(desc, count, bounds, work);
+    return hipGetLastError();
+}
+
+hipError_t launch_heavy_store_emit(const HeavyDesc *desc, int64_t count, int64_t slots, const CountStore &store,
+                                   const EmitParams &ep, const int64_t *slot_off, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    if (ep.k <= 4)
+        heavy_store_emit_kernel<4><<<wave_grid(count, 4, 16384), 256, 0, st>>>(desc, count, slots, store, ep,
+                                                                                  slot_off);
+    else
+        heavy_store_emit_kernel<SLG_MAX_S><<<wave_grid(count, 4, 16384), 256, 0, st>>>(desc, count, slots, store,
+                                                                                          ep, slot_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_i32(const int32_t *n, int64_t count, int64_t *out, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    sum_i32_kernel<<<grid_for(count, 256) < 4096 ? grid_for(count, 256) : 4096, 256, 0, st>>>(
+        n, count, reinterpret_cast<unsigned long long *>(out));
     return hipGetLastError();
 }
 

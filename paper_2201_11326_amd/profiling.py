@@ -8,7 +8,7 @@
       Per-kernel launch count / total / average / min / max duration from a
       rocprofv3 --kernel-trace database.
   python -m paper_2201_11326_amd.profiling traffic FETCH_DB WRITE_DB
-      HBM bytes per launch of the heavy emit kernel, scaled by what the same
+      HBM bytes per launch of each heavy-tier kernel, scaled by what the same
       counters read for the calibration copy (1 GiB read + 1 GiB written).
 """
 from __future__ import annotations
@@ -25,7 +25,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 KERNEL_SRC = os.path.join(HERE, "csrc", "slg_kernels.hip")
 COPY_BYTES = 1 << 30
-HEAVY_EMIT = "heavy_kernel<true, false>"
 
 
 def short_name(kname: str) -> str:
@@ -90,7 +89,14 @@ def counter_per_kernel(db: str, counter: str):
     return per
 
 
+HEAVY_KERNELS = ("heavy_kernel<false, false, true>", "heavy_kernel<false, false, false>",
+                 "heavy_store_emit_kernel<4>", "heavy_kernel<true, false, false>")
+
+
 def traffic(fetch_db: str, write_db: str) -> str:
+    """HBM bytes per launch of every heavy-tier kernel found in the two runs
+    (the counting pass, with or without the count store, and the emit pass,
+    from the store or by walking the 2-paths again)."""
     f = counter_per_kernel(fetch_db, "FETCH_SIZE")
     w = counter_per_kernel(write_db, "WRITE_SIZE")
     copy = [k for k in f if "copy" in k.lower() or "elementwise" in k.lower()]
@@ -98,27 +104,32 @@ def traffic(fetch_db: str, write_db: str) -> str:
     ck = max(copy, key=lambda k: max(f[k])) if copy else None
     fetch_factor = COPY_BYTES / (max(f[ck]) * 1024) if ck else 1.0
     write_factor = COPY_BYTES / (max(w.get(ck, [0])) * 1024) if ck and w.get(ck) else 1.0
-    fe = f.get(HEAVY_EMIT, [])
-    we = w.get(HEAVY_EMIT, [])
-    fetch_b = fetch_factor * 1024 * sum(fe) / max(len(fe), 1)
-    write_b = write_factor * 1024 * sum(we) / max(len(we), 1)
     with open(KERNEL_SRC, "rb") as fh:
         sha = hashlib.sha256(fh.read()).hexdigest()
     lines = [
-        "# HBM traffic of the heavy emit kernel (power-law ensemble S={1,2,4,8})",
+        "# HBM traffic of the heavy-tier kernels (power-law ensemble S={1,2,4,8})",
         "",
-        f"kernel: {HEAVY_EMIT}",
         f"kernel_source_sha256: {sha}",
         f"calibration kernel: {ck} (1 GiB read + 1 GiB written)",
         f"calibration FETCH_SIZE KiB: {max(f[ck]) if ck else None}; factor {fetch_factor:.4f}",
         f"calibration WRITE_SIZE KiB: {max(w[ck]) if ck and w.get(ck) else None}; factor {write_factor:.4f}",
-        f"launches measured: {len(fe)} (FETCH_SIZE), {len(we)} (WRITE_SIZE)",
-        f"FETCH_SIZE KiB per launch (raw): {sum(fe) / max(len(fe), 1):.1f}",
-        f"WRITE_SIZE KiB per launch (raw): {sum(we) / max(len(we), 1):.1f}",
-        f"hbm_fetch_bytes_per_launch: {fetch_b:.6e}",
-        f"hbm_write_bytes_per_launch: {write_b:.6e}",
-        f"hbm_bytes_per_launch: {fetch_b + write_b:.6e}",
     ]
+    for name in HEAVY_KERNELS:
+        fe, we = f.get(name, []), w.get(name, [])
+        if not fe or not we:
+            continue
+        fetch_b = fetch_factor * 1024 * sum(fe) / len(fe)
+        write_b = write_factor * 1024 * sum(we) / len(we)
+        lines += [
+            "",
+            f"kernel: {name}",
+            f"launches measured: {len(fe)} (FETCH_SIZE), {len(we)} (WRITE_SIZE)",
+            f"FETCH_SIZE KiB per launch (raw): {sum(fe) / len(fe):.1f}",
+            f"WRITE_SIZE KiB per launch (raw): {sum(we) / len(we):.1f}",
+            f"hbm_fetch_bytes_per_launch: {fetch_b:.6e}",
+            f"hbm_write_bytes_per_launch: {write_b:.6e}",
+            f"hbm_bytes_per_launch: {fetch_b + write_b:.6e}",
+        ]
     return "\n".join(lines)
 
 

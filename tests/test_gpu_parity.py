@@ -14,10 +14,18 @@ from helpers import load_toy
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def ctx():
+@pytest.fixture(scope="module", params=["store", "rewalk"])
+def ctx(request):
+    """Every parity case runs twice: with the count store (the emit pass
+    reads the heavy overlaps kept by the counting pass) and without it (the
+    emit pass walks the 2-paths again)."""
     import paper_2201_11326_amd as slg
     c = slg.Context(0)
+    if request.param == "rewalk":
+        c.set_count_store(0)
+    else:  # the store on every graph with heavy slots, however small
+        c.set_count_store(32 << 30, 0)
+    c.store_mode = request.param
     yield c
     c.close()
 
@@ -469,3 +477,18 @@ def test_batch_tuning_variants_agree(ctx):
             assert np.array_equal(outs[0][g].w.numpy()[rp[i]:rp[i + 1]], rw)
     for gr in graphs:
         gr.release()
+
+
+def test_count_store_engages_when_asked(ctx):
+    # rows sharing vertex 0 make heavy slots; with the store on, the counting
+    # pass keeps one entry per distinct heavy partner (s_min = 1: the heavy
+    # edges of L_1), with it off none
+    inc = planted(6000, 20000, [([0], 2, 0)], 3, seed=17)
+    g = ctx.register_incidence(inc)
+    p = ctx.plan(g, [1])
+    st = p.stats()
+    assert st["heavy_slots"] > 0 and st["heavy_edges"] > 0
+    want = st["heavy_edges"] if ctx.store_mode == "store" else 0
+    assert st["stored_ranks"] == want
+    p.destroy()
+    g.release()
