@@ -1486,22 +1486,27 @@ __global__ __launch_bounds__(256) void slot_work_kernel(const HeavyDesc *__restr
 }
 
 // Emit pass of the heavy slots from the counting pass's store: one
-// wavefront per slot reads its partners and overlaps in rank (partner id)
-// order, four groups of 64 ranks per step (all loads issued before any is
-// used), and compacts the survivors of every threshold with ballots into the
-// slot's output segment. Thresholds increase, so a group with no survivor of
-// s_k has none of the larger ones either. MAXK: 4 for ensembles of up to
-// four thresholds (fewer registers), else SLG_MAX_S.
+// wavefront per slot reads its entries in rank (partner id) order, eight
+// groups of 64 ranks per step (all loads issued before any is used). Each
+// threshold's survivors are compacted with ballots into a small LDS queue
+// of the wavefront and written out 64 at a time, so that every global store
+// is a full, coalesced 256-byte row even for sparse thresholds; what is
+// left is written at the end of the slot. Thresholds increase, so a group
+// with no survivor of s_k has none of the larger ones either. MAXK: 4 for
+// ensembles of up to four thresholds, else SLG_MAX_S (no queues).
 constexpr int kStoreGroups = 8;
+constexpr int kQueue = 128;  // entries per threshold queue: < 64 kept + <= 64 appended
 
 template <int MAXK>
 __global__ __launch_bounds__(256) void heavy_store_emit_kernel(const HeavyDesc *__restrict__ desc, int64_t count,
                                                                int64_t S, CountStore cs, EmitParams prm,
                                                                const int64_t *__restrict__ slot_off) {
+    constexpr bool kQueued = MAXK <= 4;
     __shared__ EmitParams sp;
+    __shared__ uint32_t queue[kQueued ? 4 : 1][kQueued ? MAXK : 1][kQueued ? kQueue : 1];
     stage_params(&sp, prm);
     __syncthreads();
-    const int lane = lane_id();
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
     const int K = prm.k;
     const bool row_thr = prm.row_s != nullptr;
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
@@ -1513,13 +1518,26 @@ __global__ __launch_bounds__(256) void heavy_store_emit_kernel(const HeavyDesc *
         const int i = d.row;
         const int id0 = prm.row_base ? as_global(prm.row_base)[i] : 0;
         const int srow = row_thr ? as_global(prm.row_s)[i] : 0;
+        const int jbase = d.ja - id0;
         long long b[MAXK];
-        int sk[MAXK];
+        int sk[MAXK], fill[MAXK];
 #pragma unroll
         for (int kk = 0; kk < MAXK; ++kk) {
             b[kk] = kk < K ? slot_off[(int64_t)kk * (S + 1) + d.slot] - sp.out_base[kk] : 0;
             sk[kk] = kk < K ? (row_thr ? srow : sp.s[kk]) : INT_MAX;
+            fill[kk] = 0;
         }
+        // writes `m` queued entries of threshold kk (lanes below m) at b[kk]
+        auto flush = [&](int kk, int m) {
+            if (lane < m) {
+                const uint32_t e = queue[wave][kk][lane];
+                const int64_t pos = b[kk] + lane;
+                as_global(sp.col[kk])[pos] = jbase + (int)(e & 0xFFFFu);
+                as_global(sp.w[kk])[pos] = (int)(e >> 16);
+                if (sp.row[kk]) as_global(sp.row[kk])[pos] = i - id0;
+            }
+            b[kk] += m;
+        };
         for (int r0 = 0; r0 < n; r0 += 64 * kStoreGroups) {
             uint32_t e[kStoreGroups];
 #pragma unroll
@@ -1527,30 +1545,43 @@ __global__ __launch_bounds__(256) void heavy_store_emit_kernel(const HeavyDesc *
                 const int r = r0 + 64 * q + lane;
                 e[q] = r < n ? as_global(cs.ent)[off + r] : 0u;
             }
-            int key[kStoreGroups], c[kStoreGroups];
-#pragma unroll
-            for (int q = 0; q < kStoreGroups; ++q) {
-                key[q] = d.ja + (int)(e[q] & 0xFFFFu);
-                c[q] = (int)(e[q] >> 16);
-            }
 #pragma unroll
             for (int q = 0; q < kStoreGroups; ++q) {
                 if (r0 + 64 * q >= n) break;  // wave-uniform
+                const int c = (int)(e[q] >> 16);
 #pragma unroll
                 for (int kk = 0; kk < MAXK; ++kk) {
                     if (kk >= K) break;
-                    const bool surv = c[q] >= sk[kk];
+                    const bool surv = c >= sk[kk];
                     const unsigned long long mask = __ballot(surv);
                     if (mask == 0ull) break;
-                    if (surv) {
+                    if (kQueued) {
+                        if (surv) queue[wave][kk][fill[kk] + bits_below(mask)] = e[q];
+                        fill[kk] += __popcll(mask);
+                        if (fill[kk] >= 64) {  // a full row out, the rest moves down
+                            wave_lds_sync();
+                            flush(kk, 64);
+                            const uint32_t rest = lane < fill[kk] - 64 ? queue[wave][kk][64 + lane] : 0u;
+                            wave_lds_sync();
+                            if (lane < fill[kk] - 64) queue[wave][kk][lane] = rest;
+                            fill[kk] -= 64;
+                        }
+                    } else if (surv) {
                         const int64_t pos = b[kk] + bits_below(mask);
-                        as_global(sp.col[kk])[pos] = key[q] - id0;
-                        as_global(sp.w[kk])[pos] = c[q];
+                        as_global(sp.col[kk])[pos] = jbase + (int)(e[q] & 0xFFFFu);
+                        as_global(sp.w[kk])[pos] = c;
                         if (sp.row[kk]) as_global(sp.row[kk])[pos] = i - id0;
                     }
-                    b[kk] += __popcll(mask);
+                    if (!kQueued) b[kk] += __popcll(mask);
                 }
             }
+        }
+        if (kQueued) {
+            wave_lds_sync();
+#pragma unroll
+            for (int kk = 0; kk < MAXK; ++kk)
+                if (kk < K && fill[kk] > 0) flush(kk, fill[kk]);
+            wave_lds_sync();  // the queues are reused by the next slot
         }
     }
 }
