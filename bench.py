@@ -526,6 +526,69 @@ def bench_preprocess(args) -> int:
     return 0
 
 
+def bench_large_skewed(args) -> int:
+    """The chunked streaming form (slg_line_graph_stream) on a tenth-size
+    instance of the large-skewed generator (n = 5e5, m = 1e6, the full-size
+    shape's |e| and vertex-weight laws), ensemble S = {8, 16}, output handed
+    over in chunks of at most 2 GiB to a callback that only tallies them.
+    value = 2-paths of E_8 per second of the whole streamed call."""
+    import torch
+
+    import hypergen as hg
+    import paper_2201_11326_amd as slg
+
+    S = [8, 16]
+    t_gen = time.perf_counter()
+    inc = hg.large_skewed(n=500_000, m=1_000_000)
+    t_gen = time.perf_counter() - t_gen
+    ctx = slg.Context(0)
+    g = ctx.register_incidence(inc)
+    p = ctx.plan(g, S)  # untimed: sizes for the checks and the rate
+    two_paths, want, stats = p.two_paths, p.num_edges(), p.stats()
+    p.destroy()
+    chunk = 2 << 30
+    got = {}
+
+    def on_chunk(k, s, r0, r1, e0, row_ptr, row, col, w):
+        got.setdefault(s, [0, 0])
+        got[s][0] += int(col.numel())
+        got[s][1] += 1
+        return False
+
+    for _ in range(args.warmup):
+        got.clear()
+        ctx.line_graph_stream(g, S, chunk, on_chunk)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        got.clear()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.line_graph_stream(g, S, chunk, on_chunk)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        for k, s in enumerate(S):  # every edge came through the callback
+            assert got[s][0] == want[k], (s, got[s], want[k])
+    elapsed = sum(times)
+    line = {
+        "metric": METRIC, "value": two_paths * args.steps / elapsed, "unit": "2-paths/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "large-skewed hypergraph at a tenth of full size: n=5e5 m=1e6 "
+                               "|e|=min(rint(LogNormal(1.5,1)),1e4) vertex weight~rank^-1.5, ensemble S={8,16}, "
+                               "streamed in chunks of <= 2 GiB", "n": inc.n, "m": inc.m, "nnz": inc.nnz, "s": S,
+                   "seed": hg.BASE_SEED + 3, "parallelism": "single GPU"},
+        "two_paths_per_step": two_paths, "edges_per_step": want,
+        "edges_per_s": sum(want) * args.steps / elapsed,
+        "chunks_per_step": {str(s): got[s][1] for s in S}, "p50_ms": 1e3 * percentile(times, 0.5),
+        "plan": stats, "generate_s": t_gen, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+    g.release()
+    ctx.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -533,12 +596,14 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("power_law", "batched", "served", "components", "preprocess"),
+    ap.add_argument("--workload", choices=("power_law", "batched", "served", "components", "preprocess",
+                                           "large_skewed"),
                     default="power_law",
                     help="power_law: the single large hypergraph (default); batched: 256 small "
                          "hypergraphs, each with its own s, as one disjoint-union batch; served: a request "
                          "loop; components: components, squeezing and symmetric CSR of the power-law L_s; "
-                         "preprocess: relabel-by-degree and toplexes of the power-law hypergraph")
+                         "preprocess: relabel-by-degree and toplexes of the power-law hypergraph; "
+                         "large_skewed: the chunked streaming form on a tenth-size large-skewed hypergraph")
     ap.add_argument("--no-tune", action="store_true", help="batched: library-default plan shape")
     ap.add_argument("--requests", type=int, default=4000, help="served: number of requests")
     ap.add_argument("--rate", type=float, default=2000.0, help="served: Poisson arrivals per second")
@@ -567,6 +632,8 @@ def main() -> int:
         return bench_components(args)
     if args.workload == "preprocess":
         return bench_preprocess(args)
+    if args.workload == "large_skewed":
+        return bench_large_skewed(args)
     t_gen = time.perf_counter()
     inc = hg.power_law()
     t_gen = time.perf_counter() - t_gen

@@ -76,7 +76,8 @@ static_assert(kCntTotal <= 32, "counter block");
 constexpr int kHbSlots = kCntTotal;      // slot table size, then 2-paths, boundary entries
 constexpr int kHbEdges = 40;             // SLG_MAX_S edge totals
 constexpr int kHbHeavyEdges = kHbEdges + SLG_MAX_S;
-static_assert(kHbSlots + 3 <= kHbEdges && kHbHeavyEdges + 2 < kPinnedSlots, "pinned staging layout");
+constexpr int kHbRange = kHbHeavyEdges + 3;  // a chunk's heavy list ranges (4 entries)
+static_assert(kHbSlots + 3 <= kHbEdges && kHbRange + 4 <= kPinnedSlots, "pinned staging layout");
 
 // Freed device blocks a context keeps for reuse unless told otherwise.
 constexpr uint64_t kDefaultCache = uint64_t(16) << 30;
@@ -188,6 +189,7 @@ struct PlanBufs {
     int32_t *tail_beg = nullptr, *jmax = nullptr, *nslots = nullptr, *slot_row = nullptr;
     int64_t *work = nullptr, *work_pre = nullptr, *counters = nullptr, *part_m = nullptr;
     int64_t *bsize = nullptr, *bbase = nullptr, *hat = nullptr, *part_s = nullptr;
+    int32_t *hcnt = nullptr;
     int64_t *pieces = nullptr;
     uint8_t *rclass = nullptr;
 };
@@ -432,7 +434,7 @@ hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
     {
         StageTimer tm(ctx, kStSlots, st);
         if ((e = launch_fill_slots(m, p->pr.he_ptr, p->slot_base, b.nslots, b.jmax, b.rclass, b.bbase, b.hat,
-                                   b.slot_row, p->lists, p->heavy, p->list_count,
+                                   b.hcnt, b.part_m, b.slot_row, p->lists, p->heavy, p->list_count,
                                    reinterpret_cast<unsigned long long *>(b.counters + kCntFill),
                                    reinterpret_cast<int *>(b.counters + kCntErr), st)) != hipSuccess)
             return e;
@@ -513,7 +515,8 @@ slg_status plan_build(slg_plan *p) {
     phase1.add(&b.rclass, m);
     phase1.add(&b.bsize, m);
     phase1.add(&b.bbase, m + 1);
-    phase1.add(&b.hat, m);
+    phase1.add(&b.hat, 2 * (m + 1));
+    phase1.add(&b.hcnt, 2 * m);
     phase1.add(&b.counters, 32);
     phase1.add(&b.pieces, 3 * plan_pieces_cap(nnz));
     phase1.add(&b.part_m, scan_partials_size(m));
@@ -553,7 +556,7 @@ slg_status plan_build(slg_plan *p) {
     AllocList phase2;
     phase2.add(&b.slot_row, p->S);
     phase2.add(&p->bounds, p->nbounds);
-    phase2.add(&p->tickets, 6);
+    phase2.add(&p->tickets, 10);
     for (int c = 0; c < kLightClasses; ++c) phase2.add(&p->lists[c], p->list_count[c]);
     for (int h = 0; h < 2; ++h) phase2.add(&p->heavy[h], p->list_count[kLightClasses + h]);
     static_assert(sizeof(HeavyDesc) % 8 == 0, "HeavyDesc is filled as int64 words");
@@ -682,16 +685,35 @@ slg_status emit_range(slg_plan *p, int64_t r0, int64_t r1, int64_t s0, int64_t s
                                       p->slot_off, st));
     }
     SLG_HIP(ctx, launch_fill_i64(p->tickets + 2, 2, 0, st));
+    // a chunk's heavy slots: a contiguous part of each heavy list (both are
+    // in slot order), found on the device and read back
+    int64_t lo[2] = {0, 0}, hi[2] = {p->list_count[kLightClasses], p->list_count[kLightClasses + 1]};
+    if (s0 > 0 || s1 < p->S) {
+        int64_t *hb = ctx->pinned + kHbRange;
+        for (int wide = 0; wide < 2; ++wide) {
+            if (hi[wide] <= 0) continue;
+            SLG_HIP(ctx, launch_heavy_range(p->heavy[wide], hi[wide], s0, s1, p->tickets + 6 + 2 * wide, st));
+            SLG_HIP(ctx, hipMemcpyAsync(hb + 2 * wide, p->tickets + 6 + 2 * wide, 2 * sizeof(int64_t),
+                                        hipMemcpyDeviceToHost, st));
+        }
+        SLG_HIP(ctx, hipStreamSynchronize(st));
+        for (int wide = 0; wide < 2; ++wide)
+            if (hi[wide] > 0) {
+                lo[wide] = hb[2 * wide];
+                hi[wide] = hb[2 * wide + 1];
+            }
+    }
     for (int wide = 0; wide < 2; ++wide) {
-        if (p->list_count[kLightClasses + wide] <= 0) continue;
+        const int64_t cnt = hi[wide] - lo[wide];
+        if (cnt <= 0) continue;
         StageTimer tm(ctx, wide ? kStEmitHeavyWide : kStEmitHeavy, st);
-        if (p->use_store && !wide)
-            SLG_HIP(ctx, launch_heavy_store_emit(p->heavy[0], p->list_count[kLightClasses], p->S, p->store, prm,
-                                                 p->slot_off, st));
-        else
-            SLG_HIP(ctx, launch_heavy(true, wide, p->heavy[wide], p->list_count[kLightClasses + wide], p->S,
-                                      p->bounds, p->pr, prm, nullptr, p->slot_off, p->tickets + 2 + wide,
-                                      p->heavy_grid, nullptr, st));
+        if (p->use_store && !wide) {
+            const CountStore part{p->store.ent, p->store.off + lo[0], p->store.n + lo[0]};
+            SLG_HIP(ctx, launch_heavy_store_emit(p->heavy[0] + lo[0], cnt, p->S, part, prm, p->slot_off, st));
+        } else {
+            SLG_HIP(ctx, launch_heavy(true, wide, p->heavy[wide] + lo[wide], cnt, p->S, p->bounds, p->pr, prm,
+                                      nullptr, p->slot_off, p->tickets + 2 + wide, p->heavy_grid, nullptr, st));
+        }
     }
     {
         StageTimer tm(ctx, kStRowPtr, st);

@@ -110,11 +110,16 @@ hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t light_max, in
                            int64_t *bsize, unsigned long long *class_count, int *err,
                            unsigned long long *heavy_work, int64_t *pieces, unsigned long long *num_pieces,
                            hipStream_t st);
+// Light lists and heavy descriptors (heavy lists in slot order). hat:
+// int64[2 (m + 1)] and hcnt: int32[2 m] scratch, partials: scan_partials_size(m).
 hipError_t launch_fill_slots(int64_t m, const int64_t *he_ptr, const int64_t *slot_base,
                              const int32_t *nslots, const int32_t *jmax, const uint8_t *rclass,
-                             const int64_t *bbase, int64_t *hat, int32_t *slot_row, int32_t *const *lists,
-                             HeavyDesc *const *heavy, const int64_t *caps, unsigned long long *list_fill,
-                             int *err, hipStream_t st);
+                             const int64_t *bbase, int64_t *hat, int32_t *hcnt, int64_t *partials,
+                             int32_t *slot_row, int32_t *const *lists, HeavyDesc *const *heavy, const int64_t *caps,
+                             unsigned long long *list_fill, int *err, hipStream_t st);
+// out[0..1] = positions of the first slot >= s0 and >= s1 in a heavy list.
+hipError_t launch_heavy_range(const HeavyDesc *desc, int64_t count, int64_t s0, int64_t s1, int64_t *out,
+                              hipStream_t st);
 hipError_t launch_bounds(const Pruned &g, const HeavyDesc *desc, int64_t count, int32_t *bounds,
                          hipStream_t st);
 

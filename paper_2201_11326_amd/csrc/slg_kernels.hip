@@ -543,12 +543,13 @@ __global__ __launch_bounds__(256) void fill_slots_kernel(
     }
     if (tid < kNumLists) cursor[tid] = 0;
     __syncthreads();
-    // entries per list: one per light row, one descriptor per heavy slot
-    for (int c = kLight0; c < kLight0 + kNumLists; ++c) {
+    // entries per light list: one per row (heavy descriptors are placed by
+    // heavy_desc_kernel, in slot order)
+    for (int c = kLight0; c < kLight0 + kLightClasses; ++c) {
         int mine = 0;
 #pragma unroll
         for (int r = 0; r < kFillRows; ++r)
-            if (cls[r] == c) mine += c >= kHeavy ? ns[r] : 1;
+            if (cls[r] == c) mine += 1;
         const int tot = wave_sum(mine);
         if (lane == 0 && tot) atomicAdd(&cursor[c - 1], (unsigned long long)tot);
     }
@@ -558,8 +559,8 @@ __global__ __launch_bounds__(256) void fill_slots_kernel(
 #pragma unroll
     for (int r = 0; r < kFillRows; ++r) {
         const int64_t i = i0 + r * 256 + tid;
-        for (int c = kLight0; c < kLight0 + kNumLists; ++c) {
-            const int w = (cls[r] == c) ? (c >= kHeavy ? ns[r] : 1) : 0;
+        for (int c = kLight0; c < kLight0 + kLightClasses; ++c) {
+            const int w = (cls[r] == c) ? 1 : 0;
             const int incl = wave_incl_scan(w);
             const int tot = __shfl(incl, 63);
             if (!tot) continue;
@@ -568,9 +569,7 @@ __global__ __launch_bounds__(256) void fill_slots_kernel(
             at = __shfl(at, 63);
             if (!w) continue;
             const unsigned long long pos = at + incl - w;
-            if (c >= kHeavy) {
-                hat[i] = (int64_t)pos;  // the row's descriptors, written by heavy_desc_kernel
-            } else if (pos < (unsigned long long)ll.cap[c - 1]) {
+            if (pos < (unsigned long long)ll.cap[c - 1]) {
                 ll.l[c - 1][pos] = (int32_t)base[r];
                 slot_row[base[r]] = (int32_t)i;
             } else {
@@ -581,6 +580,34 @@ __global__ __launch_bounds__(256) void fill_slots_kernel(
 }
 
 // One wavefront per heavy row, one lane per slot: the slot descriptors.
+// Heavy slots per row, by class: the prefix sums place every heavy row's
+// descriptors in row order, so each heavy list is in slot order.
+__global__ void heavy_counts_kernel(int64_t m, const uint8_t *__restrict__ rclass, const int32_t *__restrict__ nslots,
+                                    int32_t *__restrict__ cnt) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = rclass[i];
+        cnt[i] = c == kHeavy ? nslots[i] : 0;
+        cnt[m + i] = c == kHeavyWide ? nslots[i] : 0;
+    }
+}
+
+// First and one-past-last positions of the slots in [s0, s1) in a heavy
+// list ordered by slot.
+__global__ void heavy_range_kernel(const HeavyDesc *__restrict__ desc, int64_t count, int64_t s0, int64_t s1,
+                                   int64_t *__restrict__ out) {
+    if (threadIdx.x >= 2) return;
+    const int64_t key = threadIdx.x == 0 ? s0 : s1;
+    int64_t lo = 0, hi = count;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)desc[mid].slot < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    out[threadIdx.x] = lo;
+}
+
 __global__ __launch_bounds__(256) void heavy_desc_kernel(
     int64_t m, const int64_t *__restrict__ he_ptr, const int64_t *__restrict__ slot_base,
     const int32_t *__restrict__ nslots, const int32_t *__restrict__ jmax,
@@ -593,7 +620,7 @@ __global__ __launch_bounds__(256) void heavy_desc_kernel(
         const int cls = rclass[i];
         if (cls < kHeavy) continue;
         const int ns = nslots[i];
-        const int64_t at = hat[i];
+        const int64_t at = hat[(cls == kHeavy ? 0 : m + 1) + i];  // prefix of the class's slots
         if (at < 0 || at + ns > (cls == kHeavy ? cap_h : cap_w)) {
             if (lane == 0) atomicOr(err, 16);
             continue;
@@ -1998,9 +2025,9 @@ hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t light_max, in
 
 hipError_t launch_fill_slots(int64_t m, const int64_t *he_ptr, const int64_t *slot_base,
                              const int32_t *nslots, const int32_t *jmax, const uint8_t *rclass,
-                             const int64_t *bbase, int64_t *hat, int32_t *slot_row, int32_t *const *lists,
-                             HeavyDesc *const *heavy, const int64_t *caps, unsigned long long *list_fill,
-                             int *err, hipStream_t st) {
+                             const int64_t *bbase, int64_t *hat, int32_t *hcnt, int64_t *partials,
+                             int32_t *slot_row, int32_t *const *lists, HeavyDesc *const *heavy, const int64_t *caps,
+                             unsigned long long *list_fill, int *err, hipStream_t st) {
     if (m <= 0) return hipSuccess;
     LightLists ll;
     for (int c = 0; c < kLightClasses; ++c) ll.l[c] = lists[c];
@@ -2008,9 +2035,19 @@ hipError_t launch_fill_slots(int64_t m, const int64_t *he_ptr, const int64_t *sl
     ll.err = err;
     fill_slots_kernel<<<grid_for(m, 256 * kFillRows), 256, 0, st>>>(m, he_ptr, slot_base, nslots, jmax, rclass,
                                                                      bbase, slot_row, ll, hat, list_fill);
+    heavy_counts_kernel<<<grid_for(m, 256) < 8192 ? grid_for(m, 256) : 8192, 256, 0, st>>>(m, rclass, nslots, hcnt);
+    hipError_t e = exclusive_scan(hcnt, m, hat, partials, st);
+    if (e != hipSuccess) return e;
+    if ((e = exclusive_scan(hcnt + m, m, hat + m + 1, partials, st)) != hipSuccess) return e;
     heavy_desc_kernel<<<wave_grid(m, 4, 8192), 256, 0, st>>>(m, he_ptr, slot_base, nslots, jmax, rclass,
                                                               bbase, hat, slot_row, heavy[0], heavy[1],
                                                               caps[kLightClasses], caps[kLightClasses + 1], err);
+    return hipGetLastError();
+}
+
+hipError_t launch_heavy_range(const HeavyDesc *desc, int64_t count, int64_t s0, int64_t s1, int64_t *out,
+                              hipStream_t st) {
+    heavy_range_kernel<<<1, 64, 0, st>>>(desc, count, s0, s1, out);
     return hipGetLastError();
 }
 
