@@ -219,6 +219,9 @@ struct slg_plan {
     int64_t *slot_off = nullptr;   // [K][S+1]
     bool use_store = false;        // the counting pass keeps the heavy overlaps for the emit pass
     CountStore store{};
+    bool use_lstore = false;       // ... and the light rows' overlaps
+    LightStore lstore{};
+    int32_t *lwork = nullptr;      // [m]: 2-paths of the light rows
     int64_t *store_work = nullptr; // [heavy slots]: 2-paths per slot
     int64_t store_limit = 0;
     int64_t store_min = 0;
@@ -454,9 +457,13 @@ hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
     }
     {
         StageTimer tm(ctx, kStCountLight, st);
+        if (p->use_lstore) {  // the light store's layout
+            if ((e = launch_light_work(m, b.rclass, b.work, p->lwork, st)) != hipSuccess) return e;
+            if ((e = launch_exclusive_scan_i32(p->lwork, m, p->lstore.off, b.part_m, st)) != hipSuccess) return e;
+        }
         for (int c = 0; c < kLightClasses; ++c)
             if ((e = launch_light(c, false, p->lists[c], p->list_count[c], p->slots, p->pr, p->prm, p->slot_cnt,
-                                  nullptr, st)) != hipSuccess)
+                                  nullptr, (p->use_lstore && c > 0) ? &p->lstore : nullptr, st)) != hipSuccess)
                 return e;
     }
     if ((e = launch_fill_i64(p->tickets, 6, 0, st)) != hipSuccess) return e;
@@ -570,6 +577,18 @@ slg_status plan_build(slg_plan *p) {
         const int64_t bytes = p->heavy_two_paths * 4 + nh * 20 + 16;
         p->use_store = nh > 0 && p->store_limit > 0 && bytes <= p->store_limit &&
                        p->heavy_two_paths >= p->store_min;
+        // the light rows' pairs: at most their 2-paths (all but the heavy ones)
+        const int64_t lcap = p->two_paths - p->heavy_two_paths;
+        const int64_t lbytes = lcap * 6 + m * 16 + 16;
+        p->use_lstore = p->store_limit > 0 && lcap > 0 && p->two_paths >= p->store_min &&
+                        (p->use_store ? bytes : 0) + lbytes <= p->store_limit;
+        if (p->use_lstore) {
+            phase2.add(&p->lstore.key, lcap);
+            phase2.add(&p->lstore.cnt, lcap);
+            phase2.add(&p->lstore.off, m + 1);
+            phase2.add(&p->lstore.n, m);
+            phase2.add(&p->lwork, m);
+        }
         if (p->use_store) {
             phase2.add(&p->store.ent, p->heavy_two_paths);
             phase2.add(&p->store.off, nh + 1);
@@ -680,9 +699,14 @@ slg_status emit_range(slg_plan *p, int64_t r0, int64_t r1, int64_t s0, int64_t s
     }
     {
         StageTimer tm(ctx, kStEmitLight, st);
-        for (int c = 0; c < kLightClasses; ++c)
-            SLG_HIP(ctx, launch_light(c, true, p->lists[c], p->list_count[c], p->slots, p->pr, prm, nullptr,
-                                      p->slot_off, st));
+        for (int c = 0; c < kLightClasses; ++c) {
+            if (p->use_lstore && c > 0)
+                SLG_HIP(ctx, launch_light_store_emit(p->lists[c], p->list_count[c], p->slots, p->lstore, prm,
+                                                     p->slot_off, st));
+            else
+                SLG_HIP(ctx, launch_light(c, true, p->lists[c], p->list_count[c], p->slots, p->pr, prm, nullptr,
+                                          p->slot_off, nullptr, st));
+        }
     }
     SLG_HIP(ctx, launch_fill_i64(p->tickets + 2, 2, 0, st));
     // a chunk's heavy slots: a contiguous part of each heavy list (both are

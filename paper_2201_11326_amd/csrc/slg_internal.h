@@ -85,6 +85,16 @@ struct CountStore {
     int32_t *n;
 };
 
+// The same for the light rows (wavefront-sort tier): row i holds n[i]
+// (partner id, overlap) pairs in partner order at off[i], the exclusive
+// prefix of the light rows' 2-path counts.
+struct LightStore {
+    int32_t *key;
+    uint16_t *cnt;
+    int64_t *off;
+    int32_t *n;
+};
+
 // ---- launchers (all enqueue on `st`, return hipError_t) -------------------
 hipError_t launch_exclusive_scan_i64(const int64_t *in, int64_t n, int64_t *out, int64_t *partials,
                                      hipStream_t st);
@@ -124,9 +134,16 @@ hipError_t launch_bounds(const Pruned &g, const HeavyDesc *desc, int64_t count, 
                          hipStream_t st);
 
 // K3/K4/K5: count (EMIT=false) or emit (EMIT=true) per slot.
+// store (counting pass of the wavefront-sort classes only, or null): keep
+// the overlaps.
 hipError_t launch_light(int cls, bool emit, const int32_t *list, int64_t count, const Slots &sl,
                         const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
-                        const int64_t *slot_off, hipStream_t st);
+                        const int64_t *slot_off, const LightStore *store, hipStream_t st);
+// Emit pass of a wavefront-sort class list from the light store.
+hipError_t launch_light_store_emit(const int32_t *list, int64_t count, const Slots &sl, const LightStore &store,
+                                   const EmitParams &ep, const int64_t *slot_off, hipStream_t st);
+// lw[i] = 2-paths of row i if it is in a wavefront-sort class, else 0.
+hipError_t launch_light_work(int64_t m, const uint8_t *rclass, const int64_t *work, int32_t *lw, hipStream_t st);
 // Persistent launch: `resident` workgroups (0 = a default) take slots from
 // the device counter `ticket`, which the caller zeroes before the launch.
 // store (counting pass of non-wide slots only, or null): keep the overlaps.

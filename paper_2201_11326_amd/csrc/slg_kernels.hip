@@ -761,11 +761,14 @@ __global__ __launch_bounds__(256) void tiny_kernel(const int32_t *__restrict__ l
     }
 }
 
-template <int KPL, bool EMIT>
+// STORE (counting pass): the row's partners and overlaps are also written
+// to the light store, in partner order.
+template <int KPL, bool EMIT, bool STORE>
 __global__ __launch_bounds__(256) void light_kernel(const int32_t *__restrict__ list, int64_t count,
                                                     Slots sl, Pruned g, EmitParams prm,
                                                     int64_t *__restrict__ slot_cnt,
-                                                    const int64_t *__restrict__ slot_off) {
+                                                    const int64_t *__restrict__ slot_off, LightStore ls) {
+    static_assert(!(STORE && EMIT), "the store is written by the counting pass");
     constexpr int P = 64 * KPL;
     __shared__ int32_t buf[4][P];
     __shared__ int32_t seg_a[4][64];
@@ -860,6 +863,23 @@ __global__ __launch_bounds__(256) void light_kernel(const int32_t *__restrict__ 
         c[r] = n;  // 0 for non-heads
     }
 
+    if (STORE) {  // every run head, in partner order
+        const int64_t base = as_global(ls.off)[i];
+        int tot = 0;
+#pragma unroll
+        for (int r = 0; r < KPL; ++r) {
+            const bool head = c[r] > 0;
+            const unsigned long long mask = __ballot(head);
+            if (head) {
+                const int64_t pos = base + tot + bits_below(mask);
+                as_global(ls.key)[pos] = x[r];
+                as_global(ls.cnt)[pos] = (uint16_t)c[r];
+            }
+            tot += __popcll(mask);
+        }
+        if (lane == 0) as_global(ls.n)[i] = tot;
+    }
+
     const int K = ep->k;
     const int64_t S = sl.count;
     const int id0 = ep->row_base ? as_global(ep->row_base)[i] : 0;  // caller's id of row i is i - id0
@@ -892,6 +912,64 @@ __global__ __launch_bounds__(256) void light_kernel(const int32_t *__restrict__ 
 constexpr int kHW = kHeavyThreads / 64;              // wavefronts per heavy workgroup
 constexpr int kSuperWords = 1024;                    // words per rank superblock (32768 bits)
 constexpr int kSupers = kRangeWords / kSuperWords;
+
+// Emit pass of a wavefront-sort class from the light store: one wavefront
+// per row reads its (partner, overlap) pairs in partner order and compacts
+// every threshold's survivors with ballots.
+__global__ __launch_bounds__(256) void light_store_emit_kernel(const int32_t *__restrict__ list, int64_t count,
+                                                               Slots sl, LightStore ls, EmitParams prm,
+                                                               const int64_t *__restrict__ slot_off) {
+    __shared__ EmitParams sp;
+    stage_params(&sp, prm);
+    __syncthreads();
+    const int lane = lane_id();
+    const int64_t wid = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wid >= count) return;
+    const int slot = list[wid];
+    if (slot < prm.slot_lo || slot >= prm.slot_hi) return;  // outside the emitted chunk
+    const int i = sl.row[slot];
+    const int n = as_global(ls.n)[i];
+    const int64_t off = as_global(ls.off)[i];
+    const int K = prm.k;
+    const int64_t S = sl.count;
+    const int id0 = prm.row_base ? as_global(prm.row_base)[i] : 0;
+    const int srow = prm.row_s ? as_global(prm.row_s)[i] : 0;
+    long long b[SLG_MAX_S];
+    int sk[SLG_MAX_S];
+#pragma unroll
+    for (int kk = 0; kk < SLG_MAX_S; ++kk) {
+        b[kk] = kk < K ? slot_off[(int64_t)kk * (S + 1) + slot] - sp.out_base[kk] : 0;
+        sk[kk] = kk < K ? (prm.row_s ? srow : sp.s[kk]) : INT_MAX;
+    }
+    for (int r0 = 0; r0 < n; r0 += 64) {
+        const int r = r0 + lane;
+        const bool in = r < n;
+        const int key = in ? as_global(ls.key)[off + r] - id0 : 0;
+        const int c = in ? (int)as_global(ls.cnt)[off + r] : 0;
+#pragma unroll
+        for (int kk = 0; kk < SLG_MAX_S; ++kk) {
+            if (kk >= K) break;
+            const bool surv = c >= sk[kk];
+            const unsigned long long mask = __ballot(surv);
+            if (mask == 0ull) break;
+            if (surv) {
+                const int64_t pos = b[kk] + bits_below(mask);
+                as_global(sp.col[kk])[pos] = key;
+                as_global(sp.w[kk])[pos] = c;
+                if (sp.row[kk]) as_global(sp.row[kk])[pos] = i - id0;
+            }
+            b[kk] += __popcll(mask);
+        }
+    }
+}
+
+__global__ void light_work_kernel(int64_t m, const uint8_t *__restrict__ rclass, const int64_t *__restrict__ work,
+                                  int32_t *__restrict__ lw) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = rclass[i];
+        lw[i] = (c > kLight0 && c < kLight0 + kLightClasses) ? (int32_t)work[i] : 0;
+    }
+}
 
 template <bool WIDE>
 struct CounterCap {  // u16 counters packed in pairs, or u32 counters
@@ -2053,8 +2131,9 @@ hipError_t launch_heavy_range(const HeavyDesc *desc, int64_t count, int64_t s0, 
 
 hipError_t launch_light(int cls, bool emit, const int32_t *list, int64_t count, const Slots &sl,
                         const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
-                        const int64_t *slot_off, hipStream_t st) {
+                        const int64_t *slot_off, const LightStore *store, hipStream_t st) {
     if (count <= 0) return hipSuccess;
+    if (store && emit) return hipErrorInvalidValue;
     if (cls == 0) {  // one lane per row
         if (emit)
             tiny_kernel<true><<<grid_for(count, 256), 256, 0, st>>>(list, count, sl, g, ep, slot_cnt, slot_off);
@@ -2063,14 +2142,18 @@ hipError_t launch_light(int cls, bool emit, const int32_t *list, int64_t count, 
         return hipGetLastError();
     }
     const unsigned grid = grid_for(count, 4);
+    const LightStore ls = store ? *store : LightStore{};
 #define SLG_LIGHT(KPL)                                                                              \
     do {                                                                                           \
         if (emit)                                                                                  \
-            light_kernel<KPL, true><<<grid, 256, 0, st>>>(list, count, sl, g, ep, slot_cnt,        \
-                                                          slot_off);                               \
+            light_kernel<KPL, true, false><<<grid, 256, 0, st>>>(list, count, sl, g, ep, slot_cnt,  \
+                                                                 slot_off, ls);                    \
+        else if (store)                                                                            \
+            light_kernel<KPL, false, true><<<grid, 256, 0, st>>>(list, count, sl, g, ep, slot_cnt,  \
+                                                                 slot_off, ls);                    \
         else                                                                                       \
-            light_kernel<KPL, false><<<grid, 256, 0, st>>>(list, count, sl, g, ep, slot_cnt,       \
-                                                           slot_off);                              \
+            light_kernel<KPL, false, false><<<grid, 256, 0, st>>>(list, count, sl, g, ep, slot_cnt, \
+                                                                  slot_off, ls);                   \
     } while (0)
     switch (cls) {
         case 1: SLG_LIGHT(1); break;
@@ -2082,6 +2165,19 @@ hipError_t launch_light(int cls, bool emit, const int32_t *list, int64_t count, 
         default: return hipErrorInvalidValue;
     }
 #undef SLG_LIGHT
+    return hipGetLastError();
+}
+
+hipError_t launch_light_store_emit(const int32_t *list, int64_t count, const Slots &sl, const LightStore &store,
+                                   const EmitParams &ep, const int64_t *slot_off, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    light_store_emit_kernel<<<grid_for(count, 4), 256, 0, st>>>(list, count, sl, store, ep, slot_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_light_work(int64_t m, const uint8_t *rclass, const int64_t *work, int32_t *lw, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    light_work_kernel<<<grid_for(m, 256) < 8192 ? grid_for(m, 256) : 8192, 256, 0, st>>>(m, rclass, work, lw);
     return hipGetLastError();
 }
 
