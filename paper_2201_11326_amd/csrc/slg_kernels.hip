@@ -7,17 +7,22 @@
 //   K2  plan: per kept hyperedge e_i and member v, the tail of v's list after
 //       i (the partners e_j, j > i, reached through v: the upper triangle),
 //       the 2-path work w_i = sum of tail lengths, and a slot table that
-//       splits heavy rows by hyperedge-id range.
+//       splits heavy rows by hyperedge-id range and by work.
 //   K3  count overlaps |e_i n e_j| by walking every 2-path (e_i, v, e_j):
-//         light rows (w_i <= 512): one wavefront gathers the 2-path
+//         tiny rows (w_i <= 8): one lane sorts its partners in registers;
+//         light rows (w_i <= 2048): one wavefront gathers the 2-path
 //           partners into LDS, sorts them in registers (bitonic) and
 //           run-length counts them;
 //         heavy slots: one workgroup marks partners in an LDS bitmap over
 //           the slot's id range, ranks them by prefix popcount, and counts
-//           each partner in an LDS counter indexed by its rank; heavy
-//           vertex tails are cut into equal pieces across the wavefronts.
+//           each repeated partner in an LDS counter indexed by its rank;
+//           heavy vertex tails are cut into equal pieces across the
+//           wavefronts.
+//       The counting pass tallies every threshold's survivors (output
+//       sizes) and, when memory allows, keeps each row's or slot's
+//       (partner, overlap) pairs for the emit pass (the count stores).
 //   K4/5 threshold-and-emit for every s_k of the ensemble from the same
-//       counters (the stored overlap is the largest s for which the pair
+//       counts (the stored overlap is the largest s for which the pair
 //       survives), compacted with wavefront ballots + prefix sums. The rank
 //       order is the hyperedge-id order, so rows come out sorted.
 //   K6  assembly: prefix sums of per-slot counts give each slot's output
