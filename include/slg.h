@@ -98,7 +98,8 @@ const char *slg_version(void);
  * Create a context on HIP device `device`. Planning scratch (and the
  * outputs of slg_line_graph when `alloc` is NULL) come from a block cache
  * of the context: freed blocks are kept for reuse by later calls, up to
- * mem_budget_bytes of them (0 = 16 GiB); beyond that the largest are given
+ * mem_budget_bytes of them (0 = a quarter of the device's memory, at least
+ * 16 GiB); beyond that the largest are given
  * back to the device. `alloc` may be NULL.
  * Errors: INVALID_ARG (out == NULL), DEVICE (no such device).
  */

@@ -80,7 +80,8 @@ constexpr int kHbRange = kHbHeavyEdges + 3;  // a chunk's heavy list ranges (4 e
 static_assert(kHbSlots + 3 <= kHbEdges && kHbRange + 4 <= kPinnedSlots, "pinned staging layout");
 
 // Freed device blocks a context keeps for reuse unless told otherwise.
-constexpr uint64_t kDefaultCache = uint64_t(16) << 30;
+constexpr uint64_t kDefaultCacheMin = uint64_t(16) << 30;  // default block cache: a quarter of the
+                                                           // device's memory, at least this
 
 slg_status fail(slg_context *ctx, slg_status st, const char *fmt, ...) {
     if (ctx) {
@@ -295,7 +296,13 @@ slg_status slg_context_create(int device, uint64_t mem_budget_bytes, const slg_a
         return SLG_ERR_DEVICE;
     }
     ctx->heavy_resident = heavy_resident(device);
-    ctx->arena = std::make_shared<slg::Arena>(device, mem_budget_bytes ? mem_budget_bytes : kDefaultCache);
+    uint64_t cache = mem_budget_bytes;
+    if (!cache) {
+        size_t free_b = 0, total_b = 0;
+        cache = hipMemGetInfo(&free_b, &total_b) == hipSuccess ? total_b / 4 : 0;
+        if (cache < kDefaultCacheMin) cache = kDefaultCacheMin;
+    }
+    ctx->arena = std::make_shared<slg::Arena>(device, cache);
     // keep freed scratch in the stream-ordered pool between calls
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
@@ -1337,12 +1344,21 @@ namespace {
 // Stable sort of n int32 keys in [0, 2^key_bits) with up to two payloads
 // (b only with a), from the *_in arrays into the *_out arrays (which may be
 // caller memory), through scratch from `sc` when more than one digit pass is
-// needed. With key_bits = 0 the inputs are copied.
+// needed. With key_bits = 0 the inputs are copied. With `in_scratch`, the
+// outputs are not given: the last pass writes scratch too (two buffers per
+// array in all) and *_out receive where the sorted arrays are.
 hipError_t sort_pairs(Scratch &sc, const int32_t *key_in, const int32_t *a_in, const int32_t *b_in, int64_t n,
-                      int key_bits, int32_t *key_out, int32_t *a_out, int32_t *b_out, hipStream_t st) {
+                      int key_bits, int32_t *key_out, int32_t *a_out, int32_t *b_out, hipStream_t st,
+                      const int32_t **in_scratch = nullptr) {
     if (n <= 0) return hipSuccess;
     const int passes = sort_passes(key_bits);
     hipError_t e;
+    if (in_scratch && passes == 0) {  // already in order: the inputs themselves
+        in_scratch[0] = key_in;
+        in_scratch[1] = a_in;
+        in_scratch[2] = b_in;
+        return hipSuccess;
+    }
     if (passes == 0) {
         const int32_t *src[3] = {key_in, a_in, b_in};
         int32_t *dst[3] = {key_out, a_out, b_out};
@@ -1361,12 +1377,14 @@ hipError_t sort_pairs(Scratch &sc, const int32_t *key_in, const int32_t *a_in, c
         return e;
     const int arrays = b_in ? 3 : (a_in ? 2 : 1);
     // pass p writes tmp[p & 1] except the last, which writes the outputs
-    for (int h = 0; h < (passes > 2 ? 2 : passes - 1); ++h)
+    // (or tmp as well, with in_scratch)
+    const int bufs = in_scratch ? (passes > 1 ? 2 : 1) : (passes > 2 ? 2 : passes - 1);
+    for (int h = 0; h < bufs; ++h)
         for (int t = 0; t < arrays; ++t)
             if ((e = sc.get(&tmp[h][t], n)) != hipSuccess) return e;
     const int32_t *k = key_in, *a = a_in, *b = b_in;
     for (int p = 0; p < passes; ++p) {
-        const bool last = p + 1 == passes;
+        const bool last = p + 1 == passes && !in_scratch;
         int32_t *ko = last ? key_out : tmp[p & 1][0];
         int32_t *ao = a_in ? (last ? a_out : tmp[p & 1][1]) : nullptr;
         int32_t *bo = b_in ? (last ? b_out : tmp[p & 1][2]) : nullptr;
@@ -1377,6 +1395,11 @@ hipError_t sort_pairs(Scratch &sc, const int32_t *key_in, const int32_t *a_in, c
         k = ko;
         a = ao;
         b = bo;
+    }
+    if (in_scratch) {
+        in_scratch[0] = k;
+        in_scratch[1] = a;
+        in_scratch[2] = b;
     }
     return hipSuccess;
 }
@@ -1402,15 +1425,14 @@ slg_status slg_symmetrize(slg_context *ctx, int64_t m, const int64_t *row_ptr, c
     sc.st = st;
     sc.arena = ctx->arena.get();
     int64_t *err = nullptr, *lower_ptr = nullptr;
-    int32_t *sorted[3] = {};
+    const int32_t *sorted[3] = {};
     SLG_HIP(ctx, sc.get(&err, 1));
     SLG_HIP(ctx, sc.get(&lower_ptr, m + 1));
-    if (n > 0)
-        for (int t = 0; t < (w ? 3 : 2); ++t) SLG_HIP(ctx, sc.get(&sorted[t], n));
     SLG_HIP(ctx, launch_fill_i64(err, 1, 0, st));
     SLG_HIP(ctx, launch_check_upper(row_ptr, row, col, n, m, reinterpret_cast<int *>(err), st));
-    // the upper triangle sorted by column (stable: rows stay ascending)
-    SLG_HIP(ctx, sort_pairs(sc, col, row, w, n, bits_for(m), sorted[0], sorted[1], sorted[2], st));
+    // the upper triangle sorted by column (stable: rows stay ascending),
+    // left in the sort's own buffers
+    SLG_HIP(ctx, sort_pairs(sc, col, row, w, n, bits_for(m), nullptr, nullptr, nullptr, st, sorted));
     SLG_HIP(ctx, launch_symmetric(sorted[0], sorted[1], sorted[2], row_ptr, row, col, w, n, m, lower_ptr, sym_ptr,
                                   sym_col, sym_w, st));
     SLG_HIP(ctx, hipMemcpyAsync(ctx->pinned, err, sizeof(int64_t), hipMemcpyDeviceToHost, st));
