@@ -11,6 +11,12 @@ CPU fallback.
     g = ctx.register_incidence(inc)           # hypergen.Incidence -> device
     outs = ctx.line_graph(g, [1, 2, 4, 8])    # one L_s per threshold
     outs[0].row_ptr, outs[0].row, outs[0].col, outs[0].w   # torch tensors
+
+    ctx.line_graph_stream(g, [8, 16], 2 << 30, fn)   # chunked, for outputs beyond memory
+    ctx.batch([g1, g2, ...], [s1, s2, ...]).run()     # many graphs, one HIP-graph replay
+    ctx.server(workers=8)                             # request loop (submit / wait / next)
+    ctx.components(g, s, outs[k]); ctx.squeeze(m, outs[k]); ctx.symmetrize(outs[k])
+    ctx.relabel(g); ctx.simplify(g, l1)               # relabel-by-degree; toplexes only
 """
 from __future__ import annotations
 
