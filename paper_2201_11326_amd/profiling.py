@@ -7,6 +7,9 @@
   python -m paper_2201_11326_amd.profiling stats DB [--match NAME]
       Per-kernel launch count / total / average / min / max duration from a
       rocprofv3 --kernel-trace database.
+  python -m paper_2201_11326_amd.profiling sq SQ1_DB SQ2_DB
+      Waiting share and LDS bank-conflict rate of each heavy-tier kernel from
+      two SQ counter runs of the probe (SQ_PASS1, then SQ_PASS2).
   python -m paper_2201_11326_amd.profiling traffic FETCH_DB WRITE_DB
       HBM bytes per launch of each heavy-tier kernel, scaled by what the same
       counters read for the calibration copy (1 GiB read + 1 GiB written).
@@ -133,6 +136,36 @@ def traffic(fetch_db: str, write_db: str) -> str:
     return "\n".join(lines)
 
 
+SQ_PASS1 = ("SQ_WAVES", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_INSTS_VALU",
+            "SQ_INSTS_LDS", "SQ_INSTS_SALU")
+SQ_PASS2 = ("SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_VMEM",
+            "SQ_INSTS_VMEM_WR", "SQ_WAIT_INST_LDS", "SQ_INSTS_BRANCH")
+
+
+def sq(db1: str, db2: str) -> str:
+    """Per heavy-tier kernel: the share of wave cycles spent waiting and the
+    LDS bank-conflict rate (conflict cycles / LDS-active cycles), from one
+    run per counter pass (SQ_PASS1, SQ_PASS2)."""
+    per = {}
+    for db, names in ((db1, SQ_PASS1), (db2, SQ_PASS2)):
+        for name in names:
+            for k, vals in counter_per_kernel(db, name).items():
+                per.setdefault(k, {})[name] = sum(vals) / len(vals)
+    lines = ["# SQ counters of the heavy-tier kernels (power-law ensemble S={1,2,4,8})", ""]
+    for k in HEAVY_KERNELS:
+        c = per.get(k)
+        if not c:
+            continue
+        wait = c.get("SQ_WAIT_ANY", 0) / max(c.get("SQ_WAVE_CYCLES", 0), 1)
+        conflict = c.get("SQ_LDS_BANK_CONFLICT", 0) / max(c.get("SQ_LDS_IDX_ACTIVE", 0), 1)
+        lines += [f"kernel: {k}",
+                  f"waiting share of wave cycles (SQ_WAIT_ANY / SQ_WAVE_CYCLES): {wait:.3f}",
+                  f"LDS bank-conflict rate (SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE): {conflict:.3f}"]
+        lines += [f"  {n}: {c[n]:.4g}" for n in SQ_PASS1 + SQ_PASS2 if n in c]
+        lines.append("")
+    return "\n".join(lines)
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -143,11 +176,16 @@ def main(argv=None) -> int:
     b = sub.add_parser("traffic")
     b.add_argument("fetch_db")
     b.add_argument("write_db")
+    c = sub.add_parser("sq")
+    c.add_argument("db1")
+    c.add_argument("db2")
     args = ap.parse_args(argv)
     if args.cmd == "probe":
         probe()
     elif args.cmd == "stats":
         print(stats(args.db, args.match))
+    elif args.cmd == "sq":
+        print(sq(args.db1, args.db2))
     else:
         print(traffic(args.fetch_db, args.write_db))
     return 0
