@@ -58,6 +58,29 @@ def measured_traffic(kernel: str):
     return None
 
 
+SQ_PROFILE = os.path.join(ROOT, "profiles", "heavy_tier_power_law_sq_counters.md")
+
+
+def measured_sq(kernel: str):
+    """(waiting share of wave cycles, LDS bank-conflict rate) of `kernel` from
+    the committed SQ-counter summary, if taken on the current kernel source."""
+    try:
+        text = open(SQ_PROFILE).read()
+    except OSError:
+        return None
+    m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    if not m_hash or m_hash.group(1) != kernel_source_hash():
+        return None
+    for block in text.split("kernel: ")[1:]:
+        if block.split("\n", 1)[0].strip() != kernel:
+            continue
+        w = re.search(r"SQ_WAIT_ANY / SQ_WAVE_CYCLES\):\s*([0-9.]+)", block)
+        c = re.search(r"SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE\):\s*([0-9.]+)", block)
+        if w and c:
+            return {"waiting_share": float(w.group(1)), "lds_bank_conflict_rate": float(c.group(1))}
+    return None
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -692,7 +715,8 @@ def main() -> int:
         lines[stage] = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                         "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
                         "traffic": measured_traffic(kname), "kernel": f"{kname} ({stage})",
-                        "avg_launch_ms": avg_s * 1e3, "algorithmic_bytes_per_launch": algo_bytes}
+                        "avg_launch_ms": avg_s * 1e3, "algorithmic_bytes_per_launch": algo_bytes,
+                        "sq_counters": measured_sq(kname)}
     dominant = max(lines, key=lambda k: lines[k]["avg_launch_ms"])
     roofline = dict(lines[dominant])
     roofline["other_heavy_kernel"] = lines["emit_heavy" if dominant == "count_heavy" else "count_heavy"]
