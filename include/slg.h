@@ -63,7 +63,8 @@ typedef struct slg_batch slg_batch;
  *   v_ptr[n+1], v_idx[nnz]: hyperedges containing vertex v are
  *       v_idx[v_ptr[v] .. v_ptr[v+1]), strictly increasing; the exact
  *       transpose of the hyperedge CSR.
- * All four arrays are DEVICE pointers. Empty hyperedges and isolated
+ * All four arrays are DEVICE pointers (host or device with SLG_COPY).
+ * Empty hyperedges and isolated
  * vertices are allowed; duplicate hyperedges are distinct hyperedges.
  */
 typedef struct {
@@ -90,6 +91,7 @@ typedef struct {
 
 /* Flags for slg_graph_register. */
 #define SLG_VALIDATE 1u /* check both CSRs on the device before accepting */
+#define SLG_COPY 2u     /* keep the library's own device copies of the CSRs */
 
 /* Library version string (static storage). */
 const char *slg_version(void);
@@ -112,12 +114,17 @@ const char *slg_last_error(const slg_context *ctx);
 
 /*
  * Register a hypergraph. The incidence arrays are borrowed: they must stay
- * valid and unchanged until slg_graph_release. With SLG_VALIDATE the
+ * valid and unchanged until slg_graph_release. With SLG_COPY the library
+ * copies them (from host or device memory) into device memory the graph
+ * owns, and the caller's arrays are free again when the call returns;
+ * slg_graph_release then waits for the device and frees the copies. With
+ * SLG_VALIDATE the
  * library checks on the device, ordered on `stream`, that: pointer arrays
  * start at 0, are non-decreasing and end at nnz; ids are in range; rows of
  * both CSRs are strictly increasing; the vertex CSR is the transpose.
- * Errors: INVALID_ARG (NULL pointers with nnz > 0, negative sizes),
- * OVERFLOW (m, n or nnz >= 2^31), INVALID_GRAPH (a check failed).
+ * Errors: INVALID_ARG (NULL pointers with nnz > 0, negative sizes, an
+ * unknown flag), OVERFLOW (m, n or nnz >= 2^31), INVALID_GRAPH (a check
+ * failed), OUT_OF_MEMORY (no room for the copy).
  */
 slg_status slg_graph_register(slg_context *ctx, const slg_incidence *inc, uint32_t flags,
                               void *stream, slg_graph **out);

@@ -40,6 +40,7 @@ SLG_ERR_CANCELLED = 6
 SLG_ERR_TIMEOUT = 7
 SLG_MAX_S = 16
 SLG_VALIDATE = 1
+SLG_COPY = 2
 
 _STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "INVALID_GRAPH", 3: "OUT_OF_MEMORY", 4: "DEVICE",
                  5: "OVERFLOW", 6: "CANCELLED", 7: "TIMEOUT"}
@@ -191,8 +192,9 @@ class LineGraph:
 class Graph:
     """A registered hypergraph; keeps its device CSR tensors alive."""
 
-    def __init__(self, ctx: "Context", handle: int, tensors, m: int, n: int):
+    def __init__(self, ctx: "Context", handle: int, tensors, m: int, n: int, nnz: int = 0):
         self.ctx, self.handle, self._tensors, self.m, self.n = ctx, handle, tensors, m, n
+        self.nnz = nnz
 
     def release(self):
         if self.handle:
@@ -370,15 +372,31 @@ class Context:
 
     # -- graphs ------------------------------------------------------------
     def register(self, m: int, n: int, he_ptr, he_idx, v_ptr, v_idx, validate: bool = False,
-                 stream=None) -> Graph:
-        """Register device tensors (int64 ptrs, int32 ids) of both CSRs."""
+                 stream=None, copy: bool = False) -> Graph:
+        """Register device tensors (int64 ptrs, int32 ids) of both CSRs. With
+        copy=True the library keeps its own copies (SLG_COPY) and the tensors
+        may be reused at once."""
         inc = Incidence(n, m, int(he_idx.numel()), he_ptr.data_ptr(), he_idx.data_ptr(),
                         v_ptr.data_ptr(), v_idx.data_ptr())
         h = _p()
-        self._check(lib().slg_graph_register(self.handle, ctypes.byref(inc),
-                                             SLG_VALIDATE if validate else 0,
+        flags = (SLG_VALIDATE if validate else 0) | (SLG_COPY if copy else 0)
+        self._check(lib().slg_graph_register(self.handle, ctypes.byref(inc), flags,
                                              _stream_handle(stream), ctypes.byref(h)))
-        return Graph(self, h.value, (he_ptr, he_idx, v_ptr, v_idx), m, n)
+        return Graph(self, h.value, () if copy else (he_ptr, he_idx, v_ptr, v_idx), m, n, int(he_idx.numel()))
+
+    def register_host(self, inc, validate: bool = False, stream=None) -> Graph:
+        """Register a host hypergen.Incidence through SLG_COPY: the library
+        copies the numpy arrays to the device itself."""
+        import numpy as np
+        arrs = [np.ascontiguousarray(inc.he_ptr, dtype=np.int64), np.ascontiguousarray(inc.he_idx, dtype=np.int32),
+                np.ascontiguousarray(inc.v_ptr, dtype=np.int64), np.ascontiguousarray(inc.v_idx, dtype=np.int32)]
+        ptrs = [a.ctypes.data if a.size else None for a in arrs]
+        c = Incidence(inc.n, inc.m, int(arrs[1].size), *ptrs)
+        h = _p()
+        self._check(lib().slg_graph_register(self.handle, ctypes.byref(c),
+                                             SLG_COPY | (SLG_VALIDATE if validate else 0),
+                                             _stream_handle(stream), ctypes.byref(h)))
+        return Graph(self, h.value, (), inc.m, inc.n, int(arrs[1].size))
 
     def register_incidence(self, inc, validate: bool = False, stream=None) -> Graph:
         """Copy a host hypergen.Incidence to the device and register it."""
@@ -510,7 +528,7 @@ class Context:
         dev = f"cuda:{self.device}"
         order = order.to(device=dev, dtype=torch.int32).contiguous()
         count = int(order.numel())
-        nnz_cap = int(g._tensors[1].numel())
+        nnz_cap = int(g.nnz)
         he_ptr = torch.empty(count + 1, dtype=torch.int64, device=dev)
         v_ptr = torch.empty(g.n + 1, dtype=torch.int64, device=dev)
         he_idx = torch.empty(max(nnz_cap, 1), dtype=torch.int32, device=dev)

@@ -58,6 +58,7 @@ struct slg_context {
 struct slg_graph {
     slg_context *ctx = nullptr;
     slg_incidence inc{};
+    std::vector<void *> owned;  // SLG_COPY: the graph's own copies of the CSRs
 };
 
 namespace {
@@ -341,8 +342,47 @@ slg_status slg_graph_register(slg_context *ctx, const slg_incidence *inc, uint32
         return fail(ctx, SLG_ERR_OVERFLOW, "m, n and nnz must be below 2^31");
     if (!inc->he_ptr || !inc->v_ptr || (nnz > 0 && (!inc->he_idx || !inc->v_idx)))
         return fail(ctx, SLG_ERR_INVALID_ARG, "null CSR array");
+    if (flags & ~(SLG_VALIDATE | SLG_COPY)) return fail(ctx, SLG_ERR_INVALID_ARG, "unknown flags");
     SLG_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
+    // SLG_COPY: the library's own copies (from host or device memory); the
+    // caller's arrays are free again when the call returns
+    slg_incidence copy = *inc;
+    std::vector<void *> owned;
+    if (flags & SLG_COPY) {
+        auto drop = [&](slg_status code, const char *msg) {
+            (void)hipStreamSynchronize(st);
+            for (void *q : owned) (void)hipFree(q);
+            return fail(ctx, code, "%s", msg);
+        };
+        const void *src[4] = {inc->he_ptr, inc->he_idx, inc->v_ptr, inc->v_idx};
+        const size_t bytes[4] = {size_t(m + 1) * 8, size_t(nnz) * 4, size_t(n + 1) * 8, size_t(nnz) * 4};
+        void *dst[4] = {};
+        for (int t = 0; t < 4; ++t) {
+            if (hipMalloc(&dst[t], bytes[t] ? bytes[t] : 8) != hipSuccess) {
+                (void)hipGetLastError();
+                return drop(SLG_ERR_OUT_OF_MEMORY, "no device memory for the graph's copy");
+            }
+            owned.push_back(dst[t]);
+            if (bytes[t] && hipMemcpyAsync(dst[t], src[t], bytes[t], hipMemcpyDefault, st) != hipSuccess) {
+                (void)hipGetLastError();
+                return drop(SLG_ERR_DEVICE, "copying the incidence failed");
+            }
+        }
+        if (hipStreamSynchronize(st) != hipSuccess) {
+            (void)hipGetLastError();
+            return drop(SLG_ERR_DEVICE, "copying the incidence failed");
+        }
+        copy.he_ptr = static_cast<const int64_t *>(dst[0]);
+        copy.he_idx = static_cast<const int32_t *>(dst[1]);
+        copy.v_ptr = static_cast<const int64_t *>(dst[2]);
+        copy.v_idx = static_cast<const int32_t *>(dst[3]);
+        inc = &copy;
+    }
+    auto drop_owned = [&]() {
+        for (void *q : owned) (void)hipFree(q);
+        owned.clear();
+    };
     if (flags & SLG_VALIDATE) {
         Scratch sc;
         sc.st = st;
@@ -371,13 +411,18 @@ slg_status slg_graph_register(slg_context *ctx, const slg_incidence *inc, uint32
             code = ctx->pinned[0];
         }
         sc.release();
+        if (code) drop_owned();
         if (code & 2) return fail(ctx, SLG_ERR_INVALID_GRAPH, "CSR pointer array malformed");
         if (code & 4) return fail(ctx, SLG_ERR_INVALID_GRAPH, "CSR row holds an out-of-range or repeated id");
         if (code & 8) return fail(ctx, SLG_ERR_INVALID_GRAPH, "vertex CSR is not the transpose");
     }
     slg_graph *g = new (std::nothrow) slg_graph();
-    if (!g) return fail(ctx, SLG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    if (!g) {
+        drop_owned();
+        return fail(ctx, SLG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
     g->ctx = ctx;
+    g->owned = owned;
     g->inc = *inc;
     *out = g;
     return SLG_OK;
@@ -385,6 +430,11 @@ slg_status slg_graph_register(slg_context *ctx, const slg_incidence *inc, uint32
 
 slg_status slg_graph_release(slg_graph *g) {
     if (!g) return SLG_ERR_INVALID_ARG;
+    if (!g->owned.empty()) {
+        (void)hipSetDevice(g->ctx->device);
+        (void)hipDeviceSynchronize();  // work still reading the copies
+        for (void *q : g->owned) (void)hipFree(q);
+    }
     delete g;
     return SLG_OK;
 }
