@@ -335,6 +335,19 @@ slg_status slg_symmetrize(slg_context *ctx, int64_t m, const int64_t *row_ptr, c
                           int32_t *sym_col, int32_t *sym_w, void *stream);
 
 /*
+ * Order-independent digest of an edge list (for checking streamed or large
+ * results block by block without moving them to the host): out[0] = number
+ * of edges, out[1] = sum of the overlaps, out[2] = sum mod 2^64 of
+ * SplitMix64's output function applied to i * 2^32 + j, xor w. row/col/w:
+ * DEVICE int32[num_edges] (a chunk's arrays inside an slg_chunk_fn, or an
+ * emitted L_s); out: HOST uint64[3]. Digests of disjoint edge sets add up.
+ * Ordered on `stream`; returns after the stream has reached the end of the
+ * call. Errors: INVALID_ARG (null arrays with num_edges > 0).
+ */
+slg_status slg_digest(slg_context *ctx, const int32_t *row, const int32_t *col, const int32_t *w,
+                      int64_t num_edges, uint64_t *out, void *stream);
+
+/*
  * Relabel-by-degree (Stage 1 of the paper's framework, Section IV): the
  * order of hyperedge ids by size, ascending (descending = 0) or descending;
  * hyperedges of equal size keep their id order. order: DEVICE int32[m],

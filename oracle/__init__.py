@@ -275,3 +275,24 @@ def toplexes_from_edges(inc, row, col, w) -> np.ndarray:
     drop[a[(x == sa) & ((sb > sa) | ((sb == sa) & (b < a)))]] = True
     drop[b[(x == sb) & ((sa > sb) | ((sa == sb) & (a < b)))]] = True
     return np.flatnonzero(~drop).astype(np.int32)
+
+
+def _splitmix64(x: np.ndarray) -> np.ndarray:
+    """SplitMix64's output function on uint64 inputs (the published mixer of
+    Steele, Lea and Flood, with Vigna's constants), wrapping mod 2^64."""
+    z = x + np.uint64(0x9E3779B97F4A7C15)
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def digest(i, j, w):
+    """Order-independent digest of an edge list: (number of edges, sum of w,
+    sum mod 2^64 of SplitMix64(i * 2^32 + j) xor w)."""
+    i = np.asarray(i, dtype=np.int64).astype(np.uint64)
+    j = np.asarray(j, dtype=np.int64).astype(np.uint64)
+    w = np.asarray(w, dtype=np.int64).astype(np.uint64)
+    with np.errstate(over="ignore"):
+        h = _splitmix64((i << np.uint64(32)) | j) ^ w
+        total = int(h.sum(dtype=np.uint64)) if h.size else 0
+    return int(i.size), int(w.sum()) if w.size else 0, total % (1 << 64)

@@ -129,6 +129,7 @@ def lib() -> ctypes.CDLL:
         "slg_squeeze": (_i32, [_p, _i64, _p, _p, _i64, _i32, _p, ctypes.POINTER(_i64), _p]),
         "slg_symmetrize": (_i32, [_p, _i64, _p, _p, _p, _p, _i64, _p, _p, _p, _p]),
         "slg_relabel_order": (_i32, [_p, _p, _i32, _p, _p]),
+        "slg_digest": (_i32, [_p, _p, _p, _p, _i64, ctypes.POINTER(_u64), _p]),
         "slg_context_set_count_store": (_i32, [_p, _i64, _i64]),
         "slg_toplexes": (_i32, [_p, _p, _p, _p, _p, _i64, _p, ctypes.POINTER(_i64), _p]),
         "slg_select": (_i32, [_p, _p, _p, _i64, _p, _p, _p, _p, ctypes.POINTER(_i64), _p]),
@@ -511,6 +512,16 @@ class Context:
                                          sym_col.data_ptr(), sym_w.data_ptr() if weights else None,
                                          _stream_handle(stream)))
         return sym_ptr, sym_col, sym_w
+
+    def digest(self, row, col, w, stream=None):
+        """Order-independent digest of device edge arrays: (edges, sum of w,
+        sum mod 2^64 of SplitMix64(i * 2^32 + j) xor w); digests of disjoint
+        parts add up (chunks of a streamed result)."""
+        out = (_u64 * 3)()
+        n = int(col.numel())
+        self._check(lib().slg_digest(self.handle, row.data_ptr() if n else None, col.data_ptr() if n else None,
+                                     w.data_ptr() if n else None, n, out, _stream_handle(stream)))
+        return int(out[0]), int(out[1]), int(out[2])
 
     # -- preprocessing (relabel-by-degree, toplexes) ------------------------
     def relabel_order(self, g: Graph, descending: bool = False, stream=None):

@@ -1493,6 +1493,25 @@ slg_status slg_symmetrize(slg_context *ctx, int64_t m, const int64_t *row_ptr, c
     return SLG_OK;
 }
 
+slg_status slg_digest(slg_context *ctx, const int32_t *row, const int32_t *col, const int32_t *w,
+                      int64_t num_edges, uint64_t *out, void *stream) {
+    if (!ctx || !out || num_edges < 0 || (num_edges > 0 && (!row || !col || !w)))
+        return fail(ctx, SLG_ERR_INVALID_ARG, "bad digest arguments");
+    SLG_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Scratch sc;
+    sc.st = st;
+    sc.arena = ctx->arena.get();
+    int64_t *acc = nullptr;
+    SLG_HIP(ctx, sc.get(&acc, 3));
+    SLG_HIP(ctx, launch_fill_i64(acc, 3, 0, st));
+    SLG_HIP(ctx, launch_digest(row, col, w, num_edges, reinterpret_cast<unsigned long long *>(acc), st));
+    SLG_HIP(ctx, hipMemcpyAsync(ctx->pinned, acc, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SLG_HIP(ctx, hipStreamSynchronize(st));
+    for (int t = 0; t < 3; ++t) out[t] = static_cast<uint64_t>(ctx->pinned[t]);
+    return SLG_OK;
+}
+
 slg_status slg_relabel_order(slg_context *ctx, slg_graph *g, int32_t descending, int32_t *order, void *stream) {
     if (!ctx || !g || !order) return fail(ctx, SLG_ERR_INVALID_ARG, "bad relabel arguments");
     SLG_HIP(ctx, hipSetDevice(ctx->device));

@@ -224,6 +224,9 @@ int sort_passes(int key_bits);
 hipError_t launch_sort_pass(const int32_t *key_in, const int32_t *a_in, const int32_t *b_in, int64_t n, int shift,
                             int bits, int32_t *hist, int64_t *off, int64_t *partials, int32_t *key_out,
                             int32_t *a_out, int32_t *b_out, hipStream_t st);
+// out[0..2] += (edges, sum of w, sum of SplitMix64(i * 2^32 + j) ^ w) mod 2^64.
+hipError_t launch_digest(const int32_t *row, const int32_t *col, const int32_t *w, int64_t n,
+                         unsigned long long *out, hipStream_t st);
 // lower_ptr[c] = number of ascending keys skey[0..n) below c, c in [0, m].
 hipError_t launch_key_bounds(const int32_t *skey, int64_t n, int64_t m, int64_t *lower_ptr, hipStream_t st);
 // err |= 1 unless (row_ptr, row, col) is an upper triangle in CSR order.

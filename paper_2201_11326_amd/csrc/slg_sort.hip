@@ -309,6 +309,43 @@ __global__ void sym_upper_kernel(const int32_t *__restrict__ row, const int32_t 
     }
 }
 
+// Order-independent digest of an edge list: the number of edges, the sum
+// of the overlaps, and the sum mod 2^64 of SplitMix64's output function
+// (Steele, Lea and Flood's mixer as published by Vigna) applied to
+// i * 2^32 + j, xor the overlap. Equal edge sets give equal digests in any
+// order, and the digests of disjoint parts add up to the digest of their
+// union, so a streamed result can be checked chunk by chunk.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x) {
+    unsigned long long z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void digest_kernel(const int32_t *__restrict__ row, const int32_t *__restrict__ col,
+                                                     const int32_t *__restrict__ w, int64_t n,
+                                                     unsigned long long *__restrict__ out) {
+    unsigned long long cnt = 0, sw = 0, h = 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long i = (unsigned)row[e], j = (unsigned)col[e];
+        const unsigned long long x = (unsigned long long)(unsigned)w[e];
+        cnt += 1;
+        sw += x;
+        h += splitmix64((i << 32) | j) ^ x;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        cnt += __shfl_xor(cnt, o);
+        sw += __shfl_xor(sw, o);
+        h += __shfl_xor(h, o);
+    }
+    if ((threadIdx.x & 63) == 0 && cnt) {
+        atomicAdd(&out[0], cnt);
+        atomicAdd(&out[1], sw);
+        atomicAdd(&out[2], h);
+    }
+}
+
 inline unsigned sort_grid(int64_t items, int threads, int64_t cap) {
     int64_t b = (items + threads - 1) / threads;
     if (b > cap) b = cap;
@@ -340,6 +377,13 @@ hipError_t launch_sort_pass(const int32_t *key_in, const int32_t *a_in, const in
     else
         sort_scatter_kernel<0><<<grid, kSortThreads, 0, st>>>(key_in, nullptr, nullptr, n, shift, bits, nchunks,
                                                                off, key_out, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_digest(const int32_t *row, const int32_t *col, const int32_t *w, int64_t n,
+                         unsigned long long *out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    digest_kernel<<<sort_grid(n, 256, 8192), 256, 0, st>>>(row, col, w, n, out);
     return hipGetLastError();
 }
 

@@ -418,3 +418,34 @@ def test_select_of_a_subset():
     ptr_t, idx_t = hg.transpose_csr(len(order), inc.n, he_ptr, he_idx)
     np.testing.assert_array_equal(v_ptr, ptr_t)
     np.testing.assert_array_equal(v_idx, idx_t)
+
+
+# --- edge-list digest ------------------------------------------------------
+
+def test_splitmix64_matches_the_published_sequence():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "splitmix64_seed0.txt")
+    want = [int(l, 16) for l in open(path) if l.strip() and not l.startswith("#")]
+    gamma = 0x9E3779B97F4A7C15
+    states = np.array([(k * gamma) % (1 << 64) for k in range(len(want))], dtype=np.uint64)
+    got = [int(v) for v in oracle._splitmix64(states)]
+    assert got == want
+
+
+def test_digest_is_order_free_additive_and_sensitive():
+    inc = hg.random_small(91, 300, 100, 12, 1.0)
+    lg = oracle.line_graph(inc, 1)
+    d = oracle.digest(lg.i, lg.j, lg.w)
+    assert d[0] == len(lg.j) and d[1] == int(lg.w.sum())
+    perm = np.random.default_rng(0).permutation(len(lg.j))
+    assert oracle.digest(lg.i[perm], lg.j[perm], lg.w[perm]) == d
+    cut = len(lg.j) // 3
+    a = oracle.digest(lg.i[:cut], lg.j[:cut], lg.w[:cut])
+    b = oracle.digest(lg.i[cut:], lg.j[cut:], lg.w[cut:])
+    assert (a[0] + b[0], a[1] + b[1], (a[2] + b[2]) % (1 << 64)) == d
+    w2 = lg.w.copy()
+    w2[5] += 1
+    assert oracle.digest(lg.i, lg.j, w2)[2] != d[2]
+    j2 = lg.j.copy()
+    j2[7] += 1
+    assert oracle.digest(lg.i, j2, lg.w)[2] != d[2]
