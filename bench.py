@@ -90,6 +90,20 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
+def host_cpu() -> str:
+    """Model name of the host CPU and its logical CPU count (for the oracle timing)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical CPUs visible"
+
+
 def cpu_baseline(inc, seconds: float, seed: int = 7):
     """Oracle on a random row sample sized to about `seconds` of CPU time.
     Rate = 2-paths of the sampled rows (the work the two-hop traversal does
@@ -113,7 +127,7 @@ def cpu_baseline(inc, seconds: float, seed: int = 7):
     work = int(oracle.row_two_paths(inc, S_SET[0], rows, threads=threads).sum())
     return {"value": work / dt, "unit": "2-paths/s", "cores": threads, "kind": "oracle",
             "sample": f"{nrows} random rows (seed {seed}) of the same hypergraph, all of S={S_SET}, "
-                      f"{work} 2-paths, {dt:.2f} s wall"}
+                      f"{work} 2-paths, {dt:.2f} s wall", "host": host_cpu()}
 
 
 def batched_cpu_baseline(members, seconds: float, seed: int = 7):
@@ -136,7 +150,7 @@ def batched_cpu_baseline(members, seconds: float, seed: int = 7):
             break
     return {"value": work / dt, "unit": "2-paths/s", "cores": threads, "kind": "oracle",
             "sample": f"{used} of {len(members)} member graphs (seeded order {seed}), each at its own s, "
-                      f"{work} 2-paths, {dt:.2f} s wall"}
+                      f"{work} 2-paths, {dt:.2f} s wall", "host": host_cpu()}
 
 
 def bench_batched(args) -> int:
