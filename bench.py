@@ -654,7 +654,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the s-line graph path here runs on a single MI355X "
-              "(rows would shard across GPUs with no exchange; see DESIGN.md). Use --gpus 1.",
+              "(rows would shard across GPUs with no exchange). Use --gpus 1.",
               file=sys.stderr)
         return 2
 
