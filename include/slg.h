@@ -176,7 +176,9 @@ slg_status slg_plan_emit(slg_plan *p, int64_t *const *row_ptr, int32_t *const *r
  *   [8] heavy slots; [9] heavy slots of rows with >= 65535 members;
  *   [10] 2-paths (as slg_plan_info); [11] 2-paths in heavy slots;
  *   [12] entries of the heavy boundary table;
- *   [13] edges written by heavy slots, summed over all thresholds.
+ *   [13] edges written by heavy slots, summed over all thresholds;
+ *   [14] (partner, overlap) entries the heavy count store keeps (0 when
+ *        the plan keeps none; see slg_context_set_count_store).
  * Returns the number of entries written in *count (may be NULL).
  */
 slg_status slg_plan_stats(const slg_plan *p, int64_t *out, int32_t cap, int32_t *count);
