@@ -18,7 +18,12 @@
  *   - "device" pointers are addresses in the GPU's memory (e.g. from torch
  *     or hipMalloc); "host" pointers are ordinary CPU memory.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
- *     all device work of a call is ordered on it.
+ *     all device work of a call is ordered on it. Inside a call the library
+ *     may fork part of the work onto a stream the context owns (the light
+ *     tier's counting pass of slg_plan_create runs beside the heavy tier's
+ *     planning); the fork waits on an event recorded on `stream` and is
+ *     joined back into `stream` before the call returns, so the ordering
+ *     seen from `stream` (and HIP graph capture of it) is unchanged.
  *   - every call returns a slg_status; on failure the context's last error
  *     string (slg_last_error) says why. No call throws.
  *   - a context and everything made from it belong to one host thread at a
@@ -186,7 +191,8 @@ slg_status slg_plan_stats(const slg_plan *p, int64_t *out, int32_t cap, int32_t 
 /*
  * Opt-in device timing, for measurement. When enabled, every kernel launch
  * of the path is bracketed by HIP events recorded on the stream it runs on,
- * and the elapsed times are summed per stage. slg_context_get_timing waits
+ * and the elapsed times are summed per stage (stages on the context's
+ * second stream overlap others, so the sum can exceed the wall time). slg_context_get_timing waits
  * for the recorded events, then fills up to `cap` entries of out[] (host
  * array) with one record per stage that ran: its name (static storage),
  * the number of timed launches and their summed duration in milliseconds.

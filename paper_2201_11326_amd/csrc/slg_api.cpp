@@ -52,6 +52,8 @@ struct slg_context {
     slg_allocator alloc{};
     std::string last_error;
     int64_t *pinned = nullptr;  // host staging for readbacks
+    hipStream_t aux = nullptr;  // second stream: the light tier's counting pass beside the heavy planning
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     std::shared_ptr<slg::Arena> arena;  // scratch and library-owned outputs
 };
 
@@ -297,6 +299,16 @@ slg_status slg_context_create(int device, uint64_t mem_budget_bytes, const slg_a
         return SLG_ERR_DEVICE;
     }
     ctx->heavy_resident = heavy_resident(device);
+    if (hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();  // run everything on the caller's stream instead
+        if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+        if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+        if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
+        ctx->aux = nullptr;
+        ctx->fork_ev = ctx->join_ev = nullptr;
+    }
     uint64_t cache = mem_budget_bytes;
     if (!cache) {
         size_t free_b = 0, total_b = 0;
@@ -322,6 +334,12 @@ slg_status slg_context_destroy(slg_context *ctx) {
         ctx->event_pool.push_back(pt.stop);
     }
     for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+    if (ctx->aux) {
+        (void)hipStreamSynchronize(ctx->aux);
+        (void)hipStreamDestroy(ctx->aux);
+    }
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+    if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
     return SLG_OK;
@@ -499,39 +517,59 @@ hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
                                    reinterpret_cast<int *>(b.counters + kCntErr), st)) != hipSuccess)
             return e;
     }
-    {
-        StageTimer tm(ctx, kStBounds, st);
-        for (int h = 0; h < 2; ++h)
-            if ((e = launch_bounds(p->pr, p->heavy[h], p->list_count[kLightClasses + h], p->bounds, st)) !=
-                hipSuccess)
-                return e;
+    // the light tier's counting pass runs on the context's second stream,
+    // beside the boundary table and the heavy counting pass: it reads the
+    // light lists and writes the light slots' counts (and the light store),
+    // which nothing on the caller's stream touches before the join
+    const bool fork = ctx->aux != nullptr;
+    const hipStream_t lst = fork ? ctx->aux : st;
+    if (fork) {
+        if ((e = hipEventRecord(ctx->fork_ev, st)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0)) != hipSuccess) return e;
     }
-    if (p->use_store) {  // the store's layout: each heavy slot's 2-paths bound its partners
-        StageTimer tm(ctx, kStBounds, st);
-        const int64_t nh = p->list_count[kLightClasses];
-        if ((e = launch_slot_work(p->heavy[0], nh, p->bounds, p->store_work, st)) != hipSuccess) return e;
-        if ((e = launch_exclusive_scan_i64(p->store_work, nh, p->store.off, b.part_s, st)) != hipSuccess) return e;
-    }
-    {
-        StageTimer tm(ctx, kStCountLight, st);
-        if (p->use_lstore) {  // the light store's layout
-            if ((e = launch_light_work(m, b.rclass, b.work, p->lwork, st)) != hipSuccess) return e;
-            if ((e = launch_exclusive_scan_i32(p->lwork, m, p->lstore.off, b.part_m, st)) != hipSuccess) return e;
+    e = [&]() -> hipError_t {
+        hipError_t e;
+        {
+            StageTimer tm(ctx, kStCountLight, lst);
+            if (p->use_lstore) {  // the light store's layout
+                if ((e = launch_light_work(m, b.rclass, b.work, p->lwork, lst)) != hipSuccess) return e;
+                if ((e = launch_exclusive_scan_i32(p->lwork, m, p->lstore.off, b.part_m, lst)) != hipSuccess) return e;
+            }
+            for (int c = 0; c < kLightClasses; ++c)
+                if ((e = launch_light(c, false, p->lists[c], p->list_count[c], p->slots, p->pr, p->prm, p->slot_cnt,
+                                      nullptr, (p->use_lstore && c > 0) ? &p->lstore : nullptr, lst)) != hipSuccess)
+                    return e;
         }
-        for (int c = 0; c < kLightClasses; ++c)
-            if ((e = launch_light(c, false, p->lists[c], p->list_count[c], p->slots, p->pr, p->prm, p->slot_cnt,
-                                  nullptr, (p->use_lstore && c > 0) ? &p->lstore : nullptr, st)) != hipSuccess)
+        {
+            StageTimer tm(ctx, kStBounds, st);
+            for (int h = 0; h < 2; ++h)
+                if ((e = launch_bounds(p->pr, p->heavy[h], p->list_count[kLightClasses + h], p->bounds, st)) !=
+                    hipSuccess)
+                    return e;
+        }
+        if (p->use_store) {  // the store's layout: each heavy slot's 2-paths bound its partners
+            StageTimer tm(ctx, kStBounds, st);
+            const int64_t nh = p->list_count[kLightClasses];
+            if ((e = launch_slot_work(p->heavy[0], nh, p->bounds, p->store_work, st)) != hipSuccess) return e;
+            if ((e = launch_exclusive_scan_i64(p->store_work, nh, p->store.off, b.part_s, st)) != hipSuccess) return e;
+        }
+        if ((e = launch_fill_i64(p->tickets, 6, 0, st)) != hipSuccess) return e;
+        for (int wide = 0; wide < 2; ++wide) {
+            if (p->list_count[kLightClasses + wide] <= 0) continue;
+            StageTimer tm(ctx, wide ? kStCountHeavyWide : kStCountHeavy, st);
+            if ((e = launch_heavy(false, wide, p->heavy[wide], p->list_count[kLightClasses + wide], p->S, p->bounds,
+                                  p->pr, p->prm, p->slot_cnt, nullptr, p->tickets + wide, p->heavy_grid,
+                                  (p->use_store && !wide) ? &p->store : nullptr, st)) != hipSuccess)
                 return e;
+        }
+        return hipSuccess;
+    }();
+    if (fork) {  // joined on every path: the count scans read every slot's counts
+        const hipError_t j = hipEventRecord(ctx->join_ev, ctx->aux);
+        const hipError_t w = j == hipSuccess ? hipStreamWaitEvent(st, ctx->join_ev, 0) : j;
+        if (e == hipSuccess) e = w;
     }
-    if ((e = launch_fill_i64(p->tickets, 6, 0, st)) != hipSuccess) return e;
-    for (int wide = 0; wide < 2; ++wide) {
-        if (p->list_count[kLightClasses + wide] <= 0) continue;
-        StageTimer tm(ctx, wide ? kStCountHeavyWide : kStCountHeavy, st);
-        if ((e = launch_heavy(false, wide, p->heavy[wide], p->list_count[kLightClasses + wide], p->S, p->bounds,
-                              p->pr, p->prm, p->slot_cnt, nullptr, p->tickets + wide, p->heavy_grid,
-                              (p->use_store && !wide) ? &p->store : nullptr, st)) != hipSuccess)
-            return e;
-    }
+    if (e != hipSuccess) return e;
     StageTimer tm(ctx, kStCountScans, st);
     for (int k = 0; k < p->prm.k; ++k)
         if ((e = launch_exclusive_scan_i64(p->slot_cnt + (size_t)k * p->S, p->S,
