@@ -495,6 +495,30 @@ hipError_t enqueue_rows(slg_plan *p, hipStream_t st) {
 }
 
 // Slot table, tier lists, boundary table, counting pass and its scans.
+// Work forked onto the context's second stream after what `st` holds so far,
+// and joined back into `st` when the guard ends (on every path out).
+struct AuxFork {
+    slg_context *ctx;
+    hipStream_t st;
+    bool on = false;
+    AuxFork(slg_context *c, hipStream_t s) : ctx(c), st(s) {}
+    hipStream_t begin(hipError_t *e) {
+        *e = hipSuccess;
+        if (!ctx->aux) return st;
+        if ((*e = hipEventRecord(ctx->fork_ev, st)) != hipSuccess) return st;
+        if ((*e = hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0)) != hipSuccess) return st;
+        on = true;
+        return ctx->aux;
+    }
+    hipError_t join() {
+        if (!on) return hipSuccess;
+        on = false;
+        const hipError_t e = hipEventRecord(ctx->join_ev, ctx->aux);
+        return e != hipSuccess ? e : hipStreamWaitEvent(st, ctx->join_ev, 0);
+    }
+    ~AuxFork() { (void)join(); }
+};
+
 hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
     slg_context *ctx = p->ctx;
     const int64_t m = p->pr.m;
@@ -521,55 +545,43 @@ hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
     // beside the boundary table and the heavy counting pass: it reads the
     // light lists and writes the light slots' counts (and the light store),
     // which nothing on the caller's stream touches before the join
-    const bool fork = ctx->aux != nullptr;
-    const hipStream_t lst = fork ? ctx->aux : st;
-    if (fork) {
-        if ((e = hipEventRecord(ctx->fork_ev, st)) != hipSuccess) return e;
-        if ((e = hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0)) != hipSuccess) return e;
-    }
-    e = [&]() -> hipError_t {
-        hipError_t e;
-        {
-            StageTimer tm(ctx, kStCountLight, lst);
-            if (p->use_lstore) {  // the light store's layout
-                if ((e = launch_light_work(m, b.rclass, b.work, p->lwork, lst)) != hipSuccess) return e;
-                if ((e = launch_exclusive_scan_i32(p->lwork, m, p->lstore.off, b.part_m, lst)) != hipSuccess) return e;
-            }
-            for (int c = 0; c < kLightClasses; ++c)
-                if ((e = launch_light(c, false, p->lists[c], p->list_count[c], p->slots, p->pr, p->prm, p->slot_cnt,
-                                      nullptr, (p->use_lstore && c > 0) ? &p->lstore : nullptr, lst)) != hipSuccess)
-                    return e;
-        }
-        {
-            StageTimer tm(ctx, kStBounds, st);
-            for (int h = 0; h < 2; ++h)
-                if ((e = launch_bounds(p->pr, p->heavy[h], p->list_count[kLightClasses + h], p->bounds, st)) !=
-                    hipSuccess)
-                    return e;
-        }
-        if (p->use_store) {  // the store's layout: each heavy slot's 2-paths bound its partners
-            StageTimer tm(ctx, kStBounds, st);
-            const int64_t nh = p->list_count[kLightClasses];
-            if ((e = launch_slot_work(p->heavy[0], nh, p->bounds, p->store_work, st)) != hipSuccess) return e;
-            if ((e = launch_exclusive_scan_i64(p->store_work, nh, p->store.off, b.part_s, st)) != hipSuccess) return e;
-        }
-        if ((e = launch_fill_i64(p->tickets, 6, 0, st)) != hipSuccess) return e;
-        for (int wide = 0; wide < 2; ++wide) {
-            if (p->list_count[kLightClasses + wide] <= 0) continue;
-            StageTimer tm(ctx, wide ? kStCountHeavyWide : kStCountHeavy, st);
-            if ((e = launch_heavy(false, wide, p->heavy[wide], p->list_count[kLightClasses + wide], p->S, p->bounds,
-                                  p->pr, p->prm, p->slot_cnt, nullptr, p->tickets + wide, p->heavy_grid,
-                                  (p->use_store && !wide) ? &p->store : nullptr, st)) != hipSuccess)
-                return e;
-        }
-        return hipSuccess;
-    }();
-    if (fork) {  // joined on every path: the count scans read every slot's counts
-        const hipError_t j = hipEventRecord(ctx->join_ev, ctx->aux);
-        const hipError_t w = j == hipSuccess ? hipStreamWaitEvent(st, ctx->join_ev, 0) : j;
-        if (e == hipSuccess) e = w;
-    }
+    AuxFork fork(ctx, st);
+    const hipStream_t lst = fork.begin(&e);
     if (e != hipSuccess) return e;
+    {
+        StageTimer tm(ctx, kStCountLight, lst);
+        if (p->use_lstore) {  // the light store's layout
+            if ((e = launch_light_work(m, b.rclass, b.work, p->lwork, lst)) != hipSuccess) return e;
+            if ((e = launch_exclusive_scan_i32(p->lwork, m, p->lstore.off, b.part_m, lst)) != hipSuccess) return e;
+        }
+        for (int c = 0; c < kLightClasses; ++c)
+            if ((e = launch_light(c, false, p->lists[c], p->list_count[c], p->slots, p->pr, p->prm, p->slot_cnt,
+                                  nullptr, (p->use_lstore && c > 0) ? &p->lstore : nullptr, lst)) != hipSuccess)
+                return e;
+    }
+    {
+        StageTimer tm(ctx, kStBounds, st);
+        for (int h = 0; h < 2; ++h)
+            if ((e = launch_bounds(p->pr, p->heavy[h], p->list_count[kLightClasses + h], p->bounds, st)) !=
+                hipSuccess)
+                return e;
+    }
+    if (p->use_store) {  // the store's layout: each heavy slot's 2-paths bound its partners
+        StageTimer tm(ctx, kStBounds, st);
+        const int64_t nh = p->list_count[kLightClasses];
+        if ((e = launch_slot_work(p->heavy[0], nh, p->bounds, p->store_work, st)) != hipSuccess) return e;
+        if ((e = launch_exclusive_scan_i64(p->store_work, nh, p->store.off, b.part_s, st)) != hipSuccess) return e;
+    }
+    if ((e = launch_fill_i64(p->tickets, 6, 0, st)) != hipSuccess) return e;
+    for (int wide = 0; wide < 2; ++wide) {
+        if (p->list_count[kLightClasses + wide] <= 0) continue;
+        StageTimer tm(ctx, wide ? kStCountHeavyWide : kStCountHeavy, st);
+        if ((e = launch_heavy(false, wide, p->heavy[wide], p->list_count[kLightClasses + wide], p->S, p->bounds,
+                              p->pr, p->prm, p->slot_cnt, nullptr, p->tickets + wide, p->heavy_grid,
+                              (p->use_store && !wide) ? &p->store : nullptr, st)) != hipSuccess)
+            return e;
+    }
+    if ((e = fork.join()) != hipSuccess) return e;  // the count scans read every slot's counts
     StageTimer tm(ctx, kStCountScans, st);
     for (int k = 0; k < p->prm.k; ++k)
         if ((e = launch_exclusive_scan_i64(p->slot_cnt + (size_t)k * p->S, p->S,
@@ -1293,6 +1305,13 @@ const slg_context *graph_context(const slg_graph *g) { return g->ctx; }
 slg_status set_error(slg_context *ctx, slg_status code, const char *msg) { return fail(ctx, code, "%s", msg); }
 
 void share_arena(slg_context *ctx, const std::shared_ptr<Arena> &arena) { ctx->arena = arena; }
+
+void drop_aux_stream(slg_context *ctx) {
+    if (!ctx->aux) return;
+    (void)hipStreamSynchronize(ctx->aux);
+    (void)hipStreamDestroy(ctx->aux);
+    ctx->aux = nullptr;
+}
 
 void copy_tuning(slg_context *dst, const slg_context *src) {
     dst->light_max = src->light_max;

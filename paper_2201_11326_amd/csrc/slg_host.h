@@ -56,6 +56,10 @@ slg_status serve_query(slg_context *wctx, slg_graph *g, const int32_t *s, int32_
 int context_device(const slg_context *ctx);
 const slg_context *graph_context(const slg_graph *g);
 slg_status set_error(slg_context *ctx, slg_status code, const char *msg);
+// Makes `ctx` run all of a call's work on the caller's stream (no fork onto
+// its second stream). A server's slots already overlap whole queries; a
+// second stream per slot only adds streams to share the hardware queues.
+void drop_aux_stream(slg_context *ctx);
 // Copies the plan-shape tuning (slg_context_set_tuning) of `src` to `dst`.
 void copy_tuning(slg_context *dst, const slg_context *src);
 // Makes `ctx` take its scratch and outputs from `arena` (shared by a

@@ -228,6 +228,7 @@ slg_status slg_server_create(slg_context *ctx, int32_t workers, uint64_t mem_bud
             return undo(SLG_ERR_DEVICE, "worker context creation failed");
         slg::copy_tuning(w.ctx, ctx);
         slg::share_arena(w.ctx, arena);
+        slg::drop_aux_stream(w.ctx);
         if (hipStreamCreateWithFlags(&w.st, hipStreamNonBlocking) != hipSuccess)
             return undo(SLG_ERR_DEVICE, "worker stream creation failed");
     }
