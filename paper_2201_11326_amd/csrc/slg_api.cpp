@@ -52,7 +52,10 @@ struct slg_context {
     slg_allocator alloc{};
     std::string last_error;
     int64_t *pinned = nullptr;  // host staging for readbacks
-    hipStream_t aux = nullptr;  // second stream: the light tier's counting pass beside the heavy planning
+    // second stream: the light tier's counting pass beside the heavy
+    // planning, made at the first plan large enough to fork
+    bool aux_allowed = true;
+    hipStream_t aux = nullptr;
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     std::shared_ptr<slg::Arena> arena;  // scratch and library-owned outputs
 };
@@ -273,12 +276,9 @@ struct slg_result {
     uint64_t bytes = 0;                    // device bytes accounted to `core`
 };
 
-extern "C" {
-
-const char *slg_version(void) { return "slg 0.1.0 (gfx950)"; }
-
-slg_status slg_context_create(int device, uint64_t mem_budget_bytes, const slg_allocator *alloc,
-                              slg_context **out) {
+namespace slg {
+slg_status create_context(int device, uint64_t mem_budget_bytes, const slg_allocator *alloc, bool second_stream,
+                          slg_context **out) {
     if (!out) return SLG_ERR_INVALID_ARG;
     *out = nullptr;
     int count = 0;
@@ -299,16 +299,7 @@ slg_status slg_context_create(int device, uint64_t mem_budget_bytes, const slg_a
         return SLG_ERR_DEVICE;
     }
     ctx->heavy_resident = heavy_resident(device);
-    if (hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming) != hipSuccess) {
-        (void)hipGetLastError();  // run everything on the caller's stream instead
-        if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
-        if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
-        if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
-        ctx->aux = nullptr;
-        ctx->fork_ev = ctx->join_ev = nullptr;
-    }
+    ctx->aux_allowed = second_stream;
     uint64_t cache = mem_budget_bytes;
     if (!cache) {
         size_t free_b = 0, total_b = 0;
@@ -324,6 +315,16 @@ slg_status slg_context_create(int device, uint64_t mem_budget_bytes, const slg_a
     }
     *out = ctx;
     return SLG_OK;
+}
+}  // namespace slg
+
+extern "C" {
+
+const char *slg_version(void) { return "slg 0.1.0 (gfx950)"; }
+
+slg_status slg_context_create(int device, uint64_t mem_budget_bytes, const slg_allocator *alloc,
+                              slg_context **out) {
+    return slg::create_context(device, mem_budget_bytes, alloc, true, out);
 }
 
 slg_status slg_context_destroy(slg_context *ctx) {
@@ -495,16 +496,42 @@ hipError_t enqueue_rows(slg_plan *p, hipStream_t st) {
 }
 
 // Slot table, tier lists, boundary table, counting pass and its scans.
+// Plans with fewer 2-paths stay on one stream: their light counting pass is
+// short, and an extra stream per context, even idle, has measured slower
+// when several contexts serve concurrent queries (more streams share the
+// process's hardware queues).
+constexpr int64_t kForkMinTwoPaths = int64_t(1) << 28;
+
+// Makes the context's second stream and its events; false (and none of
+// them) when the context goes without, is capturing, or creation fails.
+bool ensure_aux(slg_context *ctx) {
+    if (ctx->aux) return true;
+    if (!ctx->aux_allowed || ctx->capturing) return false;
+    if (hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) == hipSuccess &&
+        hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) == hipSuccess &&
+        hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming) == hipSuccess)
+        return true;
+    (void)hipGetLastError();  // run everything on the caller's stream instead
+    if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+    if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
+    ctx->aux = nullptr;
+    ctx->fork_ev = ctx->join_ev = nullptr;
+    ctx->aux_allowed = false;
+    return false;
+}
+
 // Work forked onto the context's second stream after what `st` holds so far,
-// and joined back into `st` when the guard ends (on every path out).
+// and joined back into `st` when the guard ends (on every path out). Without
+// the second stream, the work stays on `st`.
 struct AuxFork {
     slg_context *ctx;
     hipStream_t st;
     bool on = false;
     AuxFork(slg_context *c, hipStream_t s) : ctx(c), st(s) {}
-    hipStream_t begin(hipError_t *e) {
+    hipStream_t begin(bool want, hipError_t *e) {
         *e = hipSuccess;
-        if (!ctx->aux) return st;
+        if (!want || !ensure_aux(ctx)) return st;
         if ((*e = hipEventRecord(ctx->fork_ev, st)) != hipSuccess) return st;
         if ((*e = hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0)) != hipSuccess) return st;
         on = true;
@@ -546,7 +573,7 @@ hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
     // light lists and writes the light slots' counts (and the light store),
     // which nothing on the caller's stream touches before the join
     AuxFork fork(ctx, st);
-    const hipStream_t lst = fork.begin(&e);
+    const hipStream_t lst = fork.begin(p->two_paths >= kForkMinTwoPaths, &e);
     if (e != hipSuccess) return e;
     {
         StageTimer tm(ctx, kStCountLight, lst);
@@ -1305,13 +1332,6 @@ const slg_context *graph_context(const slg_graph *g) { return g->ctx; }
 slg_status set_error(slg_context *ctx, slg_status code, const char *msg) { return fail(ctx, code, "%s", msg); }
 
 void share_arena(slg_context *ctx, const std::shared_ptr<Arena> &arena) { ctx->arena = arena; }
-
-void drop_aux_stream(slg_context *ctx) {
-    if (!ctx->aux) return;
-    (void)hipStreamSynchronize(ctx->aux);
-    (void)hipStreamDestroy(ctx->aux);
-    ctx->aux = nullptr;
-}
 
 void copy_tuning(slg_context *dst, const slg_context *src) {
     dst->light_max = src->light_max;

@@ -56,10 +56,13 @@ slg_status serve_query(slg_context *wctx, slg_graph *g, const int32_t *s, int32_
 int context_device(const slg_context *ctx);
 const slg_context *graph_context(const slg_graph *g);
 slg_status set_error(slg_context *ctx, slg_status code, const char *msg);
-// Makes `ctx` run all of a call's work on the caller's stream (no fork onto
-// its second stream). A server's slots already overlap whole queries; a
-// second stream per slot only adds streams to share the hardware queues.
-void drop_aux_stream(slg_context *ctx);
+// slg_context_create, with the choice of the context's second stream (on
+// which a large plan's light counting pass runs beside the heavy tier's
+// planning). A server's slots go without it: they already overlap whole
+// queries, and a second stream per slot only adds streams to share the
+// hardware queues.
+slg_status create_context(int device, uint64_t mem_budget_bytes, const slg_allocator *alloc, bool second_stream,
+                          slg_context **out);
 // Copies the plan-shape tuning (slg_context_set_tuning) of `src` to `dst`.
 void copy_tuning(slg_context *dst, const slg_context *src);
 // Makes `ctx` take its scratch and outputs from `arena` (shared by a

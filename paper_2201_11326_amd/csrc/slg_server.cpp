@@ -224,11 +224,10 @@ slg_status slg_server_create(slg_context *ctx, int32_t workers, uint64_t mem_bud
     arena = std::make_shared<slg::Arena>(sv->device, cache);
     sv->workers.resize(workers);
     for (Worker &w : sv->workers) {
-        if (slg_context_create(sv->device, 0, nullptr, &w.ctx) != SLG_OK)
+        if (slg::create_context(sv->device, 0, nullptr, false, &w.ctx) != SLG_OK)
             return undo(SLG_ERR_DEVICE, "worker context creation failed");
         slg::copy_tuning(w.ctx, ctx);
         slg::share_arena(w.ctx, arena);
-        slg::drop_aux_stream(w.ctx);
         if (hipStreamCreateWithFlags(&w.st, hipStreamNonBlocking) != hipSuccess)
             return undo(SLG_ERR_DEVICE, "worker stream creation failed");
     }

@@ -174,3 +174,26 @@ def test_unknown_ticket_and_shutdown_with_queued_queries(ctx):
     g.release()
     with pytest.raises(slg.SlgError):
         slg.Server(ctx, workers=0)
+
+
+def test_two_stream_plan_equals_one_stream_plan(ctx):
+    """A plan with at least 2^28 2-paths runs its light counting pass on the
+    context's second stream; a server's slots run everything on one stream.
+    The power-law workload (n=1e6, m=5e5, S = {1, 2, 4, 8}; 2.4e9 2-paths)
+    through both must give identical arrays."""
+    import torch
+    inc = hg.power_law()
+    g = ctx.register_incidence(inc)
+    forked = ctx.line_graph(g, [1, 2, 4, 8])
+    assert forked[0].two_paths >= 1 << 28
+    srv = ctx.server(workers=1)
+    srv.submit(g, [1, 2, 4, 8])
+    r = srv.next(timeout_ms=120_000)
+    assert r is not None and r.ok, (r and r.message)
+    for a, b in zip(forked, r.outs):
+        assert a.s == b.s and a.num_edges == b.num_edges
+        for f in ("row_ptr", "row", "col", "w"):
+            assert torch.equal(getattr(a, f), getattr(b, f)), f"s={a.s} {f}"
+    del r, forked
+    srv.close()
+    g.release()
