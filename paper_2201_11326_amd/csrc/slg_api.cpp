@@ -569,9 +569,9 @@ hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
             return e;
     }
     // the light tier's counting pass runs on the context's second stream,
-    // beside the boundary table and the heavy counting pass: it reads the
-    // light lists and writes the light slots' counts (and the light store),
-    // which nothing on the caller's stream touches before the join
+    // beside the boundary table: it reads the light lists and writes the
+    // light slots' counts (and the light store), which nothing on the
+    // caller's stream touches before the join
     AuxFork fork(ctx, st);
     const hipStream_t lst = fork.begin(p->two_paths >= kForkMinTwoPaths, &e);
     if (e != hipSuccess) return e;
@@ -599,6 +599,9 @@ hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
         if ((e = launch_slot_work(p->heavy[0], nh, p->bounds, p->store_work, st)) != hipSuccess) return e;
         if ((e = launch_exclusive_scan_i64(p->store_work, nh, p->store.off, b.part_s, st)) != hipSuccess) return e;
     }
+    // joined before the heavy counting pass: its persistent grid fills every
+    // CU, and light workgroups still resident would hold some of it back
+    if ((e = fork.join()) != hipSuccess) return e;
     if ((e = launch_fill_i64(p->tickets, 6, 0, st)) != hipSuccess) return e;
     for (int wide = 0; wide < 2; ++wide) {
         if (p->list_count[kLightClasses + wide] <= 0) continue;
@@ -608,7 +611,6 @@ hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
                               (p->use_store && !wide) ? &p->store : nullptr, st)) != hipSuccess)
             return e;
     }
-    if ((e = fork.join()) != hipSuccess) return e;  // the count scans read every slot's counts
     StageTimer tm(ctx, kStCountScans, st);
     for (int k = 0; k < p->prm.k; ++k)
         if ((e = launch_exclusive_scan_i64(p->slot_cnt + (size_t)k * p->S, p->S,
