@@ -19,11 +19,12 @@
  *     or hipMalloc); "host" pointers are ordinary CPU memory.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
  *     all device work of a call is ordered on it. Inside a call the library
- *     may fork part of the work onto a stream the context owns (the light
- *     tier's counting pass of slg_plan_create runs beside the heavy tier's
- *     planning); the fork waits on an event recorded on `stream` and is
- *     joined back into `stream` before the call returns, so the ordering
- *     seen from `stream` (and HIP graph capture of it) is unchanged.
+ *     may fork part of the work onto a stream the context owns (for plans
+ *     of at least 2^28 2-paths, the light tier's counting pass of
+ *     slg_plan_create runs beside the heavy tier's boundary table; the
+ *     context makes that stream at the first such plan). The fork waits on
+ *     an event recorded on `stream` and is joined back into `stream`
+ *     within the call, so the ordering seen from `stream` is unchanged.
  *   - every call returns a slg_status; on failure the context's last error
  *     string (slg_last_error) says why. No call throws.
  *   - a context and everything made from it belong to one host thread at a
