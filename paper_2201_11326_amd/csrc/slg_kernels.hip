@@ -1734,11 +1734,14 @@ __global__ __launch_bounds__(256) void bounds_kernel(
     const int32_t *__restrict__ he_idx, const int64_t *__restrict__ vs_ptr,
     const int32_t *__restrict__ vs_idx, const int32_t *__restrict__ tail_beg,
     int32_t *__restrict__ bounds) {
-    // workgroups are dealt to the 8 XCDs in turn; each XCD takes a
-    // contiguous run of slots instead, so that a row's slots (which search
-    // the same vertex lists) share one L2
-    const uint32_t nb = gridDim.x, b = blockIdx.x, x = b % 8u, per = nb / 8u, rem = nb % 8u;
-    const uint32_t blk = x * per + min(x, rem) + b / 8u;
+    // workgroups are dealt to the 8 XCDs in turn; each XCD takes runs of 16
+    // consecutive blocks (64 slots) instead, so that a row's slots (which
+    // search the same vertex lists) mostly share one L2, while the runs
+    // still rotate over the XCDs (rows of very different cost, e.g. sorted
+    // by size, stay spread). The tail past whole rounds keeps its place.
+    constexpr uint32_t kRun = 16;
+    const uint32_t nb = gridDim.x, b = blockIdx.x, q = b / 8u;
+    const uint32_t blk = b >= nb / (8u * kRun) * (8u * kRun) ? b : q / kRun * (8u * kRun) + b % 8u * kRun + q % kRun;
     const int lane = lane_id();
     const int64_t w = ((int64_t)blk * blockDim.x + threadIdx.x) / 64;
     if (w >= count) return;
