@@ -502,11 +502,14 @@ hipError_t enqueue_rows(slg_plan *p, hipStream_t st) {
 // process's hardware queues).
 constexpr int64_t kForkMinTwoPaths = int64_t(1) << 28;
 
-// Makes the context's second stream and its events; false (and none of
-// them) when the context goes without, is capturing, or creation fails.
+// Makes the context's second stream and its events; false when the context
+// goes without, creation fails, or a HIP-graph capture is recording (a
+// captured path never forks, even on a context that already has the
+// stream).
 bool ensure_aux(slg_context *ctx) {
+    if (ctx->capturing) return false;
     if (ctx->aux) return true;
-    if (!ctx->aux_allowed || ctx->capturing) return false;
+    if (!ctx->aux_allowed) return false;
     if (hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking) == hipSuccess &&
         hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) == hipSuccess &&
         hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming) == hipSuccess)

@@ -57,6 +57,34 @@ def test_toy_dual_is_s_clique(ctx):
     assert_matches_oracle(inc.dual(), lg, 1, "dual")
 
 
+@pytest.mark.parametrize("seed,m,n,kmax,expo,s_list", [
+    (121, 3000, 800, 25, 0.8, [1, 2, 3]),    # vertices of very uneven degree
+    (122, 2000, 300, 40, 1.5, [2, 5]),       # a few hub vertices in most hyperedges
+    (123, 5000, 1500, 8, None, [1]),         # uniform members
+])
+def test_dual_is_s_clique_full(ctx, seed, m, n, kmax, expo, s_list):
+    """The s-clique graph (the s-line graph of the dual H*, Section II-A and
+    Section III): the same library with the two CSRs swapped, compared with
+    the oracle on the dual element by element."""
+    dual = hg.random_small(seed, m, n, kmax, expo).dual()
+    outs = run_gpu(ctx, dual, s_list)
+    for lg in outs:
+        assert_matches_oracle(dual, lg, lg.s, f"dual seed {seed}")
+        assert_well_formed(dual, lg, lg.s)
+    assert outs[0].two_paths == oracle.two_paths(dual, s_list[0])
+
+
+def test_dual_of_power_law_shape_full(ctx):
+    """The dual of a power-law-shaped hypergraph (|e| ~ Zipf(2.1), vertex
+    weight ~ rank^-0.8, the power-law workload's laws at m = 6,000): its
+    hyperedges are the vertex lists, so a few are very large."""
+    dual = hg.power_law(seed=11340, n=3000, m=6000).dual()
+    outs = run_gpu(ctx, dual, [1, 2, 4])
+    for lg in outs:
+        assert_matches_oracle(dual, lg, lg.s, "power-law dual")
+    assert outs[0].two_paths == oracle.two_paths(dual, 1)
+
+
 def test_tiny_uniform_full(ctx):
     inc = hg.tiny_uniform()
     for s in (1, 2, 3, 4):
@@ -240,10 +268,14 @@ def test_power_law_config_ensemble_sampled(ctx):
     g = ctx.register_incidence(inc)
     outs = ctx.line_graph(g, [1, 2, 4, 8])
     assert outs[0].two_paths == oracle.two_paths(inc, 1)
-    sizes = np.diff(inc.he_ptr)
-    # heaviest rows by 2-path work plus the ends and a random sample
+    # heaviest rows by 2-path work (at s = 1 nothing is pruned: the entry
+    # of row i in vertex v's list has as many 2-paths as entries after it),
+    # the largest hyperedges, the ends and a random sample
     rng = np.random.default_rng(1)
-    big = np.argsort(-sizes)[:24]
+    deg = np.diff(inc.v_ptr)
+    after = np.repeat(inc.v_ptr[1:], deg) - np.arange(inc.nnz) - 1
+    work = np.bincount(inc.v_idx, weights=after, minlength=inc.m)
+    big = np.concatenate([np.argsort(-work, kind="stable")[:24], np.argsort(-np.diff(inc.he_ptr))[:8]])
     rows = np.unique(np.concatenate([big, [0, 1, inc.m - 2, inc.m - 1], rng.integers(0, inc.m, 40)]))
     for lg in outs:
         # row-wise parity on the sampled rows

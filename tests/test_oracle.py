@@ -79,6 +79,33 @@ def test_weights_equal_HtH_offdiagonal(seed, m, n, kmax, expo):
         assert edges_of(lg) == exp, f"s={s}"
 
 
+@pytest.mark.parametrize("seed,m,n,kmax,expo", [
+    (11, 300, 120, 12, None),
+    (12, 400, 90, 25, 0.8),
+    (13, 250, 300, 30, 1.5),
+])
+def test_dual_is_the_s_clique_graph_of_HHt(seed, m, n, kmax, expo):
+    """The s-line graph of the dual H* is the s-clique graph over vertices
+    (Section III, relation to the clique-expansion graph): two vertices are
+    joined when they share at least s hyperedges, with weight (H H^T)[u, v];
+    the diagonal of H H^T is the vertex degree D_V, and E_s of H* keeps the
+    vertices of degree >= s. Checked against scipy's H H^T - D_V."""
+    inc = hg.random_small(seed, m, n, kmax, expo)
+    rows = np.repeat(np.arange(inc.m), np.diff(inc.he_ptr))
+    H = sp.csr_matrix((np.ones(inc.nnz, np.int64), (inc.he_idx.astype(np.int64), rows)),
+                      shape=(inc.n, inc.m))
+    A = (H @ H.T).toarray()
+    deg = np.diff(inc.v_ptr)
+    assert np.array_equal(np.diag(A), deg)  # D_V
+    A = A - np.diag(deg)  # the clique expansion's weighted adjacency
+    for s in (1, 2, 3, 4):
+        lg = oracle.line_graph(inc.dual(), s)
+        iu, ju = np.triu_indices(inc.n, k=1)
+        keep = (A[iu, ju] >= s) & (deg[iu] >= s) & (deg[ju] >= s)
+        exp = list(zip(iu[keep].tolist(), ju[keep].tolist(), A[iu, ju][keep].tolist()))
+        assert edges_of(lg) == exp, f"s={s}"
+
+
 # --- closed form for the number of 2-paths --------------------------------
 
 @pytest.mark.parametrize("seed,expo", [(5, None), (6, 0.8), (7, 1.5)])
