@@ -312,6 +312,25 @@ slg_status slg_components(slg_context *ctx, slg_graph *g, int32_t s, const int32
                           int64_t num_edges, int32_t *labels, int64_t *num_components, void *stream);
 
 /*
+ * slg_components without any device allocation, for callers that cannot
+ * allocate: code under HIP-graph capture, tight serving loops, harnesses
+ * that forbid allocation. Same arguments, outputs and errors as
+ * slg_components, and the same kernels; the union-find parents and the
+ * two counters live in a fixed array of the library (one per GPU, made
+ * when the library is loaded on it and held until the process ends) that
+ * takes graphs of at most 2^24 hyperedges (64 MiB + 16 B per GPU). A graph
+ * with more hyperedges fails with SLG_ERR_INVALID_ARG and nothing is
+ * launched. Every call on one GPU uses that GPU's single array: calls that
+ * overlap on one GPU (from several streams or host threads) race and give
+ * wrong labels; callers serialise them. The call clears what must start at
+ * zero itself. Errors as slg_components, plus DEVICE when the array's
+ * address could not be looked up at context creation.
+ */
+slg_status slg_components_noalloc(slg_context *ctx, slg_graph *g, int32_t s, const int32_t *row,
+                                  const int32_t *col, int64_t num_edges, int32_t *labels, int64_t *num_components,
+                                  void *stream);
+
+/*
  * ID squeezing (Stage 4 of the paper's framework, Section IV): hyperedges
  * that are an end of at least one edge keep their order and are renumbered
  * 0, 1, ...: new_id DEVICE int32[m] gets the new id or -1; *num_kept (may

@@ -126,6 +126,7 @@ def lib() -> ctypes.CDLL:
         "slg_result_csr": (_i32, [_p, _i32, ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
         "slg_result_free": (_i32, [_p]),
         "slg_components": (_i32, [_p, _p, _i32, _p, _p, _i64, _p, ctypes.POINTER(_i64), _p]),
+        "slg_components_noalloc": (_i32, [_p, _p, _i32, _p, _p, _i64, _p, ctypes.POINTER(_i64), _p]),
         "slg_squeeze": (_i32, [_p, _i64, _p, _p, _i64, _i32, _p, ctypes.POINTER(_i64), _p]),
         "slg_symmetrize": (_i32, [_p, _i64, _p, _p, _p, _p, _i64, _p, _p, _p, _p]),
         "slg_relabel_order": (_i32, [_p, _p, _i32, _p, _p]),
@@ -481,6 +482,21 @@ class Context:
         self._check(lib().slg_components(self.handle, g.handle, int(s), row.data_ptr(), lg.col.data_ptr(),
                                          int(lg.num_edges), labels.data_ptr(), ctypes.byref(nc),
                                          _stream_handle(stream)))
+        return labels, int(nc.value)
+
+    def components_noalloc(self, g: Graph, s: int, lg: "LineGraph", labels=None, stream=None):
+        """components() through slg_components_noalloc: no device allocation
+        inside the library (its fixed per-GPU array, at most 2^24
+        hyperedges). `labels` (int32[m] on the device) may be given so that
+        the call allocates nothing at all."""
+        import torch
+        if labels is None:
+            labels = torch.empty(max(g.m, 1), dtype=torch.int32, device=f"cuda:{self.device}")[: g.m]
+        nc = _i64()
+        row = _need_rows(lg)
+        self._check(lib().slg_components_noalloc(self.handle, g.handle, int(s), row.data_ptr(), lg.col.data_ptr(),
+                                                 int(lg.num_edges), labels.data_ptr(), ctypes.byref(nc),
+                                                 _stream_handle(stream)))
         return labels, int(nc.value)
 
     def squeeze(self, m: int, lg: "LineGraph", remap: bool = False, stream=None):

@@ -11,8 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libslg.so")
 SOURCES = [os.path.join(CSRC, name) for name in
-           ("slg_kernels.hip", "slg_sort.hip", "slg_prep.hip", "slg_api.cpp", "slg_server.cpp",
-            "slg_arena.cpp")]
+           ("slg_kernels.hip", "slg_sort.hip", "slg_prep.hip", "slg_noalloc.hip", "slg_api.cpp",
+            "slg_server.cpp", "slg_arena.cpp")]
 ARCH = "gfx950"
 
 

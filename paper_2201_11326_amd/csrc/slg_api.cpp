@@ -58,6 +58,8 @@ struct slg_context {
     hipStream_t aux = nullptr;
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     std::shared_ptr<slg::Arena> arena;  // scratch and library-owned outputs
+    void *noalloc = nullptr;            // this device's fixed scratch array (slg_components_noalloc)
+    hipError_t noalloc_err = hipSuccess;
 };
 
 struct slg_graph {
@@ -299,6 +301,10 @@ slg_status create_context(int device, uint64_t mem_budget_bytes, const slg_alloc
         return SLG_ERR_DEVICE;
     }
     ctx->heavy_resident = heavy_resident(device);
+    // the fixed scratch of the no-allocation entry point: its address on
+    // this device, looked up once per device with the device current
+    ctx->noalloc_err = noalloc_scratch(device, &ctx->noalloc);
+    if (ctx->noalloc_err != hipSuccess) (void)hipGetLastError();
     ctx->aux_allowed = second_stream;
     uint64_t cache = mem_budget_bytes;
     if (!cache) {
@@ -1430,6 +1436,38 @@ slg_status slg_components(slg_context *ctx, slg_graph *g, int32_t s, const int32
     SLG_HIP(ctx, hipMemcpyAsync(ctx->pinned, dev, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     SLG_HIP(ctx, hipStreamSynchronize(st));
     sc.release();
+    const int64_t err = ctx->pinned[1];
+    if (err & 4) return fail(ctx, SLG_ERR_INVALID_ARG, "an edge names a hyperedge id outside [0, m)");
+    if (err & 2) return fail(ctx, SLG_ERR_INVALID_ARG, "an edge joins a hyperedge with fewer than s vertices");
+    if (err & 1) return fail(ctx, SLG_ERR_DEVICE, "internal error: a union step did not settle");
+    if (num_components) *num_components = ctx->pinned[0];
+    return SLG_OK;
+}
+
+slg_status slg_components_noalloc(slg_context *ctx, slg_graph *g, int32_t s, const int32_t *row,
+                                  const int32_t *col, int64_t num_edges, int32_t *labels, int64_t *num_components,
+                                  void *stream) {
+    if (!ctx || !g || !labels || s < 1 || num_edges < 0 || (num_edges > 0 && (!row || !col)))
+        return fail(ctx, SLG_ERR_INVALID_ARG, "bad components arguments");
+    const int64_t m = g->inc.num_hyperedges;
+    if (m > kNoAllocRows)
+        return fail(ctx, SLG_ERR_INVALID_ARG,
+                    "m = %lld exceeds the %lld hyperedges the fixed scratch holds (use slg_components)",
+                    (long long)m, (long long)kNoAllocRows);
+    if (!ctx->noalloc)
+        return fail(ctx, SLG_ERR_DEVICE, "fixed scratch unavailable: %s", hipGetErrorString(ctx->noalloc_err));
+    SLG_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // the same kernels as slg_components, on the device's fixed array: the
+    // two counters are cleared here and every parent is written by cc_init
+    int64_t *dev = static_cast<int64_t *>(ctx->noalloc);  // [0] roots, [1] error flags
+    int32_t *parent = reinterpret_cast<int32_t *>(dev + 2);
+    SLG_HIP(ctx, launch_fill_i64(dev, 2, 0, st));
+    SLG_HIP(ctx, launch_cc_init(g->inc.he_ptr, m, s, parent, st));
+    SLG_HIP(ctx, launch_cc_hook(row, col, num_edges, m, parent, reinterpret_cast<int *>(dev + 1), st));
+    SLG_HIP(ctx, launch_cc_finish(m, parent, labels, reinterpret_cast<unsigned long long *>(dev), st));
+    SLG_HIP(ctx, hipMemcpyAsync(ctx->pinned, dev, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SLG_HIP(ctx, hipStreamSynchronize(st));
     const int64_t err = ctx->pinned[1];
     if (err & 4) return fail(ctx, SLG_ERR_INVALID_ARG, "an edge names a hyperedge id outside [0, m)");
     if (err & 2) return fail(ctx, SLG_ERR_INVALID_ARG, "an edge joins a hyperedge with fewer than s vertices");

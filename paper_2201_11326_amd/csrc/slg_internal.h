@@ -258,6 +258,12 @@ hipError_t launch_toplex_flags(const int32_t *row, const int32_t *col, const int
 // out[pre[i]] = i for every i with keep[i].
 hipError_t launch_compact_ids(const int32_t *keep, const int64_t *pre, int64_t m, int32_t *out, hipStream_t st);
 
+// Fixed device scratch of slg_components_noalloc: the largest m it takes,
+// and the address of this device's copy of the array (looked up on first
+// use with `device` current; then cached).
+constexpr int64_t kNoAllocRows = int64_t(1) << 24;
+hipError_t noalloc_scratch(int device, void **out);
+
 // Validation kernels (SLG_VALIDATE).
 hipError_t launch_validate_ptr(const int64_t *ptr, int64_t rows, int64_t nnz, int *err,
                                hipStream_t st);
