@@ -1,21 +1,24 @@
 #!/usr/bin/env python3
-"""Benchmark: s-line graph ensemble of the power-law hypergraph on one GPU.
+"""Benchmark: s-line graphs of non-uniform hypergraphs on one GPU.
 
-Workload: n = 1,000,000 vertices, m = 500,000 hyperedges, sizes Zipf(2.1)
-on [2, 5000], vertices drawn with weight ~ rank^-0.8 (seeded, synthetic),
-thresholds S = {1, 2, 4, 8} computed in one ensemble pass. One step is the
-whole path on inputs already resident in HBM: pruning, 2-path work
-estimate, counting pass, prefix sums, output allocation and the emit pass
-that writes every L_s as COO + CSR.
+Default workload (the largest one): the large skewed hypergraph at full
+size, n = 5,000,000 vertices, m = 10,000,000 hyperedges, sizes
+min(rint(LogNormal(1.5, 1)), 10,000), vertices drawn with weight ~
+rank^-1.5 (seeded, synthetic), thresholds S = {8, 16} in one ensemble
+pass. Its output (about 10^12 edges) is larger than device memory, so the
+path is the streamed one: one step is one row range, of warmup + steps
+ranges of equal 2-path work that together cover every row once, taken
+through the whole path (pruning, work estimate, row-block plans, counting,
+emit in chunks handed to a consumer) on inputs already resident in HBM.
 
 Prints ONE JSON line. `value` is 2-paths traversed per second over the
 timed steps; edges/s and the per-step latency percentiles ride along. The
-`roofline` entry is for the dominant kernel, the slower of the heavy
-tier's two kernels (its counting pass or its emit pass; the other rides
-along), timed with HIP events on its own stream inside the library, with
-the algorithmic bytes of the work it does (4 B per 2-path read, 12 B per
-edge written); `cpu_baseline` times the brute-force CPU oracle on a
-bounded row sample.
+`roofline` entry is for the dominant kernel, timed with HIP events on its
+own stream inside the library, against the algorithmic bytes of the work it
+does (4 B per 2-path read; 12 B per edge written for an emit pass);
+`cpu_baseline` times the brute-force CPU oracle on a bounded row sample.
+Other workloads (--workload): power_law (the whole output in memory),
+dual, batched, served, components, preprocess.
 """
 from __future__ import annotations
 
@@ -139,29 +142,31 @@ def oracle_threads() -> int:
     return max(1, min(usable, int(os.environ.get("OMP_NUM_THREADS", "16") or 16)))
 
 
-def cpu_baseline(inc, seconds: float, seed: int = 7):
+def cpu_baseline(inc, seconds: float, s_set=None, size_min=None, seed: int = 7):
     """Oracle on a random row sample sized to about `seconds` of CPU time.
     Rate = 2-paths of the sampled rows (the work the two-hop traversal does
-    for them) / oracle wall time for every s of the ensemble."""
+    for them at the smallest s) / oracle wall time for every s of the set."""
     import numpy as np
 
     import oracle
+    s_set = list(S_SET if s_set is None else s_set)
+    size_min = s_set[0] if size_min is None else size_min
     threads = oracle_threads()
     rng = np.random.default_rng(seed)
     probe = np.sort(rng.choice(inc.m, size=4 * threads, replace=False))
     t0 = time.perf_counter()
-    for s in S_SET:
-        oracle.line_graph_rows(inc, s, probe, threads=threads)
+    for s in s_set:
+        oracle.line_graph_rows(inc, s, probe, size_min=size_min, threads=threads)
     per_row = (time.perf_counter() - t0) / probe.size
     nrows = int(max(threads, min(inc.m, seconds / max(per_row, 1e-9))))
     rows = np.sort(rng.choice(inc.m, size=nrows, replace=False))
     t0 = time.perf_counter()
-    for s in S_SET:
-        oracle.line_graph_rows(inc, s, rows, threads=threads)
+    for s in s_set:
+        oracle.line_graph_rows(inc, s, rows, size_min=size_min, threads=threads)
     dt = time.perf_counter() - t0
-    work = int(oracle.row_two_paths(inc, S_SET[0], rows, threads=threads).sum())
+    work = int(oracle.row_two_paths(inc, size_min, rows, threads=threads).sum())
     return {"value": work / dt, "unit": "2-paths/s", "cores": threads, "kind": "oracle",
-            "sample": f"{nrows} random rows (seed {seed}) of the same hypergraph, all of S={S_SET}, "
+            "sample": f"{nrows} random rows (seed {seed}) of the same hypergraph, all of S={s_set}, "
                       f"{work} 2-paths, {dt:.2f} s wall", "host": host_cpu(),
             "paper": PAPER_CPU_CONTEXT}
 
@@ -601,66 +606,111 @@ def bench_preprocess(args) -> int:
 
 
 def bench_large_skewed(args) -> int:
-    """The chunked streaming form (slg_line_graph_stream) on a tenth-size
-    instance of the large-skewed generator (n = 5e5, m = 1e6, the full-size
-    shape's |e| and vertex-weight laws), ensemble S = {8, 16}, output handed
-    over in chunks of at most 2 GiB to a callback that takes each chunk's
-    on-device digest (count, sum of w, SplitMix64 hash sum).
-    value = 2-paths of E_8 per second of the whole streamed call."""
+    """The large skewed workload at full size: n = 5e6 vertices, m = 1e7
+    hyperedges, |e| = min(rint(LogNormal(1.5, 1)), 1e4), vertex weight ~
+    rank^-1.5, ensemble S = {8, 16}. Its output (about 1e12 edges) exceeds
+    device memory, so it is streamed (slg_line_graph_stream_rows): one step
+    is one of warmup + steps row ranges of equal 2-path work at s = 8, which
+    together cover every row once, taken through the whole path (pruning,
+    work estimate, row-block plans, counting, emit in chunks of <= 2 GiB).
+    The consumer counts each chunk's edges (--digest: digests each chunk on
+    the device). value = 2-paths of the timed ranges / their wall time."""
+    import numpy as np
     import torch
 
     import hypergen as hg
     import paper_2201_11326_amd as slg
 
     S = [8, 16]
+    note = lambda msg: print(f"[bench large_skewed] {msg}", file=sys.stderr, flush=True)
     t_gen = time.perf_counter()
-    inc = hg.large_skewed(n=500_000, m=1_000_000)
+    inc = hg.large_skewed()
     t_gen = time.perf_counter() - t_gen
+    note(f"generated in {t_gen:.1f} s: nnz {inc.nnz}")
     ctx = slg.Context(0)
     g = ctx.register_incidence(inc)
-    p = ctx.plan(g, S)  # untimed: sizes for the checks and the rate
-    two_paths, want, stats = p.two_paths, p.num_edges(), p.stats()
-    p.destroy()
+    prefix = ctx.work_prefix(g, S[0])  # untimed: the ranges' cuts
+    W = int(prefix[-1])
+    B = args.steps + args.warmup
+    cuts = [0] + [int(np.searchsorted(prefix, W * b // B, side="left")) for b in range(1, B)] + [inc.m]
     chunk = 2 << 30
-    got = {}
+    edges = [0] * len(S)
+    chunks = [0]
 
     def on_chunk(k, s, r0, r1, e0, row_ptr, row, col, w):
-        d = ctx.digest(row, col, w)
-        acc = got.setdefault(s, [0, 0, 0, 0])
-        acc[0] += d[0]
-        acc[1] += 1
-        acc[2] += d[1]
-        acc[3] = (acc[3] + d[2]) % (1 << 64)
+        if args.digest:
+            ctx.digest(row, col, w)
+        edges[k] += int(col.numel())
+        chunks[0] += 1
         return False
 
-    for _ in range(args.warmup):
-        got.clear()
-        ctx.line_graph_stream(g, S, chunk, on_chunk)
+    def step(b):
+        ctx.line_graph_stream(g, S, chunk, on_chunk, rows=(cuts[b], cuts[b + 1]))
+        torch.cuda.synchronize()
+
+    for b in range(args.warmup):
+        step(b)
+        note(f"warmup range {b + 1}/{args.warmup} done")
+    edges[:] = [0] * len(S)
+    chunks[0] = 0
+    ctx.reset_timing()
+    ctx.set_timing(True)
+    lat = []
     torch.cuda.synchronize()
-    times = []
-    for _ in range(args.steps):
-        got.clear()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.line_graph_stream(g, S, chunk, on_chunk)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        for k, s in enumerate(S):  # every edge came through the callback
-            assert got[s][0] == want[k], (s, got[s], want[k])
-    elapsed = sum(times)
+    t0 = time.perf_counter()
+    for b in range(args.warmup, B):
+        ts = time.perf_counter()
+        step(b)
+        lat.append(time.perf_counter() - ts)
+        note(f"range {b + 1 - args.warmup}/{args.steps}: {1e3 * lat[-1]:.0f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.set_timing(False)
+    stages = ctx.timing()
+    work = ctx.work()
+    timed_two_paths = int(prefix[cuts[B]] - prefix[cuts[args.warmup]])
+    assert work["two_paths"] == timed_two_paths, (work, timed_two_paths)
+    assert sum(edges) == work["edges"], (edges, work)
+    ms_per_step = 1e3 * elapsed / args.steps
+    # the dominant kernel: the dense tier's counting pass, 4 B read per
+    # 2-path of its slots (algorithmic bytes, the scope table's unit)
+    launches, count_ms = stages.get("count_dense", (0, 0.0))
+    dense_bytes = 4 * work["dense_two_paths"]
+    achieved = dense_bytes / (count_ms / 1e3) / 1e9 if count_ms > 0 else None
+    emit_launches, emit_ms = stages.get("emit_dense", (0, 0.0))
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": measured_traffic("dense_kernel<false>"),
+                "kernel": "dense_kernel<false> (count_dense)", "launches": launches,
+                "avg_launch_ms": count_ms / max(launches, 1),
+                "algorithmic_bytes_per_launch": dense_bytes / max(launches, 1),
+                "overhead_bytes_per_launch": {"dense_store_written": 4 * work["dense_stored"] / max(launches, 1)},
+                "sq_counters": measured_sq("dense_kernel<false>"),
+                "emit": {"kernel": "heavy_store_emit_kernel<4> on dense slots (emit_dense)",
+                         "launches": emit_launches, "ms": emit_ms,
+                         "algorithmic_bytes": 12 * work["dense_edges"],
+                         "achieved_gbs": 12 * work["dense_edges"] / (emit_ms / 1e3) / 1e9 if emit_ms > 0 else None}}
+    edges_total = sum(edges)
+    nrows_timed = cuts[B] - cuts[args.warmup]
+    step_bytes = (4 * timed_two_paths + 12 * edges_total
+                  + args.steps * (8 * inc.nnz + 8 * (inc.m + inc.n)) + 8 * (nrows_timed + args.steps) * len(S))
+    cpu = None if args.no_cpu_baseline else cpu_baseline(inc, args.cpu_seconds, S, size_min=S[0])
     line = {
-        "metric": METRIC, "value": two_paths * args.steps / elapsed, "unit": "2-paths/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": "large-skewed hypergraph at a tenth of full size: n=5e5 m=1e6 "
-                               "|e|=min(rint(LogNormal(1.5,1)),1e4) vertex weight~rank^-1.5, ensemble S={8,16}, "
-                               "streamed in chunks of <= 2 GiB, each digested on the device", "n": inc.n, "m": inc.m, "nnz": inc.nnz, "s": S,
-                   "seed": hg.BASE_SEED + 3, "parallelism": "single GPU"},
-        "two_paths_per_step": two_paths, "edges_per_step": want,
-        "edges_per_s": sum(want) * args.steps / elapsed,
-        "chunks_per_step": {str(s): got[s][1] for s in S}, "p50_ms": 1e3 * percentile(times, 0.5),
-        "digest": {str(s): {"edges": got[s][0], "sum_w": got[s][2], "hash": f"{got[s][3]:016x}"} for s in S},
-        "plan": stats, "generate_s": t_gen, "roofline": None, "cpu_baseline": None,
+        "metric": METRIC, "value": timed_two_paths / elapsed, "unit": "2-paths/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "large skewed hypergraph n=5e6 m=1e7 |e|=min(rint(LogNormal(1.5,1)),1e4) "
+                               "vertex weight~rank^-1.5, ensemble S={8,16}, streamed in chunks of <= 2 GiB; "
+                               f"one step = one of {B} row ranges of equal 2-path work (all of them: every row once)",
+                   "n": inc.n, "m": inc.m, "nnz": inc.nnz, "s": S, "seed": hg.BASE_SEED + 3,
+                   "ranges": B, "consumer": "on-device digest per chunk" if args.digest else "edge count per chunk",
+                   "parallelism": "single GPU"},
+        "two_paths_per_step": timed_two_paths / args.steps, "two_paths_whole_graph": W,
+        "edges_timed": edges, "edges_per_s": edges_total / elapsed,
+        "p50_ms": 1e3 * percentile(lat, 0.5), "p99_ms": 1e3 * percentile(lat, 0.99),
+        "step_roofline_frac": (step_bytes / elapsed) / (PEAK_HBM_GBS * 1e9),
+        "stage_ms_per_step": {k: v[1] / args.steps for k, v in stages.items()},
+        "work_timed": work, "chunks_timed": chunks[0],
+        "roofline": roofline, "cpu_baseline": cpu, "generate_s": t_gen,
     }
     print(json.dumps(line), flush=True)
     g.release()
@@ -675,14 +725,17 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("power_law", "batched", "served", "components", "preprocess",
-                                           "large_skewed"),
-                    default="power_law",
-                    help="power_law: the single large hypergraph (default); batched: 256 small "
+    ap.add_argument("--workload", choices=("large_skewed", "power_law", "dual", "batched", "served", "components",
+                                           "preprocess"),
+                    default="large_skewed",
+                    help="large_skewed (default): the largest workload, n=5e6 m=1e7, S={8,16}, streamed in "
+                         "row ranges of equal work; power_law: n=1e6 m=5e5, S={1,2,4,8}, output in memory; "
+                         "dual: the s-clique graph of the power-law hypergraph; batched: 256 small "
                          "hypergraphs, each with its own s, as one disjoint-union batch; served: a request "
                          "loop; components: components, squeezing and symmetric CSR of the power-law L_s; "
-                         "preprocess: relabel-by-degree and toplexes of the power-law hypergraph; "
-                         "large_skewed: the chunked streaming form on a tenth-size large-skewed hypergraph")
+                         "preprocess: relabel-by-degree and toplexes of the power-law hypergraph")
+    ap.add_argument("--digest", action="store_true",
+                    help="large_skewed: digest every streamed chunk on the device (default: count its edges)")
     ap.add_argument("--no-tune", action="store_true", help="batched: library-default plan shape")
     ap.add_argument("--requests", type=int, default=4000, help="served: number of requests")
     ap.add_argument("--rate", type=float, default=2000.0, help="served: Poisson arrivals per second")
@@ -713,8 +766,28 @@ def main() -> int:
         return bench_preprocess(args)
     if args.workload == "large_skewed":
         return bench_large_skewed(args)
+    if args.workload == "dual":
+        return bench_power_law(args, dual=True)
+    return bench_power_law(args)
+
+
+def bench_power_law(args, dual: bool = False) -> int:
+    """The power-law workload (n = 1e6, m = 5e5, |e| ~ Zipf(2.1) on [2, 5000],
+    vertex weight ~ rank^-0.8), ensemble S = {1, 2, 4, 8}, the whole output
+    in device memory: one step is the whole path (pruning, 2-path work
+    estimate, counting pass, prefix sums, output allocation, the emit pass
+    writing every L_s as COO + CSR). With dual: the s-clique graph, i.e. the
+    same path on the dual hypergraph (the CSRs swapped: vertices become
+    hyperedges, Section II-A)."""
+    import torch
+
+    import hypergen as hg
+    import paper_2201_11326_amd as slg
+
     t_gen = time.perf_counter()
     inc = hg.power_law()
+    if dual:
+        inc = inc.dual()
     t_gen = time.perf_counter() - t_gen
     ctx = slg.Context(0)
     g = ctx.register_incidence(inc)
@@ -793,7 +866,8 @@ def main() -> int:
         "metric": METRIC, "value": value, "unit": "2-paths/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": "power-law hypergraph n=1e6 m=5e5 |e|~Zipf(2.1)[2,5000] "
+        "config": {"workload": ("s-clique graph (s-line graph of the dual) of " if dual else "")
+                               + "power-law hypergraph n=1e6 m=5e5 |e|~Zipf(2.1)[2,5000] "
                                "vertex weight~rank^-0.8, ensemble S={1,2,4,8}",
                    "n": inc.n, "m": inc.m, "nnz": inc.nnz, "s": S_SET, "seed": hg.BASE_SEED + 2,
                    "parallelism": "single GPU"},
@@ -808,6 +882,8 @@ def main() -> int:
     g.release()
     ctx.close()
     return 0
+
+
 
 
 if __name__ == "__main__":

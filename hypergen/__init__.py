@@ -223,11 +223,12 @@ def batched_family(seed: int = BASE_SEED + 4, count: int = 256, m_lo: int = 1000
 
 def served_pool(seed: int = BASE_SEED + 5, skewed: int = 64, power: int = 4,
                 skewed_m: Tuple[int, int] = (1_000, 10_000),
-                power_m: Tuple[int, int] = (10_000, 80_000)) -> List[Incidence]:
+                power_n: int = 1_000_000, power_m: int = 500_000) -> List[Incidence]:
     """Device-resident pool of the served workload: `skewed` graphs from the
-    large-skewed generator (n = m/2, m log-uniform in skewed_m) followed by
-    `power` graphs from the power-law generator (n = 2m, m log-spaced over
-    power_m)."""
+    large-skewed generator (n = m/2, m log-uniform in skewed_m: whole-graph
+    queries on the full-size shape are out of reach, each would emit about
+    10^13 edges) followed by `power` graphs from the power-law generator at
+    its full size (n = power_n, m = power_m), each from its own seed."""
     ss = np.random.SeedSequence(seed)
     kids = ss.spawn(skewed + power)
     out = []
@@ -237,9 +238,7 @@ def served_pool(seed: int = BASE_SEED + 5, skewed: int = 64, power: int = 4,
         out.append(large_skewed(seed=int(rng.integers(1 << 62)), n=max(m // 2, 1), m=m))
     for t in range(power):
         rng = np.random.default_rng(kids[skewed + t])
-        frac = t / max(power - 1, 1)
-        m = int(round(math.exp(math.log(power_m[0]) + frac * (math.log(power_m[1]) - math.log(power_m[0])))))
-        out.append(power_law(seed=int(rng.integers(1 << 62)), n=2 * m, m=m))
+        out.append(power_law(seed=int(rng.integers(1 << 62)), n=power_n, m=power_m))
     return out
 
 

@@ -184,7 +184,11 @@ slg_status slg_plan_emit(slg_plan *p, int64_t *const *row_ptr, int32_t *const *r
  *   [12] entries of the heavy boundary table;
  *   [13] edges written by heavy slots, summed over all thresholds;
  *   [14] (partner, overlap) entries the heavy count store keeps (0 when
- *        the plan keeps none; see slg_context_set_count_store).
+ *        the plan keeps none; see slg_context_set_count_store);
+ *   [15] dense slots; [16] 2-paths in dense slots; [17] edges written by
+ *        dense slots, summed over all thresholds; [18] survivors the dense
+ *        store keeps; [19] 1 when some dense slots found the store full
+ *        (see slg_context_set_dense).
  * Returns the number of entries written in *count (may be NULL).
  */
 slg_status slg_plan_stats(const slg_plan *p, int64_t *out, int32_t cap, int32_t *count);
@@ -198,8 +202,8 @@ slg_status slg_plan_stats(const slg_plan *p, int64_t *out, int32_t cap, int32_t 
  * array) with one record per stage that ran: its name (static storage),
  * the number of timed launches and their summed duration in milliseconds.
  * Stages: prune, row_plan, plan_scans, slots, bounds, count_light,
- * count_heavy, count_heavy_wide, count_scans, emit_light, emit_heavy,
- * emit_heavy_wide, row_ptr. Timing adds two event records per launch.
+ * count_heavy, count_heavy_wide, count_dense, count_scans, emit_light,
+ * emit_heavy, emit_heavy_wide, emit_dense, row_ptr. Timing adds two event records per launch.
  */
 typedef struct {
     const char *name;
@@ -208,22 +212,47 @@ typedef struct {
 } slg_stage_time;
 slg_status slg_context_set_timing(slg_context *ctx, int enable);
 slg_status slg_context_get_timing(slg_context *ctx, slg_stage_time *out, int32_t cap, int32_t *count);
+/* Clears the stage times and the work counters below. */
 slg_status slg_context_reset_timing(slg_context *ctx);
+/*
+ * Work done by the counting passes of ctx since the last reset (whole
+ * plans and the row blocks of streamed calls), for measurement: fills up to
+ * `cap` entries of out[] (host array) with, in order: [0] plans and row
+ * blocks counted; [1] 2-paths; [2] 2-paths of heavy slots; [3] 2-paths of
+ * dense slots; [4] edges, summed over the thresholds; [5] edges of heavy
+ * slots; [6] edges of dense slots; [7] dense slots; [8] survivors the
+ * dense store kept; [9] blocks whose dense store was full (some slots
+ * walked their 2-paths again). *count (may be NULL) gets the number
+ * written.
+ */
+slg_status slg_context_get_work(const slg_context *ctx, int64_t *out, int32_t cap, int32_t *count);
 
 /* Free a plan's device scratch (ordered on the stream it was made on). */
 slg_status slg_plan_destroy(slg_plan *p);
 
 /*
- * Chunked form for outputs larger than device memory (row-range streaming).
- * Plans once, then emits rows [0, m) in consecutive row ranges whose
- * output fits chunk_bytes (all thresholds; 12 bytes per edge plus 8 per
- * CSR offset). For every chunk and every threshold index k the callback
- * receives, after the chunk's device work has completed:
- *   rows [row_begin, row_end) of L_{s[k]}; its edges are global edges
- *   [edge_begin, edge_begin + num_edges) of the sorted edge list;
+ * Chunked form for outputs larger than device memory (row-range streaming,
+ * the union of per-row edge lists of Algorithms 2 and 3 handed over a part
+ * at a time). The per-row work estimate runs once for the whole graph;
+ * the rest of the plan (slot tables, boundary table, the counting pass and
+ * its stores) is made one block of rows at a time, each block taking rows
+ * while its scratch fits the count-store limit, so that the scratch is
+ * bounded by the block and not by the graph. Each block's rows are emitted
+ * in consecutive row ranges (chunks) whose output fits chunk_bytes (all
+ * thresholds; 12 bytes per edge plus 8 per CSR offset). For every chunk and
+ * every threshold index k the callback receives, after the chunk's device
+ * work has completed:
+ *   rows [row_begin, row_end) of L_{s[k]}; its edges are edges
+ *   [edge_begin, edge_begin + num_edges) of the call's sorted edge list;
  *   row_ptr: DEVICE int64[row_end - row_begin + 1], relative (row_ptr[0]=0);
- *   row/col/w: DEVICE int32[num_edges] (COO i, j, overlap).
- * The pointers are valid only during the callback (buffers are reused).
+ *   row/col/w: DEVICE int32[num_edges] (COO i, j, overlap);
+ *   stream: the consumer stream. The buffers stay valid for work the
+ *   callback enqueues on it; the library writes them again only after that
+ *   work. Meanwhile it emits the next chunk on the call's stream, so device
+ *   work of the callback on the consumer stream overlaps the next emit.
+ *   The consumer stream is the context's second stream when it has one,
+ *   else the call's stream.
+ * The pointers must not be used after that work (buffers are reused).
  * A nonzero return stops the stream: SLG_ERR_CANCELLED.
  * Errors: as slg_plan_create; OUT_OF_MEMORY when one row alone needs more
  * than chunk_bytes; INVALID_ARG for chunk_bytes <= 0 or a NULL callback.
@@ -233,6 +262,30 @@ typedef int (*slg_chunk_fn)(void *user, int32_t k, int32_t s, int64_t row_begin,
                             const int32_t *row, const int32_t *col, const int32_t *w, void *stream);
 slg_status slg_line_graph_stream(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num_s,
                                  int64_t chunk_bytes, slg_chunk_fn fn, void *user, void *stream);
+
+/*
+ * slg_line_graph_stream restricted to the rows [row_begin, row_end) (0 <=
+ * row_begin <= row_end <= m): their edges (i, j) with i in the range and
+ * every j > i, so that disjoint row ranges together give the whole L_s
+ * (the way the path shards: rows split into ranges of equal 2-path work,
+ * Section III-E's cost model, with no exchange between ranges). edge_begin
+ * counts from the first edge of row_begin. Errors as slg_line_graph_stream,
+ * plus INVALID_ARG for a range outside [0, m].
+ */
+slg_status slg_line_graph_stream_rows(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num_s,
+                                      int64_t row_begin, int64_t row_end, int64_t chunk_bytes, slg_chunk_fn fn,
+                                      void *user, void *stream);
+
+/*
+ * The per-hyperedge work estimate of Algorithm 2 at s_min as a prefix:
+ * prefix (HOST int64[m+1]) gets, for every i, the number of 2-paths
+ * (e_r, v, e_j), r < i, r < j, both of E_{s_min}, that the traversal
+ * takes from the rows before i (prefix[m] = all of them). Row ranges of
+ * equal work follow from it (slg_line_graph_stream_rows). Ordered on
+ * `stream`; returns after the copy. Errors: INVALID_ARG (null, s_min < 1),
+ * OUT_OF_MEMORY, DEVICE.
+ */
+slg_status slg_work_prefix(slg_context *ctx, slg_graph *g, int32_t s_min, int64_t *prefix, void *stream);
 
 /*
  * Batched form: many independent hypergraphs, each with its own threshold
@@ -271,6 +324,19 @@ slg_status slg_batch_destroy(slg_batch *b);
  * afterwards (and to a server's slots when set before slg_server_create).
  */
 slg_status slg_context_set_count_store(slg_context *ctx, int64_t max_bytes, int64_t min_two_paths);
+
+/*
+ * Dense tier (an implementation choice, not in the paper): a heavy row whose
+ * candidate partners (the hyperedges of E_{s_min} with ids in (i, j_max])
+ * number at least min_range, and which has at least min_ratio 2-paths per
+ * candidate, counts its overlaps in direct counters over windows of 2^15
+ * consecutive hyperedges of E_{s_min}, and keeps only the partners that
+ * reach s_min for the emit pass (within the count-store limit; slots that
+ * find it full walk their 2-paths again). min_ratio = 0 turns the tier off;
+ * min_range = 0 restores its default. Defaults: 4 and 8192. Results are
+ * identical either way. Applies to plans created afterwards.
+ */
+slg_status slg_context_set_dense(slg_context *ctx, int32_t min_ratio, int32_t min_range);
 
 /*
  * Tuning of the plan shape, used by the autotuner: light_max = largest row

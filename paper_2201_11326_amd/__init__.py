@@ -20,6 +20,7 @@ CPU fallback.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import re
@@ -111,6 +112,9 @@ def lib() -> ctypes.CDLL:
         "slg_plan_stats": (_i32, [_p, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i32)]),
         "slg_line_graph": (_i32, [_p, _p, ctypes.POINTER(_i32), _i32, _p, ctypes.POINTER(_p)]),
         "slg_line_graph_stream": (_i32, [_p, _p, ctypes.POINTER(_i32), _i32, _i64, _CHUNK_FN, _p, _p]),
+        "slg_line_graph_stream_rows": (_i32, [_p, _p, ctypes.POINTER(_i32), _i32, _i64, _i64, _i64, _CHUNK_FN,
+                                              _p, _p]),
+        "slg_work_prefix": (_i32, [_p, _p, _i32, _p, _p]),
         "slg_batch_create": (_i32, [_p, ctypes.POINTER(_p), ctypes.POINTER(_i32), _i32, _p, ctypes.POINTER(_p)]),
         "slg_batch_run": (_i32, [_p, _i32, _p]),
         "slg_batch_info": (_i32, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
@@ -118,9 +122,11 @@ def lib() -> ctypes.CDLL:
                                     ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
         "slg_batch_destroy": (_i32, [_p]),
         "slg_context_set_tuning": (_i32, [_p, _i32, _i64, _i32]),
+        "slg_context_set_dense": (_i32, [_p, _i32, _i32]),
         "slg_context_set_timing": (_i32, [_p, ctypes.c_int]),
         "slg_context_get_timing": (_i32, [_p, ctypes.POINTER(StageTime), _i32, ctypes.POINTER(_i32)]),
         "slg_context_reset_timing": (_i32, [_p]),
+        "slg_context_get_work": (_i32, [_p, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i32)]),
         "slg_result_info": (_i32, [_p, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
         "slg_result_coo": (_i32, [_p, _i32, ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
         "slg_result_csr": (_i32, [_p, _i32, ctypes.POINTER(_p), ctypes.POINTER(_p), ctypes.POINTER(_p)]),
@@ -230,12 +236,13 @@ class Plan:
 
     STAT_NAMES = ("slots", "tiny8", "light64", "light128", "light256", "light512", "light1024", "light2048",
                   "heavy_slots", "heavy_wide_slots", "two_paths", "heavy_two_paths", "bound_entries",
-                  "heavy_edges", "stored_ranks")
+                  "heavy_edges", "stored_ranks", "dense_slots", "dense_two_paths", "dense_edges",
+                  "dense_stored", "dense_store_full")
 
     def stats(self) -> dict:
-        out = (_i64 * 16)()
+        out = (_i64 * 32)()
         n = _i32()
-        self.ctx._check(lib().slg_plan_stats(self.handle, out, 16, ctypes.byref(n)))
+        self.ctx._check(lib().slg_plan_stats(self.handle, out, 32, ctypes.byref(n)))
         return {name: int(out[t]) for t, name in enumerate(self.STAT_NAMES[: n.value])}
 
     def emit(self, row_ptr, row, col, w, stream=None):
@@ -335,6 +342,11 @@ class Context:
     def set_tuning(self, light_max: int = 0, slot_work: int = 0, heavy_grid: int = 0):
         self._check(lib().slg_context_set_tuning(self.handle, light_max, slot_work, heavy_grid))
 
+    def set_dense(self, min_ratio: int = 4, min_range: int = 0):
+        """The dense tier's rule (min_ratio 0 turns it off; min_range 0 = its
+        default); results are identical either way."""
+        self._check(lib().slg_context_set_dense(self.handle, int(min_ratio), int(min_range)))
+
     # -- measurement ---------------------------------------------------------
     def set_count_store(self, max_bytes: int, min_two_paths: int = 1 << 24):
         """Largest count store a plan may keep (0: the emit pass walks the
@@ -354,7 +366,18 @@ class Context:
                 for t in range(n.value)}
 
     def reset_timing(self):
+        """Clears the stage times and the work counters."""
         self._check(lib().slg_context_reset_timing(self.handle))
+
+    WORK_NAMES = ("blocks", "two_paths", "heavy_two_paths", "dense_two_paths", "edges", "heavy_edges",
+                  "dense_edges", "dense_slots", "dense_stored", "dense_store_full_blocks")
+
+    def work(self) -> dict:
+        """Work of the counting passes since the last reset_timing()."""
+        out = (_i64 * 16)()
+        n = _i32()
+        self._check(lib().slg_context_get_work(self.handle, out, 16, ctypes.byref(n)))
+        return {self.WORK_NAMES[t]: int(out[t]) for t in range(n.value)}
 
     def _check(self, status: int):
         if status != SLG_OK:
@@ -438,10 +461,13 @@ class Context:
             p.destroy()
         return outs
 
-    def line_graph_stream(self, g: Graph, s: Sequence[int], chunk_bytes: int, fn, stream=None):
+    def line_graph_stream(self, g: Graph, s: Sequence[int], chunk_bytes: int, fn, stream=None,
+                          rows: Optional[Sequence[int]] = None):
         """Chunked L_s: fn(k, s, row_begin, row_end, edge_begin, row_ptr, row, col, w) is called
-        per chunk and threshold with torch views of library buffers, valid only during the
-        call; return True to stop (SlgError CANCELLED)."""
+        per chunk and threshold with torch views of library buffers; torch work inside fn runs
+        on the library's consumer stream (it overlaps the next chunk's emit) and may use the
+        views until it completes, not after fn's work is done. Return True to stop (SlgError
+        CANCELLED). rows=(row_begin, row_end) streams only those rows."""
         import torch
         dev = f"cuda:{self.device}"
         errors = []
@@ -449,8 +475,11 @@ class Context:
         def _cb(user, k, sk, r0, r1, e0, ne, rp, ri, rj, rw, st):
             try:
                 view = lambda ptr, n, ts: torch.as_tensor(_DeviceView(ptr, n, ts, None), device=dev)
-                stop = fn(int(k), int(sk), int(r0), int(r1), int(e0), view(rp, r1 - r0 + 1, "<i8"),
-                          view(ri, ne, "<i4"), view(rj, ne, "<i4"), view(rw, ne, "<i4"))
+                # torch work inside fn goes to the consumer stream
+                cm = torch.cuda.stream(torch.cuda.ExternalStream(st, device=dev)) if st else contextlib.nullcontext()
+                with cm:
+                    stop = fn(int(k), int(sk), int(r0), int(r1), int(e0), view(rp, r1 - r0 + 1, "<i8"),
+                              view(ri, ne, "<i4"), view(rj, ne, "<i4"), view(rw, ne, "<i4"))
                 return 1 if stop else 0
             except Exception as exc:  # surface Python errors after the call
                 errors.append(exc)
@@ -458,11 +487,23 @@ class Context:
 
         cb = _CHUNK_FN(_cb)
         arr, kk = _s_array(s)
-        st = lib().slg_line_graph_stream(self.handle, g.handle, arr, kk, int(chunk_bytes), cb, None,
-                                         _stream_handle(stream))
+        if rows is None:
+            st = lib().slg_line_graph_stream(self.handle, g.handle, arr, kk, int(chunk_bytes), cb, None,
+                                             _stream_handle(stream))
+        else:
+            st = lib().slg_line_graph_stream_rows(self.handle, g.handle, arr, kk, int(rows[0]), int(rows[1]),
+                                                  int(chunk_bytes), cb, None, _stream_handle(stream))
         if errors:
             raise errors[0]
         self._check(st)
+
+    def work_prefix(self, g: Graph, s_min: int, stream=None):
+        """Per-row 2-path work at s_min as an exclusive prefix (numpy int64[m+1])."""
+        import numpy as np
+        out = np.zeros(g.m + 1, dtype=np.int64)
+        self._check(lib().slg_work_prefix(self.handle, g.handle, int(s_min), out.ctypes.data,
+                                          _stream_handle(stream)))
+        return out
 
     def line_graph_result(self, g: Graph, s: Sequence[int], stream=None) -> List[LineGraph]:
         """The one-shot ABI call (slg_line_graph): library-owned result buffers."""

@@ -22,14 +22,22 @@ using namespace slg;
 namespace {
 enum Stage {
     kStPrune, kStRowPlan, kStPlanScans, kStSlots, kStBounds, kStCountLight, kStCountHeavy,
-    kStCountHeavyWide, kStCountScans, kStEmitLight, kStEmitHeavy, kStEmitHeavyWide, kStRowPtr, kNumStages
+    kStCountHeavyWide, kStCountDense, kStCountScans, kStEmitLight, kStEmitHeavy, kStEmitHeavyWide, kStEmitDense,
+    kStRowPtr, kNumStages
 };
 const char *const kStageNames[kNumStages] = {
     "prune", "row_plan", "plan_scans", "slots", "bounds", "count_light", "count_heavy",
-    "count_heavy_wide", "count_scans", "emit_light", "emit_heavy", "emit_heavy_wide", "row_ptr"};
+    "count_heavy_wide", "count_dense", "count_scans", "emit_light", "emit_heavy", "emit_heavy_wide", "emit_dense",
+    "row_ptr"};
 struct PendingTime {
     int stage;
     hipEvent_t start, stop;
+};
+// Work counters of a context, summed over every counting pass (whole plans
+// and row blocks) since the last reset.
+enum Work {
+    kWkBlocks, kWkTwoPaths, kWkHeavyTwoPaths, kWkDenseTwoPaths, kWkEdges, kWkHeavyEdges, kWkDenseEdges,
+    kWkDenseSlots, kWkDenseStored, kWkDenseRewalk, kNumWork
 };
 }  // namespace
 
@@ -41,10 +49,14 @@ struct slg_context {
     std::vector<hipEvent_t> event_pool;
     int64_t stage_launches[kNumStages] = {};
     double stage_ms[kNumStages] = {};
+    int64_t work[kNumWork] = {};  // work counters since the last reset (slg_context_get_work)
     bool capturing = false;  // a hipGraph capture is recording: no event timing
     int32_t light_max = kLightMax;
     int64_t slot_work = kSlotWork;
     int heavy_grid = 0;
+    int dense_resident = 0;  // persistent workgroups of the dense tier
+    int32_t dense_ratio = kDenseRatio;  // the dense tier's rule (ratio 0: off)
+    int32_t dense_min = kDenseMinRange;
     int64_t store_limit = int64_t(32) << 30;  // largest count store a plan keeps (0: none)
     int64_t store_min = int64_t(1) << 24;     // fewest heavy 2-paths for which a plan keeps one
     uint64_t budget = 0;
@@ -70,7 +82,7 @@ struct slg_graph {
 
 namespace {
 
-constexpr int kPinnedSlots = 64;
+constexpr int kPinnedSlots = 96;
 
 // Layout of the plan's small device counter block (int64 entries).
 constexpr int kCntClass = 0;                    // kNumLists: rows / slots per tier list
@@ -78,14 +90,27 @@ constexpr int kCntErr = kCntClass + kNumLists;  // malformed-input flag (low 32 
 constexpr int kCntFill = kCntErr + 1;           // kNumLists: append cursors of the tier lists
 constexpr int kCntHeavyWork = kCntFill + kNumLists;  // 2-paths in heavy rows
 constexpr int kCntPieces = kCntHeavyWork + 1;     // large-row pieces of row planning
-constexpr int kCntTotal = kCntPieces + 1;
+constexpr int kCntDenseWork = kCntPieces + 1;     // 2-paths in dense rows
+constexpr int kCntTotal = kCntDenseWork + 1;
 static_assert(kCntTotal <= 32, "counter block");
 // Host staging slots for readbacks.
 constexpr int kHbSlots = kCntTotal;      // slot table size, then 2-paths, boundary entries
 constexpr int kHbEdges = 40;             // SLG_MAX_S edge totals
 constexpr int kHbHeavyEdges = kHbEdges + SLG_MAX_S;
-constexpr int kHbRange = kHbHeavyEdges + 3;  // a chunk's heavy list ranges (4 entries)
-static_assert(kHbSlots + 3 <= kHbEdges && kHbRange + 4 <= kPinnedSlots, "pinned staging layout");
+constexpr int kHbRange = kHbHeavyEdges + 5;  // a chunk's heavy list ranges (2 per list)
+static_assert(kHbSlots + 3 <= kHbEdges && kHbRange + 2 * kNumHeavyLists <= kPinnedSlots, "pinned staging layout");
+// Device counters of a plan (int64 entries of `tickets`).
+constexpr int kTkCount = 0;       // kNumHeavyLists: slot tickets of the counting passes
+constexpr int kTkEmit = 3;        // kNumHeavyLists: slot tickets of the emit passes
+constexpr int kTkHeavyEdges = 6;  // edges of heavy and heavy-wide slots
+constexpr int kTkStored = 7;      // entries of the heavy count store
+constexpr int kTkDenseCursor = 8; // room taken from the dense store
+constexpr int kTkDenseEdges = 9;  // edges of dense slots
+constexpr int kTkRange = 10;      // 2 per heavy list: a chunk's part of it
+constexpr int kTkTotal = kTkRange + 2 * kNumHeavyLists;
+static_assert(kTkHeavyEdges + 1 == kTkStored && kTkStored + 1 == kTkDenseCursor &&
+                  kTkDenseCursor + 1 == kTkDenseEdges,
+              "plan counters read back together");
 
 // Freed device blocks a context keeps for reuse unless told otherwise.
 constexpr uint64_t kDefaultCacheMin = uint64_t(16) << 30;  // default block cache: a quarter of the
@@ -201,6 +226,12 @@ struct PlanBufs {
     int32_t *hcnt = nullptr;
     int64_t *pieces = nullptr;
     uint8_t *rclass = nullptr;
+    int32_t *nslots_all = nullptr;  // row blocks: every row's slots, class and boundary
+    uint8_t *rclass_all = nullptr;  // entries, kept while each block masks the
+    int64_t *bsize_all = nullptr;   // others out
+    uint8_t *keep = nullptr;     // E_s positions (dense tier): kept-row flags,
+    int64_t *kpre = nullptr;     // their exclusive scan,
+    int32_t *cid = nullptr, *cid_row = nullptr, *vs_cid = nullptr;  // ranks, rows of ranks, lists in ranks
 };
 
 struct slg_plan {
@@ -209,8 +240,11 @@ struct slg_plan {
     hipStream_t st = nullptr;
     EmitParams prm{};
     Pruned pr{};
-    Scratch scratch;
+    Scratch scratch;   // the rows phase: kept for the plan's life
+    Scratch scratch2;  // a row block's slot tables, lists, stores (released per block)
     PlanBufs b;
+    bool blocks = false;           // planned block by block (the rows phase keeps every row's facts)
+    int64_t row_lo = 0, row_hi = 0;  // the rows of the current block
     bool prune = false;            // vertex lists are compacted to E_{s_min}
     int32_t s_min = 1;
     int32_t light_max = kLightMax; // tuning: wavefront-sort tier bound
@@ -221,11 +255,20 @@ struct slg_plan {
     Slots slots{};
     int32_t *bounds = nullptr;
     int64_t *tickets = nullptr;    // work counters of the persistent heavy launches
-    HeavyDesc *heavy[2] = {};      // heavy and heavy-wide slot descriptors
+    HeavyDesc *heavy[kNumHeavyLists] = {};  // heavy, heavy-wide and dense slot descriptors
     int32_t *lists[kNumLists] = {};
     int64_t list_count[kNumLists] = {};
     int64_t *slot_cnt = nullptr;   // [K][S]
     int64_t *slot_off = nullptr;   // [K][S+1]
+    bool dense = false;            // rows may take the dense tier (E_s positions computed)
+    int32_t dense_ratio = 0, dense_min = 0;
+    int dense_grid = 0;
+    bool use_dstore = false;       // dense slots keep their survivors for the emit pass
+    CountStore dstore{};
+    int64_t dstore_cap = 0;        // entries of the dense store
+    int64_t dense_two_paths = 0;
+    int64_t dense_edges = 0;
+    int64_t dense_stored = 0;      // entries the dense slots asked for (> cap: some walk again)
     bool use_store = false;        // the counting pass keeps the heavy overlaps for the emit pass
     CountStore store{};
     bool use_lstore = false;       // ... and the light rows' overlaps
@@ -301,6 +344,7 @@ slg_status create_context(int device, uint64_t mem_budget_bytes, const slg_alloc
         return SLG_ERR_DEVICE;
     }
     ctx->heavy_resident = heavy_resident(device);
+    ctx->dense_resident = dense_resident(device);
     // the fixed scratch of the no-allocation entry point: its address on
     // this device, looked up once per device with the device current
     ctx->noalloc_err = noalloc_scratch(device, &ctx->noalloc);
@@ -484,13 +528,21 @@ hipError_t enqueue_rows(slg_plan *p, hipStream_t st) {
                                              st)) != hipSuccess)
             return e;
     }
+    if (p->dense) {  // E_s positions: ranks of the kept rows, and the pruned lists in ranks
+        StageTimer tm(ctx, kStPrune, st);
+        if ((e = launch_row_keep(m, inc.he_ptr, p->s_min, p->pr.row_s, b.keep, st)) != hipSuccess) return e;
+        if ((e = launch_exclusive_scan_u8(b.keep, m, b.kpre, b.part_m, st)) != hipSuccess) return e;
+        if ((e = launch_cid(m, b.keep, b.kpre, b.cid, b.cid_row, st)) != hipSuccess) return e;
+        if ((e = launch_vs_cid(n, m, nnz, p->pr.vs_ptr, p->pr.vs_idx, b.cid, b.vs_cid, st)) != hipSuccess) return e;
+    }
     {
         StageTimer tm(ctx, kStRowPlan, st);
-        if ((e = launch_row_plan(p->pr, p->s_min, p->light_max, p->slot_work, b.tail_beg, b.work, b.jmax,
-                                 b.nslots, b.rclass, b.bsize,
+        if ((e = launch_row_plan(p->pr, p->s_min, p->light_max, p->slot_work, p->dense ? p->dense_ratio : 0,
+                                 p->dense_min, b.tail_beg, b.work, b.jmax, b.nslots, b.rclass, b.bsize,
                                  reinterpret_cast<unsigned long long *>(b.counters + kCntClass),
                                  reinterpret_cast<int *>(b.counters + kCntErr),
-                                 reinterpret_cast<unsigned long long *>(b.counters + kCntHeavyWork), b.pieces,
+                                 reinterpret_cast<unsigned long long *>(b.counters + kCntHeavyWork),
+                                 reinterpret_cast<unsigned long long *>(b.counters + kCntDenseWork), b.pieces,
                                  reinterpret_cast<unsigned long long *>(b.counters + kCntPieces), st)) !=
             hipSuccess)
             return e;
@@ -564,15 +616,15 @@ hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
     // overflow, flagged in err) names slot 0 / an empty descriptor
     for (int c = 0; c < kLightClasses; ++c)
         if ((e = launch_fill_i32(p->lists[c], p->list_count[c], 0, st)) != hipSuccess) return e;
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < kNumHeavyLists; ++h)
         if ((e = launch_fill_i64(reinterpret_cast<int64_t *>(p->heavy[h]),
                                  p->list_count[kLightClasses + h] * (int64_t)(sizeof(HeavyDesc) / 8), 0, st)) !=
             hipSuccess)
             return e;
     {
         StageTimer tm(ctx, kStSlots, st);
-        if ((e = launch_fill_slots(m, p->pr.he_ptr, p->slot_base, b.nslots, b.jmax, b.rclass, b.bbase, b.hat,
-                                   b.hcnt, b.part_m, b.slot_row, p->lists, p->heavy, p->list_count,
+        if ((e = launch_fill_slots(m, p->pr.he_ptr, p->slot_base, b.nslots, b.jmax, b.rclass, b.bbase, b.cid,
+                                   b.hat, b.hcnt, b.part_m, b.slot_row, p->lists, p->heavy, p->list_count,
                                    reinterpret_cast<unsigned long long *>(b.counters + kCntFill),
                                    reinterpret_cast<int *>(b.counters + kCntErr), st)) != hipSuccess)
             return e;
@@ -597,10 +649,13 @@ hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
     }
     {
         StageTimer tm(ctx, kStBounds, st);
-        for (int h = 0; h < 2; ++h)
-            if ((e = launch_bounds(p->pr, p->heavy[h], p->list_count[kLightClasses + h], p->bounds, st)) !=
-                hipSuccess)
+        for (int h = 0; h < kNumHeavyLists; ++h) {
+            // dense slots bound their members' tails by E_s position
+            Pruned pg = p->pr;
+            if (h == 2) pg.vs_idx = b.vs_cid;
+            if ((e = launch_bounds(pg, p->heavy[h], p->list_count[kLightClasses + h], p->bounds, st)) != hipSuccess)
                 return e;
+        }
     }
     if (p->use_store) {  // the store's layout: each heavy slot's 2-paths bound its partners
         StageTimer tm(ctx, kStBounds, st);
@@ -611,13 +666,21 @@ hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
     // joined before the heavy counting pass: its persistent grid fills every
     // CU, and light workgroups still resident would hold some of it back
     if ((e = fork.join()) != hipSuccess) return e;
-    if ((e = launch_fill_i64(p->tickets, 6, 0, st)) != hipSuccess) return e;
+    if ((e = launch_fill_i64(p->tickets, kTkTotal, 0, st)) != hipSuccess) return e;
     for (int wide = 0; wide < 2; ++wide) {
         if (p->list_count[kLightClasses + wide] <= 0) continue;
         StageTimer tm(ctx, wide ? kStCountHeavyWide : kStCountHeavy, st);
         if ((e = launch_heavy(false, wide, p->heavy[wide], p->list_count[kLightClasses + wide], p->S, p->bounds,
-                              p->pr, p->prm, p->slot_cnt, nullptr, p->tickets + wide, p->heavy_grid,
+                              p->pr, p->prm, p->slot_cnt, nullptr, p->tickets + kTkCount + wide, p->heavy_grid,
                               (p->use_store && !wide) ? &p->store : nullptr, st)) != hipSuccess)
+            return e;
+    }
+    if (p->list_count[kLightClasses + 2] > 0) {
+        StageTimer tm(ctx, kStCountDense, st);
+        if ((e = launch_dense(false, p->heavy[2], p->list_count[kLightClasses + 2], p->S, p->bounds, p->pr, p->prm,
+                              p->slot_cnt, nullptr, p->tickets + kTkCount + 2, p->dense_grid,
+                              p->use_dstore ? &p->dstore : nullptr, p->tickets + kTkDenseCursor, p->dstore_cap,
+                              st)) != hipSuccess)
             return e;
     }
     StageTimer tm(ctx, kStCountScans, st);
@@ -628,15 +691,6 @@ hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
     return hipSuccess;
 }
 
-// Builds a plan: allocations, the planning launches, and the two readbacks
-// that size the slot table and the outputs.
-slg_status plan_build(slg_plan *p) {
-    slg_context *ctx = p->ctx;
-    const slg_incidence &inc = p->g->inc;
-    const int64_t m = inc.num_hyperedges, n = inc.num_vertices, nnz = inc.nnz;
-    hipStream_t st = p->st;
-    Scratch &sc = p->scratch;
-    PlanBufs &b = p->b;
 #define BUILD_HIP(call)                                                                            \
     do {                                                                                           \
         hipError_t e_ = (call);                                                                    \
@@ -644,6 +698,17 @@ slg_status plan_build(slg_plan *p) {
             return fail(ctx, e_ == hipErrorOutOfMemory ? SLG_ERR_OUT_OF_MEMORY : SLG_ERR_DEVICE,     \
                         "%s: %s", #call, hipGetErrorString(e_));                                   \
     } while (0)
+
+// The rows phase of a plan: pruning, E_s positions, the per-row work
+// estimate and tiers, and their scans over every row, with the readback
+// that sizes a plan of all rows.
+slg_status plan_rows(slg_plan *p) {
+    slg_context *ctx = p->ctx;
+    const slg_incidence &inc = p->g->inc;
+    const int64_t m = inc.num_hyperedges, n = inc.num_vertices, nnz = inc.nnz;
+    hipStream_t st = p->st;
+    Scratch &sc = p->scratch;
+    PlanBufs &b = p->b;
     Pruned &pr = p->pr;
     pr.m = m;
     pr.n = n;
@@ -651,6 +716,9 @@ slg_status plan_build(slg_plan *p) {
     pr.he_ptr = inc.he_ptr;
     pr.he_idx = inc.he_idx;
     p->prune = (p->s_min > 1 || pr.row_s) && nnz > 0;
+    // the dense tier works in E_s positions; the batched form (a threshold
+    // per row) keeps to the other tiers
+    p->dense = p->dense_ratio > 0 && !pr.row_s && nnz > 0 && m > 0;
     AllocList phase1;
     if (p->prune) {
         phase1.add(&b.flag, nnz);
@@ -667,8 +735,20 @@ slg_status plan_build(slg_plan *p) {
     phase1.add(&b.rclass, m);
     phase1.add(&b.bsize, m);
     phase1.add(&b.bbase, m + 1);
-    phase1.add(&b.hat, 2 * (m + 1));
-    phase1.add(&b.hcnt, 2 * m);
+    phase1.add(&b.hat, kNumHeavyLists * (m + 1));
+    phase1.add(&b.hcnt, kNumHeavyLists * m);
+    if (p->dense) {
+        phase1.add(&b.keep, m);
+        phase1.add(&b.kpre, m + 1);
+        phase1.add(&b.cid, m);
+        phase1.add(&b.cid_row, m);
+        phase1.add(&b.vs_cid, nnz);
+    }
+    if (p->blocks) {
+        phase1.add(&b.nslots_all, m);
+        phase1.add(&b.rclass_all, m);
+        phase1.add(&b.bsize_all, m);
+    }
     phase1.add(&b.counters, 32);
     phase1.add(&b.pieces, 3 * plan_pieces_cap(nnz));
     phase1.add(&b.part_m, scan_partials_size(m));
@@ -686,7 +766,15 @@ slg_status plan_build(slg_plan *p) {
         pr.vs_idx = inc.v_idx;
     }
     pr.tail_beg = b.tail_beg;
+    pr.cid = b.cid;
+    pr.cid_row = b.cid_row;
+    pr.vs_cid = b.vs_cid;
     BUILD_HIP(enqueue_rows(p, st));
+    if (p->blocks && m > 0) {
+        BUILD_HIP(hipMemcpyAsync(b.nslots_all, b.nslots, m * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+        BUILD_HIP(hipMemcpyAsync(b.rclass_all, b.rclass, m, hipMemcpyDeviceToDevice, st));
+        BUILD_HIP(hipMemcpyAsync(b.bsize_all, b.bsize, m * sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    }
     int64_t *hb = ctx->pinned;
     BUILD_HIP(hipMemcpyAsync(hb, b.counters, kCntTotal * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     BUILD_HIP(hipMemcpyAsync(hb + kHbSlots, p->slot_base + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -698,19 +786,64 @@ slg_status plan_build(slg_plan *p) {
                     "malformed incidence (bad pointer, id out of range, or vertex CSR not the transpose)");
     for (int c = 0; c < kNumLists; ++c) p->list_count[c] = hb[kCntClass + c];
     p->S = hb[kHbSlots];
-    if (p->S >= (int64_t(1) << 31)) return fail(ctx, SLG_ERR_OVERFLOW, "more than 2^31 output slots");
     p->two_paths = hb[kHbSlots + 1];
     p->nbounds = hb[kHbSlots + 2];
     p->heavy_two_paths = hb[kCntHeavyWork];
+    p->dense_two_paths = hb[kCntDenseWork];
+    p->row_lo = 0;
+    p->row_hi = m;
+    return SLG_OK;
+}
+
+// The block phase: the slot table, tier lists, boundary table, stores and
+// the counting pass of rows [r0, r1) (all rows: [0, m), sized by the rows
+// phase; a part of them: the other rows are masked out first). Its
+// allocations come from scratch2, released by the next block or the plan's
+// end.
+slg_status plan_block(slg_plan *p, int64_t r0, int64_t r1) {
+    slg_context *ctx = p->ctx;
+    const int64_t m = p->pr.m;
+    hipStream_t st = p->st;
+    Scratch &sc = p->scratch2;
+    PlanBufs &b = p->b;
+    int64_t *hb = ctx->pinned;
+    sc.release();
+    if (r0 > 0 || r1 < m) {
+        if (!p->blocks) return fail(ctx, SLG_ERR_INVALID_ARG, "internal error: a row block of a whole plan");
+        BUILD_HIP(launch_fill_i64(b.counters, 32, 0, st));
+        BUILD_HIP(launch_block_mask(m, r0, r1, b.nslots_all, b.rclass_all, b.bsize_all, b.work, b.nslots, b.rclass,
+                                    b.bsize, reinterpret_cast<unsigned long long *>(b.counters + kCntClass),
+                                    reinterpret_cast<unsigned long long *>(b.counters + kCntHeavyWork),
+                                    reinterpret_cast<unsigned long long *>(b.counters + kCntDenseWork), st));
+        BUILD_HIP(launch_exclusive_scan_i32(b.nslots, m, p->slot_base, b.part_m, st));
+        BUILD_HIP(launch_exclusive_scan_i64(b.bsize, m, b.bbase, b.part_m, st));
+        BUILD_HIP(hipMemcpyAsync(hb, b.counters, kCntTotal * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        BUILD_HIP(hipMemcpyAsync(hb + kHbSlots, p->slot_base + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        BUILD_HIP(hipMemcpyAsync(hb + kHbSlots + 1, b.work_pre + r0, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        BUILD_HIP(hipMemcpyAsync(hb + kHbSlots + 2, b.bbase + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        BUILD_HIP(hipMemcpyAsync(hb + kHbRange, b.work_pre + r1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        BUILD_HIP(hipStreamSynchronize(st));
+        for (int c = 0; c < kNumLists; ++c) p->list_count[c] = hb[kCntClass + c];
+        p->S = hb[kHbSlots];
+        p->two_paths = hb[kHbRange] - hb[kHbSlots + 1];
+        p->nbounds = hb[kHbSlots + 2];
+        p->heavy_two_paths = hb[kCntHeavyWork];
+        p->dense_two_paths = hb[kCntDenseWork];
+    } else if (p->blocks && (p->row_lo != 0 || p->row_hi != m)) {
+        return fail(ctx, SLG_ERR_INVALID_ARG, "internal error: all rows after a row block");
+    }
+    p->row_lo = r0;
+    p->row_hi = r1;
+    if (p->S >= (int64_t(1) << 31)) return fail(ctx, SLG_ERR_OVERFLOW, "more than 2^31 output slots");
     if (p->nbounds >= (int64_t(1) << 40)) return fail(ctx, SLG_ERR_OVERFLOW, "boundary table too large");
 
     const int K = p->prm.k;
     AllocList phase2;
     phase2.add(&b.slot_row, p->S);
     phase2.add(&p->bounds, p->nbounds);
-    phase2.add(&p->tickets, 10);
+    phase2.add(&p->tickets, kTkTotal);
     for (int c = 0; c < kLightClasses; ++c) phase2.add(&p->lists[c], p->list_count[c]);
-    for (int h = 0; h < 2; ++h) phase2.add(&p->heavy[h], p->list_count[kLightClasses + h]);
+    for (int h = 0; h < kNumHeavyLists; ++h) phase2.add(&p->heavy[h], p->list_count[kLightClasses + h]);
     static_assert(sizeof(HeavyDesc) % 8 == 0, "HeavyDesc is filled as int64 words");
     phase2.add(&p->slot_cnt, (size_t)K * p->S);
     phase2.add(&p->slot_off, (size_t)K * (p->S + 1));
@@ -722,8 +855,8 @@ slg_status plan_build(slg_plan *p) {
         const int64_t bytes = p->heavy_two_paths * 4 + nh * 20 + 16;
         p->use_store = nh > 0 && p->store_limit > 0 && bytes <= p->store_limit &&
                        p->heavy_two_paths >= p->store_min;
-        // the light rows' pairs: at most their 2-paths (all but the heavy ones)
-        const int64_t lcap = p->two_paths - p->heavy_two_paths;
+        // the light rows' pairs: at most their 2-paths (all but the heavy and dense ones)
+        const int64_t lcap = p->two_paths - p->heavy_two_paths - p->dense_two_paths;
         const int64_t lbytes = lcap * 6 + m * 16 + 16;
         p->use_lstore = p->store_limit > 0 && lcap > 0 && p->two_paths >= p->store_min &&
                         (p->use_store ? bytes : 0) + lbytes <= p->store_limit;
@@ -740,6 +873,20 @@ slg_status plan_build(slg_plan *p) {
             phase2.add(&p->store.n, nh);
             phase2.add(&p->store_work, nh);
         }
+        // the dense slots' survivors: at most one per s_min of their 2-paths,
+        // in what the limit leaves (slots that find it full walk again)
+        const int64_t nd = p->list_count[kLightClasses + 2];
+        const int64_t left = p->store_limit - (p->use_store ? bytes : 0) - (p->use_lstore ? lbytes : 0) -
+                             nd * 12 - 16;
+        p->dstore_cap = std::min<int64_t>(p->dense_two_paths / std::max(p->s_min, 1) + 1, left / 4);
+        p->use_dstore = nd > 0 && p->dstore_cap > 0;
+        if (p->use_dstore) {
+            phase2.add(&p->dstore.ent, p->dstore_cap);
+            phase2.add(&p->dstore.off, nd);
+            phase2.add(&p->dstore.n, nd);
+        } else {
+            p->dstore_cap = 0;
+        }
     }
     if (p->reserve) {
         if (!(*p->reserve)(phase2.bytes)) return fail(ctx, SLG_ERR_OUT_OF_MEMORY, "device-memory budget refused");
@@ -754,22 +901,43 @@ slg_status plan_build(slg_plan *p) {
                                  hipMemcpyDeviceToHost, st));
     for (int h = 0; h < 2; ++h)
         BUILD_HIP(launch_heavy_edges(p->heavy[h], p->list_count[kLightClasses + h], p->slot_cnt, p->S, K,
-                                     p->tickets + 4, st));
-    BUILD_HIP(hipMemcpyAsync(hb + kHbHeavyEdges, p->tickets + 4, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+                                     p->tickets + kTkHeavyEdges, st));
+    BUILD_HIP(launch_heavy_edges(p->heavy[2], p->list_count[kLightClasses + 2], p->slot_cnt, p->S, K,
+                                 p->tickets + kTkDenseEdges, st));
     if (p->use_store)
-        BUILD_HIP(launch_sum_i32(p->store.n, p->list_count[kLightClasses], p->tickets + 5, st));
-    BUILD_HIP(hipMemcpyAsync(hb + kHbHeavyEdges + 2, p->tickets + 5, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    BUILD_HIP(hipMemcpyAsync(hb + kHbHeavyEdges + 1, b.counters + kCntErr, sizeof(int64_t),
+        BUILD_HIP(launch_sum_i32(p->store.n, p->list_count[kLightClasses], p->tickets + kTkStored, st));
+    BUILD_HIP(hipMemcpyAsync(hb + kHbHeavyEdges, p->tickets + kTkHeavyEdges, 4 * sizeof(int64_t),
+                             hipMemcpyDeviceToHost, st));  // heavy edges, stored, dense cursor, dense edges
+    BUILD_HIP(hipMemcpyAsync(hb + kHbHeavyEdges + 4, b.counters + kCntErr, sizeof(int64_t),
                              hipMemcpyDeviceToHost, st));
     BUILD_HIP(hipStreamSynchronize(st));
-#undef BUILD_HIP
-    if (hb[kHbHeavyEdges + 1] & 0xffffffff)
+    if (hb[kHbHeavyEdges + 4] & 0xffffffff)
         return fail(ctx, SLG_ERR_DEVICE, "internal error: a tier list overflowed its planned size");
     for (int k = 0; k < K; ++k) p->num_edges[k] = hb[kHbEdges + k];
     p->heavy_edges = hb[kHbHeavyEdges];
-    p->stored_ranks = hb[kHbHeavyEdges + 2];
+    p->stored_ranks = hb[kHbHeavyEdges + 1];
+    p->dense_stored = hb[kHbHeavyEdges + 2];
+    p->dense_edges = hb[kHbHeavyEdges + 3];
+    int64_t *wk = ctx->work;
+    wk[kWkBlocks] += 1;
+    wk[kWkTwoPaths] += p->two_paths;
+    wk[kWkHeavyTwoPaths] += p->heavy_two_paths;
+    wk[kWkDenseTwoPaths] += p->dense_two_paths;
+    for (int k = 0; k < K; ++k) wk[kWkEdges] += p->num_edges[k];
+    wk[kWkHeavyEdges] += p->heavy_edges;
+    wk[kWkDenseEdges] += p->dense_edges;
+    wk[kWkDenseSlots] += p->list_count[kLightClasses + 2];
+    wk[kWkDenseStored] += std::min(p->dense_stored, p->dstore_cap);
+    wk[kWkDenseRewalk] += (p->list_count[kLightClasses + 2] > 0 && p->dense_stored > p->dstore_cap) ? 1 : 0;
     return SLG_OK;
 }
+
+// Builds a plan of all rows.
+slg_status plan_build(slg_plan *p) {
+    slg_status rc = plan_rows(p);
+    return rc != SLG_OK ? rc : plan_block(p, 0, p->pr.m);
+}
+#undef BUILD_HIP
 
 slg_plan *plan_new(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num_s, hipStream_t st) {
     slg_plan *p = new (std::nothrow) slg_plan();
@@ -779,18 +947,24 @@ slg_plan *plan_new(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num
     p->st = st;
     p->scratch.st = st;
     p->scratch.arena = ctx->arena.get();
+    p->scratch2.st = st;
+    p->scratch2.arena = ctx->arena.get();
     p->prm.k = num_s;
     for (int t = 0; t < num_s; ++t) p->prm.s[t] = s[t];
     p->s_min = s[0];
     p->light_max = ctx->light_max;
     p->slot_work = ctx->slot_work;
     p->heavy_grid = ctx->heavy_grid > 0 ? ctx->heavy_grid : ctx->heavy_resident;
+    p->dense_ratio = ctx->dense_ratio;
+    p->dense_min = ctx->dense_min;
+    p->dense_grid = ctx->dense_resident;
     p->store_limit = ctx->store_limit;
     p->store_min = ctx->store_min;
     return p;
 }
 
 void plan_free(slg_plan *p) {
+    p->scratch2.release();
     p->scratch.release();
     (void)hipStreamSynchronize(p->st);
     delete p;
@@ -853,23 +1027,24 @@ slg_status emit_range(slg_plan *p, int64_t r0, int64_t r1, int64_t s0, int64_t s
                                           p->slot_off, nullptr, st));
         }
     }
-    SLG_HIP(ctx, launch_fill_i64(p->tickets + 2, 2, 0, st));
-    // a chunk's heavy slots: a contiguous part of each heavy list (both are
+    SLG_HIP(ctx, launch_fill_i64(p->tickets + kTkEmit, kNumHeavyLists, 0, st));
+    // a chunk's heavy slots: a contiguous part of each heavy list (all are
     // in slot order), found on the device and read back
-    int64_t lo[2] = {0, 0}, hi[2] = {p->list_count[kLightClasses], p->list_count[kLightClasses + 1]};
+    int64_t lo[kNumHeavyLists] = {}, hi[kNumHeavyLists];
+    for (int h = 0; h < kNumHeavyLists; ++h) hi[h] = p->list_count[kLightClasses + h];
     if (s0 > 0 || s1 < p->S) {
         int64_t *hb = ctx->pinned + kHbRange;
-        for (int wide = 0; wide < 2; ++wide) {
-            if (hi[wide] <= 0) continue;
-            SLG_HIP(ctx, launch_heavy_range(p->heavy[wide], hi[wide], s0, s1, p->tickets + 6 + 2 * wide, st));
-            SLG_HIP(ctx, hipMemcpyAsync(hb + 2 * wide, p->tickets + 6 + 2 * wide, 2 * sizeof(int64_t),
+        for (int h = 0; h < kNumHeavyLists; ++h) {
+            if (hi[h] <= 0) continue;
+            SLG_HIP(ctx, launch_heavy_range(p->heavy[h], hi[h], s0, s1, p->tickets + kTkRange + 2 * h, st));
+            SLG_HIP(ctx, hipMemcpyAsync(hb + 2 * h, p->tickets + kTkRange + 2 * h, 2 * sizeof(int64_t),
                                         hipMemcpyDeviceToHost, st));
         }
         SLG_HIP(ctx, hipStreamSynchronize(st));
-        for (int wide = 0; wide < 2; ++wide)
-            if (hi[wide] > 0) {
-                lo[wide] = hb[2 * wide];
-                hi[wide] = hb[2 * wide + 1];
+        for (int h = 0; h < kNumHeavyLists; ++h)
+            if (hi[h] > 0) {
+                lo[h] = hb[2 * h];
+                hi[h] = hb[2 * h + 1];
             }
     }
     for (int wide = 0; wide < 2; ++wide) {
@@ -878,11 +1053,25 @@ slg_status emit_range(slg_plan *p, int64_t r0, int64_t r1, int64_t s0, int64_t s
         StageTimer tm(ctx, wide ? kStEmitHeavyWide : kStEmitHeavy, st);
         if (p->use_store && !wide) {
             const CountStore part{p->store.ent, p->store.off + lo[0], p->store.n + lo[0]};
-            SLG_HIP(ctx, launch_heavy_store_emit(p->heavy[0] + lo[0], cnt, p->S, part, prm, p->slot_off, st));
+            SLG_HIP(ctx, launch_heavy_store_emit(p->heavy[0] + lo[0], cnt, p->S, part, prm, p->slot_off, nullptr,
+                                                 st));
         } else {
             SLG_HIP(ctx, launch_heavy(true, wide, p->heavy[wide] + lo[wide], cnt, p->S, p->bounds, p->pr, prm,
-                                      nullptr, p->slot_off, p->tickets + 2 + wide, p->heavy_grid, nullptr, st));
+                                      nullptr, p->slot_off, p->tickets + kTkEmit + wide, p->heavy_grid, nullptr,
+                                      st));
         }
+    }
+    if (hi[2] > lo[2]) {  // dense slots: from their store, then any the store could not hold
+        StageTimer tm(ctx, kStEmitDense, st);
+        const int64_t cnt = hi[2] - lo[2];
+        const CountStore part{p->dstore.ent, p->dstore.off + lo[2], p->dstore.n + lo[2]};
+        if (p->use_dstore)
+            SLG_HIP(ctx, launch_heavy_store_emit(p->heavy[2] + lo[2], cnt, p->S, part, prm, p->slot_off,
+                                                 p->pr.cid_row, st));
+        if (!p->use_dstore || p->dense_stored > p->dstore_cap)
+            SLG_HIP(ctx, launch_dense(true, p->heavy[2] + lo[2], cnt, p->S, p->bounds, p->pr, prm, nullptr,
+                                      p->slot_off, p->tickets + kTkEmit + 2, p->dense_grid,
+                                      p->use_dstore ? &part : nullptr, nullptr, 0, st));
     }
     {
         StageTimer tm(ctx, kStRowPtr, st);
@@ -922,23 +1111,50 @@ slg_status slg_plan_emit(slg_plan *p, int64_t *const *row_ptr, int32_t *const *r
     return order_after(ctx, p->st, st);  // scratch is freed on the plan's stream
 }
 
-slg_status slg_line_graph_stream(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num_s,
-                                 int64_t chunk_bytes, slg_chunk_fn fn, void *user, void *stream) {
-    if (!ctx || !g || !fn || chunk_bytes <= 0) return fail(ctx, SLG_ERR_INVALID_ARG, "bad stream arguments");
-    slg_plan *p = nullptr;
-    slg_status rc = slg_plan_create(ctx, g, s, num_s, stream, &p);
-    if (rc != SLG_OK) return rc;
-    hipStream_t st = static_cast<hipStream_t>(stream);
+namespace {
+// Rows [row_begin, row_end) of every L_s of the s-set, handed to `fn` in
+// chunks. The rows phase runs once for the whole graph; the rest is planned
+// and counted one row block at a time, so that the slot tables, boundary
+// table and stores are bounded by the block, not by the graph: a block
+// takes rows while its estimated scratch fits the count-store limit (the
+// dense tier's survivors per 2-path are estimated from the blocks before).
+// Inside a block, chunks are row ranges whose output fits chunk_bytes. Two
+// sets of chunk buffers alternate: chunk c + 1 is emitted on `st` while the
+// callback consumes chunk c on the consumer stream (the context's second
+// stream when it has one), which waits for chunk c alone; a buffer set is
+// written again only after the consumer's work on it.
+slg_status stream_rows(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num_s, int64_t row_begin,
+                       int64_t row_end, int64_t chunk_bytes, slg_chunk_fn fn, void *user, hipStream_t st) {
+    if (!valid_s(s, num_s))
+        return fail(ctx, SLG_ERR_INVALID_ARG, "s must be strictly increasing, s[0] >= 1, 1 <= num_s <= %d",
+                    SLG_MAX_S);
+    SLG_HIP(ctx, hipSetDevice(ctx->device));
+    slg_plan *p = plan_new(ctx, g, s, num_s, st);
+    if (!p) return fail(ctx, SLG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    p->blocks = true;
     const int K = num_s;
-    const int64_t m = p->pr.m;
-    Scratch bufs;
+    const int64_t m = g->inc.num_hyperedges;
+    Scratch bufs;  // chunk-cut scratch of the call
     bufs.st = st;
     bufs.arena = ctx->arena.get();
+    hipEvent_t done[2] = {}, used[2] = {};  // chunk written / consumer finished, per buffer set
+    hipStream_t cst = st;
     auto cleanup = [&](slg_status code) {
+        if (cst != st) {  // the consumer's last work before the buffers go back
+            hipEvent_t ev;
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+                (void)hipEventRecord(ev, cst);
+                (void)hipStreamWaitEvent(st, ev, 0);
+                (void)hipEventDestroy(ev);
+            }
+        }
         (void)hipStreamSynchronize(st);
         bufs.release();
-        slg_plan_destroy(p);
-        (void)hipStreamSynchronize(st);
+        plan_free(p);
+        for (int t = 0; t < 2; ++t) {
+            if (done[t]) (void)hipEventDestroy(done[t]);
+            if (used[t]) (void)hipEventDestroy(used[t]);
+        }
         return code;
     };
 #define STREAM_HIP(call)                                                                            \
@@ -948,72 +1164,194 @@ slg_status slg_line_graph_stream(slg_context *ctx, slg_graph *g, const int32_t *
             return cleanup(fail(ctx, e_ == hipErrorOutOfMemory ? SLG_ERR_OUT_OF_MEMORY : SLG_ERR_DEVICE, \
                                 "%s: %s", #call, hipGetErrorString(e_)));                           \
     } while (0)
-    // output bytes before every row; chunks are greedy row ranges
-    int64_t *dbytes;
-    STREAM_HIP(bufs.get(&dbytes, m + 1));
-    STREAM_HIP(launch_row_bytes(m, p->slot_base, p->slot_off, p->S, K, dbytes, st));
-    std::vector<int64_t> rbytes(m + 1);
-    STREAM_HIP(hipMemcpyAsync(rbytes.data(), dbytes, (m + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    slg_status rc = plan_rows(p);
+    if (rc != SLG_OK) return cleanup(rc);
+    for (int t = 0; t < 2; ++t) {
+        STREAM_HIP(hipEventCreateWithFlags(&done[t], hipEventDisableTiming));
+        STREAM_HIP(hipEventCreateWithFlags(&used[t], hipEventDisableTiming));
+    }
+    if (ensure_aux(ctx)) cst = ctx->aux;
+    const int64_t nr = row_end - row_begin;
+    if (nr <= 0) return cleanup(SLG_OK);
+    // every row's facts, to cut the blocks
+    std::vector<int64_t> work(nr), bsz(nr);
+    std::vector<int32_t> nsl(nr);
+    std::vector<uint8_t> cls(nr);
+    STREAM_HIP(hipMemcpyAsync(work.data(), p->b.work + row_begin, nr * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    STREAM_HIP(hipMemcpyAsync(bsz.data(), p->b.bsize_all + row_begin, nr * sizeof(int64_t), hipMemcpyDeviceToHost,
+                              st));
+    STREAM_HIP(hipMemcpyAsync(nsl.data(), p->b.nslots_all + row_begin, nr * sizeof(int32_t), hipMemcpyDeviceToHost,
+                              st));
+    STREAM_HIP(hipMemcpyAsync(cls.data(), p->b.rclass_all + row_begin, nr, hipMemcpyDeviceToHost, st));
     STREAM_HIP(hipStreamSynchronize(st));
-    std::vector<int64_t> cuts{0};
-    while (cuts.back() < m) {
-        const int64_t r0 = cuts.back();
-        const int64_t limit = rbytes[r0] + chunk_bytes - 8 * K;  // room for the closing row_ptr entry
-        int64_t r1 = (int64_t)(std::upper_bound(rbytes.begin() + r0 + 1, rbytes.end(), limit) - rbytes.begin()) - 1;
-        if (r1 <= r0) {
-            return cleanup(fail(ctx, SLG_ERR_OUT_OF_MEMORY,
-                                "row %lld alone needs %lld bytes, more than chunk_bytes", (long long)r0,
-                                (long long)(rbytes[r0 + 1] - rbytes[r0] + 8 * K)));
+    const int64_t budget = p->store_limit > 0 ? p->store_limit : (int64_t(8) << 30);
+    double dense_ratio = 0.125;  // survivors per dense 2-path, until a block has measured it
+    int64_t base[SLG_MAX_S] = {};  // edges of the call before the current block
+    int64_t *rp[2][SLG_MAX_S] = {};
+    int32_t *ri[2][SLG_MAX_S] = {}, *rj[2][SLG_MAX_S] = {}, *rw[2][SLG_MAX_S] = {};
+    int pending = -1;           // buffer set of a chunk emitted but not yet handed over
+    int64_t pr0 = 0, pr1 = 0;   // its rows
+    int64_t pe0[SLG_MAX_S] = {}, pne[SLG_MAX_S] = {};
+    auto hand_over = [&]() -> slg_status {  // the pending chunk to the callback, on the consumer stream
+        const int t = pending;
+        pending = -1;
+        if (hipEventSynchronize(done[t]) != hipSuccess ||
+            (cst != st && hipStreamWaitEvent(cst, done[t], 0) != hipSuccess))
+            return fail(ctx, SLG_ERR_DEVICE, "waiting for a chunk failed");
+        for (int k = 0; k < K; ++k)
+            if (fn(user, k, s[k], pr0, pr1, pe0[k], pne[k], rp[t][k], ri[t][k], rj[t][k], rw[t][k], cst) != 0)
+                return fail(ctx, SLG_ERR_CANCELLED, "chunk callback stopped the stream at row %lld",
+                            (long long)pr0);
+        if (hipEventRecord(used[t], cst) != hipSuccess) return fail(ctx, SLG_ERR_DEVICE, "event record failed");
+        return SLG_OK;
+    };
+    int64_t b0 = 0;
+    int next_set = 0;
+    while (b0 < nr) {
+        // the block: rows while the estimated scratch fits
+        const double per_dense = 4.0 * dense_ratio * 1.25;
+        double bytes = 0;
+        int64_t b1 = b0;
+        while (b1 < nr) {
+            const int c = cls[b1];
+            double r = (double)nsl[b1] * (24.0 + 16.0 * K) + 4.0 * (double)bsz[b1];
+            if (c == kHeavy || c == kHeavyWide) r += 4.0 * (double)work[b1];
+            else if (c == kDense) r += per_dense * (double)work[b1];
+            else if (c != kNone) r += 6.0 * (double)work[b1];
+            if (b1 > b0 && bytes + r > 0.5 * (double)budget) break;
+            bytes += r;
+            ++b1;
         }
-        cuts.push_back(r1);
-    }
-    // slot offsets of every threshold at every cut
-    const int64_t nc = (int64_t)cuts.size();
-    int64_t *dcuts, *doffs;
-    STREAM_HIP(bufs.get(&dcuts, nc));
-    STREAM_HIP(bufs.get(&doffs, nc * K));
-    STREAM_HIP(hipMemcpyAsync(dcuts, cuts.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    STREAM_HIP(launch_gather_offsets(dcuts, nc, p->slot_base, p->slot_off, p->S, K, doffs, st));
-    std::vector<int64_t> offs(nc * K), sb(nc);
-    STREAM_HIP(hipMemcpyAsync(offs.data(), doffs, nc * K * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    for (int64_t c = 0; c < nc; ++c)  // first slot of every cut row
-        STREAM_HIP(hipMemcpyAsync(&sb[c], p->slot_base + cuts[c], sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    STREAM_HIP(hipStreamSynchronize(st));
-    // chunk buffers sized for the largest chunk of every threshold
-    int64_t max_rows = 0, max_e[SLG_MAX_S] = {};
-    for (int64_t c = 0; c + 1 < nc; ++c) {
-        max_rows = std::max(max_rows, cuts[c + 1] - cuts[c]);
-        for (int k = 0; k < K; ++k) max_e[k] = std::max(max_e[k], offs[(c + 1) * K + k] - offs[c * K + k]);
-    }
-    int64_t *rp[SLG_MAX_S];
-    int32_t *ri[SLG_MAX_S], *rj[SLG_MAX_S], *rw[SLG_MAX_S];
-    for (int k = 0; k < K; ++k) {
-        STREAM_HIP(bufs.get(&rp[k], max_rows + 1));
-        void *q[3];
-        for (int t = 0; t < 3; ++t) STREAM_HIP(bufs.get(&q[t], std::max<int64_t>(max_e[k], 1) * sizeof(int32_t)));
-        ri[k] = static_cast<int32_t *>(q[0]);
-        rj[k] = static_cast<int32_t *>(q[1]);
-        rw[k] = static_cast<int32_t *>(q[2]);
-    }
-    for (int64_t c = 0; c + 1 < nc; ++c) {
-        const int64_t r0 = cuts[c], r1 = cuts[c + 1];
-        rc = emit_range(p, r0, r1, sb[c], sb[c + 1], &offs[c * K], rp, ri, rj, rw, st);
+        const int64_t R0 = row_begin + b0, R1 = row_begin + b1;
+        // the consumer's use of both buffer sets ends before the block's
+        // scratch (and the buffers in it) goes back
+        if (pending >= 0 && (rc = hand_over()) != SLG_OK) return cleanup(rc);
+        for (int t = 0; t < 2; ++t) STREAM_HIP(hipStreamWaitEvent(st, used[t], 0));
+        rc = plan_block(p, R0, R1);
         if (rc != SLG_OK) return cleanup(rc);
+        if (p->dense_two_paths > 0 && p->use_dstore)  // the room asked for, whether or not it fitted
+            dense_ratio = std::max(1e-4, (double)p->dense_stored / (double)p->dense_two_paths);
+        // output bytes before every row of the block; chunks are greedy row ranges
+        const int64_t nb = R1 - R0;
+        int64_t *dbytes;
+        STREAM_HIP(p->scratch2.get(&dbytes, m + 1));
+        STREAM_HIP(launch_row_bytes(m, p->slot_base, p->slot_off, p->S, K, dbytes, st));
+        std::vector<int64_t> rbytes(nb + 1);
+        STREAM_HIP(hipMemcpyAsync(rbytes.data(), dbytes + R0, (nb + 1) * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                  st));
         STREAM_HIP(hipStreamSynchronize(st));
-        for (int k = 0; k < K; ++k) {
-            const int64_t e0 = offs[c * K + k], ne = offs[(c + 1) * K + k] - e0;
-            if (fn(user, k, s[k], r0, r1, e0, ne, rp[k], ri[k], rj[k], rw[k], stream) != 0)
-                return cleanup(fail(ctx, SLG_ERR_CANCELLED, "chunk callback stopped the stream at row %lld",
-                                    (long long)r0));
+        std::vector<int64_t> cuts{R0};
+        while (cuts.back() < R1) {
+            const int64_t r0 = cuts.back();
+            const int64_t limit = rbytes[r0 - R0] + chunk_bytes - 8 * K;  // room for the closing row_ptr entry
+            int64_t r1 = R0 + (int64_t)(std::upper_bound(rbytes.begin() + (r0 - R0) + 1, rbytes.end(), limit) -
+                                        rbytes.begin()) - 1;
+            if (r1 <= r0)
+                return cleanup(fail(ctx, SLG_ERR_OUT_OF_MEMORY,
+                                    "row %lld alone needs %lld bytes, more than chunk_bytes", (long long)r0,
+                                    (long long)(rbytes[r0 - R0 + 1] - rbytes[r0 - R0] + 8 * K)));
+            cuts.push_back(r1);
         }
+        // slot offsets of every threshold at every cut
+        const int64_t nc = (int64_t)cuts.size();
+        int64_t *dcuts, *doffs;
+        STREAM_HIP(p->scratch2.get(&dcuts, nc));
+        STREAM_HIP(p->scratch2.get(&doffs, nc * K));
+        STREAM_HIP(hipMemcpyAsync(dcuts, cuts.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        STREAM_HIP(launch_gather_offsets(dcuts, nc, p->slot_base, p->slot_off, p->S, K, doffs, st));
+        std::vector<int64_t> offs(nc * K), sb(nc);
+        STREAM_HIP(hipMemcpyAsync(offs.data(), doffs, nc * K * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        for (int64_t c = 0; c < nc; ++c)  // first slot of every cut row
+            STREAM_HIP(hipMemcpyAsync(&sb[c], p->slot_base + cuts[c], sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        STREAM_HIP(hipStreamSynchronize(st));
+        // two buffer sets sized for the block's largest chunk of every threshold
+        int64_t max_rows = 0, max_e[SLG_MAX_S] = {};
+        for (int64_t c = 0; c + 1 < nc; ++c) {
+            max_rows = std::max(max_rows, cuts[c + 1] - cuts[c]);
+            for (int k = 0; k < K; ++k) max_e[k] = std::max(max_e[k], offs[(c + 1) * K + k] - offs[c * K + k]);
+        }
+        for (int t = 0; t < 2; ++t)
+            for (int k = 0; k < K; ++k) {
+                STREAM_HIP(p->scratch2.get(&rp[t][k], max_rows + 1));
+                void *q[3];
+                for (int u = 0; u < 3; ++u)
+                    STREAM_HIP(p->scratch2.get(&q[u], std::max<int64_t>(max_e[k], 1) * sizeof(int32_t)));
+                ri[t][k] = static_cast<int32_t *>(q[0]);
+                rj[t][k] = static_cast<int32_t *>(q[1]);
+                rw[t][k] = static_cast<int32_t *>(q[2]);
+            }
+        for (int64_t c = 0; c + 1 < nc; ++c) {
+            const int t = next_set;
+            next_set ^= 1;
+            STREAM_HIP(hipStreamWaitEvent(st, used[t], 0));  // the consumer is done with this set
+            int64_t *rpk[SLG_MAX_S];
+            int32_t *rik[SLG_MAX_S], *rjk[SLG_MAX_S], *rwk[SLG_MAX_S];
+            for (int k = 0; k < K; ++k) {
+                rpk[k] = rp[t][k];
+                rik[k] = ri[t][k];
+                rjk[k] = rj[t][k];
+                rwk[k] = rw[t][k];
+            }
+            rc = emit_range(p, cuts[c], cuts[c + 1], sb[c], sb[c + 1], &offs[c * K], rpk, rik, rjk, rwk, st);
+            if (rc != SLG_OK) return cleanup(rc);
+            STREAM_HIP(hipEventRecord(done[t], st));
+            if (pending >= 0 && (rc = hand_over()) != SLG_OK) return cleanup(rc);
+            pending = t;
+            pr0 = cuts[c];
+            pr1 = cuts[c + 1];
+            for (int k = 0; k < K; ++k) {
+                pe0[k] = base[k] + offs[c * K + k];
+                pne[k] = offs[(c + 1) * K + k] - offs[c * K + k];
+            }
+        }
+        for (int k = 0; k < K; ++k) base[k] += offs[(nc - 1) * K + k] - offs[k];
+        b0 = b1;
     }
+    if (pending >= 0 && (rc = hand_over()) != SLG_OK) return cleanup(rc);
 #undef STREAM_HIP
     return cleanup(SLG_OK);
+}
+}  // namespace
+
+slg_status slg_line_graph_stream(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num_s,
+                                 int64_t chunk_bytes, slg_chunk_fn fn, void *user, void *stream) {
+    if (!ctx || !g || !fn || chunk_bytes <= 0) return fail(ctx, SLG_ERR_INVALID_ARG, "bad stream arguments");
+    return stream_rows(ctx, g, s, num_s, 0, g->inc.num_hyperedges, chunk_bytes, fn, user,
+                       static_cast<hipStream_t>(stream));
+}
+
+slg_status slg_line_graph_stream_rows(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num_s,
+                                      int64_t row_begin, int64_t row_end, int64_t chunk_bytes, slg_chunk_fn fn,
+                                      void *user, void *stream) {
+    if (!ctx || !g || !fn || chunk_bytes <= 0) return fail(ctx, SLG_ERR_INVALID_ARG, "bad stream arguments");
+    if (row_begin < 0 || row_end < row_begin || row_end > g->inc.num_hyperedges)
+        return fail(ctx, SLG_ERR_INVALID_ARG, "rows [%lld, %lld) outside [0, m)", (long long)row_begin,
+                    (long long)row_end);
+    return stream_rows(ctx, g, s, num_s, row_begin, row_end, chunk_bytes, fn, user,
+                       static_cast<hipStream_t>(stream));
+}
+
+slg_status slg_work_prefix(slg_context *ctx, slg_graph *g, int32_t s_min, int64_t *prefix, void *stream) {
+    if (!ctx || !g || !prefix || s_min < 1) return fail(ctx, SLG_ERR_INVALID_ARG, "bad work prefix arguments");
+    SLG_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    slg_plan *p = plan_new(ctx, g, &s_min, 1, st);
+    if (!p) return fail(ctx, SLG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    slg_status rc = plan_rows(p);
+    if (rc == SLG_OK) {
+        const int64_t m = g->inc.num_hyperedges;
+        if (hipMemcpyAsync(prefix, p->b.work_pre, (m + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            rc = fail(ctx, SLG_ERR_DEVICE, "copying the work prefix failed");
+    }
+    plan_free(p);
+    return rc;
 }
 
 slg_status slg_plan_stats(const slg_plan *p, int64_t *out, int32_t cap, int32_t *count) {
     if (!p || (!out && cap > 0) || cap < 0) return SLG_ERR_INVALID_ARG;
-    int64_t vals[15];
+    int64_t vals[20];
     vals[0] = p->S;
     for (int c = 0; c < kLightClasses; ++c) vals[1 + c] = p->list_count[c];
     vals[8] = p->list_count[kLightClasses];
@@ -1023,8 +1361,13 @@ slg_status slg_plan_stats(const slg_plan *p, int64_t *out, int32_t cap, int32_t 
     vals[12] = p->nbounds;
     vals[13] = p->heavy_edges;
     vals[14] = p->stored_ranks;
+    vals[15] = p->list_count[kLightClasses + 2];
+    vals[16] = p->dense_two_paths;
+    vals[17] = p->dense_edges;
+    vals[18] = std::min(p->dense_stored, p->dstore_cap);
+    vals[19] = p->dense_stored > p->dstore_cap ? 1 : 0;
     static_assert(kLightClasses == 7, "plan stats layout");
-    int32_t n = cap < 15 ? cap : 15;
+    int32_t n = cap < 20 ? cap : 20;
     for (int32_t t = 0; t < n; ++t) out[t] = vals[t];
     if (count) *count = n;
     return SLG_OK;
@@ -1070,11 +1413,21 @@ slg_status slg_context_reset_timing(slg_context *ctx) {
         ctx->stage_launches[sg] = 0;
         ctx->stage_ms[sg] = 0.0;
     }
+    for (int t = 0; t < kNumWork; ++t) ctx->work[t] = 0;
+    return SLG_OK;
+}
+
+slg_status slg_context_get_work(const slg_context *ctx, int64_t *out, int32_t cap, int32_t *count) {
+    if (!ctx || cap < 0 || (cap > 0 && !out)) return SLG_ERR_INVALID_ARG;
+    const int32_t n = cap < kNumWork ? cap : kNumWork;
+    for (int32_t t = 0; t < n; ++t) out[t] = ctx->work[t];
+    if (count) *count = n;
     return SLG_OK;
 }
 
 slg_status slg_plan_destroy(slg_plan *p) {
     if (!p) return SLG_ERR_INVALID_ARG;
+    p->scratch2.release();
     p->scratch.release();
     delete p;
     return SLG_OK;
@@ -1086,6 +1439,14 @@ slg_status slg_context_set_count_store(slg_context *ctx, int64_t max_bytes, int6
         return fail(ctx, SLG_ERR_INVALID_ARG, "max_bytes and min_two_paths must be >= 0");
     ctx->store_limit = max_bytes;
     ctx->store_min = min_two_paths;
+    return SLG_OK;
+}
+
+slg_status slg_context_set_dense(slg_context *ctx, int32_t min_ratio, int32_t min_range) {
+    if (!ctx) return SLG_ERR_INVALID_ARG;
+    if (min_ratio < 0 || min_range < 0) return fail(ctx, SLG_ERR_INVALID_ARG, "min_ratio and min_range must be >= 0");
+    ctx->dense_ratio = min_ratio;
+    ctx->dense_min = min_range > 0 ? min_range : kDenseMinRange;
     return SLG_OK;
 }
 
@@ -1350,6 +1711,8 @@ void copy_tuning(slg_context *dst, const slg_context *src) {
     dst->heavy_grid = src->heavy_grid;
     dst->store_limit = src->store_limit;
     dst->store_min = src->store_min;
+    dst->dense_ratio = src->dense_ratio;
+    dst->dense_min = src->dense_min;
 }
 
 slg_status serve_query(slg_context *wctx, slg_graph *g, const int32_t *s, int32_t num_s, hipStream_t st,

@@ -20,15 +20,25 @@ constexpr int kRangeWords = kRangeBits / 32;
 constexpr int kRankCap = 4096;         // overlap counters per rank window (LDS, u16)
 constexpr int64_t kSlotWork = 4096;    // 2-paths per heavy slot before a row is split
 constexpr int kWideMembers = 65535;    // rows this large need u32 overlap counters
+// Dense tier: a row whose partners fill most of E_s (at least dense_ratio
+// 2-paths per candidate partner) counts into direct LDS counters over
+// aligned windows of kDenseWindow consecutive E_s positions.
+constexpr int kDenseBits = 15;
+constexpr int kDenseWindow = 1 << kDenseBits;  // E_s positions per dense slot (u16 counters, 64 KB)
+constexpr int kDenseThreads = 512;            // workgroup of the dense tier (2 per CU)
+constexpr int kDenseRatio = 4;                // default: 2-paths per candidate partner to go dense
+constexpr int kDenseMinRange = kDenseWindow / 4;  // default: fewest candidate partners to go dense
 
 // Row classes written by the planning kernel.
 enum RowClass : uint8_t {
     kNone = 0,
     kLight0 = 1,
     kHeavy = kLight0 + kLightClasses,  // bitmap-rank tier, u16 counters
-    kHeavyWide = kHeavy + 1            // bitmap-rank tier, u32 counters
+    kHeavyWide = kHeavy + 1,           // bitmap-rank tier, u32 counters
+    kDense = kHeavyWide + 1            // direct-counter tier over E_s windows
 };
-constexpr int kNumLists = kLightClasses + 2;  // light classes + heavy + heavy-wide slots
+constexpr int kNumLists = kLightClasses + 3;  // light classes + heavy + heavy-wide + dense slots
+constexpr int kNumHeavyLists = 3;             // heavy, heavy-wide, dense descriptor lists
 
 // Per-call parameters, passed by value and staged in LDS by each kernel so
 // that a runtime threshold index reads LDS, not a private copy.
@@ -55,6 +65,13 @@ struct Pruned {
     const int32_t *vs_idx;
     const int32_t *tail_beg;  // per incidence (i, v): first position in v's list after i
     const int32_t *row_s;     // per-row threshold (batched form), or null for s_min
+    // E_s positions (the dense tier; null when the plan has none): cid[i] =
+    // rank of row i among the kept rows (-1 if pruned), cid_row[c] = the row
+    // of rank c, and vs_cid = vs_idx with every id replaced by its rank
+    // (ranks keep the id order, so the lists stay sorted).
+    const int32_t *cid;
+    const int32_t *cid_row;
+    const int32_t *vs_cid;
 };
 
 // Slot table: a slot is (row i, hyperedge-id range) with its own output
@@ -67,7 +84,9 @@ struct Slots {
 // One heavy slot, stored in processing order. The row's boundary table
 // holds, for member q of e_i, bounds[bptr + q] = first position of q's tail
 // with a partner >= ja, and bounds[bptr + k + q] = the same for jb (the next
-// slot's start, or the tail end for the row's last slot).
+// slot's start, or the tail end for the row's last slot). A dense slot's
+// ja, jb are E_s positions: ja is a multiple of kDenseWindow and the slot's
+// partners lie in [ja, ja + kDenseWindow).
 struct HeavyDesc {
     int32_t row, ja, jb, k;  // row i, partner range [ja, jb), k = |e_i|
     int32_t slot, last;      // output segment; 1 on the row's last slot
@@ -79,6 +98,11 @@ struct HeavyDesc {
 // (partner - ja) | overlap << 16 (a slot spans at most 2^16 ids, and a
 // non-wide row has fewer than 2^16 members); off is the exclusive prefix of
 // the slots' 2-path counts, which bound their distinct partners.
+// The dense tier's store holds only the partners whose overlap reaches the
+// smallest threshold, each (E_s position - ja) | overlap << 16; a slot
+// reserves its room when it knows its count (off[t] from a device cursor),
+// and n[t] = -1 marks a slot that found the store full (its emit walks the
+// 2-paths again).
 struct CountStore {
     uint32_t *ent;
     int64_t *off;
@@ -114,19 +138,38 @@ hipError_t launch_compact_vertex_lists(int64_t n, int64_t nnz, const int64_t *v_
                                        const int64_t *pos, int64_t *vs_ptr, int32_t *vs_idx,
                                        hipStream_t st);
 
-// K1/K2: per kept row, tail offsets, 2-path work, last partner, slot count.
-hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t light_max, int64_t slot_work,
-                           int32_t *tail_beg, int64_t *work, int32_t *jmax, int32_t *nslots, uint8_t *rclass,
-                           int64_t *bsize, unsigned long long *class_count, int *err,
-                           unsigned long long *heavy_work, int64_t *pieces, unsigned long long *num_pieces,
+// E_s positions: flag[i] = row i kept at s_min (or its own threshold), pre =
+// its exclusive scan (int64[m+1]), then cid / cid_row, and vs_cid over the
+// pruned lists (vs_ptr[n] entries).
+hipError_t launch_row_keep(int64_t m, const int64_t *he_ptr, int32_t s_min, const int32_t *row_s, uint8_t *flag,
                            hipStream_t st);
+hipError_t launch_cid(int64_t m, const uint8_t *flag, const int64_t *pre, int32_t *cid, int32_t *cid_row,
+                      hipStream_t st);
+hipError_t launch_vs_cid(int64_t n, int64_t m, int64_t nnz, const int64_t *vs_ptr, const int32_t *vs_idx,
+                         const int32_t *cid, int32_t *vs_cid, hipStream_t st);
+
+// K1/K2: per kept row, tail offsets, 2-path work, last partner, slot count.
+// dense_ratio = 0 keeps every row off the dense tier (then g.cid may be
+// null); dense_work gets the 2-paths of dense rows.
+hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t light_max, int64_t slot_work,
+                           int32_t dense_ratio, int32_t dense_min, int32_t *tail_beg, int64_t *work, int32_t *jmax,
+                           int32_t *nslots, uint8_t *rclass, int64_t *bsize, unsigned long long *class_count,
+                           int *err, unsigned long long *heavy_work, unsigned long long *dense_work, int64_t *pieces,
+                           unsigned long long *num_pieces, hipStream_t st);
 // Light lists and heavy descriptors (heavy lists in slot order). hat:
-// int64[2 (m + 1)] and hcnt: int32[2 m] scratch, partials: scan_partials_size(m).
+// int64[3 (m + 1)] and hcnt: int32[3 m] scratch, partials: scan_partials_size(m).
 hipError_t launch_fill_slots(int64_t m, const int64_t *he_ptr, const int64_t *slot_base,
                              const int32_t *nslots, const int32_t *jmax, const uint8_t *rclass,
-                             const int64_t *bbase, int64_t *hat, int32_t *hcnt, int64_t *partials,
-                             int32_t *slot_row, int32_t *const *lists, HeavyDesc *const *heavy, const int64_t *caps,
-                             unsigned long long *list_fill, int *err, hipStream_t st);
+                             const int64_t *bbase, const int32_t *cid, int64_t *hat, int32_t *hcnt,
+                             int64_t *partials, int32_t *slot_row, int32_t *const *lists, HeavyDesc *const *heavy,
+                             const int64_t *caps, unsigned long long *list_fill, int *err, hipStream_t st);
+// A row block [r0, r1): nslots / rclass / bsize of the other rows zeroed
+// (from the *_all copies of every row), the block's list sizes and heavy /
+// dense 2-paths added to class_count / heavy_work / dense_work.
+hipError_t launch_block_mask(int64_t m, int64_t r0, int64_t r1, const int32_t *nslots_all, const uint8_t *rclass_all,
+                             const int64_t *bsize_all, const int64_t *work, int32_t *nslots, uint8_t *rclass,
+                             int64_t *bsize, unsigned long long *class_count, unsigned long long *heavy_work,
+                             unsigned long long *dense_work, hipStream_t st);
 // out[0..1] = positions of the first slot >= s0 and >= s1 in a heavy list.
 hipError_t launch_heavy_range(const HeavyDesc *desc, int64_t count, int64_t s0, int64_t s1, int64_t *out,
                               hipStream_t st);
@@ -154,9 +197,24 @@ hipError_t launch_heavy(bool emit, bool wide, const HeavyDesc *desc, int64_t cou
 // work[t] = 2-paths of heavy slot t (from the boundary table).
 hipError_t launch_slot_work(const HeavyDesc *desc, int64_t count, const int32_t *bounds, int64_t *work,
                             hipStream_t st);
-// Emit pass of the heavy slots from the counting pass's store.
+// Emit pass of the heavy slots from the counting pass's store. cid_row
+// (dense slots) maps the stored E_s positions back to row ids; slots with
+// n[t] < 0 are left to launch_dense(emit).
 hipError_t launch_heavy_store_emit(const HeavyDesc *desc, int64_t count, int64_t slots, const CountStore &store,
-                                   const EmitParams &ep, const int64_t *slot_off, hipStream_t st);
+                                   const EmitParams &ep, const int64_t *slot_off, const int32_t *cid_row,
+                                   hipStream_t st);
+// Dense tier, persistent like launch_heavy. Counting pass (emit = false):
+// slot_cnt gets every threshold's survivors and, with a store, the slot's
+// survivors of the smallest threshold go to the store (room reserved from
+// store_cursor, up to store_cap entries). Emit pass: writes the outputs by
+// walking the 2-paths again, for every slot (store == null) or only those
+// the store could not hold (n[t] < 0).
+hipError_t launch_dense(bool emit, const HeavyDesc *desc, int64_t count, int64_t slots, const int32_t *bounds,
+                        const Pruned &g, const EmitParams &ep, int64_t *slot_cnt, const int64_t *slot_off,
+                        int64_t *ticket, int resident, const CountStore *store, int64_t *store_cursor,
+                        int64_t store_cap, hipStream_t st);
+// Workgroups of the dense kernel that fit on the device at once.
+int dense_resident(int device);
 // *out += sum of n[0..count) (int32).
 hipError_t launch_sum_i32(const int32_t *n, int64_t count, int64_t *out, hipStream_t st);
 hipError_t launch_heavy_edges(const HeavyDesc *desc, int64_t count, const int64_t *slot_cnt, int64_t S,

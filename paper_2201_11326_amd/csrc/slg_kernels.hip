@@ -274,6 +274,41 @@ __global__ void compact_ptr_kernel(int64_t n, int64_t nnz, const int64_t *__rest
     vs_ptr[v] = pos[q];
 }
 
+// E_s positions of the kept rows (the dense tier's counter index): the rank
+// of every kept row among the kept rows, its inverse, and the pruned vertex
+// lists rewritten in ranks. Ranks keep the id order, so a list stays sorted
+// and its tails are at the same positions.
+__global__ void row_keep_kernel(int64_t m, const int64_t *__restrict__ he_ptr, int32_t s_min,
+                                const int32_t *__restrict__ row_s, uint8_t *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int64_t size = he_ptr[i + 1] - he_ptr[i];
+    flag[i] = size > 0 && size >= (row_s ? row_s[i] : s_min);
+}
+
+__global__ void cid_kernel(int64_t m, const uint8_t *__restrict__ flag, const int64_t *__restrict__ pre,
+                           int32_t *__restrict__ cid, int32_t *__restrict__ cid_row) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const bool kept = flag[i] != 0;
+    cid[i] = kept ? (int32_t)pre[i] : -1;
+    if (kept) cid_row[pre[i]] = (int32_t)i;
+}
+
+// An id outside [0, m) (a malformed vertex CSR, which the row plan flags)
+// gets -1, which no window holds.
+__global__ void vs_cid_kernel(int64_t n, int64_t m, int64_t cap, const int64_t *__restrict__ vs_ptr,
+                              const int32_t *__restrict__ vs_idx, const int32_t *__restrict__ cid,
+                              int32_t *__restrict__ vs_cid) {
+    int64_t total = vs_ptr[n];
+    if (total > cap) total = cap;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += stride) {
+        const int32_t r = vs_idx[p];
+        vs_cid[p] = (r >= 0 && r < m) ? cid[r] : -1;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // K2: per-row plan (one wavefront per hyperedge, grid-stride)
 // ---------------------------------------------------------------------------
@@ -302,6 +337,9 @@ struct RowPlanOut {
     int32_t *nslots;
     uint8_t *rclass;
     int64_t *bsize;
+    int32_t dense_ratio;  // the dense tier's rule (0: off)
+    int32_t dense_min;
+    unsigned long long *dense_work;
 };
 
 // One member of row i: its tail in v's list; returns false when the
@@ -327,18 +365,31 @@ __device__ __forceinline__ bool plan_member(const Pruned &g, int64_t i, int64_t 
     return found;
 }
 
-// Tier, slot count and boundary-table size of row i from its totals.
-__device__ __forceinline__ void plan_finish(int64_t i, int64_t p0, int64_t p1, int64_t w, int jm, bool bad,
-                                            int32_t light_max, int64_t slot_work, const RowPlanOut &o,
+// Tier, slot count and boundary-table size of row i from its totals. A
+// heavy row goes to the dense tier when its candidate partners (the kept
+// rows in (i, jm]) number at least dense_min and it has at least
+// dense_ratio 2-paths per candidate: its slots are then the aligned
+// kDenseWindow windows of E_s positions that (i, jm] touches.
+__device__ __forceinline__ void plan_finish(const Pruned &g, int64_t i, int64_t p0, int64_t p1, int64_t w, int jm,
+                                            bool bad, int32_t light_max, int64_t slot_work, const RowPlanOut &o,
                                             unsigned long long *ccount, unsigned long long *hwork, int *err) {
     int cls = kNone;
     int64_t ns = 0;
     if (bad) {
         atomicOr(err, 1);
     } else if (w > 0) {
+        int64_t ci = -1, cj = -1;
+        if (w > light_max && o.dense_ratio > 0 && g.cid && p1 - p0 < kWideMembers && jm > i && jm < g.m) {
+            ci = g.cid[i];
+            cj = g.cid[jm];
+        }
+        const int64_t crange = cj - ci;  // kept rows in (i, jm]
         if (w <= light_max) {
             cls = kLight0 + light_class(w);
             ns = 1;
+        } else if (ci >= 0 && cj > ci && crange >= o.dense_min && w >= (int64_t)o.dense_ratio * crange) {
+            cls = kDense;
+            ns = (cj >> kDenseBits) - ((ci + 1) >> kDenseBits) + 1;
         } else {
             cls = (p1 - p0 >= kWideMembers) ? kHeavyWide : kHeavy;
             const int64_t range = (int64_t)jm - i;  // partners lie in [i+1, jm]
@@ -354,7 +405,8 @@ __device__ __forceinline__ void plan_finish(int64_t i, int64_t p0, int64_t p1, i
     o.rclass[i] = (uint8_t)cls;
     o.bsize[i] = cls >= kHeavy ? (ns + 1) * (p1 - p0) : 0;
     if (cls != kNone) atomicAdd(&ccount[cls - 1], (unsigned long long)ns);
-    if (cls >= kHeavy) atomicAdd(hwork, (unsigned long long)w);
+    if (cls == kHeavy || cls == kHeavyWide) atomicAdd(hwork, (unsigned long long)w);
+    if (cls == kDense) atomicAdd(o.dense_work, (unsigned long long)w);
 }
 
 // Small and middle rows, and the piece list of the large ones: a large row
@@ -381,7 +433,7 @@ __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min, 
         if (i < g.m) {
             const int64_t p0 = g.he_ptr[i], p1 = g.he_ptr[i + 1];
             if (p0 < 0 || p1 > g.nnz || p1 < p0) {  // malformed pointers
-                plan_finish(i, p0, p1, 0, -1, true, light_max, slot_work, o, ccount, &hwork, err);
+                plan_finish(g, i, p0, p1, 0, -1, true, light_max, slot_work, o, ccount, &hwork, err);
             } else {
                 const int64_t size = p1 - p0;
                 const bool kept = size > 0 && size >= (g.row_s ? g.row_s[i] : s_min);
@@ -395,7 +447,7 @@ __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min, 
                     bool rbad = false;
                     if (kept)
                         for (int64_t p = p0; p < p1; ++p) rbad |= !plan_member(g, i, p, o.tail_beg, w, jm);
-                    plan_finish(i, p0, p1, w, jm, rbad, light_max, slot_work, o, ccount, &hwork, err);
+                    plan_finish(g, i, p0, p1, w, jm, rbad, light_max, slot_work, o, ccount, &hwork, err);
                 }
             }
         }
@@ -414,7 +466,7 @@ __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min, 
             w = wave_sum(w);
             jm = wave_max(jm);
             rbad = wave_max(rbad);
-            if (lane == 0) plan_finish(r, q0, q1, w, jm, rbad != 0, light_max, slot_work, o, ccount, &hwork, err);
+            if (lane == 0) plan_finish(g, r, q0, q1, w, jm, rbad != 0, light_max, slot_work, o, ccount, &hwork, err);
         }
         // one reservation per wavefront for the pieces of its large rows
         const unsigned long long incl = wave_incl_scan(np);
@@ -499,12 +551,48 @@ __global__ __launch_bounds__(256) void row_piece_finish_kernel(Pruned g, int32_t
             jm = max(jm, piece_jm[t + k]);
         }
         // a malformed member has already set err
-        plan_finish(r, q0, q1, w, jm, false, light_max, slot_work, o, ccount, &hwork, err);
+        plan_finish(g, r, q0, q1, w, jm, false, light_max, slot_work, o, ccount, &hwork, err);
     }
     __syncthreads();
     if (threadIdx.x < kNumLists && ccount[threadIdx.x])
         atomicAdd(&class_count[threadIdx.x], ccount[threadIdx.x]);
     if (threadIdx.x == 0 && hwork) atomicAdd(heavy_work, hwork);
+}
+
+// A row block: rows outside [r0, r1) get no slots, no class and no boundary
+// entries (from the rows phase's values of every row), and the block's
+// list sizes and heavy / dense 2-paths are summed as the row plan sums them.
+__global__ __launch_bounds__(256) void block_mask_kernel(int64_t m, int64_t r0, int64_t r1,
+                                                         const int32_t *__restrict__ nslots_all,
+                                                         const uint8_t *__restrict__ rclass_all,
+                                                         const int64_t *__restrict__ bsize_all,
+                                                         const int64_t *__restrict__ work,
+                                                         int32_t *__restrict__ nslots, uint8_t *__restrict__ rclass,
+                                                         int64_t *__restrict__ bsize,
+                                                         unsigned long long *__restrict__ class_count,
+                                                         unsigned long long *__restrict__ heavy_work,
+                                                         unsigned long long *__restrict__ dense_work) {
+    __shared__ unsigned long long cc[kNumLists];
+    __shared__ unsigned long long hw, dw;
+    if (threadIdx.x < kNumLists) cc[threadIdx.x] = 0;
+    if (threadIdx.x == 0) hw = dw = 0;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+        const bool in = i >= r0 && i < r1;
+        const int c = in ? rclass_all[i] : kNone;
+        const int ns = in ? nslots_all[i] : 0;
+        nslots[i] = ns;
+        rclass[i] = (uint8_t)c;
+        bsize[i] = in ? bsize_all[i] : 0;
+        if (c != kNone) atomicAdd(&cc[c - 1], (unsigned long long)ns);
+        if (c == kHeavy || c == kHeavyWide) atomicAdd(&hw, (unsigned long long)work[i]);
+        if (c == kDense) atomicAdd(&dw, (unsigned long long)work[i]);
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumLists && cc[threadIdx.x]) atomicAdd(&class_count[threadIdx.x], cc[threadIdx.x]);
+    if (threadIdx.x == 0 && hw) atomicAdd(heavy_work, hw);
+    if (threadIdx.x == 0 && dw) atomicAdd(dense_work, dw);
 }
 
 // Tier lists filled by fill_slots_kernel.
@@ -593,6 +681,7 @@ __global__ void heavy_counts_kernel(int64_t m, const uint8_t *__restrict__ rclas
         const int c = rclass[i];
         cnt[i] = c == kHeavy ? nslots[i] : 0;
         cnt[m + i] = c == kHeavyWide ? nslots[i] : 0;
+        cnt[2 * m + i] = c == kDense ? nslots[i] : 0;
     }
 }
 
@@ -613,33 +702,47 @@ __global__ void heavy_range_kernel(const HeavyDesc *__restrict__ desc, int64_t c
     out[threadIdx.x] = lo;
 }
 
+struct HeavyLists {
+    HeavyDesc *l[kNumHeavyLists];  // heavy, heavy-wide, dense
+    int64_t cap[kNumHeavyLists];
+};
+
 __global__ __launch_bounds__(256) void heavy_desc_kernel(
     int64_t m, const int64_t *__restrict__ he_ptr, const int64_t *__restrict__ slot_base,
     const int32_t *__restrict__ nslots, const int32_t *__restrict__ jmax,
     const uint8_t *__restrict__ rclass, const int64_t *__restrict__ bbase,
-    const int64_t *__restrict__ hat, int32_t *__restrict__ slot_row, HeavyDesc *hh, HeavyDesc *hw,
-    int64_t cap_h, int64_t cap_w, int *__restrict__ err) {
+    const int64_t *__restrict__ hat, int32_t *__restrict__ slot_row, HeavyLists hl,
+    const int32_t *__restrict__ cid, int *__restrict__ err) {
     const int lane = lane_id();
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
     for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; i < m; i += nwaves) {
         const int cls = rclass[i];
         if (cls < kHeavy) continue;
+        const int h = cls - kHeavy;  // list: heavy, heavy-wide, dense
         const int ns = nslots[i];
-        const int64_t at = hat[(cls == kHeavy ? 0 : m + 1) + i];  // prefix of the class's slots
-        if (at < 0 || at + ns > (cls == kHeavy ? cap_h : cap_w)) {
+        const int64_t at = hat[h * (m + 1) + i];  // prefix of the class's slots
+        if (at < 0 || at + ns > hl.cap[h]) {
             if (lane == 0) atomicOr(err, 16);
             continue;
         }
-        HeavyDesc *lst = (cls == kHeavy ? hh : hw) + at;
+        HeavyDesc *lst = hl.l[h] + at;
         const int64_t base = slot_base[i];
         const int64_t range = (int64_t)jmax[i] - i;
         const int k = (int)(he_ptr[i + 1] - he_ptr[i]);
         const int64_t bb = bbase[i];
+        // dense slots: aligned windows of E_s positions from the window of
+        // the row's first candidate (its own position + 1)
+        const int64_t w0 = cls == kDense ? ((int64_t)cid[i] + 1) >> kDenseBits : 0;
         for (int t = lane; t < ns; t += 64) {
             HeavyDesc d;
             d.row = (int32_t)i;
-            d.ja = (int32_t)(i + 1 + range * t / ns);
-            d.jb = (int32_t)(i + 1 + range * (t + 1) / ns);
+            if (cls == kDense) {
+                d.ja = (int32_t)((w0 + t) << kDenseBits);
+                d.jb = (int32_t)((w0 + t + 1) << kDenseBits);
+            } else {
+                d.ja = (int32_t)(i + 1 + range * t / ns);
+                d.jb = (int32_t)(i + 1 + range * (t + 1) / ns);
+            }
             d.k = k;
             d.slot = (int32_t)(base + t);
             d.last = t == ns - 1;
@@ -1610,7 +1713,8 @@ constexpr int kQueue = 128;  // entries per threshold queue: < 64 kept + <= 64 a
 template <int MAXK>
 __global__ __launch_bounds__(256) void heavy_store_emit_kernel(const HeavyDesc *__restrict__ desc, int64_t count,
                                                                int64_t S, CountStore cs, EmitParams prm,
-                                                               const int64_t *__restrict__ slot_off) {
+                                                               const int64_t *__restrict__ slot_off,
+                                                               const int32_t *__restrict__ cid_row) {
     constexpr bool kQueued = MAXK <= 4;
     __shared__ EmitParams sp;
     __shared__ uint32_t queue[kQueued ? 4 : 1][kQueued ? MAXK : 1][kQueued ? kQueue : 1];
@@ -1624,6 +1728,7 @@ __global__ __launch_bounds__(256) void heavy_store_emit_kernel(const HeavyDesc *
         const HeavyDesc d = desc[t];
         if (d.slot < prm.slot_lo || d.slot >= prm.slot_hi) continue;  // outside the emitted chunk
         const int n = as_global(cs.n)[t];
+        if (n < 0) continue;  // the store was full: the slot's emit walks its 2-paths again
         const int64_t off = as_global(cs.off)[t];
         const int i = d.row;
         const int id0 = prm.row_base ? as_global(prm.row_base)[i] : 0;
@@ -1637,12 +1742,18 @@ __global__ __launch_bounds__(256) void heavy_store_emit_kernel(const HeavyDesc *
             sk[kk] = kk < K ? (row_thr ? srow : sp.s[kk]) : INT_MAX;
             fill[kk] = 0;
         }
+        // the partner of a stored entry: an id offset from ja, or (dense
+        // slots) an E_s position offset from ja, mapped back to its row id
+        auto partner = [&](uint32_t e) -> int {
+            const int local = (int)(e & 0xFFFFu);
+            return cid_row ? as_global(cid_row)[d.ja + local] - id0 : jbase + local;
+        };
         // writes `m` queued entries of threshold kk (lanes below m) at b[kk]
         auto flush = [&](int kk, int m) {
             if (lane < m) {
                 const uint32_t e = queue[wave][kk][lane];
                 const int64_t pos = b[kk] + lane;
-                as_global(sp.col[kk])[pos] = jbase + (int)(e & 0xFFFFu);
+                as_global(sp.col[kk])[pos] = partner(e);
                 as_global(sp.w[kk])[pos] = (int)(e >> 16);
                 if (sp.row[kk]) as_global(sp.row[kk])[pos] = i - id0;
             }
@@ -1678,7 +1789,7 @@ __global__ __launch_bounds__(256) void heavy_store_emit_kernel(const HeavyDesc *
                         }
                     } else if (surv) {
                         const int64_t pos = b[kk] + bits_below(mask);
-                        as_global(sp.col[kk])[pos] = jbase + (int)(e[q] & 0xFFFFu);
+                        as_global(sp.col[kk])[pos] = partner(e[q]);
                         as_global(sp.w[kk])[pos] = c;
                         if (sp.row[kk]) as_global(sp.row[kk])[pos] = i - id0;
                     }
@@ -1757,6 +1868,266 @@ __global__ __launch_bounds__(256) void bounds_kernel(
             val = vs_idx[end - 1] < d.ja ? end : lower_bound_i32(vs_idx, beg, end, d.ja);
         bounds[d.bptr + q] = val;
         if (d.last) bounds[d.bptr + d.k + q] = end;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K3-K5 dense tier: one workgroup per slot, direct LDS counters
+// ---------------------------------------------------------------------------
+// A dense slot is a row i and an aligned window [ja, ja + kDenseWindow) of
+// E_s positions; its 2-paths are the parts of its members' tails that fall
+// in the window (vertex lists in E_s positions, so the counter of partner c
+// is c - ja with no search). The counters are u16, two to a word: position
+// c - ja = x sits in word x mod kDenseWords, low half for x < kDenseWords,
+// so that partners that follow each other in a list (consecutive lanes)
+// hit consecutive words. A row of fewer than 2^16 members cannot overflow
+// a u16 overlap.
+constexpr int kDW = kDenseThreads / 64;                        // wavefronts per dense workgroup
+constexpr int kDenseWords = kDenseWindow / 2;                  // counter words (two u16 each)
+constexpr int kDenseWordsPer = kDenseWords / kDenseThreads;    // words per thread (32)
+constexpr int kDenseUnroll = 8;                                // loads in flight per lane
+static_assert(kDenseWordsPer % 4 == 0, "16-byte LDS accesses");
+static_assert(kDenseWords <= (1 << 16) && kDenseWindow <= (1 << 16), "16-bit store fields");
+
+struct DenseSmem {
+    uint32_t cnt[kDenseWords];
+    int32_t seg_a[kDenseThreads];        // segment start per member of the batch
+    int32_t seg_pre[kDenseThreads + 1];  // flattened start per member of the batch
+    int32_t wsum[kDW];
+    int32_t wsum2[kDW];
+    unsigned long long tally[SLG_MAX_S];
+    long long base;                      // store room of the slot (or -1)
+    int64_t next;                        // the next slot claimed
+};
+
+// Exclusive scan over the dense workgroup (trailing barrier included).
+__device__ __forceinline__ int dense_scan(int x, int32_t *wsum, int &total) {
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const int incl = wave_incl_scan(x);
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kDW; ++w) {
+        const int t = wsum[w];
+        pre += (w < wave) ? t : 0;
+        tot += t;
+    }
+    total = tot;
+    __syncthreads();  // wsum is free again
+    return pre + incl - x;
+}
+
+// Walks the laid-out segments (2-path f of the batch is member u's tail
+// position seg_a[u] + f - seg_pre[u]) and adds one to the counter of each
+// partner. Each wavefront takes an equal share of the flattened list, in
+// pieces of 64 * kDenseUnroll positions whose loads are all issued first.
+__device__ __forceinline__ void dense_walk(const int32_t *__restrict__ vs_cid, int total, int nseg, DenseSmem &sm,
+                                           int ja) {
+    if (total <= 0) return;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const int per = (total + kDW - 1) / kDW;
+    const int c0 = wave * per;
+    const int c1 = min(total, c0 + per);
+    if (c0 >= c1) return;
+    const int useg = min(nseg, kDenseThreads) - 1;
+    int ufirst = wave_segment_of(sm.seg_pre, 0, useg, c0);
+    for (int pb = c0; pb < c1; pb += 64 * kDenseUnroll) {
+        const int plast = min(c1, pb + 64 * kDenseUnroll) - 1;
+        const int ulast = wave_segment_of(sm.seg_pre, ufirst, useg, plast);
+        int src[kDenseUnroll];
+        if (ufirst == ulast) {  // the whole piece in one tail (the common case)
+            const int base = sm.seg_a[ufirst] - sm.seg_pre[ufirst];
+#pragma unroll
+            for (int r = 0; r < kDenseUnroll; ++r) src[r] = base + min(pb + lane + 64 * r, plast);
+        } else {
+            int fq[kDenseUnroll], u[kDenseUnroll];
+#pragma unroll
+            for (int r = 0; r < kDenseUnroll; ++r) {
+                fq[r] = min(pb + lane + 64 * r, plast);
+                u[r] = ufirst;
+            }
+            for (int len = ulast - ufirst + 1; len > 1;) {
+                const int half = len >> 1;
+#pragma unroll
+                for (int r = 0; r < kDenseUnroll; ++r)
+                    u[r] = sm.seg_pre[u[r] + half] <= fq[r] ? u[r] + half : u[r];
+                len -= half;
+            }
+#pragma unroll
+            for (int r = 0; r < kDenseUnroll; ++r) src[r] = sm.seg_a[u[r]] + (fq[r] - sm.seg_pre[u[r]]);
+        }
+        int c[kDenseUnroll];
+#pragma unroll
+        for (int r = 0; r < kDenseUnroll; ++r) c[r] = vs_cid[src[r]];
+#pragma unroll
+        for (int r = 0; r < kDenseUnroll; ++r) {
+            const unsigned x = (unsigned)(c[r] - ja);
+            if (pb + lane + 64 * r <= plast && x < (unsigned)kDenseWindow)
+                atomicAdd(&sm.cnt[x & (kDenseWords - 1)], 1u << ((x >> (kDenseBits - 1)) << 4));
+        }
+        ufirst = ulast;
+    }
+}
+
+// EMIT = false: the counting pass. Every threshold's survivors are tallied
+// into slot_cnt; with a store, the survivors of the smallest threshold are
+// kept, in partner order, for the emit pass. EMIT = true: the emit pass of
+// the slots without stored survivors (every slot when there is no store),
+// writing each threshold's edges in partner order at the slot's offsets.
+// Persistent workgroups take slots from a ticket counter; two fit per CU
+// (LDS), which takes at most 128 VGPRs (4 waves per SIMD).
+template <bool EMIT>
+__global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4))) void dense_kernel(const HeavyDesc *__restrict__ desc, int64_t count,
+                                                              int64_t S, const int32_t *__restrict__ bounds,
+                                                              const int32_t *__restrict__ vs_cid,
+                                                              const int32_t *__restrict__ cid_row, EmitParams prm,
+                                                              int64_t *__restrict__ slot_cnt,
+                                                              const int64_t *__restrict__ slot_off,
+                                                              unsigned long long *__restrict__ ticket,
+                                                              CountStore cs, unsigned long long *__restrict__ cursor,
+                                                              int64_t cap) {
+    __shared__ DenseSmem sm;
+    __shared__ EmitParams sp;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    stage_params(&sp, prm);
+    for (int x = tid; x < kDenseWords; x += kDenseThreads) sm.cnt[x] = 0u;
+    if (tid == 0) sm.next = (int64_t)atomicAdd(ticket, 1ull);
+    __syncthreads();
+    const int K = sp.k;
+    const bool store = cs.ent != nullptr;
+    while (true) {
+        const int64_t t = sm.next;
+        if (t >= count) break;
+        const HeavyDesc d = desc[t];
+        const int ja = d.ja, k = d.k;
+        bool skip = false;
+        if (EMIT) skip = d.slot < sp.slot_lo || d.slot >= sp.slot_hi || (store && as_global(cs.n)[t] >= 0);
+        __syncthreads();  // every thread has read sm.next
+        if (tid == 0) sm.next = (int64_t)atomicAdd(ticket, 1ull);
+        if (tid < SLG_MAX_S) sm.tally[tid] = 0ull;
+        if (skip) {  // workgroup-uniform
+            __syncthreads();
+            continue;
+        }
+        // count: every member's part of its tail inside the window
+        for (int qb = 0; qb < k; qb += kDenseThreads) {
+            const int q = qb + tid;
+            int a = 0, len = 0;
+            if (q < k) {
+                a = bounds[d.bptr + q];
+                const int b = bounds[d.bptr + k + q];
+                len = b > a ? b - a : 0;
+            }
+            int total;
+            const int excl = dense_scan(len, sm.wsum, total);
+            sm.seg_a[tid] = a;
+            sm.seg_pre[tid] = excl;
+            if (tid == 0) sm.seg_pre[kDenseThreads] = total;
+            __syncthreads();
+            dense_walk(vs_cid, total, k - qb, sm, ja);
+            __syncthreads();
+        }
+        // this thread's counters: words [tid * 32, tid * 32 + 32); half h
+        // holds the partners at positions h * kDenseWords + word. They are
+        // read 16 bytes (four words) at a time; `f(word, low, high)` sees
+        // each word in order, and with `clear` the words are zeroed for the
+        // next slot. A compiler barrier keeps every pass a fresh read.
+        auto for_words = [&](bool clear, auto &&f) {
+            __asm__ volatile("" ::: "memory");
+            uint4 *q = reinterpret_cast<uint4 *>(sm.cnt) + tid * (kDenseWordsPer / 4);
+#pragma unroll 2
+            for (int r = 0; r < kDenseWordsPer / 4; ++r) {
+                const uint4 v = q[r];
+                const int x = tid * kDenseWordsPer + 4 * r;
+                f(x, v.x & 0xFFFFu, v.x >> 16);
+                f(x + 1, v.y & 0xFFFFu, v.y >> 16);
+                f(x + 2, v.z & 0xFFFFu, v.z >> 16);
+                f(x + 3, v.w & 0xFFFFu, v.w >> 16);
+                if (clear) q[r] = make_uint4(0u, 0u, 0u, 0u);
+            }
+        };
+        const int s0 = sp.s[0];
+        if (!EMIT) {
+            // tallies of the larger thresholds, then the survivors of the
+            // smallest (kept in the store)
+            for (int kk = 1; kk < K; ++kk) {
+                const unsigned sk = (unsigned)sp.s[kk];
+                int c = 0;
+                for_words(false, [&](int, unsigned lo, unsigned hi) { c += (lo >= sk) + (hi >= sk); });
+                c = wave_sum(c);
+                if (lane == 0 && c) atomicAdd(&sm.tally[kk], (unsigned long long)c);
+            }
+            int n0 = 0, n1 = 0;
+            for_words(!store, [&](int, unsigned lo, unsigned hi) {
+                n0 += lo >= (unsigned)s0;
+                n1 += hi >= (unsigned)s0;
+            });
+            int tot0, tot1;
+            const int pos0 = dense_scan(n0, sm.wsum, tot0);
+            const int pos1 = dense_scan(n1, sm.wsum2, tot1);
+            const int n = tot0 + tot1;
+            if (tid == 0) sm.tally[0] = (unsigned long long)n;
+            if (store && tid == 0) {
+                long long b = -1;
+                if (n > 0) {
+                    const unsigned long long at = atomicAdd(cursor, (unsigned long long)n);
+                    b = at + (unsigned long long)n <= (unsigned long long)cap ? (long long)at : -1;
+                }
+                sm.base = b;
+                as_global(cs.off)[t] = b < 0 ? 0 : b;
+                as_global(cs.n)[t] = (n > 0 && b < 0) ? -1 : n;
+            }
+            __syncthreads();
+            if (store) {
+                const long long base = sm.base;
+                const auto ent = as_global(cs.ent);
+                long long q0 = base + pos0, q1 = base + tot0 + pos1;
+                for_words(true, [&](int x, unsigned lo, unsigned hi) {
+                    if (base < 0) return;
+                    if (lo >= (unsigned)s0) ent[q0++] = (uint32_t)x | (lo << 16);
+                    if (hi >= (unsigned)s0) ent[q1++] = (uint32_t)(x + kDenseWords) | (hi << 16);
+                });
+            }
+            if (tid < K) slot_cnt[(int64_t)tid * S + d.slot] = (int64_t)sm.tally[tid];
+        } else {
+            // per threshold, this slot's survivors in partner order
+            const int i = d.row;
+            for (int kk = 0; kk < K; ++kk) {
+                const unsigned sk = (unsigned)sp.s[kk];
+                int n0 = 0, n1 = 0;
+                for_words(false, [&](int, unsigned lo, unsigned hi) {
+                    n0 += lo >= sk;
+                    n1 += hi >= sk;
+                });
+                int tot0, tot1;
+                const int pos0 = dense_scan(n0, sm.wsum, tot0);
+                const int pos1 = dense_scan(n1, sm.wsum2, tot1);
+                if (tot0 + tot1 == 0) break;  // workgroup-uniform: larger thresholds have none either
+                const int64_t b = slot_off[(int64_t)kk * (S + 1) + d.slot] - sp.out_base[kk];
+                const auto colp = as_global(sp.col[kk]);
+                const auto wp = as_global(sp.w[kk]);
+                const auto rowp = as_global(sp.row[kk]);
+                const auto crow = as_global(cid_row) + ja;
+                int64_t q0 = b + pos0, q1 = b + tot0 + pos1;
+                for_words(false, [&](int x, unsigned lo, unsigned hi) {
+                    if (lo >= sk) {
+                        colp[q0] = crow[x];
+                        wp[q0] = (int)lo;
+                        if (rowp) rowp[q0] = i;
+                        ++q0;
+                    }
+                    if (hi >= sk) {
+                        colp[q1] = crow[x + kDenseWords];
+                        wp[q1] = (int)hi;
+                        if (rowp) rowp[q1] = i;
+                        ++q1;
+                    }
+                });
+            }
+            for_words(true, [](int, unsigned, unsigned) {});  // cleared for the next slot
+        }
+        __syncthreads();  // counters cleared, sm.next published
     }
 }
 
@@ -2010,6 +2381,12 @@ inline unsigned grid_for(int64_t n, int threads) {
     return (unsigned)(b < 1 ? 1 : b);
 }
 
+inline unsigned stride_grid(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 16384) b = 16384;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+
 inline unsigned wave_grid(int64_t rows, int waves_per_block, int64_t cap) {
     int64_t b = (rows + waves_per_block - 1) / waves_per_block;
     if (b > cap) b = cap;
@@ -2090,15 +2467,37 @@ hipError_t launch_compact_vertex_lists(int64_t n, int64_t nnz, const int64_t *v_
     return hipGetLastError();
 }
 
-hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t light_max, int64_t slot_work,
-                           int32_t *tail_beg, int64_t *work, int32_t *jmax, int32_t *nslots, uint8_t *rclass,
-                           int64_t *bsize, unsigned long long *class_count, int *err,
-                           unsigned long long *heavy_work, int64_t *pieces, unsigned long long *num_pieces,
+hipError_t launch_row_keep(int64_t m, const int64_t *he_ptr, int32_t s_min, const int32_t *row_s, uint8_t *flag,
                            hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    row_keep_kernel<<<grid_for(m, 256), 256, 0, st>>>(m, he_ptr, s_min, row_s, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_cid(int64_t m, const uint8_t *flag, const int64_t *pre, int32_t *cid, int32_t *cid_row,
+                      hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    cid_kernel<<<grid_for(m, 256), 256, 0, st>>>(m, flag, pre, cid, cid_row);
+    return hipGetLastError();
+}
+
+hipError_t launch_vs_cid(int64_t n, int64_t m, int64_t nnz, const int64_t *vs_ptr, const int32_t *vs_idx,
+                         const int32_t *cid, int32_t *vs_cid, hipStream_t st) {
+    if (nnz <= 0) return hipSuccess;
+    vs_cid_kernel<<<stride_grid(nnz), 256, 0, st>>>(n, m, nnz, vs_ptr, vs_idx, cid, vs_cid);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t light_max, int64_t slot_work,
+                           int32_t dense_ratio, int32_t dense_min, int32_t *tail_beg, int64_t *work, int32_t *jmax,
+                           int32_t *nslots, uint8_t *rclass, int64_t *bsize, unsigned long long *class_count,
+                           int *err, unsigned long long *heavy_work, unsigned long long *dense_work, int64_t *pieces,
+                           unsigned long long *num_pieces, hipStream_t st) {
     if (g.m <= 0) return hipSuccess;
     if (light_max <= 0 || light_max > kLightMax) light_max = kLightMax;
     if (slot_work <= 0) slot_work = kSlotWork;
-    const RowPlanOut o{tail_beg, work, jmax, nslots, rclass, bsize};
+    if (!g.cid) dense_ratio = 0;
+    const RowPlanOut o{tail_beg, work, jmax, nslots, rclass, bsize, dense_ratio, dense_min, dense_work};
     row_plan_kernel<<<wave_grid((g.m + 63) / 64, 4, 8192), 256, 0, st>>>(g, s_min, light_max, slot_work, o,
                                                                           class_count, err, heavy_work, pieces,
                                                                           plan_pieces_cap(g.nnz), num_pieces);
@@ -2116,9 +2515,9 @@ hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t light_max, in
 
 hipError_t launch_fill_slots(int64_t m, const int64_t *he_ptr, const int64_t *slot_base,
                              const int32_t *nslots, const int32_t *jmax, const uint8_t *rclass,
-                             const int64_t *bbase, int64_t *hat, int32_t *hcnt, int64_t *partials,
-                             int32_t *slot_row, int32_t *const *lists, HeavyDesc *const *heavy, const int64_t *caps,
-                             unsigned long long *list_fill, int *err, hipStream_t st) {
+                             const int64_t *bbase, const int32_t *cid, int64_t *hat, int32_t *hcnt,
+                             int64_t *partials, int32_t *slot_row, int32_t *const *lists, HeavyDesc *const *heavy,
+                             const int64_t *caps, unsigned long long *list_fill, int *err, hipStream_t st) {
     if (m <= 0) return hipSuccess;
     LightLists ll;
     for (int c = 0; c < kLightClasses; ++c) ll.l[c] = lists[c];
@@ -2127,12 +2526,28 @@ hipError_t launch_fill_slots(int64_t m, const int64_t *he_ptr, const int64_t *sl
     fill_slots_kernel<<<grid_for(m, 256 * kFillRows), 256, 0, st>>>(m, he_ptr, slot_base, nslots, jmax, rclass,
                                                                      bbase, slot_row, ll, hat, list_fill);
     heavy_counts_kernel<<<grid_for(m, 256) < 8192 ? grid_for(m, 256) : 8192, 256, 0, st>>>(m, rclass, nslots, hcnt);
-    hipError_t e = exclusive_scan(hcnt, m, hat, partials, st);
-    if (e != hipSuccess) return e;
-    if ((e = exclusive_scan(hcnt + m, m, hat + m + 1, partials, st)) != hipSuccess) return e;
+    hipError_t e;
+    for (int h = 0; h < kNumHeavyLists; ++h)
+        if ((e = exclusive_scan(hcnt + (int64_t)h * m, m, hat + (int64_t)h * (m + 1), partials, st)) != hipSuccess)
+            return e;
+    HeavyLists hl;
+    for (int h = 0; h < kNumHeavyLists; ++h) {
+        hl.l[h] = heavy[h];
+        hl.cap[h] = caps[kLightClasses + h];
+    }
     heavy_desc_kernel<<<wave_grid(m, 4, 8192), 256, 0, st>>>(m, he_ptr, slot_base, nslots, jmax, rclass,
-                                                              bbase, hat, slot_row, heavy[0], heavy[1],
-                                                              caps[kLightClasses], caps[kLightClasses + 1], err);
+                                                              bbase, hat, slot_row, hl, cid, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_mask(int64_t m, int64_t r0, int64_t r1, const int32_t *nslots_all, const uint8_t *rclass_all,
+                             const int64_t *bsize_all, const int64_t *work, int32_t *nslots, uint8_t *rclass,
+                             int64_t *bsize, unsigned long long *class_count, unsigned long long *heavy_work,
+                             unsigned long long *dense_work, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    const unsigned grid = grid_for(m, 256) < 4096 ? grid_for(m, 256) : 4096;
+    block_mask_kernel<<<grid, 256, 0, st>>>(m, r0, r1, nslots_all, rclass_all, bsize_all, work, nslots, rclass, bsize,
+                                            class_count, heavy_work, dense_work);
     return hipGetLastError();
 }
 
@@ -2224,15 +2639,51 @@ hipError_t launch_slot_work(const HeavyDesc *desc, int64_t count, const int32_t 
 }
 
 hipError_t launch_heavy_store_emit(const HeavyDesc *desc, int64_t count, int64_t slots, const CountStore &store,
-                                   const EmitParams &ep, const int64_t *slot_off, hipStream_t st) {
+                                   const EmitParams &ep, const int64_t *slot_off, const int32_t *cid_row,
+                                   hipStream_t st) {
     if (count <= 0) return hipSuccess;
     if (ep.k <= 4)
         heavy_store_emit_kernel<4><<<wave_grid(count, 4, 16384), 256, 0, st>>>(desc, count, slots, store, ep,
-                                                                                  slot_off);
+                                                                                  slot_off, cid_row);
     else
         heavy_store_emit_kernel<SLG_MAX_S><<<wave_grid(count, 4, 16384), 256, 0, st>>>(desc, count, slots, store,
-                                                                                          ep, slot_off);
+                                                                                          ep, slot_off, cid_row);
     return hipGetLastError();
+}
+
+hipError_t launch_dense(bool emit, const HeavyDesc *desc, int64_t count, int64_t slots, const int32_t *bounds,
+                        const Pruned &g, const EmitParams &ep, int64_t *slot_cnt, const int64_t *slot_off,
+                        int64_t *ticket, int resident, const CountStore *store, int64_t *store_cursor,
+                        int64_t store_cap, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    if (!g.vs_cid || !g.cid_row || (store && !emit && !store_cursor)) return hipErrorInvalidValue;
+    const int64_t want = resident > 0 ? resident : 512;
+    const unsigned grid = (unsigned)(count < want ? count : want);
+    unsigned long long *tk = reinterpret_cast<unsigned long long *>(ticket);
+    unsigned long long *cur = reinterpret_cast<unsigned long long *>(store_cursor);
+    const CountStore cs = store ? *store : CountStore{};
+    if (emit)
+        dense_kernel<true><<<grid, kDenseThreads, 0, st>>>(desc, count, slots, bounds, g.vs_cid, g.cid_row, ep,
+                                                            slot_cnt, slot_off, tk, cs, cur, store_cap);
+    else
+        dense_kernel<false><<<grid, kDenseThreads, 0, st>>>(desc, count, slots, bounds, g.vs_cid, g.cid_row, ep,
+                                                             slot_cnt, slot_off, tk, cs, cur, store_cap);
+    return hipGetLastError();
+}
+
+int dense_resident(int device) {
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 0;
+    const void *variants[2] = {reinterpret_cast<const void *>(dense_kernel<false>),
+                               reinterpret_cast<const void *>(dense_kernel<true>)};
+    for (const void *f : variants) {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, f, kDenseThreads, 0) != hipSuccess) v = 0;
+        per = (per == 0 || (v > 0 && v < per)) ? v : per;
+    }
+    if (cus <= 0) cus = 256;
+    if (per <= 0) per = 1;
+    return cus * per;
 }
 
 hipError_t launch_sum_i32(const int32_t *n, int64_t count, int64_t *out, hipStream_t st) {
@@ -2293,11 +2744,6 @@ hipError_t launch_union(const UnionPart *parts, int32_t count, int64_t max_elems
     return hipGetLastError();
 }
 
-inline unsigned stride_grid(int64_t n) {
-    int64_t b = (n + 255) / 256;
-    if (b > 16384) b = 16384;
-    return (unsigned)(b < 1 ? 1 : b);
-}
 
 hipError_t launch_cc_init(const int64_t *he_ptr, int64_t m, int32_t s, int32_t *label, hipStream_t st) {
     if (m <= 0) return hipSuccess;

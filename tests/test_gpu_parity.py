@@ -14,18 +14,23 @@ from helpers import load_toy
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module", params=["store", "rewalk"])
+@pytest.fixture(scope="module", params=["store", "rewalk", "dense", "dense_rewalk"])
 def ctx(request):
-    """Every parity case runs twice: with the count store (the emit pass
-    reads the heavy overlaps kept by the counting pass) and without it (the
-    emit pass walks the 2-paths again)."""
+    """Every parity case runs four times: with the count store (the emit
+    pass reads the heavy overlaps kept by the counting pass) and without it
+    (the emit pass walks the 2-paths again), each with the library's own
+    tier choice and with every heavy row that has at least one 2-path per
+    candidate partner forced onto the dense tier."""
     import paper_2201_11326_amd as slg
     c = slg.Context(0)
-    if request.param == "rewalk":
+    if request.param.endswith("rewalk"):
         c.set_count_store(0)
-    else:  # the store on every graph with heavy slots, however small
+    else:  # the stores on every graph with heavy or dense slots, however small
         c.set_count_store(32 << 30, 0)
-    c.store_mode = request.param
+    if request.param.startswith("dense"):
+        c.set_dense(1, 1)
+    c.store_mode = "rewalk" if request.param.endswith("rewalk") else "store"
+    c.dense_mode = request.param.startswith("dense")
     yield c
     c.close()
 
@@ -512,15 +517,21 @@ def test_batch_tuning_variants_agree(ctx):
 
 
 def test_count_store_engages_when_asked(ctx):
-    # rows sharing vertex 0 make heavy slots; with the store on, the counting
-    # pass keeps one entry per distinct heavy partner (s_min = 1: the heavy
-    # edges of L_1), with it off none
-    inc = planted(6000, 20000, [([0], 2, 0)], 3, seed=17)
+    # every row holds vertex 0, so rows have heavy slots (or, with the dense
+    # tier forced, at least one 2-path per candidate partner: dense slots);
+    # with the store on, the counting pass keeps one entry per distinct
+    # heavy partner (s_min = 1: the heavy edges of L_1), with it off none
+    inc = planted(6000, 20000, [([0], 1, 0)], 3, seed=17)
     g = ctx.register_incidence(inc)
     p = ctx.plan(g, [1])
     st = p.stats()
-    assert st["heavy_slots"] > 0 and st["heavy_edges"] > 0
-    want = st["heavy_edges"] if ctx.store_mode == "store" else 0
-    assert st["stored_ranks"] == want
+    if ctx.dense_mode:  # the same rows on the dense tier: its store keeps the survivors of s_min
+        assert st["dense_slots"] > 0 and st["dense_edges"] > 0
+        want = st["dense_edges"] if ctx.store_mode == "store" else 0
+        assert st["dense_stored"] == want and st["dense_store_full"] == 0
+    else:
+        assert st["heavy_slots"] > 0 and st["heavy_edges"] > 0
+        want = st["heavy_edges"] if ctx.store_mode == "store" else 0
+        assert st["stored_ranks"] == want
     p.destroy()
     g.release()

@@ -1,5 +1,5 @@
 """A seeded sweep of random hypergraph shapes and s-sets through the C ABI,
-with and without the count store, each compared with the oracle element by
+with and without the count store and with the dense tier forced, each compared with the oracle element by
 element (sizes from a single row to a few thousand, empty hyperedges,
 ragged tiles)."""
 from __future__ import annotations
@@ -17,12 +17,15 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def contexts():
     import paper_2201_11326_amd as slg
-    store, rewalk = slg.Context(0), slg.Context(0)
+    store, rewalk, dense = slg.Context(0), slg.Context(0), slg.Context(0)
     store.set_count_store(32 << 30, 0)  # the store wherever there are heavy slots
     rewalk.set_count_store(0)
-    yield {"store": store, "rewalk": rewalk}
+    dense.set_count_store(32 << 30, 0)
+    dense.set_dense(1, 1)  # every heavy row with a 2-path per candidate on the dense tier
+    yield {"store": store, "rewalk": rewalk, "dense": dense}
     store.close()
     rewalk.close()
+    dense.close()
 
 
 def _case(seed: int):

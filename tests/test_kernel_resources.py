@@ -46,5 +46,12 @@ def test_kernel_register_lds_budgets(tmp_path):
     for name, r in heavy.items():
         assert r["VGPRs"] <= 128 and r["Occupancy"] >= 4, (name, r)
         assert per_cu * r["LDS"] <= 160 * 1024, (name, r, per_cu)
+    # the dense tier: 512-thread workgroups, two per CU (8 waves per SIMD
+    # would need <= 64 VGPRs; two workgroups need <= 128 and 2 x LDS <= 160 KiB)
+    dense = {k: v for k, v in rows.items() if "dense_kernel" in k}
+    assert len(dense) == 2, sorted(rows)  # count, emit
+    for name, r in dense.items():
+        assert r["VGPRs"] <= 128 and r["Occupancy"] >= 4, (name, r)
+        assert 2 * r["LDS"] <= 160 * 1024, (name, r)
     for name, r in rows.items():
         assert r.get("ScratchSize", 0) == 0, (name, r)  # no register spills
