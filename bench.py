@@ -47,11 +47,15 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(kernel: str):
+DENSE_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "dense_tier_large_skewed_traffic.md")
+DENSE_SQ_PROFILE = os.path.join(ROOT, "profiles", "dense_tier_large_skewed_sq_counters.md")
+
+
+def measured_traffic(kernel: str, profile: str = TRAFFIC_PROFILE):
     """HBM bytes per launch of `kernel` from the committed PMC summary, if it
     was taken on the current kernel source; else None."""
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(profile).read()
     except OSError:
         return None
     m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
@@ -68,11 +72,11 @@ def measured_traffic(kernel: str):
 SQ_PROFILE = os.path.join(ROOT, "profiles", "heavy_tier_power_law_sq_counters.md")
 
 
-def measured_sq(kernel: str):
+def measured_sq(kernel: str, profile: str = None):
     """(waiting share of wave cycles, LDS bank-conflict rate) of `kernel` from
     the committed SQ-counter summary, if taken on the current kernel source."""
     try:
-        text = open(SQ_PROFILE).read()
+        text = open(profile or SQ_PROFILE).read()
     except OSError:
         return None
     m_hash = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
@@ -628,6 +632,8 @@ def bench_large_skewed(args) -> int:
     t_gen = time.perf_counter() - t_gen
     note(f"generated in {t_gen:.1f} s: nnz {inc.nnz}")
     ctx = slg.Context(0)
+    if args.dense_ratio is not None:
+        ctx.set_dense(args.dense_ratio, 0)
     g = ctx.register_incidence(inc)
     prefix = ctx.work_prefix(g, S[0])  # untimed: the ranges' cuts
     W = int(prefix[-1])
@@ -679,12 +685,12 @@ def bench_large_skewed(args) -> int:
     achieved = dense_bytes / (count_ms / 1e3) / 1e9 if count_ms > 0 else None
     emit_launches, emit_ms = stages.get("emit_dense", (0, 0.0))
     roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": measured_traffic("dense_kernel<false>"),
+                "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": measured_traffic("dense_kernel<false>", DENSE_TRAFFIC_PROFILE),
                 "kernel": "dense_kernel<false> (count_dense)", "launches": launches,
                 "avg_launch_ms": count_ms / max(launches, 1),
                 "algorithmic_bytes_per_launch": dense_bytes / max(launches, 1),
                 "overhead_bytes_per_launch": {"dense_store_written": 4 * work["dense_stored"] / max(launches, 1)},
-                "sq_counters": measured_sq("dense_kernel<false>"),
+                "sq_counters": measured_sq("dense_kernel<false>", DENSE_SQ_PROFILE),
                 "emit": {"kernel": "heavy_store_emit_kernel<4> on dense slots (emit_dense)",
                          "launches": emit_launches, "ms": emit_ms,
                          "algorithmic_bytes": 12 * work["dense_edges"],
@@ -703,6 +709,7 @@ def bench_large_skewed(args) -> int:
                                f"one step = one of {B} row ranges of equal 2-path work (all of them: every row once)",
                    "n": inc.n, "m": inc.m, "nnz": inc.nnz, "s": S, "seed": hg.BASE_SEED + 3,
                    "ranges": B, "consumer": "on-device digest per chunk" if args.digest else "edge count per chunk",
+                   "dense_ratio": args.dense_ratio,
                    "parallelism": "single GPU"},
         "two_paths_per_step": timed_two_paths / args.steps, "two_paths_whole_graph": W,
         "edges_timed": edges, "edges_per_s": edges_total / elapsed,
@@ -734,6 +741,8 @@ def main() -> int:
                          "hypergraphs, each with its own s, as one disjoint-union batch; served: a request "
                          "loop; components: components, squeezing and symmetric CSR of the power-law L_s; "
                          "preprocess: relabel-by-degree and toplexes of the power-law hypergraph")
+    ap.add_argument("--dense-ratio", type=int, default=None,
+                    help="large_skewed: the dense tier's 2-paths per candidate partner (default: the library's)")
     ap.add_argument("--digest", action="store_true",
                     help="large_skewed: digest every streamed chunk on the device (default: count its edges)")
     ap.add_argument("--no-tune", action="store_true", help="batched: library-default plan shape")

@@ -213,6 +213,75 @@ bool valid_s(const int32_t *s, int32_t k) {
     return true;
 }
 
+// Stable sort of n int32 keys in [0, 2^key_bits) with up to two payloads
+// (b only with a), from the *_in arrays into the *_out arrays (which may be
+// caller memory), through scratch from `sc` when more than one digit pass is
+// needed. With key_bits = 0 the inputs are copied. With `in_scratch`, the
+// outputs are not given: the last pass writes scratch too (two buffers per
+// array in all) and *_out receive where the sorted arrays are.
+hipError_t sort_pairs(Scratch &sc, const int32_t *key_in, const int32_t *a_in, const int32_t *b_in, int64_t n,
+                      int key_bits, int32_t *key_out, int32_t *a_out, int32_t *b_out, hipStream_t st,
+                      const int32_t **in_scratch = nullptr) {
+    if (n <= 0) return hipSuccess;
+    const int passes = sort_passes(key_bits);
+    hipError_t e;
+    if (in_scratch && passes == 0) {  // already in order: the inputs themselves
+        in_scratch[0] = key_in;
+        in_scratch[1] = a_in;
+        in_scratch[2] = b_in;
+        return hipSuccess;
+    }
+    if (passes == 0) {
+        const int32_t *src[3] = {key_in, a_in, b_in};
+        int32_t *dst[3] = {key_out, a_out, b_out};
+        for (int t = 0; t < 3; ++t)
+            if (src[t] && dst[t] && src[t] != dst[t] &&
+                (e = hipMemcpyAsync(dst[t], src[t], n * sizeof(int32_t), hipMemcpyDeviceToDevice, st)) != hipSuccess)
+                return e;
+        return hipSuccess;
+    }
+    const int digit = (key_bits + passes - 1) / passes;
+    const int64_t hist_n = (int64_t(1) << digit) * sort_chunks(n);
+    int32_t *hist = nullptr, *tmp[2][3] = {};
+    int64_t *off = nullptr, *part = nullptr;
+    if ((e = sc.get(&hist, hist_n)) != hipSuccess || (e = sc.get(&off, hist_n + 1)) != hipSuccess ||
+        (e = sc.get(&part, scan_partials_size(hist_n))) != hipSuccess)
+        return e;
+    const int arrays = b_in ? 3 : (a_in ? 2 : 1);
+    // pass p writes tmp[p & 1] except the last, which writes the outputs
+    // (or tmp as well, with in_scratch)
+    const int bufs = in_scratch ? (passes > 1 ? 2 : 1) : (passes > 2 ? 2 : passes - 1);
+    for (int h = 0; h < bufs; ++h)
+        for (int t = 0; t < arrays; ++t)
+            if ((e = sc.get(&tmp[h][t], n)) != hipSuccess) return e;
+    const int32_t *k = key_in, *a = a_in, *b = b_in;
+    for (int p = 0; p < passes; ++p) {
+        const bool last = p + 1 == passes && !in_scratch;
+        int32_t *ko = last ? key_out : tmp[p & 1][0];
+        int32_t *ao = a_in ? (last ? a_out : tmp[p & 1][1]) : nullptr;
+        int32_t *bo = b_in ? (last ? b_out : tmp[p & 1][2]) : nullptr;
+        const int shift = p * digit;
+        if ((e = launch_sort_pass(k, a, b, n, shift, std::min(digit, key_bits - shift), hist, off, part, ko, ao, bo,
+                                  st)) != hipSuccess)
+            return e;
+        k = ko;
+        a = ao;
+        b = bo;
+    }
+    if (in_scratch) {
+        in_scratch[0] = k;
+        in_scratch[1] = a;
+        in_scratch[2] = b;
+    }
+    return hipSuccess;
+}
+
+int bits_for(int64_t values) {  // bits of the largest value below `values`
+    int b = 0;
+    while ((int64_t(1) << b) < values) ++b;
+    return b;
+}
+
 }  // namespace
 
 // Device buffers of a plan, kept so the planning launches can be replayed.
@@ -274,6 +343,8 @@ struct slg_plan {
     bool use_lstore = false;       // ... and the light rows' overlaps
     LightStore lstore{};
     int32_t *lwork = nullptr;      // [m]: 2-paths of the light rows
+    int32_t *dorder = nullptr;     // [dense slots]: the counting pass's order (window-major)
+    int64_t kept_rows = 0;         // |E_{s_min}|
     int64_t *store_work = nullptr; // [heavy slots]: 2-paths per slot
     int64_t store_limit = 0;
     int64_t store_min = 0;
@@ -675,12 +746,29 @@ hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
                               (p->use_store && !wide) ? &p->store : nullptr, st)) != hipSuccess)
             return e;
     }
-    if (p->list_count[kLightClasses + 2] > 0) {
+    const int64_t nd = p->list_count[kLightClasses + 2];
+    if (nd > 0) {
+        // window-major order: the workgroups in flight count the same
+        // window of E_s for many rows, so the vertex-list segments of that
+        // window are read from L2 instead of HBM (stable: rows stay in order)
+        const int32_t *order = nullptr;
+        if (nd > 1 && p->dorder) {
+            StageTimer tm(ctx, kStSlots, st);
+            int32_t *key = nullptr, *id = nullptr, *skey = nullptr;
+            if ((e = p->scratch2.get(&key, nd)) != hipSuccess || (e = p->scratch2.get(&id, nd)) != hipSuccess ||
+                (e = p->scratch2.get(&skey, nd)) != hipSuccess)
+                return e;
+            if ((e = launch_dense_keys(p->heavy[2], nd, key, id, st)) != hipSuccess) return e;
+            const int64_t windows = (p->kept_rows >> kDenseBits) + 1;
+            if ((e = sort_pairs(p->scratch2, key, id, nullptr, nd, bits_for(windows), skey, p->dorder, nullptr, st)) !=
+                hipSuccess)
+                return e;
+            order = p->dorder;
+        }
         StageTimer tm(ctx, kStCountDense, st);
-        if ((e = launch_dense(false, p->heavy[2], p->list_count[kLightClasses + 2], p->S, p->bounds, p->pr, p->prm,
-                              p->slot_cnt, nullptr, p->tickets + kTkCount + 2, p->dense_grid,
-                              p->use_dstore ? &p->dstore : nullptr, p->tickets + kTkDenseCursor, p->dstore_cap,
-                              st)) != hipSuccess)
+        if ((e = launch_dense(false, p->heavy[2], nd, order, p->S, p->bounds, p->pr, p->prm, p->slot_cnt, nullptr,
+                              p->tickets + kTkCount + 2, p->dense_grid, p->use_dstore ? &p->dstore : nullptr,
+                              p->tickets + kTkDenseCursor, p->dstore_cap, st)) != hipSuccess)
             return e;
     }
     StageTimer tm(ctx, kStCountScans, st);
@@ -780,7 +868,9 @@ slg_status plan_rows(slg_plan *p) {
     BUILD_HIP(hipMemcpyAsync(hb + kHbSlots, p->slot_base + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     BUILD_HIP(hipMemcpyAsync(hb + kHbSlots + 1, b.work_pre + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     BUILD_HIP(hipMemcpyAsync(hb + kHbSlots + 2, b.bbase + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    if (p->dense) BUILD_HIP(hipMemcpyAsync(hb + kHbRange + 1, b.kpre + m, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     BUILD_HIP(hipStreamSynchronize(st));
+    p->kept_rows = p->dense ? hb[kHbRange + 1] : 0;
     if (hb[kCntErr] & 0xffffffff)
         return fail(ctx, SLG_ERR_INVALID_GRAPH,
                     "malformed incidence (bad pointer, id out of range, or vertex CSR not the transpose)");
@@ -880,6 +970,7 @@ slg_status plan_block(slg_plan *p, int64_t r0, int64_t r1) {
                              nd * 12 - 16;
         p->dstore_cap = std::min<int64_t>(p->dense_two_paths / std::max(p->s_min, 1) + 1, left / 4);
         p->use_dstore = nd > 0 && p->dstore_cap > 0;
+        if (nd > 1) phase2.add(&p->dorder, nd);
         if (p->use_dstore) {
             phase2.add(&p->dstore.ent, p->dstore_cap);
             phase2.add(&p->dstore.off, nd);
@@ -1069,7 +1160,7 @@ slg_status emit_range(slg_plan *p, int64_t r0, int64_t r1, int64_t s0, int64_t s
             SLG_HIP(ctx, launch_heavy_store_emit(p->heavy[2] + lo[2], cnt, p->S, part, prm, p->slot_off,
                                                  p->pr.cid_row, st));
         if (!p->use_dstore || p->dense_stored > p->dstore_cap)
-            SLG_HIP(ctx, launch_dense(true, p->heavy[2] + lo[2], cnt, p->S, p->bounds, p->pr, prm, nullptr,
+            SLG_HIP(ctx, launch_dense(true, p->heavy[2] + lo[2], cnt, nullptr, p->S, p->bounds, p->pr, prm, nullptr,
                                       p->slot_off, p->tickets + kTkEmit + 2, p->dense_grid,
                                       p->use_dstore ? &part : nullptr, nullptr, 0, st));
     }
@@ -1872,78 +1963,6 @@ slg_status slg_squeeze(slg_context *ctx, int64_t m, int32_t *row, int32_t *col, 
     return SLG_OK;
 }
 
-namespace {
-
-// Stable sort of n int32 keys in [0, 2^key_bits) with up to two payloads
-// (b only with a), from the *_in arrays into the *_out arrays (which may be
-// caller memory), through scratch from `sc` when more than one digit pass is
-// needed. With key_bits = 0 the inputs are copied. With `in_scratch`, the
-// outputs are not given: the last pass writes scratch too (two buffers per
-// array in all) and *_out receive where the sorted arrays are.
-hipError_t sort_pairs(Scratch &sc, const int32_t *key_in, const int32_t *a_in, const int32_t *b_in, int64_t n,
-                      int key_bits, int32_t *key_out, int32_t *a_out, int32_t *b_out, hipStream_t st,
-                      const int32_t **in_scratch = nullptr) {
-    if (n <= 0) return hipSuccess;
-    const int passes = sort_passes(key_bits);
-    hipError_t e;
-    if (in_scratch && passes == 0) {  // already in order: the inputs themselves
-        in_scratch[0] = key_in;
-        in_scratch[1] = a_in;
-        in_scratch[2] = b_in;
-        return hipSuccess;
-    }
-    if (passes == 0) {
-        const int32_t *src[3] = {key_in, a_in, b_in};
-        int32_t *dst[3] = {key_out, a_out, b_out};
-        for (int t = 0; t < 3; ++t)
-            if (src[t] && dst[t] && src[t] != dst[t] &&
-                (e = hipMemcpyAsync(dst[t], src[t], n * sizeof(int32_t), hipMemcpyDeviceToDevice, st)) != hipSuccess)
-                return e;
-        return hipSuccess;
-    }
-    const int digit = (key_bits + passes - 1) / passes;
-    const int64_t hist_n = (int64_t(1) << digit) * sort_chunks(n);
-    int32_t *hist = nullptr, *tmp[2][3] = {};
-    int64_t *off = nullptr, *part = nullptr;
-    if ((e = sc.get(&hist, hist_n)) != hipSuccess || (e = sc.get(&off, hist_n + 1)) != hipSuccess ||
-        (e = sc.get(&part, scan_partials_size(hist_n))) != hipSuccess)
-        return e;
-    const int arrays = b_in ? 3 : (a_in ? 2 : 1);
-    // pass p writes tmp[p & 1] except the last, which writes the outputs
-    // (or tmp as well, with in_scratch)
-    const int bufs = in_scratch ? (passes > 1 ? 2 : 1) : (passes > 2 ? 2 : passes - 1);
-    for (int h = 0; h < bufs; ++h)
-        for (int t = 0; t < arrays; ++t)
-            if ((e = sc.get(&tmp[h][t], n)) != hipSuccess) return e;
-    const int32_t *k = key_in, *a = a_in, *b = b_in;
-    for (int p = 0; p < passes; ++p) {
-        const bool last = p + 1 == passes && !in_scratch;
-        int32_t *ko = last ? key_out : tmp[p & 1][0];
-        int32_t *ao = a_in ? (last ? a_out : tmp[p & 1][1]) : nullptr;
-        int32_t *bo = b_in ? (last ? b_out : tmp[p & 1][2]) : nullptr;
-        const int shift = p * digit;
-        if ((e = launch_sort_pass(k, a, b, n, shift, std::min(digit, key_bits - shift), hist, off, part, ko, ao, bo,
-                                  st)) != hipSuccess)
-            return e;
-        k = ko;
-        a = ao;
-        b = bo;
-    }
-    if (in_scratch) {
-        in_scratch[0] = k;
-        in_scratch[1] = a;
-        in_scratch[2] = b;
-    }
-    return hipSuccess;
-}
-
-int bits_for(int64_t values) {  // bits of the largest value below `values`
-    int b = 0;
-    while ((int64_t(1) << b) < values) ++b;
-    return b;
-}
-
-}  // namespace
 
 slg_status slg_symmetrize(slg_context *ctx, int64_t m, const int64_t *row_ptr, const int32_t *row,
                           const int32_t *col, const int32_t *w, int64_t num_edges, int64_t *sym_ptr,

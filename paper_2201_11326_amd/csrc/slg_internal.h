@@ -26,7 +26,7 @@ constexpr int kWideMembers = 65535;    // rows this large need u32 overlap count
 constexpr int kDenseBits = 15;
 constexpr int kDenseWindow = 1 << kDenseBits;  // E_s positions per dense slot (u16 counters, 64 KB)
 constexpr int kDenseThreads = 512;            // workgroup of the dense tier (2 per CU)
-constexpr int kDenseRatio = 4;                // default: 2-paths per candidate partner to go dense
+constexpr int kDenseRatio = 2;                // default: 2-paths per candidate partner to go dense
 constexpr int kDenseMinRange = kDenseWindow / 4;  // default: fewest candidate partners to go dense
 
 // Row classes written by the planning kernel.
@@ -209,10 +209,15 @@ hipError_t launch_heavy_store_emit(const HeavyDesc *desc, int64_t count, int64_t
 // store_cursor, up to store_cap entries). Emit pass: writes the outputs by
 // walking the 2-paths again, for every slot (store == null) or only those
 // the store could not hold (n[t] < 0).
-hipError_t launch_dense(bool emit, const HeavyDesc *desc, int64_t count, int64_t slots, const int32_t *bounds,
+// order (or null: list order): the slots in the order the workgroups take
+// them, as positions in desc.
+hipError_t launch_dense(bool emit, const HeavyDesc *desc, int64_t count, const int32_t *order, int64_t slots,
+                        const int32_t *bounds,
                         const Pruned &g, const EmitParams &ep, int64_t *slot_cnt, const int64_t *slot_off,
                         int64_t *ticket, int resident, const CountStore *store, int64_t *store_cursor,
                         int64_t store_cap, hipStream_t st);
+// key[t] = the E_s window of dense slot t (its ja >> kDenseBits), id[t] = t.
+hipError_t launch_dense_keys(const HeavyDesc *desc, int64_t count, int32_t *key, int32_t *id, hipStream_t st);
 // Workgroups of the dense kernel that fit on the device at once.
 int dense_resident(int device);
 // *out += sum of n[0..count) (int32).

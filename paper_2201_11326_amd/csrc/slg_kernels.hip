@@ -1979,6 +1979,7 @@ __device__ __forceinline__ void dense_walk(const int32_t *__restrict__ vs_cid, i
 // (LDS), which takes at most 128 VGPRs (4 waves per SIMD).
 template <bool EMIT>
 __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4))) void dense_kernel(const HeavyDesc *__restrict__ desc, int64_t count,
+                                                              const int32_t *__restrict__ order,
                                                               int64_t S, const int32_t *__restrict__ bounds,
                                                               const int32_t *__restrict__ vs_cid,
                                                               const int32_t *__restrict__ cid_row, EmitParams prm,
@@ -1997,8 +1998,9 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
     const int K = sp.k;
     const bool store = cs.ent != nullptr;
     while (true) {
-        const int64_t t = sm.next;
-        if (t >= count) break;
+        const int64_t tk = sm.next;
+        if (tk >= count) break;
+        const int64_t t = order ? (int64_t)order[tk] : tk;  // the slot's position in desc
         const HeavyDesc d = desc[t];
         const int ja = d.ja, k = d.k;
         bool skip = false;
@@ -2129,6 +2131,14 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
         }
         __syncthreads();  // counters cleared, sm.next published
     }
+}
+
+__global__ void dense_keys_kernel(const HeavyDesc *__restrict__ desc, int64_t count, int32_t *__restrict__ key,
+                                  int32_t *__restrict__ id) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    key[t] = desc[t].ja >> kDenseBits;
+    id[t] = (int32_t)t;
 }
 
 // ---------------------------------------------------------------------------
@@ -2651,10 +2661,16 @@ hipError_t launch_heavy_store_emit(const HeavyDesc *desc, int64_t count, int64_t
     return hipGetLastError();
 }
 
-hipError_t launch_dense(bool emit, const HeavyDesc *desc, int64_t count, int64_t slots, const int32_t *bounds,
-                        const Pruned &g, const EmitParams &ep, int64_t *slot_cnt, const int64_t *slot_off,
-                        int64_t *ticket, int resident, const CountStore *store, int64_t *store_cursor,
-                        int64_t store_cap, hipStream_t st) {
+hipError_t launch_dense_keys(const HeavyDesc *desc, int64_t count, int32_t *key, int32_t *id, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    dense_keys_kernel<<<grid_for(count, 256), 256, 0, st>>>(desc, count, key, id);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense(bool emit, const HeavyDesc *desc, int64_t count, const int32_t *order, int64_t slots,
+                        const int32_t *bounds, const Pruned &g, const EmitParams &ep, int64_t *slot_cnt,
+                        const int64_t *slot_off, int64_t *ticket, int resident, const CountStore *store,
+                        int64_t *store_cursor, int64_t store_cap, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     if (!g.vs_cid || !g.cid_row || (store && !emit && !store_cursor)) return hipErrorInvalidValue;
     const int64_t want = resident > 0 ? resident : 512;
@@ -2663,10 +2679,10 @@ hipError_t launch_dense(bool emit, const HeavyDesc *desc, int64_t count, int64_t
     unsigned long long *cur = reinterpret_cast<unsigned long long *>(store_cursor);
     const CountStore cs = store ? *store : CountStore{};
     if (emit)
-        dense_kernel<true><<<grid, kDenseThreads, 0, st>>>(desc, count, slots, bounds, g.vs_cid, g.cid_row, ep,
+        dense_kernel<true><<<grid, kDenseThreads, 0, st>>>(desc, count, order, slots, bounds, g.vs_cid, g.cid_row, ep,
                                                             slot_cnt, slot_off, tk, cs, cur, store_cap);
     else
-        dense_kernel<false><<<grid, kDenseThreads, 0, st>>>(desc, count, slots, bounds, g.vs_cid, g.cid_row, ep,
+        dense_kernel<false><<<grid, kDenseThreads, 0, st>>>(desc, count, order, slots, bounds, g.vs_cid, g.cid_row, ep,
                                                              slot_cnt, slot_off, tk, cs, cur, store_cap);
     return hipGetLastError();
 }

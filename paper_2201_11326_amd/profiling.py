@@ -4,6 +4,10 @@
       The power-law ensemble twice, preceded by a plain 1 GiB device copy
       whose HBM traffic is known; run it under `rocprofv3 --pmc FETCH_SIZE`
       and again under `--pmc WRITE_SIZE`.
+  python -m paper_2201_11326_amd.profiling probe_large
+      The same calibration copy, then one row range of the large skewed
+      workload at full size (range 5 of 25 ranges of equal 2-path work, the
+      first one a default bench run times), S = {8, 16}, streamed.
   python -m paper_2201_11326_amd.profiling stats DB [--match NAME]
       Per-kernel launch count / total / average / min / max duration from a
       rocprofv3 --kernel-trace database.
@@ -57,6 +61,38 @@ def probe() -> None:
     print("probe done", flush=True)
 
 
+def probe_large() -> None:
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import torch
+
+    import hypergen as hg
+    import paper_2201_11326_amd as slg
+    x = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)  # calibration: 1 GiB read, 1 GiB written
+    torch.cuda.synchronize()
+    del x, y
+    inc = hg.large_skewed()
+    ctx = slg.Context(0)
+    g = ctx.register_incidence(inc)
+    prefix = ctx.work_prefix(g, 8)
+    W, B, b = int(prefix[-1]), 25, 5
+    r0 = int(np.searchsorted(prefix, W * b // B, side="left"))
+    r1 = int(np.searchsorted(prefix, W * (b + 1) // B, side="left"))
+    edges = [0]
+
+    def on_chunk(k, s, c0, c1, e0, row_ptr, row, col, w):
+        edges[0] += int(col.numel())
+        return False
+
+    ctx.reset_timing()
+    ctx.line_graph_stream(g, [8, 16], 2 << 30, on_chunk, rows=(r0, r1))
+    torch.cuda.synchronize()
+    print(f"probe done: rows [{r0}, {r1}), {edges[0]} edges, work {ctx.work()}", flush=True)
+
+
 def kernel_rows(db: str):
     con = sqlite3.connect(db)
     cols = [r[1] for r in con.execute("pragma table_info(kernels)")]
@@ -94,9 +130,15 @@ def counter_per_kernel(db: str, counter: str):
 
 HEAVY_KERNELS = ("heavy_kernel<false, false, true>", "heavy_kernel<false, false, false>",
                  "heavy_store_emit_kernel<4>", "heavy_kernel<true, false, false>")
+DENSE_KERNELS = ("dense_kernel<false>", "heavy_store_emit_kernel<4>", "dense_kernel<true>")
+WORKLOADS = {  # probe -> (title, kernels)
+    "power_law": ("the heavy-tier kernels (power-law ensemble S={1,2,4,8})", HEAVY_KERNELS),
+    "large_skewed": ("the dense-tier kernels (large skewed workload at full size, one row range, S={8,16})",
+                     DENSE_KERNELS),
+}
 
 
-def traffic(fetch_db: str, write_db: str) -> str:
+def traffic(fetch_db: str, write_db: str, workload: str = "power_law") -> str:
     """HBM bytes per launch of every heavy-tier kernel found in the two runs
     (the counting pass, with or without the count store, and the emit pass,
     from the store or by walking the 2-paths again)."""
@@ -109,15 +151,16 @@ def traffic(fetch_db: str, write_db: str) -> str:
     write_factor = COPY_BYTES / (max(w.get(ck, [0])) * 1024) if ck and w.get(ck) else 1.0
     with open(KERNEL_SRC, "rb") as fh:
         sha = hashlib.sha256(fh.read()).hexdigest()
+    title, kernels = WORKLOADS[workload]
     lines = [
-        "# HBM traffic of the heavy-tier kernels (power-law ensemble S={1,2,4,8})",
+        f"# HBM traffic of {title}",
         "",
         f"kernel_source_sha256: {sha}",
         f"calibration kernel: {ck} (1 GiB read + 1 GiB written)",
         f"calibration FETCH_SIZE KiB: {max(f[ck]) if ck else None}; factor {fetch_factor:.4f}",
         f"calibration WRITE_SIZE KiB: {max(w[ck]) if ck and w.get(ck) else None}; factor {write_factor:.4f}",
     ]
-    for name in HEAVY_KERNELS:
+    for name in kernels:
         fe, we = f.get(name, []), w.get(name, [])
         if not fe or not we:
             continue
@@ -142,7 +185,7 @@ SQ_PASS2 = ("SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", "SQ_ACTIVE_INST_LDS", "
             "SQ_INSTS_VMEM_WR", "SQ_WAIT_INST_LDS", "SQ_INSTS_BRANCH")
 
 
-def sq(db1: str, db2: str) -> str:
+def sq(db1: str, db2: str, workload: str = "power_law") -> str:
     """Per heavy-tier kernel: the share of wave cycles spent waiting and the
     LDS bank-conflict rate (conflict cycles / LDS-active cycles), from one
     run per counter pass (SQ_PASS1, SQ_PASS2)."""
@@ -151,8 +194,9 @@ def sq(db1: str, db2: str) -> str:
         for name in names:
             for k, vals in counter_per_kernel(db, name).items():
                 per.setdefault(k, {})[name] = sum(vals) / len(vals)
-    lines = ["# SQ counters of the heavy-tier kernels (power-law ensemble S={1,2,4,8})", ""]
-    for k in HEAVY_KERNELS:
+    title, kernels = WORKLOADS[workload]
+    lines = [f"# SQ counters of {title}", ""]
+    for k in kernels:
         c = per.get(k)
         if not c:
             continue
@@ -170,24 +214,29 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     sub.add_parser("probe")
+    sub.add_parser("probe_large")
     a = sub.add_parser("stats")
     a.add_argument("db")
     a.add_argument("--match", default="")
     b = sub.add_parser("traffic")
     b.add_argument("fetch_db")
     b.add_argument("write_db")
+    b.add_argument("--workload", choices=sorted(WORKLOADS), default="power_law")
     c = sub.add_parser("sq")
     c.add_argument("db1")
     c.add_argument("db2")
+    c.add_argument("--workload", choices=sorted(WORKLOADS), default="power_law")
     args = ap.parse_args(argv)
     if args.cmd == "probe":
         probe()
+    elif args.cmd == "probe_large":
+        probe_large()
     elif args.cmd == "stats":
         print(stats(args.db, args.match))
     elif args.cmd == "sq":
-        print(sq(args.db1, args.db2))
+        print(sq(args.db1, args.db2, args.workload))
     else:
-        print(traffic(args.fetch_db, args.write_db))
+        print(traffic(args.fetch_db, args.write_db, args.workload))
     return 0
 
 
