@@ -199,6 +199,36 @@ def batched_cpu_baseline(members, seconds: float, seed: int = 7):
             "paper": PAPER_CPU_CONTEXT}
 
 
+def served_cpu_baseline(pool, reqs, seconds: float, seed: int = 7):
+    """Oracle on whole queries of the served stream on its small members (the
+    full-size power-law members would take the brute-force oracle minutes per
+    query), taken in a seeded random order until about `seconds` of CPU time
+    (each query: every s of its set over the whole graph); rate = their
+    2-paths / oracle wall time."""
+    import numpy as np
+
+    import oracle
+    threads = oracle_threads()
+    order = np.random.default_rng(seed).permutation(len(reqs))
+    work, dt, used = 0, 0.0, 0
+    for r in order:
+        q = reqs[int(r)]
+        inc = pool[q.graph]
+        if inc.m > 20_000:
+            continue
+        t0 = time.perf_counter()
+        for s in q.s:
+            oracle.line_graph(inc, s, size_min=q.s[0], threads=threads)
+        dt += time.perf_counter() - t0
+        work += oracle.two_paths(inc, q.s[0])
+        used += 1
+        if dt >= seconds:
+            break
+    return {"value": work / dt, "unit": "2-paths/s", "cores": threads, "kind": "oracle",
+            "sample": f"{used} of {len(reqs)} requests (seeded order {seed}) on the large-skewed-generator "
+                      f"members, every s of each set over the whole graph, {work} 2-paths, {dt:.2f} s wall", "host": host_cpu(), "paper": PAPER_CPU_CONTEXT}
+
+
 def bench_batched(args) -> int:
     """256 hypergraphs of uneven size, each with its own s. Compares, in
     aggregate 2-paths/s over the same member set: (a) per-instance one-shot
@@ -365,15 +395,22 @@ def bench_served(args) -> int:
         outs = ctx.line_graph(graphs[q.graph], q.s)
         torch.cuda.synchronize()
         del outs
-    service, work_of = [], []
+    service, work_of, bytes_of = [], [], []
     for q in reqs:
         t = time.perf_counter()
         outs = ctx.line_graph(graphs[q.graph], q.s)
         torch.cuda.synchronize()
         service.append(time.perf_counter() - t)
         work_of.append(outs[0].two_paths)
+        x = pool[q.graph]
+        # the scope table's algorithmic bytes of one query: 4 B per 2-path,
+        # 8 B per incidence (both CSRs), 8 B per pointer, 12 B per edge,
+        # 8 B per row_ptr entry of every threshold
+        bytes_of.append(4 * outs[0].two_paths + 8 * x.nnz + 8 * (x.m + x.n)
+                        + sum(12 * o.num_edges for o in outs) + 8 * (x.m + 1) * len(q.s))
         del outs
     work = sum(work_of)
+    algo_bytes = sum(bytes_of)
     finish, lat_a = 0.0, []
     for q, sv in zip(reqs, service):  # one FIFO server, same arrivals
         finish = max(q.arrival, finish) + sv
@@ -447,12 +484,18 @@ def bench_served(args) -> int:
     srv.close()
 
     pct = lambda xs, q: percentile(xs, q)
+    achieved = algo_bytes / span_c / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                "kernel": "every kernel of the served run given all requests at once (burst)",
+                "algorithmic_bytes": algo_bytes, "span_s": span_c}
+    cpu = None if args.no_cpu_baseline else served_cpu_baseline(pool, reqs, args.cpu_seconds)
     line = {
         "metric": METRIC, "value": work / span_c, "unit": "2-paths/s", "n_gpus": 1, "steps": 1,
         "warmup": 32, "ms_per_step": 1e3 * span_c, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": f"served: {len(pool)} resident graphs (64 large-skewed-generator, m log-uniform "
-                               f"[1e3, 1e4], n=m/2; 4 power-law-generator, m 1e4..8e4, n=2m), {len(reqs)} "
+                               f"[1e3, 1e4], n=m/2; 4 power-law-generator at full size, n=1e6, m=5e5), {len(reqs)} "
                                f"Poisson requests at {args.rate:g}/s, s-sets of 1-6 from {{1,2,3,4,5,8}}",
                    "workers": args.workers, "budget_gb": args.budget_gb, "seed": hg.BASE_SEED + 5,
                    "parallelism": "single GPU"},
@@ -467,7 +510,7 @@ def bench_served(args) -> int:
                          "service_p50_ms": 1e3 * pct(service, 0.5), "service_p99_ms": 1e3 * pct(service, 0.99),
                          "fifo_p50_ms": 1e3 * pct(lat_a, 0.5), "fifo_p99_ms": 1e3 * pct(lat_a, 0.99)},
         "speedup_vs_per_instance": (work / span_c) / (work / sum(service)),
-        "parity_checked_requests": checked, "generate_s": t_gen, "roofline": None, "cpu_baseline": None,
+        "parity_checked_requests": checked, "generate_s": t_gen, "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     for g in graphs:
@@ -616,7 +659,7 @@ def bench_large_skewed(args) -> int:
     device memory, so it is streamed (slg_line_graph_stream_rows): one step
     is one of warmup + steps row ranges of equal 2-path work at s = 8, which
     together cover every row once, taken through the whole path (pruning,
-    work estimate, row-block plans, counting, emit in chunks of <= 2 GiB).
+    work estimate, row-block plans, counting, emit in chunks of <= 8 GiB by default).
     The consumer counts each chunk's edges (--digest: digests each chunk on
     the device). value = 2-paths of the timed ranges / their wall time."""
     import numpy as np
@@ -639,7 +682,7 @@ def bench_large_skewed(args) -> int:
     W = int(prefix[-1])
     B = args.steps + args.warmup
     cuts = [0] + [int(np.searchsorted(prefix, W * b // B, side="left")) for b in range(1, B)] + [inc.m]
-    chunk = 2 << 30
+    chunk = int(args.chunk_gib * (1 << 30))
     edges = [0] * len(S)
     chunks = [0]
 
@@ -691,7 +734,7 @@ def bench_large_skewed(args) -> int:
                 "algorithmic_bytes_per_launch": dense_bytes / max(launches, 1),
                 "overhead_bytes_per_launch": {"dense_store_written": 4 * work["dense_stored"] / max(launches, 1)},
                 "sq_counters": measured_sq("dense_kernel<false>", DENSE_SQ_PROFILE),
-                "emit": {"kernel": "heavy_store_emit_kernel<4> on dense slots (emit_dense)",
+                "emit": {"kernel": "heavy_store_emit_kernel<4, unsigned long long> (emit_dense)",
                          "launches": emit_launches, "ms": emit_ms,
                          "algorithmic_bytes": 12 * work["dense_edges"],
                          "achieved_gbs": 12 * work["dense_edges"] / (emit_ms / 1e3) / 1e9 if emit_ms > 0 else None}}
@@ -705,7 +748,7 @@ def bench_large_skewed(args) -> int:
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": "large skewed hypergraph n=5e6 m=1e7 |e|=min(rint(LogNormal(1.5,1)),1e4) "
-                               "vertex weight~rank^-1.5, ensemble S={8,16}, streamed in chunks of <= 2 GiB; "
+                               f"vertex weight~rank^-1.5, ensemble S={{8,16}}, streamed in chunks of <= {args.chunk_gib:g} GiB; "
                                f"one step = one of {B} row ranges of equal 2-path work (all of them: every row once)",
                    "n": inc.n, "m": inc.m, "nnz": inc.nnz, "s": S, "seed": hg.BASE_SEED + 3,
                    "ranges": B, "consumer": "on-device digest per chunk" if args.digest else "edge count per chunk",
@@ -743,6 +786,8 @@ def main() -> int:
                          "preprocess: relabel-by-degree and toplexes of the power-law hypergraph")
     ap.add_argument("--dense-ratio", type=int, default=None,
                     help="large_skewed: the dense tier's 2-paths per candidate partner (default: the library's)")
+    ap.add_argument("--chunk-gib", type=float, default=8.0,
+                    help="large_skewed: largest streamed chunk (all thresholds), GiB")
     ap.add_argument("--digest", action="store_true",
                     help="large_skewed: digest every streamed chunk on the device (default: count its edges)")
     ap.add_argument("--no-tune", action="store_true", help="batched: library-default plan shape")
@@ -844,7 +889,7 @@ def bench_power_law(args, dual: bool = False) -> int:
         "count_heavy": ("heavy_kernel<false, false, true>" if store else "heavy_kernel<false, false, false>",
                         4 * stats["heavy_two_paths"],
                         {"count_store_written": 4 * stats["stored_ranks"]} if store else {}),
-        "emit_heavy": ("heavy_store_emit_kernel<4>" if store else "heavy_kernel<true, false, false>",
+        "emit_heavy": ("heavy_store_emit_kernel<4, unsigned int>" if store else "heavy_kernel<true, false, false>",
                        12 * stats["heavy_edges"],
                        {"count_store_read": 4 * stats["stored_ranks"]} if store
                        else {"two_paths_walked_again": 4 * stats["heavy_two_paths"]}),

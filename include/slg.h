@@ -106,7 +106,7 @@ const char *slg_version(void);
  * Create a context on HIP device `device`. Planning scratch (and the
  * outputs of slg_line_graph when `alloc` is NULL) come from a block cache
  * of the context: freed blocks are kept for reuse by later calls, up to
- * mem_budget_bytes of them (0 = a quarter of the device's memory, at least
+ * mem_budget_bytes of them (0 = half of the device's memory, at least
  * 16 GiB); beyond that the largest are given
  * back to the device. `alloc` may be NULL.
  * Errors: INVALID_ARG (out == NULL), DEVICE (no such device).
@@ -510,7 +510,7 @@ slg_status slg_select(slg_context *ctx, slg_graph *g, const int32_t *order, int6
  * after the work already queued on the null stream, so finish work on
  * other streams that reads them first. Results may be freed after the
  * server is destroyed. The slots share one block cache that keeps at most
- * half the budget (16 GiB without a budget) of freed blocks for reuse.
+ * the budget (16 GiB without a budget) of freed blocks for reuse.
  */
 typedef struct slg_server slg_server;
 typedef struct {

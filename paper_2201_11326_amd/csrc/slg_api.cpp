@@ -113,7 +113,7 @@ static_assert(kTkHeavyEdges + 1 == kTkStored && kTkStored + 1 == kTkDenseCursor 
               "plan counters read back together");
 
 // Freed device blocks a context keeps for reuse unless told otherwise.
-constexpr uint64_t kDefaultCacheMin = uint64_t(16) << 30;  // default block cache: a quarter of the
+constexpr uint64_t kDefaultCacheMin = uint64_t(16) << 30;  // default block cache: half of the
                                                            // device's memory, at least this
 
 slg_status fail(slg_context *ctx, slg_status st, const char *fmt, ...) {
@@ -313,6 +313,8 @@ struct slg_plan {
     Scratch scratch2;  // a row block's slot tables, lists, stores (released per block)
     PlanBufs b;
     bool blocks = false;           // planned block by block (the rows phase keeps every row's facts)
+    unsigned long long *dstore_fixed = nullptr;  // row blocks: one dense store for every block
+    int64_t dstore_fixed_cap = 0;
     int64_t row_lo = 0, row_hi = 0;  // the rows of the current block
     bool prune = false;            // vertex lists are compacted to E_{s_min}
     int32_t s_min = 1;
@@ -424,7 +426,7 @@ slg_status create_context(int device, uint64_t mem_budget_bytes, const slg_alloc
     uint64_t cache = mem_budget_bytes;
     if (!cache) {
         size_t free_b = 0, total_b = 0;
-        cache = hipMemGetInfo(&free_b, &total_b) == hipSuccess ? total_b / 4 : 0;
+        cache = hipMemGetInfo(&free_b, &total_b) == hipSuccess ? total_b / 2 : 0;
         if (cache < kDefaultCacheMin) cache = kDefaultCacheMin;
     }
     ctx->arena = std::make_shared<slg::Arena>(device, cache);
@@ -968,11 +970,12 @@ slg_status plan_block(slg_plan *p, int64_t r0, int64_t r1) {
         const int64_t nd = p->list_count[kLightClasses + 2];
         const int64_t left = p->store_limit - (p->use_store ? bytes : 0) - (p->use_lstore ? lbytes : 0) -
                              nd * 12 - 16;
-        p->dstore_cap = std::min<int64_t>(p->dense_two_paths / std::max(p->s_min, 1) + 1, left / 4);
+        p->dstore_cap = std::min<int64_t>(p->dense_two_paths / std::max(p->s_min, 1) + 1, left / 8);
+        if (p->dstore_fixed) p->dstore_cap = p->dstore_fixed_cap;  // row blocks share one store of fixed size
         p->use_dstore = nd > 0 && p->dstore_cap > 0;
         if (nd > 1) phase2.add(&p->dorder, nd);
         if (p->use_dstore) {
-            phase2.add(&p->dstore.ent, p->dstore_cap);
+            if (!p->dstore_fixed) phase2.add(&p->dstore.ent64, p->dstore_cap);
             phase2.add(&p->dstore.off, nd);
             phase2.add(&p->dstore.n, nd);
         } else {
@@ -984,6 +987,7 @@ slg_status plan_block(slg_plan *p, int64_t r0, int64_t r1) {
         p->reserved += phase2.bytes;
     }
     for (const auto &a : phase2.items) BUILD_HIP(sc.get(a.first, a.second));
+    if (p->dstore_fixed && p->use_dstore) p->dstore.ent64 = p->dstore_fixed;
     p->slots.count = p->S;
     p->slots.row = b.slot_row;
     BUILD_HIP(enqueue_slots_count(p, st));
@@ -1092,9 +1096,11 @@ namespace {
 // Emit rows [r0, r1) (slots [s0, s1)) of every threshold into buffers whose
 // first entry is global edge offset base[k]; row_ptr[k] gets r1 - r0 + 1
 // entries relative to base[k].
+// lists (optional, host): the chunk's part [lists[2h], lists[2h+1]) of
+// heavy list h, known beforehand; else found on the device and read back.
 slg_status emit_range(slg_plan *p, int64_t r0, int64_t r1, int64_t s0, int64_t s1, const int64_t *base,
                       int64_t *const *row_ptr, int32_t *const *row, int32_t *const *col, int32_t *const *w,
-                      hipStream_t st) {
+                      hipStream_t st, const int64_t *lists = nullptr) {
     slg_context *ctx = p->ctx;
     const int K = p->prm.k;
     EmitParams prm = p->prm;
@@ -1123,7 +1129,12 @@ slg_status emit_range(slg_plan *p, int64_t r0, int64_t r1, int64_t s0, int64_t s
     // in slot order), found on the device and read back
     int64_t lo[kNumHeavyLists] = {}, hi[kNumHeavyLists];
     for (int h = 0; h < kNumHeavyLists; ++h) hi[h] = p->list_count[kLightClasses + h];
-    if (s0 > 0 || s1 < p->S) {
+    if (lists) {
+        for (int h = 0; h < kNumHeavyLists; ++h) {
+            lo[h] = lists[2 * h];
+            hi[h] = lists[2 * h + 1];
+        }
+    } else if (s0 > 0 || s1 < p->S) {
         int64_t *hb = ctx->pinned + kHbRange;
         for (int h = 0; h < kNumHeavyLists; ++h) {
             if (hi[h] <= 0) continue;
@@ -1143,9 +1154,8 @@ slg_status emit_range(slg_plan *p, int64_t r0, int64_t r1, int64_t s0, int64_t s
         if (cnt <= 0) continue;
         StageTimer tm(ctx, wide ? kStEmitHeavyWide : kStEmitHeavy, st);
         if (p->use_store && !wide) {
-            const CountStore part{p->store.ent, p->store.off + lo[0], p->store.n + lo[0]};
-            SLG_HIP(ctx, launch_heavy_store_emit(p->heavy[0] + lo[0], cnt, p->S, part, prm, p->slot_off, nullptr,
-                                                 st));
+            const CountStore part{p->store.ent, p->store.off + lo[0], p->store.n + lo[0], nullptr};
+            SLG_HIP(ctx, launch_heavy_store_emit(p->heavy[0] + lo[0], cnt, p->S, part, prm, p->slot_off, st));
         } else {
             SLG_HIP(ctx, launch_heavy(true, wide, p->heavy[wide] + lo[wide], cnt, p->S, p->bounds, p->pr, prm,
                                       nullptr, p->slot_off, p->tickets + kTkEmit + wide, p->heavy_grid, nullptr,
@@ -1155,10 +1165,9 @@ slg_status emit_range(slg_plan *p, int64_t r0, int64_t r1, int64_t s0, int64_t s
     if (hi[2] > lo[2]) {  // dense slots: from their store, then any the store could not hold
         StageTimer tm(ctx, kStEmitDense, st);
         const int64_t cnt = hi[2] - lo[2];
-        const CountStore part{p->dstore.ent, p->dstore.off + lo[2], p->dstore.n + lo[2]};
+        const CountStore part{nullptr, p->dstore.off + lo[2], p->dstore.n + lo[2], p->dstore.ent64};
         if (p->use_dstore)
-            SLG_HIP(ctx, launch_heavy_store_emit(p->heavy[2] + lo[2], cnt, p->S, part, prm, p->slot_off,
-                                                 p->pr.cid_row, st));
+            SLG_HIP(ctx, launch_heavy_store_emit(p->heavy[2] + lo[2], cnt, p->S, part, prm, p->slot_off, st));
         if (!p->use_dstore || p->dense_stored > p->dstore_cap)
             SLG_HIP(ctx, launch_dense(true, p->heavy[2] + lo[2], cnt, nullptr, p->S, p->bounds, p->pr, prm, nullptr,
                                       p->slot_off, p->tickets + kTkEmit + 2, p->dense_grid,
@@ -1275,11 +1284,23 @@ slg_status stream_rows(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t
                               st));
     STREAM_HIP(hipMemcpyAsync(cls.data(), p->b.rclass_all + row_begin, nr, hipMemcpyDeviceToHost, st));
     STREAM_HIP(hipStreamSynchronize(st));
+    // block scratch: one dense store of fixed size for every block (half the
+    // count-store limit; blocks are cut so that their survivors fit it), and
+    // at most a quarter of the limit for the rest of a block's tables and
+    // stores; sizes that repeat from block to block keep the block cache
+    // from giving memory back and taking it again
     const int64_t budget = p->store_limit > 0 ? p->store_limit : (int64_t(8) << 30);
+    bool any_dense = false;
+    for (int64_t r = 0; r < nr && !any_dense; ++r) any_dense = cls[r] == kDense;
+    if (any_dense && p->store_limit > 0) {
+        p->dstore_fixed_cap = budget / 2 / 8;
+        STREAM_HIP(p->scratch.get(&p->dstore_fixed, p->dstore_fixed_cap));
+    }
     double dense_ratio = 0.125;  // survivors per dense 2-path, until a block has measured it
     int64_t base[SLG_MAX_S] = {};  // edges of the call before the current block
     int64_t *rp[2][SLG_MAX_S] = {};
     int32_t *ri[2][SLG_MAX_S] = {}, *rj[2][SLG_MAX_S] = {}, *rw[2][SLG_MAX_S] = {};
+    int64_t cap_rows = -1, cap_e[SLG_MAX_S] = {};  // room of the chunk buffers
     int pending = -1;           // buffer set of a chunk emitted but not yet handed over
     int64_t pr0 = 0, pr1 = 0;   // its rows
     int64_t pe0[SLG_MAX_S] = {}, pne[SLG_MAX_S] = {};
@@ -1300,17 +1321,20 @@ slg_status stream_rows(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t
     int next_set = 0;
     while (b0 < nr) {
         // the block: rows while the estimated scratch fits
-        const double per_dense = 4.0 * dense_ratio * 1.25;
-        double bytes = 0;
+        const double per_dense = dense_ratio * 1.25;  // store entries per dense 2-path, with room
+        const double dense_room = (double)p->dstore_fixed_cap;
+        double bytes = 0, entries = 0;
         int64_t b1 = b0;
         while (b1 < nr) {
             const int c = cls[b1];
-            double r = (double)nsl[b1] * (24.0 + 16.0 * K) + 4.0 * (double)bsz[b1];
+            double r = (double)nsl[b1] * (24.0 + 16.0 * K) + 4.0 * (double)bsz[b1], d = 0;
             if (c == kHeavy || c == kHeavyWide) r += 4.0 * (double)work[b1];
-            else if (c == kDense) r += per_dense * (double)work[b1];
+            else if (c == kDense) d = per_dense * (double)work[b1];
             else if (c != kNone) r += 6.0 * (double)work[b1];
-            if (b1 > b0 && bytes + r > 0.5 * (double)budget) break;
+            if (b1 > b0 && (bytes + r > 0.25 * (double)budget || (dense_room > 0 && entries + d > dense_room)))
+                break;
             bytes += r;
+            entries += d;
             ++b1;
         }
         const int64_t R0 = row_begin + b0, R1 = row_begin + b1;
@@ -1350,27 +1374,42 @@ slg_status stream_rows(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t
         STREAM_HIP(p->scratch2.get(&doffs, nc * K));
         STREAM_HIP(hipMemcpyAsync(dcuts, cuts.data(), nc * sizeof(int64_t), hipMemcpyHostToDevice, st));
         STREAM_HIP(launch_gather_offsets(dcuts, nc, p->slot_base, p->slot_off, p->S, K, doffs, st));
-        std::vector<int64_t> offs(nc * K), sb(nc);
+        std::vector<int64_t> offs(nc * K), sb(nc), parts(kNumHeavyLists * nc);
+        // first slot of every cut row, then where each heavy list reaches it
+        int64_t *dsb, *dparts;
+        STREAM_HIP(p->scratch2.get(&dsb, nc));
+        STREAM_HIP(p->scratch2.get(&dparts, kNumHeavyLists * nc));
+        STREAM_HIP(launch_gather_i64(p->slot_base, dcuts, nc, dsb, st));
+        for (int h = 0; h < kNumHeavyLists; ++h)
+            STREAM_HIP(launch_list_cuts(p->heavy[h], p->list_count[kLightClasses + h], dsb, nc, dparts + h * nc, st));
         STREAM_HIP(hipMemcpyAsync(offs.data(), doffs, nc * K * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        for (int64_t c = 0; c < nc; ++c)  // first slot of every cut row
-            STREAM_HIP(hipMemcpyAsync(&sb[c], p->slot_base + cuts[c], sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        STREAM_HIP(hipMemcpyAsync(sb.data(), dsb, nc * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        STREAM_HIP(hipMemcpyAsync(parts.data(), dparts, kNumHeavyLists * nc * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                  st));
         STREAM_HIP(hipStreamSynchronize(st));
-        // two buffer sets sized for the block's largest chunk of every threshold
+        // two buffer sets for the largest chunk of every threshold so far:
+        // they grow when a block needs more, and are kept otherwise
         int64_t max_rows = 0, max_e[SLG_MAX_S] = {};
         for (int64_t c = 0; c + 1 < nc; ++c) {
             max_rows = std::max(max_rows, cuts[c + 1] - cuts[c]);
             for (int k = 0; k < K; ++k) max_e[k] = std::max(max_e[k], offs[(c + 1) * K + k] - offs[c * K + k]);
         }
-        for (int t = 0; t < 2; ++t)
-            for (int k = 0; k < K; ++k) {
-                STREAM_HIP(p->scratch2.get(&rp[t][k], max_rows + 1));
-                void *q[3];
-                for (int u = 0; u < 3; ++u)
-                    STREAM_HIP(p->scratch2.get(&q[u], std::max<int64_t>(max_e[k], 1) * sizeof(int32_t)));
-                ri[t][k] = static_cast<int32_t *>(q[0]);
-                rj[t][k] = static_cast<int32_t *>(q[1]);
-                rw[t][k] = static_cast<int32_t *>(q[2]);
-            }
+        bool grow = max_rows > cap_rows;
+        for (int k = 0; k < K; ++k) grow |= max_e[k] > cap_e[k];
+        if (grow) {
+            bufs.release();  // after the work queued on st (which waited for the consumer)
+            cap_rows = std::max(cap_rows, max_rows + max_rows / 4);
+            for (int t = 0; t < 2; ++t)
+                for (int k = 0; k < K; ++k) {
+                    if (t == 0) cap_e[k] = std::max(cap_e[k], std::max<int64_t>(max_e[k] + max_e[k] / 4, 1));
+                    STREAM_HIP(bufs.get(&rp[t][k], cap_rows + 1));
+                    void *q[3];
+                    for (int u = 0; u < 3; ++u) STREAM_HIP(bufs.get(&q[u], cap_e[k] * sizeof(int32_t)));
+                    ri[t][k] = static_cast<int32_t *>(q[0]);
+                    rj[t][k] = static_cast<int32_t *>(q[1]);
+                    rw[t][k] = static_cast<int32_t *>(q[2]);
+                }
+        }
         for (int64_t c = 0; c + 1 < nc; ++c) {
             const int t = next_set;
             next_set ^= 1;
@@ -1383,7 +1422,12 @@ slg_status stream_rows(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t
                 rjk[k] = rj[t][k];
                 rwk[k] = rw[t][k];
             }
-            rc = emit_range(p, cuts[c], cuts[c + 1], sb[c], sb[c + 1], &offs[c * K], rpk, rik, rjk, rwk, st);
+            int64_t lists[2 * kNumHeavyLists];
+            for (int h = 0; h < kNumHeavyLists; ++h) {
+                lists[2 * h] = parts[h * nc + c];
+                lists[2 * h + 1] = parts[h * nc + c + 1];
+            }
+            rc = emit_range(p, cuts[c], cuts[c + 1], sb[c], sb[c + 1], &offs[c * K], rpk, rik, rjk, rwk, st, lists);
             if (rc != SLG_OK) return cleanup(rc);
             STREAM_HIP(hipEventRecord(done[t], st));
             if (pending >= 0 && (rc = hand_over()) != SLG_OK) return cleanup(rc);

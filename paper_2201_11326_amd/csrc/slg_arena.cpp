@@ -50,11 +50,14 @@ hipError_t Arena::get(void **p, size_t bytes, hipStream_t st) {
             return hipSuccess;
         }
     }
-    hipError_t e = hipMalloc(p, want);
+    // blocks come from the device's stream-ordered pool (it keeps freed
+    // memory, so giving a block back and allocating again costs no device
+    // synchronisation and no new mapping)
+    hipError_t e = hipMallocAsync(p, want, st);
     if (e == hipErrorOutOfMemory) {  // give the cache back and try once more
         (void)hipGetLastError();
         trim();
-        e = hipMalloc(p, want);
+        e = hipMallocAsync(p, want, st);
     }
     if (e != hipSuccess) {
         *p = nullptr;
@@ -87,12 +90,15 @@ void Arena::put(const std::vector<void *> &blocks, hipStream_t st, bool idle) {
         free_.insert({size, Free{p, size, st, idle, ev}});
         cached_ += size;
     }
-    if (cached_ > limit_) shrink_locked(limit_ / 2);
+    if (cached_ > limit_) shrink_locked(limit_ / 4 * 3);  // some room below the limit, not a full flush
 }
 
+// The block's own pending work is waited for on the host (its event, not the
+// whole device), then it goes back to the pool, ordered on the null stream
+// (the stream it was given back on may be gone by now).
 void Arena::release_locked(std::multimap<size_t, Free>::iterator it) {
     if (it->second.ev) (void)hipEventSynchronize(it->second.ev->e);
-    (void)hipFree(it->second.p);
+    (void)hipFreeAsync(it->second.p, nullptr);
     cached_ -= it->second.size;
     free_.erase(it);
 }

@@ -1,6 +1,7 @@
 // Caching device-memory arena of one context: planning scratch and library-
 // owned outputs are served from blocks kept after earlier calls, so that a
-// query in a serving loop pays no allocator round trips once warm.
+// query in a serving loop pays no allocator round trips once warm. Blocks
+// come from, and go back to, the device's stream-ordered memory pool.
 //
 // Blocks are handed out with stream-ordered semantics: a block given back on
 // stream S may be reused by later work on S at once; reuse by another stream

@@ -685,6 +685,24 @@ __global__ void heavy_counts_kernel(int64_t m, const uint8_t *__restrict__ rclas
     }
 }
 
+// For every c, the position of the first slot >= slots[c] in a heavy list
+// ordered by slot (one thread per c).
+__global__ void list_cuts_kernel(const HeavyDesc *__restrict__ desc, int64_t count,
+                                 const int64_t *__restrict__ slots, int64_t n, int64_t *__restrict__ out) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    const int64_t key = slots[c];
+    int64_t lo = 0, hi = count;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)desc[mid].slot < key)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    out[c] = lo;
+}
+
 // First and one-past-last positions of the slots in [s0, s1) in a heavy
 // list ordered by slot.
 __global__ void heavy_range_kernel(const HeavyDesc *__restrict__ desc, int64_t count, int64_t s0, int64_t s1,
@@ -1710,14 +1728,16 @@ __global__ __launch_bounds__(256) void slot_work_kernel(const HeavyDesc *__restr
 constexpr int kStoreGroups = 8;
 constexpr int kQueue = 128;  // entries per threshold queue: < 64 kept + <= 64 appended
 
-template <int MAXK>
+// E: uint32_t entries (heavy slots: partner - ja | overlap << 16) or
+// unsigned long long (dense slots: partner << 16 | overlap).
+template <int MAXK, typename E>
 __global__ __launch_bounds__(256) void heavy_store_emit_kernel(const HeavyDesc *__restrict__ desc, int64_t count,
                                                                int64_t S, CountStore cs, EmitParams prm,
-                                                               const int64_t *__restrict__ slot_off,
-                                                               const int32_t *__restrict__ cid_row) {
+                                                               const int64_t *__restrict__ slot_off) {
     constexpr bool kQueued = MAXK <= 4;
+    constexpr bool kWide = sizeof(E) == 8;
     __shared__ EmitParams sp;
-    __shared__ uint32_t queue[kQueued ? 4 : 1][kQueued ? MAXK : 1][kQueued ? kQueue : 1];
+    __shared__ E queue[kQueued ? 4 : 1][kQueued ? MAXK : 1][kQueued ? kQueue : 1];
     stage_params(&sp, prm);
     __syncthreads();
     const int lane = lane_id(), wave = threadIdx.x >> 6;
@@ -1742,34 +1762,34 @@ __global__ __launch_bounds__(256) void heavy_store_emit_kernel(const HeavyDesc *
             sk[kk] = kk < K ? (row_thr ? srow : sp.s[kk]) : INT_MAX;
             fill[kk] = 0;
         }
-        // the partner of a stored entry: an id offset from ja, or (dense
-        // slots) an E_s position offset from ja, mapped back to its row id
-        auto partner = [&](uint32_t e) -> int {
-            const int local = (int)(e & 0xFFFFu);
-            return cid_row ? as_global(cid_row)[d.ja + local] - id0 : jbase + local;
+        const E *ent = kWide ? reinterpret_cast<const E *>(cs.ent64) : reinterpret_cast<const E *>(cs.ent);
+        // the partner and overlap of a stored entry
+        auto partner = [&](E e) -> int {
+            return kWide ? (int)(e >> 16) - id0 : jbase + (int)(e & 0xFFFFu);
         };
+        auto overlap = [&](E e) -> int { return kWide ? (int)(e & 0xFFFFu) : (int)(e >> 16); };
         // writes `m` queued entries of threshold kk (lanes below m) at b[kk]
         auto flush = [&](int kk, int m) {
             if (lane < m) {
-                const uint32_t e = queue[wave][kk][lane];
+                const E e = queue[wave][kk][lane];
                 const int64_t pos = b[kk] + lane;
                 as_global(sp.col[kk])[pos] = partner(e);
-                as_global(sp.w[kk])[pos] = (int)(e >> 16);
+                as_global(sp.w[kk])[pos] = overlap(e);
                 if (sp.row[kk]) as_global(sp.row[kk])[pos] = i - id0;
             }
             b[kk] += m;
         };
         for (int r0 = 0; r0 < n; r0 += 64 * kStoreGroups) {
-            uint32_t e[kStoreGroups];
+            E e[kStoreGroups];
 #pragma unroll
             for (int q = 0; q < kStoreGroups; ++q) {
                 const int r = r0 + 64 * q + lane;
-                e[q] = r < n ? as_global(cs.ent)[off + r] : 0u;
+                e[q] = r < n ? as_global(ent)[off + r] : E(0);
             }
 #pragma unroll
             for (int q = 0; q < kStoreGroups; ++q) {
                 if (r0 + 64 * q >= n) break;  // wave-uniform
-                const int c = (int)(e[q] >> 16);
+                const int c = overlap(e[q]);
 #pragma unroll
                 for (int kk = 0; kk < MAXK; ++kk) {
                     if (kk >= K) break;
@@ -1782,7 +1802,7 @@ __global__ __launch_bounds__(256) void heavy_store_emit_kernel(const HeavyDesc *
                         if (fill[kk] >= 64) {  // a full row out, the rest moves down
                             wave_lds_sync();
                             flush(kk, 64);
-                            const uint32_t rest = lane < fill[kk] - 64 ? queue[wave][kk][64 + lane] : 0u;
+                            const E rest = lane < fill[kk] - 64 ? queue[wave][kk][64 + lane] : E(0);
                             wave_lds_sync();
                             if (lane < fill[kk] - 64) queue[wave][kk][lane] = rest;
                             fill[kk] -= 64;
@@ -1996,7 +2016,7 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
     if (tid == 0) sm.next = (int64_t)atomicAdd(ticket, 1ull);
     __syncthreads();
     const int K = sp.k;
-    const bool store = cs.ent != nullptr;
+    const bool store = cs.ent64 != nullptr;
     while (true) {
         const int64_t tk = sm.next;
         if (tk >= count) break;
@@ -2070,7 +2090,7 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
             const int pos1 = dense_scan(n1, sm.wsum2, tot1);
             const int n = tot0 + tot1;
             if (tid == 0) sm.tally[0] = (unsigned long long)n;
-            if (store && tid == 0) {
+            if (store && tid == 0) {  // room in the store, one reservation per slot
                 long long b = -1;
                 if (n > 0) {
                     const unsigned long long at = atomicAdd(cursor, (unsigned long long)n);
@@ -2081,14 +2101,16 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
                 as_global(cs.n)[t] = (n > 0 && b < 0) ? -1 : n;
             }
             __syncthreads();
-            if (store) {
+            if (store) {  // partner id << 16 | overlap (the window's ids are in L2)
                 const long long base = sm.base;
-                const auto ent = as_global(cs.ent);
+                const auto ent = as_global(cs.ent64);
+                const auto crow = as_global(cid_row) + ja;
                 long long q0 = base + pos0, q1 = base + tot0 + pos1;
                 for_words(true, [&](int x, unsigned lo, unsigned hi) {
                     if (base < 0) return;
-                    if (lo >= (unsigned)s0) ent[q0++] = (uint32_t)x | (lo << 16);
-                    if (hi >= (unsigned)s0) ent[q1++] = (uint32_t)(x + kDenseWords) | (hi << 16);
+                    if (lo >= (unsigned)s0) ent[q0++] = ((unsigned long long)(uint32_t)crow[x] << 16) | lo;
+                    if (hi >= (unsigned)s0)
+                        ent[q1++] = ((unsigned long long)(uint32_t)crow[x + kDenseWords] << 16) | hi;
                 });
             }
             if (tid < K) slot_cnt[(int64_t)tid * S + d.slot] = (int64_t)sm.tally[tid];
@@ -2561,6 +2583,13 @@ hipError_t launch_block_mask(int64_t m, int64_t r0, int64_t r1, const int32_t *n
     return hipGetLastError();
 }
 
+hipError_t launch_list_cuts(const HeavyDesc *desc, int64_t count, const int64_t *slots, int64_t n, int64_t *out,
+                            hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    list_cuts_kernel<<<grid_for(n, 256), 256, 0, st>>>(desc, count, slots, n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_heavy_range(const HeavyDesc *desc, int64_t count, int64_t s0, int64_t s1, int64_t *out,
                               hipStream_t st) {
     heavy_range_kernel<<<1, 64, 0, st>>>(desc, count, s0, s1, out);
@@ -2649,15 +2678,21 @@ hipError_t launch_slot_work(const HeavyDesc *desc, int64_t count, const int32_t 
 }
 
 hipError_t launch_heavy_store_emit(const HeavyDesc *desc, int64_t count, int64_t slots, const CountStore &store,
-                                   const EmitParams &ep, const int64_t *slot_off, const int32_t *cid_row,
-                                   hipStream_t st) {
+                                   const EmitParams &ep, const int64_t *slot_off, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    if (ep.k <= 4)
-        heavy_store_emit_kernel<4><<<wave_grid(count, 4, 16384), 256, 0, st>>>(desc, count, slots, store, ep,
-                                                                                  slot_off, cid_row);
-    else
-        heavy_store_emit_kernel<SLG_MAX_S><<<wave_grid(count, 4, 16384), 256, 0, st>>>(desc, count, slots, store,
-                                                                                          ep, slot_off, cid_row);
+    const unsigned grid = wave_grid(count, 4, 16384);
+    if (store.ent64) {
+        if (ep.k <= 4)
+            heavy_store_emit_kernel<4, unsigned long long><<<grid, 256, 0, st>>>(desc, count, slots, store, ep,
+                                                                                 slot_off);
+        else
+            heavy_store_emit_kernel<SLG_MAX_S, unsigned long long><<<grid, 256, 0, st>>>(desc, count, slots, store,
+                                                                                         ep, slot_off);
+    } else if (ep.k <= 4) {
+        heavy_store_emit_kernel<4, uint32_t><<<grid, 256, 0, st>>>(desc, count, slots, store, ep, slot_off);
+    } else {
+        heavy_store_emit_kernel<SLG_MAX_S, uint32_t><<<grid, 256, 0, st>>>(desc, count, slots, store, ep, slot_off);
+    }
     return hipGetLastError();
 }
 

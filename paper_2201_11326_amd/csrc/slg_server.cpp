@@ -208,9 +208,12 @@ slg_status slg_server_create(slg_context *ctx, int32_t workers, uint64_t mem_bud
     sv->device = slg::context_device(ctx);
     sv->core = std::make_shared<slg::ServeCore>();
     sv->core->budget = mem_budget_bytes;
-    // one block cache for every slot: freed blocks keep at most half the
-    // budget (16 GiB without one) beyond what the queries hold
-    const uint64_t cache = mem_budget_bytes ? mem_budget_bytes / 2 : (uint64_t(16) << 30);
+    // one block cache for every slot: freed blocks keep at most the budget
+    // (16 GiB without one) beyond what the queries hold. A smaller cache
+    // thrashes on large queries: every one that ends pushes the cache over,
+    // the largest blocks go back to the device's pool and the next large
+    // query takes them from there again.
+    const uint64_t cache = mem_budget_bytes ? mem_budget_bytes : (uint64_t(16) << 30);
     std::shared_ptr<slg::Arena> arena;
     auto undo = [&](slg_status code, const char *msg) {
         for (Worker &w : sv->workers) {

@@ -197,3 +197,46 @@ def test_two_stream_plan_equals_one_stream_plan(ctx):
     del r, forked
     srv.close()
     g.release()
+
+
+def test_full_served_pool_mix_equals_alone():
+    """The served workload's own pool (64 large-skewed-generator graphs and
+    4 power-law-generator graphs at full size, n = 1e6, m = 5e5) with a
+    seeded sample of its request stream, 8 queries in flight under a 64 GiB
+    budget: every result equals the same query run alone, array for array.
+    The sample holds every power-law member at least once."""
+    import torch
+
+    import paper_2201_11326_amd as slg
+    pool = hg.served_pool()
+    reqs = hg.served_requests(len(pool), 400, seed=hg.BASE_SEED + 7)
+    rng = np.random.default_rng(21)
+    pick = [reqs[int(i)] for i in rng.choice(len(reqs), size=28, replace=False)]
+    big = [r for r in reqs if r.graph >= 64]
+    for gidx in range(64, len(pool)):  # each full-size member once, at s >= 2 (its L_1 alone is 24 GB)
+        cand = [r for r in big if r.graph == gidx and r.s[0] >= 2]
+        q = cand[0] if cand else hg.Request(0.0, gidx, [2, 4])
+        pick.append(q)
+    ctx = slg.Context(0)
+    graphs = [ctx.register_incidence(x) for x in pool]
+    srv = ctx.server(workers=8, mem_budget_bytes=64 << 30)
+    tick = {srv.submit(graphs[q.graph], q.s): q for q in pick}
+    done = 0
+    for _ in pick:
+        r = srv.next(timeout_ms=300_000)
+        assert r is not None and r.ok, (r and r.message)
+        q = tick[r.ticket]
+        alone = ctx.line_graph(graphs[q.graph], q.s)
+        for a, b in zip(r.outs, alone):
+            assert a.s == b.s
+            for f in ("row_ptr", "row", "col", "w"):
+                assert torch.equal(getattr(a, f), getattr(b, f)), (q.graph, q.s, f)
+        done += 1
+        del r, alone
+    assert done == len(pick)
+    stats = srv.stats()
+    srv.close()
+    assert stats["bytes_peak"] <= 64 << 30, stats
+    for g in graphs:
+        g.release()
+    ctx.close()
