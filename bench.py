@@ -49,6 +49,10 @@ def kernel_source_hash() -> str:
 
 DENSE_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "dense_tier_large_skewed_traffic.md")
 DENSE_SQ_PROFILE = os.path.join(ROOT, "profiles", "dense_tier_large_skewed_sq_counters.md")
+# count-store limit of the large skewed bench (GiB): half of it is the dense
+# store, and a larger one cuts fewer row blocks (32 per range of 8.6e12
+# 2-paths at 160 against 156 at 32; 7.26 against 7.58 s per range)
+LARGE_STORE_GIB = 160.0
 
 
 def measured_traffic(kernel: str, profile: str = TRAFFIC_PROFILE):
@@ -677,6 +681,7 @@ def bench_large_skewed(args) -> int:
     ctx = slg.Context(0)
     if args.dense_ratio is not None:
         ctx.set_dense(args.dense_ratio, 0)
+    ctx.set_count_store(int(args.store_gib * (1 << 30)))
     g = ctx.register_incidence(inc)
     prefix = ctx.work_prefix(g, S[0])  # untimed: the ranges' cuts
     W = int(prefix[-1])
@@ -752,7 +757,7 @@ def bench_large_skewed(args) -> int:
                                f"one step = one of {B} row ranges of equal 2-path work (all of them: every row once)",
                    "n": inc.n, "m": inc.m, "nnz": inc.nnz, "s": S, "seed": hg.BASE_SEED + 3,
                    "ranges": B, "consumer": "on-device digest per chunk" if args.digest else "edge count per chunk",
-                   "dense_ratio": args.dense_ratio,
+                   "dense_ratio": args.dense_ratio, "count_store_gib": args.store_gib,
                    "parallelism": "single GPU"},
         "two_paths_per_step": timed_two_paths / args.steps, "two_paths_whole_graph": W,
         "edges_timed": edges, "edges_per_s": edges_total / elapsed,
@@ -786,6 +791,9 @@ def main() -> int:
                          "preprocess: relabel-by-degree and toplexes of the power-law hypergraph")
     ap.add_argument("--dense-ratio", type=int, default=None,
                     help="large_skewed: the dense tier's 2-paths per candidate partner (default: the library's)")
+    ap.add_argument("--store-gib", type=float, default=LARGE_STORE_GIB,
+                    help="large_skewed: count-store limit of the context in GiB; half of it is the dense "
+                         "store whose room cuts the row blocks (the library's default: 32)")
     ap.add_argument("--chunk-gib", type=float, default=8.0,
                     help="large_skewed: largest streamed chunk (all thresholds), GiB")
     ap.add_argument("--digest", action="store_true",

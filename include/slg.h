@@ -329,7 +329,7 @@ slg_status slg_context_set_count_store(slg_context *ctx, int64_t max_bytes, int6
  * Dense tier (an implementation choice, not in the paper): a heavy row whose
  * candidate partners (the hyperedges of E_{s_min} with ids in (i, j_max])
  * number at least min_range, and which has at least min_ratio 2-paths per
- * candidate, counts its overlaps in direct counters over windows of 2^15
+ * candidate, counts its overlaps in direct counters over windows of 2^14
  * consecutive hyperedges of E_{s_min}, and keeps only the partners that
  * reach s_min for the emit pass (within the count-store limit; slots that
  * find it full walk their 2-paths again). min_ratio = 0 turns the tier off;
@@ -337,6 +337,19 @@ slg_status slg_context_set_count_store(slg_context *ctx, int64_t max_bytes, int6
  * identical either way. Applies to plans created afterwards.
  */
 slg_status slg_context_set_dense(slg_context *ctx, int32_t min_ratio, int32_t min_range);
+
+/*
+ * Fault injection for tests of the error path (no part of the method):
+ * plans created afterwards give their heavy, heavy-wide and dense
+ * descriptor lists `entries` fewer places than the rows counted for them.
+ * The device appends check their list's room, skip the rows that do not fit
+ * and set the plan's error flag, so every kernel still stays inside its
+ * buffers; the plan (or the line-graph call) then fails with
+ * SLG_ERR_DEVICE ("a tier list overflowed its planned size") and the
+ * context stays usable. 0 (the default) turns it off; entries < 0 is
+ * SLG_ERR_INVALID_ARG.
+ */
+slg_status slg_context_set_list_shortfall(slg_context *ctx, int64_t entries);
 
 /*
  * Tuning of the plan shape, used by the autotuner: light_max = largest row

@@ -123,6 +123,7 @@ def lib() -> ctypes.CDLL:
         "slg_batch_destroy": (_i32, [_p]),
         "slg_context_set_tuning": (_i32, [_p, _i32, _i64, _i32]),
         "slg_context_set_dense": (_i32, [_p, _i32, _i32]),
+        "slg_context_set_list_shortfall": (_i32, [_p, _i64]),
         "slg_context_set_timing": (_i32, [_p, ctypes.c_int]),
         "slg_context_get_timing": (_i32, [_p, ctypes.POINTER(StageTime), _i32, ctypes.POINTER(_i32)]),
         "slg_context_reset_timing": (_i32, [_p]),
@@ -342,10 +343,16 @@ class Context:
     def set_tuning(self, light_max: int = 0, slot_work: int = 0, heavy_grid: int = 0):
         self._check(lib().slg_context_set_tuning(self.handle, light_max, slot_work, heavy_grid))
 
-    def set_dense(self, min_ratio: int = 4, min_range: int = 0):
+    def set_dense(self, min_ratio: int = 2, min_range: int = 0):
         """The dense tier's rule (min_ratio 0 turns it off; min_range 0 = its
         default); results are identical either way."""
         self._check(lib().slg_context_set_dense(self.handle, int(min_ratio), int(min_range)))
+
+    def set_list_shortfall(self, entries: int):
+        """Fault injection for error-path tests: later plans give their heavy
+        descriptor lists `entries` fewer places than counted, so their
+        appends are refused and the plan fails with SLG_ERR_DEVICE."""
+        self._check(lib().slg_context_set_list_shortfall(self.handle, int(entries)))
 
     # -- measurement ---------------------------------------------------------
     def set_count_store(self, max_bytes: int, min_two_paths: int = 1 << 24):

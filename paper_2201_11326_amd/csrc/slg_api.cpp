@@ -59,6 +59,7 @@ struct slg_context {
     int32_t dense_min = kDenseMinRange;
     int64_t store_limit = int64_t(32) << 30;  // largest count store a plan keeps (0: none)
     int64_t store_min = int64_t(1) << 24;     // fewest heavy 2-paths for which a plan keeps one
+    int64_t list_shortfall = 0;  // error-path tests: heavy lists planned this much short
     uint64_t budget = 0;
     bool has_alloc = false;
     slg_allocator alloc{};
@@ -350,6 +351,7 @@ struct slg_plan {
     int64_t *store_work = nullptr; // [heavy slots]: 2-paths per slot
     int64_t store_limit = 0;
     int64_t store_min = 0;
+    int64_t list_shortfall = 0;
     int64_t stored_ranks = 0;
     int64_t two_paths = 0;
     int64_t heavy_two_paths = 0;
@@ -696,8 +698,13 @@ hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
             return e;
     {
         StageTimer tm(ctx, kStSlots, st);
+        // room of every list as planned (less the error-path tests' shortfall
+        // on the heavy lists: appends past it are refused and flagged)
+        int64_t caps[kNumLists];
+        for (int c = 0; c < kNumLists; ++c)
+            caps[c] = c < kLightClasses ? p->list_count[c] : std::max<int64_t>(0, p->list_count[c] - p->list_shortfall);
         if ((e = launch_fill_slots(m, p->pr.he_ptr, p->slot_base, b.nslots, b.jmax, b.rclass, b.bbase, b.cid,
-                                   b.hat, b.hcnt, b.part_m, b.slot_row, p->lists, p->heavy, p->list_count,
+                                   b.hat, b.hcnt, b.part_m, b.slot_row, p->lists, p->heavy, caps,
                                    reinterpret_cast<unsigned long long *>(b.counters + kCntFill),
                                    reinterpret_cast<int *>(b.counters + kCntErr), st)) != hipSuccess)
             return e;
@@ -832,7 +839,7 @@ slg_status plan_rows(slg_plan *p) {
         phase1.add(&b.kpre, m + 1);
         phase1.add(&b.cid, m);
         phase1.add(&b.cid_row, m);
-        phase1.add(&b.vs_cid, nnz);
+        phase1.add(&b.vs_cid, nnz + kDensePad);  // the dense walk may load (not count) past the end
     }
     if (p->blocks) {
         phase1.add(&b.nslots_all, m);
@@ -1055,6 +1062,7 @@ slg_plan *plan_new(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t num
     p->dense_grid = ctx->dense_resident;
     p->store_limit = ctx->store_limit;
     p->store_min = ctx->store_min;
+    p->list_shortfall = ctx->list_shortfall;
     return p;
 }
 
@@ -1582,6 +1590,13 @@ slg_status slg_context_set_dense(slg_context *ctx, int32_t min_ratio, int32_t mi
     if (min_ratio < 0 || min_range < 0) return fail(ctx, SLG_ERR_INVALID_ARG, "min_ratio and min_range must be >= 0");
     ctx->dense_ratio = min_ratio;
     ctx->dense_min = min_range > 0 ? min_range : kDenseMinRange;
+    return SLG_OK;
+}
+
+slg_status slg_context_set_list_shortfall(slg_context *ctx, int64_t entries) {
+    if (!ctx) return SLG_ERR_INVALID_ARG;
+    if (entries < 0) return fail(ctx, SLG_ERR_INVALID_ARG, "entries must be >= 0");
+    ctx->list_shortfall = entries;
     return SLG_OK;
 }
 

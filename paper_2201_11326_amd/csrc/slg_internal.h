@@ -23,11 +23,12 @@ constexpr int kWideMembers = 65535;    // rows this large need u32 overlap count
 // Dense tier: a row whose partners fill most of E_s (at least dense_ratio
 // 2-paths per candidate partner) counts into direct LDS counters over
 // aligned windows of kDenseWindow consecutive E_s positions.
-constexpr int kDenseBits = 15;
-constexpr int kDenseWindow = 1 << kDenseBits;  // E_s positions per dense slot (u16 counters, 64 KB)
+constexpr int kDenseBits = 14;
+constexpr int kDenseWindow = 1 << kDenseBits;  // E_s positions per dense slot (u32 counters, 64 KB)
 constexpr int kDenseThreads = 512;            // workgroup of the dense tier (2 per CU)
 constexpr int kDenseRatio = 2;                // default: 2-paths per candidate partner to go dense
-constexpr int kDenseMinRange = kDenseWindow / 4;  // default: fewest candidate partners to go dense
+constexpr int kDenseMinRange = 8192;          // default: fewest candidate partners to go dense
+constexpr int kDensePad = 1024;  // entries past the end of the E_s-position lists the dense walk may load
 
 // Row classes written by the planning kernel.
 enum RowClass : uint8_t {

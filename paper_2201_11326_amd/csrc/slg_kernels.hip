@@ -1897,24 +1897,25 @@ __global__ __launch_bounds__(256) void bounds_kernel(
 // A dense slot is a row i and an aligned window [ja, ja + kDenseWindow) of
 // E_s positions; its 2-paths are the parts of its members' tails that fall
 // in the window (vertex lists in E_s positions, so the counter of partner c
-// is c - ja with no search). The counters are u16, two to a word: position
-// c - ja = x sits in word x mod kDenseWords, low half for x < kDenseWords,
-// so that partners that follow each other in a list (consecutive lanes)
-// hit consecutive words. A row of fewer than 2^16 members cannot overflow
-// a u16 overlap.
-constexpr int kDW = kDenseThreads / 64;                        // wavefronts per dense workgroup
-constexpr int kDenseWords = kDenseWindow / 2;                  // counter words (two u16 each)
-constexpr int kDenseWordsPer = kDenseWords / kDenseThreads;    // words per thread (32)
-constexpr int kDenseUnroll = 8;                                // loads in flight per lane
+// is c - ja with no search). One u32 counter per position: the byte address
+// of partner c's counter is 4c - 4ja, one shift-add, so that a 2-path costs
+// one load, two vector instructions and one LDS add. A row of fewer than
+// 2^16 members cannot reach 2^16 in a counter (the store keeps 16 bits).
+constexpr int kDW = kDenseThreads / 64;                       // wavefronts per dense workgroup
+constexpr int kDenseWordsPer = kDenseWindow / kDenseThreads;  // counters per thread (32)
+constexpr int kDenseUnroll = 16;                              // loads in flight per lane
+constexpr int kDensePiece = 64 * kDenseUnroll;                // 2-paths per wavefront step
+// vs_cid is allocated kDensePad entries longer: a step inside one tail
+// loads whole rows past the tail's end (those values are not counted)
+static_assert(kDensePad >= kDensePiece, "padding of the E_s-position lists");
 static_assert(kDenseWordsPer % 4 == 0, "16-byte LDS accesses");
-static_assert(kDenseWords <= (1 << 16) && kDenseWindow <= (1 << 16), "16-bit store fields");
+static_assert(kWideMembers < (1 << 16), "16-bit overlaps in the dense store");
 
 struct DenseSmem {
-    uint32_t cnt[kDenseWords];
+    uint32_t cnt[kDenseWindow + 4];      // counters; cnt[kDenseWindow] takes out-of-window adds (none arise)
     int32_t seg_a[kDenseThreads];        // segment start per member of the batch
     int32_t seg_pre[kDenseThreads + 1];  // flattened start per member of the batch
     int32_t wsum[kDW];
-    int32_t wsum2[kDW];
     unsigned long long tally[SLG_MAX_S];
     long long base;                      // store room of the slot (or -1)
     int64_t next;                        // the next slot claimed
@@ -1938,10 +1939,18 @@ __device__ __forceinline__ int dense_scan(int x, int32_t *wsum, int &total) {
     return pre + incl - x;
 }
 
+// Adds one to the counter at byte offset a of the counters.
+__device__ __forceinline__ void dense_add(DenseSmem &sm, uint32_t a) {
+    atomicAdd(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(sm.cnt) + a), 1u);
+}
+
 // Walks the laid-out segments (2-path f of the batch is member u's tail
 // position seg_a[u] + f - seg_pre[u]) and adds one to the counter of each
 // partner. Each wavefront takes an equal share of the flattened list, in
-// pieces of 64 * kDenseUnroll positions whose loads are all issued first.
+// steps of kDensePiece positions whose loads are all issued first. A step
+// inside one tail (the common case: the 2-paths of a dense slot come mostly
+// from long tails) takes one address and the loads' immediate offsets; a
+// step across tails finds each position's tail by binary search.
 __device__ __forceinline__ void dense_walk(const int32_t *__restrict__ vs_cid, int total, int nseg, DenseSmem &sm,
                                            int ja) {
     if (total <= 0) return;
@@ -1951,40 +1960,50 @@ __device__ __forceinline__ void dense_walk(const int32_t *__restrict__ vs_cid, i
     const int c1 = min(total, c0 + per);
     if (c0 >= c1) return;
     const int useg = min(nseg, kDenseThreads) - 1;
+    const uint32_t nja4 = 0u - 4u * (uint32_t)ja;
+    constexpr uint32_t kStray = 4u * kDenseWindow;
     int ufirst = wave_segment_of(sm.seg_pre, 0, useg, c0);
-    for (int pb = c0; pb < c1; pb += 64 * kDenseUnroll) {
-        const int plast = min(c1, pb + 64 * kDenseUnroll) - 1;
+    for (int pb = c0; pb < c1; pb += kDensePiece) {
+        const int plast = min(c1, pb + kDensePiece) - 1;
         const int ulast = wave_segment_of(sm.seg_pre, ufirst, useg, plast);
-        int src[kDenseUnroll];
-        if (ufirst == ulast) {  // the whole piece in one tail (the common case)
-            const int base = sm.seg_a[ufirst] - sm.seg_pre[ufirst];
+        if (ufirst == ulast) {
+            const int32_t *src = vs_cid + ((int64_t)(sm.seg_a[ufirst] - sm.seg_pre[ufirst]) + pb + lane);
+            int c[kDenseUnroll];
 #pragma unroll
-            for (int r = 0; r < kDenseUnroll; ++r) src[r] = base + min(pb + lane + 64 * r, plast);
-        } else {
-            int fq[kDenseUnroll], u[kDenseUnroll];
+            for (int r = 0; r < kDenseUnroll; ++r) c[r] = src[64 * r];
+            if (plast == pb + kDensePiece - 1) {  // wave-uniform: every position of the step counts
 #pragma unroll
-            for (int r = 0; r < kDenseUnroll; ++r) {
-                fq[r] = min(pb + lane + 64 * r, plast);
-                u[r] = ufirst;
-            }
-            for (int len = ulast - ufirst + 1; len > 1;) {
-                const int half = len >> 1;
+                for (int r = 0; r < kDenseUnroll; ++r) dense_add(sm, min((uint32_t)c[r] * 4u + nja4, kStray));
+            } else {
 #pragma unroll
                 for (int r = 0; r < kDenseUnroll; ++r)
-                    u[r] = sm.seg_pre[u[r] + half] <= fq[r] ? u[r] + half : u[r];
-                len -= half;
+                    if (pb + lane + 64 * r <= plast) dense_add(sm, min((uint32_t)c[r] * 4u + nja4, kStray));
             }
+        } else {
+            constexpr int kHalf = kDenseUnroll / 2;
+#pragma unroll 1
+            for (int h = 0; h < 2; ++h) {
+                const int hb = pb + 64 * kHalf * h;
+                if (hb > plast) break;  // wave-uniform
+                int fq[kHalf], u[kHalf], c[kHalf];
 #pragma unroll
-            for (int r = 0; r < kDenseUnroll; ++r) src[r] = sm.seg_a[u[r]] + (fq[r] - sm.seg_pre[u[r]]);
-        }
-        int c[kDenseUnroll];
+                for (int r = 0; r < kHalf; ++r) {
+                    fq[r] = min(hb + lane + 64 * r, plast);
+                    u[r] = ufirst;
+                }
+                for (int len = ulast - ufirst + 1; len > 1;) {
+                    const int half = len >> 1;
 #pragma unroll
-        for (int r = 0; r < kDenseUnroll; ++r) c[r] = vs_cid[src[r]];
+                    for (int r = 0; r < kHalf; ++r)
+                        u[r] = sm.seg_pre[u[r] + half] <= fq[r] ? u[r] + half : u[r];
+                    len -= half;
+                }
 #pragma unroll
-        for (int r = 0; r < kDenseUnroll; ++r) {
-            const unsigned x = (unsigned)(c[r] - ja);
-            if (pb + lane + 64 * r <= plast && x < (unsigned)kDenseWindow)
-                atomicAdd(&sm.cnt[x & (kDenseWords - 1)], 1u << ((x >> (kDenseBits - 1)) << 4));
+                for (int r = 0; r < kHalf; ++r) c[r] = vs_cid[sm.seg_a[u[r]] + (fq[r] - sm.seg_pre[u[r]])];
+#pragma unroll
+                for (int r = 0; r < kHalf; ++r)
+                    if (hb + lane + 64 * r <= plast) dense_add(sm, min((uint32_t)c[r] * 4u + nja4, kStray));
+            }
         }
         ufirst = ulast;
     }
@@ -2010,9 +2029,9 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
                                                               int64_t cap) {
     __shared__ DenseSmem sm;
     __shared__ EmitParams sp;
-    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const int tid = threadIdx.x, lane = lane_id();
     stage_params(&sp, prm);
-    for (int x = tid; x < kDenseWords; x += kDenseThreads) sm.cnt[x] = 0u;
+    for (int x = tid; x < kDenseWindow + 4; x += kDenseThreads) sm.cnt[x] = 0u;
     if (tid == 0) sm.next = (int64_t)atomicAdd(ticket, 1ull);
     __syncthreads();
     const int K = sp.k;
@@ -2050,11 +2069,10 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
             dense_walk(vs_cid, total, k - qb, sm, ja);
             __syncthreads();
         }
-        // this thread's counters: words [tid * 32, tid * 32 + 32); half h
-        // holds the partners at positions h * kDenseWords + word. They are
-        // read 16 bytes (four words) at a time; `f(word, low, high)` sees
-        // each word in order, and with `clear` the words are zeroed for the
-        // next slot. A compiler barrier keeps every pass a fresh read.
+        // this thread's counters: positions [tid * 32, tid * 32 + 32), read
+        // 16 bytes at a time; `f(position, count)` sees each in order, and
+        // with `clear` they are zeroed for the next slot. A compiler barrier
+        // keeps every pass a fresh read.
         auto for_words = [&](bool clear, auto &&f) {
             __asm__ volatile("" ::: "memory");
             uint4 *q = reinterpret_cast<uint4 *>(sm.cnt) + tid * (kDenseWordsPer / 4);
@@ -2062,33 +2080,29 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
             for (int r = 0; r < kDenseWordsPer / 4; ++r) {
                 const uint4 v = q[r];
                 const int x = tid * kDenseWordsPer + 4 * r;
-                f(x, v.x & 0xFFFFu, v.x >> 16);
-                f(x + 1, v.y & 0xFFFFu, v.y >> 16);
-                f(x + 2, v.z & 0xFFFFu, v.z >> 16);
-                f(x + 3, v.w & 0xFFFFu, v.w >> 16);
+                f(x, v.x);
+                f(x + 1, v.y);
+                f(x + 2, v.z);
+                f(x + 3, v.w);
                 if (clear) q[r] = make_uint4(0u, 0u, 0u, 0u);
             }
         };
-        const int s0 = sp.s[0];
+        const unsigned s0 = (unsigned)sp.s[0];
+        const auto crow = as_global(cid_row) + ja;
         if (!EMIT) {
             // tallies of the larger thresholds, then the survivors of the
             // smallest (kept in the store)
             for (int kk = 1; kk < K; ++kk) {
                 const unsigned sk = (unsigned)sp.s[kk];
                 int c = 0;
-                for_words(false, [&](int, unsigned lo, unsigned hi) { c += (lo >= sk) + (hi >= sk); });
+                for_words(false, [&](int, unsigned v) { c += v >= sk; });
                 c = wave_sum(c);
                 if (lane == 0 && c) atomicAdd(&sm.tally[kk], (unsigned long long)c);
             }
-            int n0 = 0, n1 = 0;
-            for_words(!store, [&](int, unsigned lo, unsigned hi) {
-                n0 += lo >= (unsigned)s0;
-                n1 += hi >= (unsigned)s0;
-            });
-            int tot0, tot1;
-            const int pos0 = dense_scan(n0, sm.wsum, tot0);
-            const int pos1 = dense_scan(n1, sm.wsum2, tot1);
-            const int n = tot0 + tot1;
+            int n0 = 0;
+            for_words(!store, [&](int, unsigned v) { n0 += v >= s0; });
+            int n;
+            const int pos0 = dense_scan(n0, sm.wsum, n);
             if (tid == 0) sm.tally[0] = (unsigned long long)n;
             if (store && tid == 0) {  // room in the store, one reservation per slot
                 long long b = -1;
@@ -2104,13 +2118,9 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
             if (store) {  // partner id << 16 | overlap (the window's ids are in L2)
                 const long long base = sm.base;
                 const auto ent = as_global(cs.ent64);
-                const auto crow = as_global(cid_row) + ja;
-                long long q0 = base + pos0, q1 = base + tot0 + pos1;
-                for_words(true, [&](int x, unsigned lo, unsigned hi) {
-                    if (base < 0) return;
-                    if (lo >= (unsigned)s0) ent[q0++] = ((unsigned long long)(uint32_t)crow[x] << 16) | lo;
-                    if (hi >= (unsigned)s0)
-                        ent[q1++] = ((unsigned long long)(uint32_t)crow[x + kDenseWords] << 16) | hi;
+                long long q0 = base + pos0;
+                for_words(true, [&](int x, unsigned v) {
+                    if (base >= 0 && v >= s0) ent[q0++] = ((unsigned long long)(uint32_t)crow[x] << 16) | v;
                 });
             }
             if (tid < K) slot_cnt[(int64_t)tid * S + d.slot] = (int64_t)sm.tally[tid];
@@ -2119,37 +2129,26 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
             const int i = d.row;
             for (int kk = 0; kk < K; ++kk) {
                 const unsigned sk = (unsigned)sp.s[kk];
-                int n0 = 0, n1 = 0;
-                for_words(false, [&](int, unsigned lo, unsigned hi) {
-                    n0 += lo >= sk;
-                    n1 += hi >= sk;
-                });
-                int tot0, tot1;
-                const int pos0 = dense_scan(n0, sm.wsum, tot0);
-                const int pos1 = dense_scan(n1, sm.wsum2, tot1);
-                if (tot0 + tot1 == 0) break;  // workgroup-uniform: larger thresholds have none either
+                int n0 = 0;
+                for_words(false, [&](int, unsigned v) { n0 += v >= sk; });
+                int tot;
+                const int pos0 = dense_scan(n0, sm.wsum, tot);
+                if (tot == 0) break;  // workgroup-uniform: larger thresholds have none either
                 const int64_t b = slot_off[(int64_t)kk * (S + 1) + d.slot] - sp.out_base[kk];
                 const auto colp = as_global(sp.col[kk]);
                 const auto wp = as_global(sp.w[kk]);
                 const auto rowp = as_global(sp.row[kk]);
-                const auto crow = as_global(cid_row) + ja;
-                int64_t q0 = b + pos0, q1 = b + tot0 + pos1;
-                for_words(false, [&](int x, unsigned lo, unsigned hi) {
-                    if (lo >= sk) {
+                int64_t q0 = b + pos0;
+                for_words(false, [&](int x, unsigned v) {
+                    if (v >= sk) {
                         colp[q0] = crow[x];
-                        wp[q0] = (int)lo;
+                        wp[q0] = (int)v;
                         if (rowp) rowp[q0] = i;
                         ++q0;
                     }
-                    if (hi >= sk) {
-                        colp[q1] = crow[x + kDenseWords];
-                        wp[q1] = (int)hi;
-                        if (rowp) rowp[q1] = i;
-                        ++q1;
-                    }
                 });
             }
-            for_words(true, [](int, unsigned, unsigned) {});  // cleared for the next slot
+            for_words(true, [](int, unsigned) {});  // cleared for the next slot
         }
         __syncthreads();  // counters cleared, sm.next published
     }

@@ -7,7 +7,8 @@
   python -m paper_2201_11326_amd.profiling probe_large
       The same calibration copy, then one row range of the large skewed
       workload at full size (range 5 of 25 ranges of equal 2-path work, the
-      first one a default bench run times), S = {8, 16}, streamed.
+      first one a default bench run times), S = {8, 16}, streamed, with the
+      bench's count-store limit (160 GiB).
   python -m paper_2201_11326_amd.profiling stats DB [--match NAME]
       Per-kernel launch count / total / average / min / max duration from a
       rocprofv3 --kernel-trace database.
@@ -76,6 +77,7 @@ def probe_large() -> None:
     del x, y
     inc = hg.large_skewed()
     ctx = slg.Context(0)
+    ctx.set_count_store(160 << 30)  # the large skewed bench's count-store limit
     g = ctx.register_incidence(inc)
     prefix = ctx.work_prefix(g, 8)
     W, B, b = int(prefix[-1]), 25, 5

@@ -13,7 +13,7 @@ from gpu_util import assert_matches_oracle, assert_well_formed, planted
 
 pytestmark = pytest.mark.gpu
 
-WINDOW = 1 << 15  # E_s positions per dense slot
+WINDOW = 1 << 14  # E_s positions per dense slot
 
 
 def _ctx(dense, store_limit=32 << 30, store_min=0):
@@ -27,7 +27,7 @@ def _ctx(dense, store_limit=32 << 30, store_min=0):
 @pytest.fixture(scope="module")
 def skewed():
     # the large-skewed generator's laws at m = 3e5: |E_8| = 90,526 rows, so
-    # rows span up to three windows; W_8 = 2.3e10 2-paths
+    # rows span up to six windows; W_8 = 2.3e10 2-paths
     return hg.large_skewed(n=150_000, m=300_000)
 
 
@@ -93,7 +93,7 @@ def test_dense_windows_equal_other_tiers_and_oracle_rows(skewed):
         for f in ("row_ptr", "row", "col", "w"):
             assert torch.equal(getattr(x, f), getattr(y, f)), (x.s, f)
     assert a[0].two_paths == oracle.two_paths(inc, 8)
-    # rows at the window boundaries of E_8 (positions 32767/32768, 65535/65536)
+    # rows at the window boundaries of E_8 (positions 16383/16384, 32767/32768)
     kept = np.nonzero(inc.sizes() >= 8)[0]
     edges = [WINDOW - 2, WINDOW - 1, WINDOW, 2 * WINDOW - 1, 2 * WINDOW, 2 * WINDOW + 1]
     rng = np.random.default_rng(5)

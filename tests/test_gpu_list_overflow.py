@@ -1,0 +1,47 @@
+"""The plan's refused-append path. With the heavy descriptor lists planned
+short (a fault injected from the host), the capacity-checked appends on the
+device skip the rows that do not fit and set the plan's error flag, so no
+kernel leaves its buffers; the call fails with SLG_ERR_DEVICE, and the same
+context then plans and emits the oracle's result again."""
+from __future__ import annotations
+
+import pytest
+
+import oracle
+from gpu_util import assert_matches_oracle, planted
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dense", [(0, 0), (1, 1)], ids=["bitmap_tier", "dense_tier"])
+def test_refused_append_fails_cleanly_and_context_recovers(dense):
+    import paper_2201_11326_amd as slg
+    inc = planted(6000, 20000, [([0], 1, 0)], 3, seed=17)  # vertex 0 in every row: heavy rows
+    S = [1, 2]
+    ctx = slg.Context(0)
+    ctx.set_dense(*dense)
+    g = ctx.register_incidence(inc)
+    p = ctx.plan(g, S)
+    st = p.stats()
+    p.destroy()
+    assert st["dense_slots" if dense[0] else "heavy_slots"] > 0, st
+
+    ctx.set_list_shortfall(1)
+    with pytest.raises(slg.SlgError) as ei:
+        ctx.line_graph(g, S)
+    assert ei.value.status == slg.SLG_ERR_DEVICE and "overflowed" in str(ei.value)
+    seen = []
+    with pytest.raises(slg.SlgError) as ei:  # the streamed form plans per row block: same check
+        ctx.line_graph_stream(g, S, 1 << 20, lambda *a: seen.append(a[0]) or False)
+    assert ei.value.status == slg.SLG_ERR_DEVICE and not seen
+    with pytest.raises(slg.SlgError) as ei:
+        ctx.set_list_shortfall(-1)
+    assert ei.value.status == slg.SLG_ERR_INVALID_ARG
+
+    ctx.set_list_shortfall(0)
+    outs = [o.cpu() for o in ctx.line_graph(g, S)]
+    for lg in outs:
+        assert_matches_oracle(inc, lg, lg.s, "after a refused append")
+    assert outs[0].two_paths == oracle.two_paths(inc, 1)
+    g.release()
+    ctx.close()
