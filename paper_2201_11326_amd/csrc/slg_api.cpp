@@ -98,20 +98,23 @@ static_assert(kCntTotal <= 32, "counter block");
 constexpr int kHbSlots = kCntTotal;      // slot table size, then 2-paths, boundary entries
 constexpr int kHbEdges = 40;             // SLG_MAX_S edge totals
 constexpr int kHbHeavyEdges = kHbEdges + SLG_MAX_S;
-constexpr int kHbRange = kHbHeavyEdges + 5;  // a chunk's heavy list ranges (2 per list)
+constexpr int kHbRange = kHbHeavyEdges + 7;  // a chunk's heavy list ranges (2 per list)
 static_assert(kHbSlots + 3 <= kHbEdges && kHbRange + 2 * kNumHeavyLists <= kPinnedSlots, "pinned staging layout");
 // Device counters of a plan (int64 entries of `tickets`).
 constexpr int kTkCount = 0;       // kNumHeavyLists: slot tickets of the counting passes
 constexpr int kTkEmit = 3;        // kNumHeavyLists: slot tickets of the emit passes
 constexpr int kTkHeavyEdges = 6;  // edges of heavy and heavy-wide slots
 constexpr int kTkStored = 7;      // entries of the heavy count store
-constexpr int kTkDenseCursor = 8; // room taken from the dense store
-constexpr int kTkDenseEdges = 9;  // edges of dense slots
-constexpr int kTkRange = 10;      // 2 per heavy list: a chunk's part of it
+constexpr int kTkDenseCursor = 8; // room taken from the dense store (in chunks)
+constexpr int kTkDenseAsked = 9;  // survivors the dense slots asked the store to keep
+constexpr int kTkDenseKept = 10;  // ... and those it kept (fewer: some slots walk again)
+constexpr int kTkDenseEdges = 11; // edges of dense slots
+constexpr int kTkRange = 12;      // 2 per heavy list: a chunk's part of it
 constexpr int kTkTotal = kTkRange + 2 * kNumHeavyLists;
 static_assert(kTkHeavyEdges + 1 == kTkStored && kTkStored + 1 == kTkDenseCursor &&
-                  kTkDenseCursor + 1 == kTkDenseEdges,
-              "plan counters read back together");
+                  kTkDenseCursor + 1 == kTkDenseAsked && kTkDenseAsked + 1 == kTkDenseKept &&
+                  kTkDenseKept + 1 == kTkDenseEdges,
+              "plan counters read back together; the dense kernel takes cursor, asked, kept in a row");
 
 // Freed device blocks a context keeps for reuse unless told otherwise.
 constexpr uint64_t kDefaultCacheMin = uint64_t(16) << 30;  // default block cache: half of the
@@ -340,7 +343,8 @@ struct slg_plan {
     int64_t dstore_cap = 0;        // entries of the dense store
     int64_t dense_two_paths = 0;
     int64_t dense_edges = 0;
-    int64_t dense_stored = 0;      // entries the dense slots asked for (> cap: some walk again)
+    int64_t dense_stored = 0;      // survivors the dense slots asked the store to keep
+    int64_t dense_kept = 0;        // ... and those it kept (fewer: some slots walk again)
     bool use_store = false;        // the counting pass keeps the heavy overlaps for the emit pass
     CountStore store{};
     bool use_lstore = false;       // ... and the light rows' overlaps
@@ -468,6 +472,7 @@ slg_status slg_context_destroy(slg_context *ctx) {
     if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx;
+    (void)hipGetLastError();  // teardown errors stay out of later calls' launch checks
     return SLG_OK;
 }
 
@@ -578,6 +583,7 @@ slg_status slg_graph_release(slg_graph *g) {
         (void)hipSetDevice(g->ctx->device);
         (void)hipDeviceSynchronize();  // work still reading the copies
         for (void *q : g->owned) (void)hipFree(q);
+        (void)hipGetLastError();
     }
     delete g;
     return SLG_OK;
@@ -799,6 +805,10 @@ hipError_t enqueue_slots_count(slg_plan *p, hipStream_t st) {
 // The rows phase of a plan: pruning, E_s positions, the per-row work
 // estimate and tiers, and their scans over every row, with the readback
 // that sizes a plan of all rows.
+// Workgroups of the dense tier's launches, at most (each may leave one
+// store chunk partly unused).
+int64_t dense_workgroups(const slg_plan *p) { return p->dense_grid > 0 ? p->dense_grid : 512; }
+
 slg_status plan_rows(slg_plan *p) {
     slg_context *ctx = p->ctx;
     const slg_incidence &inc = p->g->inc;
@@ -977,7 +987,9 @@ slg_status plan_block(slg_plan *p, int64_t r0, int64_t r1) {
         const int64_t nd = p->list_count[kLightClasses + 2];
         const int64_t left = p->store_limit - (p->use_store ? bytes : 0) - (p->use_lstore ? lbytes : 0) -
                              nd * 12 - 16;
-        p->dstore_cap = std::min<int64_t>(p->dense_two_paths / std::max(p->s_min, 1) + 1, left / 8);
+        // (room is handed out in chunks: each persistent workgroup may leave one unfilled)
+        p->dstore_cap = std::min<int64_t>(
+            p->dense_two_paths / std::max(p->s_min, 1) + 1 + (int64_t)dense_workgroups(p) * kDenseChunk, left / 8);
         if (p->dstore_fixed) p->dstore_cap = p->dstore_fixed_cap;  // row blocks share one store of fixed size
         p->use_dstore = nd > 0 && p->dstore_cap > 0;
         if (nd > 1) phase2.add(&p->dorder, nd);
@@ -1008,18 +1020,19 @@ slg_status plan_block(slg_plan *p, int64_t r0, int64_t r1) {
                                  p->tickets + kTkDenseEdges, st));
     if (p->use_store)
         BUILD_HIP(launch_sum_i32(p->store.n, p->list_count[kLightClasses], p->tickets + kTkStored, st));
-    BUILD_HIP(hipMemcpyAsync(hb + kHbHeavyEdges, p->tickets + kTkHeavyEdges, 4 * sizeof(int64_t),
-                             hipMemcpyDeviceToHost, st));  // heavy edges, stored, dense cursor, dense edges
-    BUILD_HIP(hipMemcpyAsync(hb + kHbHeavyEdges + 4, b.counters + kCntErr, sizeof(int64_t),
+    BUILD_HIP(hipMemcpyAsync(hb + kHbHeavyEdges, p->tickets + kTkHeavyEdges, 6 * sizeof(int64_t),
+                             hipMemcpyDeviceToHost, st));  // heavy edges, stored, dense room, asked, kept, edges
+    BUILD_HIP(hipMemcpyAsync(hb + kHbHeavyEdges + 6, b.counters + kCntErr, sizeof(int64_t),
                              hipMemcpyDeviceToHost, st));
     BUILD_HIP(hipStreamSynchronize(st));
-    if (hb[kHbHeavyEdges + 4] & 0xffffffff)
+    if (hb[kHbHeavyEdges + 6] & 0xffffffff)
         return fail(ctx, SLG_ERR_DEVICE, "internal error: a tier list overflowed its planned size");
     for (int k = 0; k < K; ++k) p->num_edges[k] = hb[kHbEdges + k];
     p->heavy_edges = hb[kHbHeavyEdges];
     p->stored_ranks = hb[kHbHeavyEdges + 1];
-    p->dense_stored = hb[kHbHeavyEdges + 2];
-    p->dense_edges = hb[kHbHeavyEdges + 3];
+    p->dense_stored = hb[kHbHeavyEdges + 3];
+    p->dense_kept = hb[kHbHeavyEdges + 4];
+    p->dense_edges = hb[kHbHeavyEdges + 5];
     int64_t *wk = ctx->work;
     wk[kWkBlocks] += 1;
     wk[kWkTwoPaths] += p->two_paths;
@@ -1029,8 +1042,8 @@ slg_status plan_block(slg_plan *p, int64_t r0, int64_t r1) {
     wk[kWkHeavyEdges] += p->heavy_edges;
     wk[kWkDenseEdges] += p->dense_edges;
     wk[kWkDenseSlots] += p->list_count[kLightClasses + 2];
-    wk[kWkDenseStored] += std::min(p->dense_stored, p->dstore_cap);
-    wk[kWkDenseRewalk] += (p->list_count[kLightClasses + 2] > 0 && p->dense_stored > p->dstore_cap) ? 1 : 0;
+    wk[kWkDenseStored] += p->dense_kept;
+    wk[kWkDenseRewalk] += (p->list_count[kLightClasses + 2] > 0 && p->dense_stored > p->dense_kept) ? 1 : 0;
     return SLG_OK;
 }
 
@@ -1070,6 +1083,7 @@ void plan_free(slg_plan *p) {
     p->scratch2.release();
     p->scratch.release();
     (void)hipStreamSynchronize(p->st);
+    (void)hipGetLastError();
     delete p;
 }
 }  // namespace
@@ -1176,7 +1190,7 @@ slg_status emit_range(slg_plan *p, int64_t r0, int64_t r1, int64_t s0, int64_t s
         const CountStore part{nullptr, p->dstore.off + lo[2], p->dstore.n + lo[2], p->dstore.ent64};
         if (p->use_dstore)
             SLG_HIP(ctx, launch_heavy_store_emit(p->heavy[2] + lo[2], cnt, p->S, part, prm, p->slot_off, st));
-        if (!p->use_dstore || p->dense_stored > p->dstore_cap)
+        if (!p->use_dstore || p->dense_stored > p->dense_kept)
             SLG_HIP(ctx, launch_dense(true, p->heavy[2] + lo[2], cnt, nullptr, p->S, p->bounds, p->pr, prm, nullptr,
                                       p->slot_off, p->tickets + kTkEmit + 2, p->dense_grid,
                                       p->use_dstore ? &part : nullptr, nullptr, 0, st));
@@ -1263,6 +1277,7 @@ slg_status stream_rows(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t
             if (done[t]) (void)hipEventDestroy(done[t]);
             if (used[t]) (void)hipEventDestroy(used[t]);
         }
+        (void)hipGetLastError();  // the status returned is `code`
         return code;
     };
 #define STREAM_HIP(call)                                                                            \
@@ -1330,7 +1345,9 @@ slg_status stream_rows(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t
     while (b0 < nr) {
         // the block: rows while the estimated scratch fits
         const double per_dense = dense_ratio * 1.25;  // store entries per dense 2-path, with room
-        const double dense_room = (double)p->dstore_fixed_cap;
+        // (less what the workgroups' unfilled chunks may take)
+        const double dense_room =
+            std::max(0.0, (double)p->dstore_fixed_cap - (double)dense_workgroups(p) * (double)kDenseChunk);
         double bytes = 0, entries = 0;
         int64_t b1 = b0;
         while (b1 < nr) {
@@ -1507,8 +1524,8 @@ slg_status slg_plan_stats(const slg_plan *p, int64_t *out, int32_t cap, int32_t 
     vals[15] = p->list_count[kLightClasses + 2];
     vals[16] = p->dense_two_paths;
     vals[17] = p->dense_edges;
-    vals[18] = std::min(p->dense_stored, p->dstore_cap);
-    vals[19] = p->dense_stored > p->dstore_cap ? 1 : 0;
+    vals[18] = p->dense_kept;
+    vals[19] = p->dense_stored > p->dense_kept ? 1 : 0;
     static_assert(kLightClasses == 7, "plan stats layout");
     int32_t n = cap < 20 ? cap : 20;
     for (int32_t t = 0; t < n; ++t) out[t] = vals[t];
@@ -1630,6 +1647,7 @@ void batch_free(slg_batch *b) {
     for (void *q : b->owned) (void)hipFreeAsync(q, b->st);
     (void)hipStreamSynchronize(b->st);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    (void)hipGetLastError();
     delete b;
 }
 }  // namespace

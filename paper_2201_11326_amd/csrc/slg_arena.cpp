@@ -10,7 +10,14 @@ Arena::Event::~Event() {
 
 Arena::Arena(int device, uint64_t cache_limit) : device_(device), limit_(cache_limit) {}
 
-Arena::~Arena() { trim(); }
+Arena::~Arena() {
+    trim();
+    if (free_st_) {
+        (void)hipStreamSynchronize(free_st_);
+        (void)hipStreamDestroy(free_st_);
+    }
+    (void)hipGetLastError();  // nothing of the teardown reaches a later call's error check
+}
 
 // 256 B granules up to 4 KiB, then four classes per power of two (at most
 // 25% slack).
@@ -77,6 +84,7 @@ void Arena::put(const std::vector<void *> &blocks, hipStream_t st, bool idle) {
             hipEventRecord(ev->e, st) != hipSuccess) {
             // cannot mark the point in the stream: wait for it instead
             (void)hipStreamSynchronize(st);
+            (void)hipGetLastError();
             idle = true;
             ev.reset();
         }
@@ -94,11 +102,16 @@ void Arena::put(const std::vector<void *> &blocks, hipStream_t st, bool idle) {
 }
 
 // The block's own pending work is waited for on the host (its event, not the
-// whole device), then it goes back to the pool, ordered on the null stream
-// (the stream it was given back on may be gone by now).
+// whole device), then it goes back to the pool on the arena's own stream
+// (the stream it was given back on may be gone by now, and the legacy null
+// stream would order the free after every other stream's work). Errors are
+// dropped here and cleared, so that they do not surface in a later,
+// unrelated launch check; a block whose free fails is freed synchronously.
 void Arena::release_locked(std::multimap<size_t, Free>::iterator it) {
     if (it->second.ev) (void)hipEventSynchronize(it->second.ev->e);
-    (void)hipFreeAsync(it->second.p, nullptr);
+    if (!free_st_ && hipStreamCreateWithFlags(&free_st_, hipStreamNonBlocking) != hipSuccess) free_st_ = nullptr;
+    if (hipFreeAsync(it->second.p, free_st_) != hipSuccess) (void)hipFree(it->second.p);
+    (void)hipGetLastError();
     cached_ -= it->second.size;
     free_.erase(it);
 }

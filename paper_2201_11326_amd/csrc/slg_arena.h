@@ -56,6 +56,7 @@ class Arena {
 
     std::mutex mu_;
     int device_;
+    hipStream_t free_st_ = nullptr;  // frees of cached blocks (made at the first)
     uint64_t limit_;
     uint64_t cached_ = 0;
     std::multimap<size_t, Free> free_;

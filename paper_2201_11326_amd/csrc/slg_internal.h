@@ -29,6 +29,7 @@ constexpr int kDenseThreads = 512;            // workgroup of the dense tier (2 
 constexpr int kDenseRatio = 2;                // default: 2-paths per candidate partner to go dense
 constexpr int kDenseMinRange = 8192;          // default: fewest candidate partners to go dense
 constexpr int kDensePad = 1024;  // entries past the end of the E_s-position lists the dense walk may load
+constexpr long long kDenseChunk = 1 << 16;  // dense-store entries a workgroup takes at a time
 
 // Row classes written by the planning kernel.
 enum RowClass : uint8_t {

@@ -1915,13 +1915,16 @@ struct DenseSmem {
     uint32_t cnt[kDenseWindow + 4];      // counters; cnt[kDenseWindow] takes out-of-window adds (none arise)
     int32_t seg_a[kDenseThreads];        // segment start per member of the batch
     int32_t seg_pre[kDenseThreads + 1];  // flattened start per member of the batch
-    int32_t wsum[kDW];
+    int32_t wsum[2][kDW];                // wavefront totals of a scan (two, used in turn)
     unsigned long long tally[SLG_MAX_S];
     long long base;                      // store room of the slot (or -1)
-    int64_t next;                        // the next slot claimed
+    long long chunk_at, chunk_end;       // the workgroup's store room not yet handed out
+    int64_t next[2];                     // tickets claimed ahead, by slot parity
 };
 
-// Exclusive scan over the dense workgroup (trailing barrier included).
+// Exclusive scan over the dense workgroup. wsum is read after the scan's
+// barrier: the next scan takes the other buffer, so that no second barrier
+// is needed.
 __device__ __forceinline__ int dense_scan(int x, int32_t *wsum, int &total) {
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     const int incl = wave_incl_scan(x);
@@ -1935,7 +1938,6 @@ __device__ __forceinline__ int dense_scan(int x, int32_t *wsum, int &total) {
         tot += t;
     }
     total = tot;
-    __syncthreads();  // wsum is free again
     return pre + incl - x;
 }
 
@@ -1947,10 +1949,13 @@ __device__ __forceinline__ void dense_add(DenseSmem &sm, uint32_t a) {
 // Walks the laid-out segments (2-path f of the batch is member u's tail
 // position seg_a[u] + f - seg_pre[u]) and adds one to the counter of each
 // partner. Each wavefront takes an equal share of the flattened list, in
-// steps of kDensePiece positions whose loads are all issued first. A step
-// inside one tail (the common case: the 2-paths of a dense slot come mostly
-// from long tails) takes one address and the loads' immediate offsets; a
-// step across tails finds each position's tail by binary search.
+// steps of kDensePiece positions whose loads are all issued first. The
+// wavefront keeps its current tail (start and end) in scalar registers: a
+// step inside it (the common case: the 2-paths of a dense slot come mostly
+// from long tails) takes one address and the loads' immediate offsets, with
+// no LDS lookup; a step across tails finds each position's tail by binary
+// search. (Keeping the next step's loads in flight while adding the
+// current one's measured the same: the walk is not bound by load latency.)
 __device__ __forceinline__ void dense_walk(const int32_t *__restrict__ vs_cid, int total, int nseg, DenseSmem &sm,
                                            int ja) {
     if (total <= 0) return;
@@ -1962,50 +1967,70 @@ __device__ __forceinline__ void dense_walk(const int32_t *__restrict__ vs_cid, i
     const int useg = min(nseg, kDenseThreads) - 1;
     const uint32_t nja4 = 0u - 4u * (uint32_t)ja;
     constexpr uint32_t kStray = 4u * kDenseWindow;
-    int ufirst = wave_segment_of(sm.seg_pre, 0, useg, c0);
-    for (int pb = c0; pb < c1; pb += kDensePiece) {
-        const int plast = min(c1, pb + kDensePiece) - 1;
-        const int ulast = wave_segment_of(sm.seg_pre, ufirst, useg, plast);
-        if (ufirst == ulast) {
-            const int32_t *src = vs_cid + ((int64_t)(sm.seg_a[ufirst] - sm.seg_pre[ufirst]) + pb + lane);
-            int c[kDenseUnroll];
+    // tail u covers flattened positions [seg_pre[u], uend); position f of it
+    // is vs_cid[ubase + f]
+    int u = wave_segment_of(sm.seg_pre, 0, useg, c0);
+    int uend = uniform(sm.seg_pre[u + 1]);
+    int ubase = uniform(sm.seg_a[u] - sm.seg_pre[u]);
+    // adds the step at b (its positions up to c1 - 1) from values c
+    auto add_step = [&](const int (&c)[kDenseUnroll], int b) {
+        const int last = min(c1, b + kDensePiece) - 1;
+        if (last == b + kDensePiece - 1) {  // wave-uniform: every position of the step counts
 #pragma unroll
-            for (int r = 0; r < kDenseUnroll; ++r) c[r] = src[64 * r];
-            if (plast == pb + kDensePiece - 1) {  // wave-uniform: every position of the step counts
-#pragma unroll
-                for (int r = 0; r < kDenseUnroll; ++r) dense_add(sm, min((uint32_t)c[r] * 4u + nja4, kStray));
-            } else {
-#pragma unroll
-                for (int r = 0; r < kDenseUnroll; ++r)
-                    if (pb + lane + 64 * r <= plast) dense_add(sm, min((uint32_t)c[r] * 4u + nja4, kStray));
-            }
+            for (int r = 0; r < kDenseUnroll; ++r) dense_add(sm, min((uint32_t)c[r] * 4u + nja4, kStray));
         } else {
+#pragma unroll
+            for (int r = 0; r < kDenseUnroll; ++r)
+                if (b + lane + 64 * r <= last) dense_add(sm, min((uint32_t)c[r] * 4u + nja4, kStray));
+        }
+    };
+    int pb = c0;
+    while (pb < c1) {
+        if (pb >= uend) {
+            u = wave_segment_of(sm.seg_pre, u, useg, pb);
+            uend = uniform(sm.seg_pre[u + 1]);
+            ubase = uniform(sm.seg_a[u] - sm.seg_pre[u]);
+        }
+        const int plast = min(c1, pb + kDensePiece) - 1;
+        if (plast < uend) {
+            // a step inside tail u
+            const int32_t *src = vs_cid + ((int64_t)ubase + lane);
+            int ca[kDenseUnroll];
+#pragma unroll
+            for (int r = 0; r < kDenseUnroll; ++r) ca[r] = src[pb + 64 * r];
+            add_step(ca, pb);
+            pb += kDensePiece;
+        } else {
+            const int ulast = wave_segment_of(sm.seg_pre, u, useg, plast);
             constexpr int kHalf = kDenseUnroll / 2;
 #pragma unroll 1
             for (int h = 0; h < 2; ++h) {
                 const int hb = pb + 64 * kHalf * h;
                 if (hb > plast) break;  // wave-uniform
-                int fq[kHalf], u[kHalf], c[kHalf];
+                int fq[kHalf], uq[kHalf], c[kHalf];
 #pragma unroll
                 for (int r = 0; r < kHalf; ++r) {
                     fq[r] = min(hb + lane + 64 * r, plast);
-                    u[r] = ufirst;
+                    uq[r] = u;
                 }
-                for (int len = ulast - ufirst + 1; len > 1;) {
+                for (int len = ulast - u + 1; len > 1;) {
                     const int half = len >> 1;
 #pragma unroll
                     for (int r = 0; r < kHalf; ++r)
-                        u[r] = sm.seg_pre[u[r] + half] <= fq[r] ? u[r] + half : u[r];
+                        uq[r] = sm.seg_pre[uq[r] + half] <= fq[r] ? uq[r] + half : uq[r];
                     len -= half;
                 }
 #pragma unroll
-                for (int r = 0; r < kHalf; ++r) c[r] = vs_cid[sm.seg_a[u[r]] + (fq[r] - sm.seg_pre[u[r]])];
+                for (int r = 0; r < kHalf; ++r) c[r] = vs_cid[sm.seg_a[uq[r]] + (fq[r] - sm.seg_pre[uq[r]])];
 #pragma unroll
                 for (int r = 0; r < kHalf; ++r)
                     if (hb + lane + 64 * r <= plast) dense_add(sm, min((uint32_t)c[r] * 4u + nja4, kStray));
             }
+            u = ulast;
+            uend = uniform(sm.seg_pre[u + 1]);
+            ubase = uniform(sm.seg_a[u] - sm.seg_pre[u]);
+            pb += kDensePiece;
         }
-        ufirst = ulast;
     }
 }
 
@@ -2015,7 +2040,12 @@ __device__ __forceinline__ void dense_walk(const int32_t *__restrict__ vs_cid, i
 // the slots without stored survivors (every slot when there is no store),
 // writing each threshold's edges in partner order at the slot's offsets.
 // Persistent workgroups take slots from a ticket counter; two fit per CU
-// (LDS), which takes at most 128 VGPRs (4 waves per SIMD).
+// (LDS), which takes at most 128 VGPRs (4 waves per SIMD). The next slot's
+// ticket, position, descriptor and first member segments are loaded while
+// the current slot is counted, so that a slot starts with no global round
+// trip. Store room is taken kDenseChunk entries at a time per workgroup
+// (one global atomic per chunk rather than per slot); cursor[0] is the room
+// taken, cursor[1] and cursor[2] sum the survivors asked for and kept.
 template <bool EMIT>
 __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4))) void dense_kernel(const HeavyDesc *__restrict__ desc, int64_t count,
                                                               const int32_t *__restrict__ order,
@@ -2032,43 +2062,77 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
     const int tid = threadIdx.x, lane = lane_id();
     stage_params(&sp, prm);
     for (int x = tid; x < kDenseWindow + 4; x += kDenseThreads) sm.cnt[x] = 0u;
-    if (tid == 0) sm.next = (int64_t)atomicAdd(ticket, 1ull);
+    if (tid == 0) {
+        sm.next[0] = (int64_t)atomicAdd(ticket, 1ull);
+        sm.chunk_at = 0;
+        sm.chunk_end = 0;
+    }
     __syncthreads();
     const int K = sp.k;
     const bool store = cs.ent64 != nullptr;
-    while (true) {
-        const int64_t tk = sm.next;
-        if (tk >= count) break;
-        const int64_t t = order ? (int64_t)order[tk] : tk;  // the slot's position in desc
-        const HeavyDesc d = desc[t];
+    // the slot of ticket tk: its position in desc (window-major order) and
+    // descriptor; this thread's member segment of its first batch
+    auto slot_of = [&](int64_t tk) -> int64_t { return order ? (int64_t)order[tk] : tk; };
+    auto first_segment = [&](const HeavyDesc &d, int &a, int &len) {
+        a = 0;
+        len = 0;
+        if (tid < d.k) {
+            a = bounds[d.bptr + tid];
+            const int b = bounds[d.bptr + d.k + tid];
+            len = b > a ? b - a : 0;
+        }
+    };
+    int64_t tk = uniform((long long)sm.next[0]);
+    if (tid == 0) sm.next[1] = (int64_t)atomicAdd(ticket, 1ull);  // the following slot
+    int par = 1;  // next[par] holds the following slot's ticket
+    int64_t t = 0;
+    HeavyDesc d{};
+    int a0 = 0, len0 = 0;
+    if (tk < count) {
+        t = uniform((long long)slot_of(tk));
+        d = desc[t];
+        first_segment(d, a0, len0);
+    }
+    while (tk < count) {
+        // the following slot's ticket is in next[par]; the previous slot's
+        // counters are cleared and its reads of the shared arrays are done
+        __syncthreads();
+        const int64_t tkn = uniform((long long)sm.next[par]);
+        const int64_t tn = tkn < count ? uniform((long long)slot_of(tkn)) : 0;  // used after the walk
         const int ja = d.ja, k = d.k;
         bool skip = false;
         if (EMIT) skip = d.slot < sp.slot_lo || d.slot >= sp.slot_hi || (store && as_global(cs.n)[t] >= 0);
-        __syncthreads();  // every thread has read sm.next
-        if (tid == 0) sm.next = (int64_t)atomicAdd(ticket, 1ull);
         if (tid < SLG_MAX_S) sm.tally[tid] = 0ull;
-        if (skip) {  // workgroup-uniform
-            __syncthreads();
-            continue;
-        }
-        // count: every member's part of its tail inside the window
-        for (int qb = 0; qb < k; qb += kDenseThreads) {
-            const int q = qb + tid;
-            int a = 0, len = 0;
-            if (q < k) {
-                a = bounds[d.bptr + q];
-                const int b = bounds[d.bptr + k + q];
-                len = b > a ? b - a : 0;
+        if (!skip) {  // workgroup-uniform
+            // count: every member's part of its tail inside the window
+            for (int qb = 0; qb < k; qb += kDenseThreads) {
+                int a = a0, len = len0;
+                if (qb > 0) {
+                    const int q = qb + tid;
+                    a = 0;
+                    len = 0;
+                    if (q < k) {
+                        a = bounds[d.bptr + q];
+                        const int b = bounds[d.bptr + k + q];
+                        len = b > a ? b - a : 0;
+                    }
+                }
+                int total;
+                const int excl = dense_scan(len, sm.wsum[0], total);
+                sm.seg_a[tid] = a;
+                sm.seg_pre[tid] = excl;
+                if (tid == 0) sm.seg_pre[kDenseThreads] = total;
+                __syncthreads();
+                dense_walk(vs_cid, total, k - qb, sm, ja);
+                __syncthreads();
             }
-            int total;
-            const int excl = dense_scan(len, sm.wsum, total);
-            sm.seg_a[tid] = a;
-            sm.seg_pre[tid] = excl;
-            if (tid == 0) sm.seg_pre[kDenseThreads] = total;
-            __syncthreads();
-            dense_walk(vs_cid, total, k - qb, sm, ja);
-            __syncthreads();
         }
+        // the slot after the following one (next[par ^ 1] was read before this slot's first barrier)
+        if (tid == 0) sm.next[par ^ 1] = (int64_t)atomicAdd(ticket, 1ull);
+        par ^= 1;
+        HeavyDesc dn{};
+        if (tkn < count) dn = desc[tn];
+        int an = 0, lenn = 0;
         // this thread's counters: positions [tid * 32, tid * 32 + 32), read
         // 16 bytes at a time; `f(position, count)` sees each in order, and
         // with `clear` they are zeroed for the next slot. A compiler barrier
@@ -2089,26 +2153,53 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
         };
         const unsigned s0 = (unsigned)sp.s[0];
         const auto crow = as_global(cid_row) + ja;
-        if (!EMIT) {
-            // tallies of the larger thresholds, then the survivors of the
-            // smallest (kept in the store)
-            for (int kk = 1; kk < K; ++kk) {
-                const unsigned sk = (unsigned)sp.s[kk];
-                int c = 0;
-                for_words(false, [&](int, unsigned v) { c += v >= sk; });
-                c = wave_sum(c);
-                if (lane == 0 && c) atomicAdd(&sm.tally[kk], (unsigned long long)c);
-            }
+        if (skip) {
+            if (tkn < count) first_segment(dn, an, lenn);
+        } else if (!EMIT) {
+            // every threshold's survivors (one pass for up to two
+            // thresholds), then the survivors of the smallest kept in the store
             int n0 = 0;
-            for_words(!store, [&](int, unsigned v) { n0 += v >= s0; });
+            if (K <= 2) {
+                const unsigned s1 = K > 1 ? (unsigned)sp.s[1] : ~0u;
+                int n1 = 0;
+                for_words(!store, [&](int, unsigned v) {
+                    n0 += v >= s0;
+                    n1 += v >= s1;
+                });
+                n1 = wave_sum(n1);
+                if (K > 1 && lane == 0 && n1) atomicAdd(&sm.tally[1], (unsigned long long)n1);
+            } else {
+                for (int kk = 1; kk < K; ++kk) {
+                    const unsigned sk = (unsigned)sp.s[kk];
+                    int c = 0;
+                    for_words(false, [&](int, unsigned v) { c += v >= sk; });
+                    c = wave_sum(c);
+                    if (lane == 0 && c) atomicAdd(&sm.tally[kk], (unsigned long long)c);
+                }
+                for_words(!store, [&](int, unsigned v) { n0 += v >= s0; });
+            }
             int n;
-            const int pos0 = dense_scan(n0, sm.wsum, n);
+            const int pos0 = dense_scan(n0, sm.wsum[1], n);
+            if (tkn < count) first_segment(dn, an, lenn);  // the descriptor has arrived by now
             if (tid == 0) sm.tally[0] = (unsigned long long)n;
-            if (store && tid == 0) {  // room in the store, one reservation per slot
+            if (store && tid == 0) {  // room for the slot's survivors, from the workgroup's chunk
                 long long b = -1;
                 if (n > 0) {
-                    const unsigned long long at = atomicAdd(cursor, (unsigned long long)n);
-                    b = at + (unsigned long long)n <= (unsigned long long)cap ? (long long)at : -1;
+                    if ((long long)n > sm.chunk_end - sm.chunk_at) {
+                        // a chunk, or less in a small store (a quarter of it over the workgroups)
+                        long long want = cap / (4ll * (long long)gridDim.x);
+                        want = want < kDenseChunk ? want : kDenseChunk;
+                        want = (long long)n > want ? (long long)n : want;
+                        const long long at = (long long)atomicAdd(cursor, (unsigned long long)want);
+                        sm.chunk_at = at;
+                        sm.chunk_end = at + want <= cap ? at + want : (at + n <= cap ? at + n : at);
+                    }
+                    if ((long long)n <= sm.chunk_end - sm.chunk_at) {
+                        b = sm.chunk_at;
+                        sm.chunk_at += n;
+                        atomicAdd(cursor + 2, (unsigned long long)n);
+                    }
+                    atomicAdd(cursor + 1, (unsigned long long)n);
                 }
                 sm.base = b;
                 as_global(cs.off)[t] = b < 0 ? 0 : b;
@@ -2126,13 +2217,14 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
             if (tid < K) slot_cnt[(int64_t)tid * S + d.slot] = (int64_t)sm.tally[tid];
         } else {
             // per threshold, this slot's survivors in partner order
+            if (tkn < count) first_segment(dn, an, lenn);
             const int i = d.row;
             for (int kk = 0; kk < K; ++kk) {
                 const unsigned sk = (unsigned)sp.s[kk];
                 int n0 = 0;
                 for_words(false, [&](int, unsigned v) { n0 += v >= sk; });
                 int tot;
-                const int pos0 = dense_scan(n0, sm.wsum, tot);
+                const int pos0 = dense_scan(n0, sm.wsum[(kk + 1) & 1], tot);
                 if (tot == 0) break;  // workgroup-uniform: larger thresholds have none either
                 const int64_t b = slot_off[(int64_t)kk * (S + 1) + d.slot] - sp.out_base[kk];
                 const auto colp = as_global(sp.col[kk]);
@@ -2150,7 +2242,11 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
             }
             for_words(true, [](int, unsigned) {});  // cleared for the next slot
         }
-        __syncthreads();  // counters cleared, sm.next published
+        tk = tkn;
+        t = tn;
+        d = dn;
+        a0 = an;
+        len0 = lenn;
     }
 }
 

@@ -336,6 +336,7 @@ slg_status slg_server_destroy(slg_server *sv) {
         (void)hipStreamDestroy(w.st);
         (void)slg_context_destroy(w.ctx);
     }
+    (void)hipGetLastError();
     delete sv;  // the ledger lives on while served results remain
     return SLG_OK;
 }
