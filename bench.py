@@ -55,9 +55,11 @@ DENSE_SQ_PROFILE = os.path.join(ROOT, "profiles", "dense_tier_large_skewed_sq_co
 LARGE_STORE_GIB = 160.0
 
 
-def measured_traffic(kernel: str, profile: str = TRAFFIC_PROFILE):
+def measured_traffic(kernel: str, profile: str = TRAFFIC_PROFILE, work_per_launch: float = None):
     """HBM bytes per launch of `kernel` from the committed PMC summary, if it
-    was taken on the current kernel source; else None."""
+    was taken on the current kernel source; else None. Where the summary
+    states the 2-paths of its launches (a probe whose launches are smaller
+    than the bench's), the bytes are scaled to `work_per_launch` 2-paths."""
     try:
         text = open(profile).read()
     except OSError:
@@ -69,6 +71,9 @@ def measured_traffic(kernel: str, profile: str = TRAFFIC_PROFILE):
         name = block.split("\n", 1)[0].strip()
         m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", block)
         if name == kernel and m_bytes:
+            m_work = re.search(r"dense_two_paths_per_launch:\s*([0-9.eE+]+)", block)
+            if m_work and work_per_launch:
+                return float(m_bytes.group(1)) * work_per_launch / float(m_work.group(1))
             return float(m_bytes.group(1))
     return None
 
@@ -733,11 +738,12 @@ def bench_large_skewed(args) -> int:
     achieved = dense_bytes / (count_ms / 1e3) / 1e9 if count_ms > 0 else None
     emit_launches, emit_ms = stages.get("emit_dense", (0, 0.0))
     roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": measured_traffic("dense_kernel<false>", DENSE_TRAFFIC_PROFILE),
+                "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": measured_traffic("dense_kernel<false>", DENSE_TRAFFIC_PROFILE,
+                                                                                     work["dense_two_paths"] / max(launches, 1)),
                 "kernel": "dense_kernel<false> (count_dense)", "launches": launches,
                 "avg_launch_ms": count_ms / max(launches, 1),
                 "algorithmic_bytes_per_launch": dense_bytes / max(launches, 1),
-                "overhead_bytes_per_launch": {"dense_store_written": 4 * work["dense_stored"] / max(launches, 1)},
+                "overhead_bytes_per_launch": {"dense_store_written": 8 * work["dense_stored"] / max(launches, 1)},
                 "sq_counters": measured_sq("dense_kernel<false>", DENSE_SQ_PROFILE),
                 "emit": {"kernel": "heavy_store_emit_kernel<4, unsigned long long> (emit_dense)",
                          "launches": emit_launches, "ms": emit_ms,
