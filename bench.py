@@ -155,6 +155,42 @@ def oracle_threads() -> int:
     return max(1, min(usable, int(os.environ.get("OMP_NUM_THREADS", "16") or 16)))
 
 
+def heavy_roofline(stats, stages, profiled: bool = True):
+    """The heavy tier's two kernels, each against the HBM roofline with the
+    algorithmic bytes of the work it does: the counting pass reads one
+    4-byte partner id per heavy 2-path; the emit pass writes 12 bytes
+    (i, j, w) per heavy edge. The count store that carries the overlaps from
+    one to the other is this implementation's own traffic, reported apart as
+    overhead, never as algorithmic bytes. Returns the slower kernel's entry,
+    with the other's under "other_heavy_kernel". `profiled`: the committed
+    traffic and SQ summaries (taken on the power-law instance) apply."""
+    store = stats.get("stored_ranks", 0) > 0
+    kernels = {
+        "count_heavy": ("heavy_kernel<false, false, true>" if store else "heavy_kernel<false, false, false>",
+                        4 * stats["heavy_two_paths"],
+                        {"count_store_written": 4 * stats["stored_ranks"]} if store else {}),
+        "emit_heavy": ("heavy_store_emit_kernel<4, unsigned int>" if store else "heavy_kernel<true, false, false>",
+                       12 * stats["heavy_edges"],
+                       {"count_store_read": 4 * stats["stored_ranks"]} if store
+                       else {"two_paths_walked_again": 4 * stats["heavy_two_paths"]}),
+    }
+    lines = {}
+    for stage, (kname, algo_bytes, overhead) in kernels.items():
+        launches, ms = stages.get(stage, (0, 0.0))
+        avg_s = ms / 1e3 / max(launches, 1)
+        achieved = algo_bytes / avg_s / 1e9 if avg_s > 0 else None
+        lines[stage] = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
+                        "traffic": measured_traffic(kname) if profiled else None, "kernel": f"{kname} ({stage})",
+                        "avg_launch_ms": avg_s * 1e3, "algorithmic_bytes_per_launch": algo_bytes,
+                        "overhead_bytes_per_launch": overhead,
+                        "sq_counters": measured_sq(kname) if profiled else None}
+    dominant = max(lines, key=lambda k: lines[k]["avg_launch_ms"])
+    roofline = dict(lines[dominant])
+    roofline["other_heavy_kernel"] = lines["emit_heavy" if dominant == "count_heavy" else "count_heavy"]
+    return roofline
+
+
 def cpu_baseline(inc, seconds: float, s_set=None, size_min=None, seed: int = 7):
     """Oracle on a random row sample sized to about `seconds` of CPU time.
     Rate = 2-paths of the sampled rows (the work the two-hop traversal does
@@ -528,6 +564,33 @@ def bench_served(args) -> int:
     return 0
 
 
+def components_cpu_baseline(inc, seconds: float, seed: int = 7):
+    """The oracle's s-connected components (breadth-first search over an
+    edge list) on its own L_1 edges of a seeded random row sample, grown
+    fourfold until the search takes a second (or a quarter of `seconds`);
+    rate = edges searched per second."""
+    import numpy as np
+
+    import oracle
+    threads = oracle_threads()
+    rng = np.random.default_rng(seed)
+    nrows, dt, ne = 1000, 0.0, 0
+    while True:
+        rows = np.sort(rng.choice(inc.m, size=min(nrows, inc.m), replace=False))
+        sub = oracle.line_graph_rows(inc, 1, rows, threads=threads)
+        ends_i = np.repeat(sub.rows, np.diff(sub.ptr)).astype(np.int32)
+        t0 = time.perf_counter()
+        oracle.components(inc, 1, ends_i, sub.j)
+        dt = time.perf_counter() - t0
+        ne = int(sub.j.size)
+        if dt >= min(seconds / 4, 1.0) or nrows >= inc.m:  # the oracle's construction costs ten times more
+            break
+        nrows *= 4
+    return {"value": ne / dt, "unit": "s-line edges/s (components)", "cores": 1, "kind": "oracle",
+            "sample": f"the oracle's L_1 edges of {rows.size} random rows (seed {seed}): {ne} edges, "
+                      f"breadth-first search {dt:.2f} s wall (single thread)", "host": host_cpu()}
+
+
 def bench_components(args) -> int:
     """s-connected components, ID squeezing and the symmetric CSR (the
     framework's stages after construction, Section IV) on the power-law
@@ -574,6 +637,18 @@ def bench_components(args) -> int:
             t_sym += t3 - t2
             counts[lg.s] = {"components": nc, "squeezed": nk}
     total = sum(edges) * args.steps
+    # the union-find: 8 B read per edge (its two ends), 4 B written per row
+    # at the start and 4 B read + 4 B written per row at the end; the label
+    # reads of the finds depend on the trees and are not counted. Timed on the
+    # host around each call (three launches and a count read back), so the
+    # fraction is a lower bound for the kernels.
+    cc_bytes = (8 * sum(edges) + 12 * inc.m * len(edges)) * args.steps
+    cc_gbs = cc_bytes / t_cc / 1e9
+    roofline = {"bound": "hbm", "achieved": cc_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": cc_gbs / PEAK_HBM_GBS, "traffic": None,
+                "kernel": "cc_init_kernel + cc_hook_kernel + cc_finish_kernel (components, host-timed)",
+                "algorithmic_bytes_per_call": cc_bytes / (args.steps * len(edges))}
+    cpu = None if args.no_cpu_baseline else components_cpu_baseline(inc, args.cpu_seconds)
     line = {
         "metric": METRIC, "value": total / t_cc, "unit": "s-line edges/s (components)", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * t_cc / args.steps,
@@ -583,13 +658,22 @@ def bench_components(args) -> int:
                                "S={1,2,4,8}", "s": S_SET, "edges": edges, "parallelism": "single GPU"},
         "squeeze_edges_per_s": total / t_sq, "squeeze_ms_per_step": 1e3 * t_sq / args.steps,
         "symmetric_edges_per_s": total / t_sym, "symmetric_ms_per_step": 1e3 * t_sym / args.steps,
-        "per_s": counts, "roofline": None, "cpu_baseline": None,
+        "per_s": counts, "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
     del outs
     g.release()
     ctx.close()
     return 0
+
+
+def ascending_incidence(inc):
+    """The hypergraph relabelled by ascending size, built by the oracle (for
+    the CPU baseline of the preprocessing line)."""
+    import hypergen as hg
+    import oracle
+    he_ptr, he_idx, v_ptr, v_idx = oracle.select(inc, oracle.relabel_order(inc))
+    return hg.Incidence(inc.m, inc.n, he_ptr, he_idx, v_ptr, v_idx)
 
 
 def bench_preprocess(args) -> int:
@@ -620,23 +704,33 @@ def bench_preprocess(args) -> int:
             ts.append(time.perf_counter() - t0)
         return sorted(ts)[len(ts) // 2] * 1e3, out
 
-    def construction(graph):
+    stage_times = {}
+
+    def construction(graph, name):
         for _ in range(args.warmup):
             outs = ctx.line_graph(graph, S_SET)
             del outs
+        ctx.reset_timing()
+        ctx.set_timing(True)
         ms, outs = timed(lambda: ctx.line_graph(graph, S_SET), args.steps)
+        ctx.set_timing(False)
+        stage_times[name] = ctx.timing()
         two_paths = outs[0].two_paths
         del outs
         return ms, two_paths
 
     res = {}
-    res["original_ms"], W = construction(g)
+    res["original_ms"], W = construction(g, "original")
     for desc in (False, True):
         name = "descending" if desc else "ascending"
         timed(lambda: ctx.relabel(g, desc), args.warmup)
         rl_ms, (sub, _) = timed(lambda: ctx.relabel(g, desc), args.steps)
         res[f"relabel_{name}_ms"] = rl_ms
-        res[f"{name}_ms"], _ = construction(sub)
+        res[f"{name}_ms"], _ = construction(sub, name)
+        if not desc:  # the roofline of the line's construction (ascending order)
+            p = ctx.plan(sub, S_SET)
+            asc_stats = p.stats()
+            p.destroy()
         sub.release()
     l1 = ctx.line_graph(g, [1])[0]
     timed(lambda: ctx.simplify(g, l1), args.warmup)
@@ -653,7 +747,8 @@ def bench_preprocess(args) -> int:
                                "n=1e6 m=5e5; ensemble S={1,2,4,8} on each order", "s": S_SET,
                    "parallelism": "single GPU"},
         "original_two_paths_per_s": W / (res["original_ms"] * 1e-3), "stages_ms": res,
-        "roofline": None, "cpu_baseline": None,
+        "roofline": heavy_roofline(asc_stats, stage_times["ascending"], profiled=False),
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(ascending_incidence(inc), args.cpu_seconds),
     }
     print(json.dumps(line), flush=True)
     g.release()
@@ -892,35 +987,7 @@ def bench_power_law(args, dual: bool = False) -> int:
     value = two_paths * args.steps / elapsed
     edges_total = sum(edges)
 
-    # the heavy tier's two kernels, each against the HBM roofline with the
-    # algorithmic bytes of the work it does: the counting pass reads one
-    # 4-byte partner id per heavy 2-path; the emit pass writes 12 bytes
-    # (i, j, w) per heavy edge. The count store that carries the overlaps from
-    # one to the other is this implementation's own traffic, reported apart
-    # as overhead, never as algorithmic bytes.
-    store = stats.get("stored_ranks", 0) > 0
-    kernels = {
-        "count_heavy": ("heavy_kernel<false, false, true>" if store else "heavy_kernel<false, false, false>",
-                        4 * stats["heavy_two_paths"],
-                        {"count_store_written": 4 * stats["stored_ranks"]} if store else {}),
-        "emit_heavy": ("heavy_store_emit_kernel<4, unsigned int>" if store else "heavy_kernel<true, false, false>",
-                       12 * stats["heavy_edges"],
-                       {"count_store_read": 4 * stats["stored_ranks"]} if store
-                       else {"two_paths_walked_again": 4 * stats["heavy_two_paths"]}),
-    }
-    lines = {}
-    for stage, (kname, algo_bytes, overhead) in kernels.items():
-        launches, ms = stages.get(stage, (0, 0.0))
-        avg_s = ms / 1e3 / max(launches, 1)
-        achieved = algo_bytes / avg_s / 1e9 if avg_s > 0 else None
-        lines[stage] = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                        "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
-                        "traffic": measured_traffic(kname), "kernel": f"{kname} ({stage})",
-                        "avg_launch_ms": avg_s * 1e3, "algorithmic_bytes_per_launch": algo_bytes,
-                        "overhead_bytes_per_launch": overhead, "sq_counters": measured_sq(kname)}
-    dominant = max(lines, key=lambda k: lines[k]["avg_launch_ms"])
-    roofline = dict(lines[dominant])
-    roofline["other_heavy_kernel"] = lines["emit_heavy" if dominant == "count_heavy" else "count_heavy"]
+    roofline = heavy_roofline(stats, stages, profiled=not dual)  # the summaries are of the power-law instance
     # whole-step algorithmic bytes: 4 B per 2-path, 8 B per incidence (both
     # CSRs), 8 B per row/vertex pointer, 12 B per edge, 8 B per row_ptr entry
     step_bytes = (4 * two_paths + 8 * inc.nnz + 8 * (inc.m + inc.n) + 12 * edges_total
