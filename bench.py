@@ -169,7 +169,7 @@ def heavy_roofline(stats, stages, profiled: bool = True):
         "count_heavy": ("heavy_kernel<false, false, true>" if store else "heavy_kernel<false, false, false>",
                         4 * stats["heavy_two_paths"],
                         {"count_store_written": 4 * stats["stored_ranks"]} if store else {}),
-        "emit_heavy": ("heavy_store_emit_kernel<4, unsigned int>" if store else "heavy_kernel<true, false, false>",
+        "emit_heavy": ("heavy_store_emit_kernel<4, false>" if store else "heavy_kernel<true, false, false>",
                        12 * stats["heavy_edges"],
                        {"count_store_read": 4 * stats["stored_ranks"]} if store
                        else {"two_paths_walked_again": 4 * stats["heavy_two_paths"]}),
@@ -838,9 +838,9 @@ def bench_large_skewed(args) -> int:
                 "kernel": "dense_kernel<false> (count_dense)", "launches": launches,
                 "avg_launch_ms": count_ms / max(launches, 1),
                 "algorithmic_bytes_per_launch": dense_bytes / max(launches, 1),
-                "overhead_bytes_per_launch": {"dense_store_written": 8 * work["dense_stored"] / max(launches, 1)},
+                "overhead_bytes_per_launch": {"dense_store_written": 4 * work["dense_stored"] / max(launches, 1)},
                 "sq_counters": measured_sq("dense_kernel<false>", DENSE_SQ_PROFILE),
-                "emit": {"kernel": "heavy_store_emit_kernel<4, unsigned long long> (emit_dense)",
+                "emit": {"kernel": "heavy_store_emit_kernel<4, true> (emit_dense)",
                          "launches": emit_launches, "ms": emit_ms,
                          "algorithmic_bytes": 12 * work["dense_edges"],
                          "achieved_gbs": 12 * work["dense_edges"] / (emit_ms / 1e3) / 1e9 if emit_ms > 0 else None}}

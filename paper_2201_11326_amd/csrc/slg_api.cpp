@@ -317,7 +317,7 @@ struct slg_plan {
     Scratch scratch2;  // a row block's slot tables, lists, stores (released per block)
     PlanBufs b;
     bool blocks = false;           // planned block by block (the rows phase keeps every row's facts)
-    unsigned long long *dstore_fixed = nullptr;  // row blocks: one dense store for every block
+    uint32_t *dstore_fixed = nullptr;  // row blocks: one dense store for every block
     int64_t dstore_fixed_cap = 0;
     int64_t row_lo = 0, row_hi = 0;  // the rows of the current block
     bool prune = false;            // vertex lists are compacted to E_{s_min}
@@ -989,12 +989,12 @@ slg_status plan_block(slg_plan *p, int64_t r0, int64_t r1) {
                              nd * 12 - 16;
         // (room is handed out in chunks: each persistent workgroup may leave one unfilled)
         p->dstore_cap = std::min<int64_t>(
-            p->dense_two_paths / std::max(p->s_min, 1) + 1 + (int64_t)dense_workgroups(p) * kDenseChunk, left / 8);
+            p->dense_two_paths / std::max(p->s_min, 1) + 1 + (int64_t)dense_workgroups(p) * kDenseChunk, left / 4);
         if (p->dstore_fixed) p->dstore_cap = p->dstore_fixed_cap;  // row blocks share one store of fixed size
         p->use_dstore = nd > 0 && p->dstore_cap > 0;
         if (nd > 1) phase2.add(&p->dorder, nd);
         if (p->use_dstore) {
-            if (!p->dstore_fixed) phase2.add(&p->dstore.ent64, p->dstore_cap);
+            if (!p->dstore_fixed) phase2.add(&p->dstore.ent, p->dstore_cap);
             phase2.add(&p->dstore.off, nd);
             phase2.add(&p->dstore.n, nd);
         } else {
@@ -1006,7 +1006,7 @@ slg_status plan_block(slg_plan *p, int64_t r0, int64_t r1) {
         p->reserved += phase2.bytes;
     }
     for (const auto &a : phase2.items) BUILD_HIP(sc.get(a.first, a.second));
-    if (p->dstore_fixed && p->use_dstore) p->dstore.ent64 = p->dstore_fixed;
+    if (p->dstore_fixed && p->use_dstore) p->dstore.ent = p->dstore_fixed;
     p->slots.count = p->S;
     p->slots.row = b.slot_row;
     BUILD_HIP(enqueue_slots_count(p, st));
@@ -1176,8 +1176,8 @@ slg_status emit_range(slg_plan *p, int64_t r0, int64_t r1, int64_t s0, int64_t s
         if (cnt <= 0) continue;
         StageTimer tm(ctx, wide ? kStEmitHeavyWide : kStEmitHeavy, st);
         if (p->use_store && !wide) {
-            const CountStore part{p->store.ent, p->store.off + lo[0], p->store.n + lo[0], nullptr};
-            SLG_HIP(ctx, launch_heavy_store_emit(p->heavy[0] + lo[0], cnt, p->S, part, prm, p->slot_off, st));
+            const CountStore part{p->store.ent, p->store.off + lo[0], p->store.n + lo[0]};
+            SLG_HIP(ctx, launch_heavy_store_emit(p->heavy[0] + lo[0], cnt, p->S, part, prm, p->slot_off, nullptr, st));
         } else {
             SLG_HIP(ctx, launch_heavy(true, wide, p->heavy[wide] + lo[wide], cnt, p->S, p->bounds, p->pr, prm,
                                       nullptr, p->slot_off, p->tickets + kTkEmit + wide, p->heavy_grid, nullptr,
@@ -1187,9 +1187,10 @@ slg_status emit_range(slg_plan *p, int64_t r0, int64_t r1, int64_t s0, int64_t s
     if (hi[2] > lo[2]) {  // dense slots: from their store, then any the store could not hold
         StageTimer tm(ctx, kStEmitDense, st);
         const int64_t cnt = hi[2] - lo[2];
-        const CountStore part{nullptr, p->dstore.off + lo[2], p->dstore.n + lo[2], p->dstore.ent64};
+        const CountStore part{p->dstore.ent, p->dstore.off + lo[2], p->dstore.n + lo[2]};
         if (p->use_dstore)
-            SLG_HIP(ctx, launch_heavy_store_emit(p->heavy[2] + lo[2], cnt, p->S, part, prm, p->slot_off, st));
+            SLG_HIP(ctx, launch_heavy_store_emit(p->heavy[2] + lo[2], cnt, p->S, part, prm, p->slot_off,
+                                                 p->pr.cid_row, st));
         if (!p->use_dstore || p->dense_stored > p->dense_kept)
             SLG_HIP(ctx, launch_dense(true, p->heavy[2] + lo[2], cnt, nullptr, p->S, p->bounds, p->pr, prm, nullptr,
                                       p->slot_off, p->tickets + kTkEmit + 2, p->dense_grid,
@@ -1316,7 +1317,7 @@ slg_status stream_rows(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t
     bool any_dense = false;
     for (int64_t r = 0; r < nr && !any_dense; ++r) any_dense = cls[r] == kDense;
     if (any_dense && p->store_limit > 0) {
-        p->dstore_fixed_cap = budget / 2 / 8;
+        p->dstore_fixed_cap = budget / 2 / 4;
         STREAM_HIP(p->scratch.get(&p->dstore_fixed, p->dstore_fixed_cap));
     }
     double dense_ratio = 0.125;  // survivors per dense 2-path, until a block has measured it

@@ -100,17 +100,16 @@ struct HeavyDesc {
 // (partner - ja) | overlap << 16 (a slot spans at most 2^16 ids, and a
 // non-wide row has fewer than 2^16 members); off is the exclusive prefix of
 // the slots' 2-path counts, which bound their distinct partners.
-// The dense tier's store (ent64 instead of ent) holds only the partners
-// whose overlap reaches the smallest threshold, each partner id << 16 |
-// overlap in 64 bits (the counting pass maps the E_s position back to the
-// id while the window's part of the map is in L2); a slot reserves its
-// room when it knows its count (off[t] from a device cursor), and n[t] = -1
-// marks a slot that found the store full (its emit walks the 2-paths again).
+// The dense tier's store holds only the partners whose overlap reaches the
+// smallest threshold, each (position - window start) | overlap << 16 (a
+// window spans 2^14 positions of E_s; its emit maps positions back to ids);
+// a slot's room comes from a device cursor once it knows its count (off[t]),
+// and n[t] = -1 marks a slot that found the store full (its emit walks the
+// 2-paths again).
 struct CountStore {
     uint32_t *ent;
     int64_t *off;
     int32_t *n;
-    unsigned long long *ent64;
 };
 
 // The same for the light rows (wavefront-sort tier): row i holds n[i]
@@ -205,11 +204,12 @@ hipError_t launch_heavy(bool emit, bool wide, const HeavyDesc *desc, int64_t cou
 // work[t] = 2-paths of heavy slot t (from the boundary table).
 hipError_t launch_slot_work(const HeavyDesc *desc, int64_t count, const int32_t *bounds, int64_t *work,
                             hipStream_t st);
-// Emit pass of the heavy slots from the counting pass's store (store.ent),
-// or of the dense slots from theirs (store.ent64; slots with n[t] < 0 are
-// left to launch_dense(emit)).
+// Emit pass of the heavy slots from the counting pass's store, or, with
+// cid_row, of the dense slots from theirs (entries hold E_s positions, mapped
+// to ids through cid_row; slots with n[t] < 0 are left to launch_dense(emit)).
 hipError_t launch_heavy_store_emit(const HeavyDesc *desc, int64_t count, int64_t slots, const CountStore &store,
-                                   const EmitParams &ep, const int64_t *slot_off, hipStream_t st);
+                                   const EmitParams &ep, const int64_t *slot_off, const int32_t *cid_row,
+                                   hipStream_t st);
 // Dense tier, persistent like launch_heavy. Counting pass (emit = false):
 // slot_cnt gets every threshold's survivors and, with a store, the slot's
 // survivors of the smallest threshold go to the store (room reserved from

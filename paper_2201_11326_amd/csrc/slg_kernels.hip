@@ -30,6 +30,8 @@
 // Every step is exact integer work; no floating point is involved.
 #include <limits.h>
 
+#include <type_traits>
+
 #include "slg_internal.h"
 
 namespace slg {
@@ -1728,32 +1730,40 @@ __global__ __launch_bounds__(256) void slot_work_kernel(const HeavyDesc *__restr
 constexpr int kStoreGroups = 8;
 constexpr int kQueue = 128;  // entries per threshold queue: < 64 kept + <= 64 appended
 
-// E: uint32_t entries (heavy slots: partner - ja | overlap << 16) or
-// unsigned long long (dense slots: partner << 16 | overlap).
-template <int MAXK, typename E>
+// Entries are (partner - ja) | overlap << 16. DENSE: ja is a window of E_s
+// positions and the partner's id is cid_row[ja + low half], looked up for a
+// whole group of entries at once (the lookups overlap) before they are
+// queued as id << 16 | overlap. Slots are taken in list (row) order, so the
+// outputs are written in order; taking them window by window kept cid_row
+// in L2 but scattered the writes, and measured a third slower.
+template <int MAXK, bool DENSE>
 __global__ __launch_bounds__(256) void heavy_store_emit_kernel(const HeavyDesc *__restrict__ desc, int64_t count,
                                                                int64_t S, CountStore cs, EmitParams prm,
-                                                               const int64_t *__restrict__ slot_off) {
+                                                               const int64_t *__restrict__ slot_off,
+                                                               const int32_t *__restrict__ cid_row) {
+    using E = uint32_t;                                        // stored entry
+    using Q = typename std::conditional<DENSE, unsigned long long, uint32_t>::type;  // queued entry
     constexpr bool kQueued = MAXK <= 4;
-    constexpr bool kWide = sizeof(E) == 8;
     __shared__ EmitParams sp;
-    __shared__ E queue[kQueued ? 4 : 1][kQueued ? MAXK : 1][kQueued ? kQueue : 1];
+    __shared__ Q queue[kQueued ? 4 : 1][kQueued ? MAXK : 1][kQueued ? kQueue : 1];
     stage_params(&sp, prm);
     __syncthreads();
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     const int K = prm.k;
     const bool row_thr = prm.row_s != nullptr;
     const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / 64);
-    for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; t < count; t += nwaves) {
+    // one slot: its stored entries to the outputs of every threshold
+    auto emit_slot = [&](int64_t t) {
         const HeavyDesc d = desc[t];
-        if (d.slot < prm.slot_lo || d.slot >= prm.slot_hi) continue;  // outside the emitted chunk
+        if (d.slot < prm.slot_lo || d.slot >= prm.slot_hi) return;  // outside the emitted chunk
         const int n = as_global(cs.n)[t];
-        if (n < 0) continue;  // the store was full: the slot's emit walks its 2-paths again
+        if (n < 0) return;  // the store was full: the slot's emit walks its 2-paths again
         const int64_t off = as_global(cs.off)[t];
         const int i = d.row;
         const int id0 = prm.row_base ? as_global(prm.row_base)[i] : 0;
         const int srow = row_thr ? as_global(prm.row_s)[i] : 0;
         const int jbase = d.ja - id0;
+        const int32_t *crow = DENSE ? cid_row + d.ja : nullptr;
         long long b[MAXK];
         int sk[MAXK], fill[MAXK];
 #pragma unroll
@@ -1762,16 +1772,15 @@ __global__ __launch_bounds__(256) void heavy_store_emit_kernel(const HeavyDesc *
             sk[kk] = kk < K ? (row_thr ? srow : sp.s[kk]) : INT_MAX;
             fill[kk] = 0;
         }
-        const E *ent = kWide ? reinterpret_cast<const E *>(cs.ent64) : reinterpret_cast<const E *>(cs.ent);
-        // the partner and overlap of a stored entry
-        auto partner = [&](E e) -> int {
-            return kWide ? (int)(e >> 16) - id0 : jbase + (int)(e & 0xFFFFu);
+        // queued entry: DENSE, the partner's id << 16 | overlap; else the stored entry
+        auto partner = [&](Q e) -> int {
+            return DENSE ? (int)(e >> 16) - id0 : jbase + (int)(e & 0xFFFFu);
         };
-        auto overlap = [&](E e) -> int { return kWide ? (int)(e & 0xFFFFu) : (int)(e >> 16); };
+        auto overlap = [&](Q e) -> int { return DENSE ? (int)(e & 0xFFFFu) : (int)(e >> 16); };
         // writes `m` queued entries of threshold kk (lanes below m) at b[kk]
         auto flush = [&](int kk, int m) {
             if (lane < m) {
-                const E e = queue[wave][kk][lane];
+                const Q e = queue[wave][kk][lane];
                 const int64_t pos = b[kk] + lane;
                 as_global(sp.col[kk])[pos] = partner(e);
                 as_global(sp.w[kk])[pos] = overlap(e);
@@ -1784,12 +1793,22 @@ __global__ __launch_bounds__(256) void heavy_store_emit_kernel(const HeavyDesc *
 #pragma unroll
             for (int q = 0; q < kStoreGroups; ++q) {
                 const int r = r0 + 64 * q + lane;
-                e[q] = r < n ? as_global(ent)[off + r] : E(0);
+                e[q] = r < n ? as_global(cs.ent)[off + r] : E(0);
+            }
+            Q v[kStoreGroups];
+#pragma unroll
+            for (int q = 0; q < kStoreGroups; ++q) {
+                if (DENSE)
+                    v[q] = r0 + 64 * q + lane < n
+                               ? ((Q)(uint32_t)as_global(crow)[e[q] & 0xFFFFu] << 16) | (Q)(e[q] >> 16)
+                               : Q(0);
+                else
+                    v[q] = (Q)e[q];
             }
 #pragma unroll
             for (int q = 0; q < kStoreGroups; ++q) {
                 if (r0 + 64 * q >= n) break;  // wave-uniform
-                const int c = overlap(e[q]);
+                const int c = overlap(v[q]);
 #pragma unroll
                 for (int kk = 0; kk < MAXK; ++kk) {
                     if (kk >= K) break;
@@ -1797,19 +1816,19 @@ __global__ __launch_bounds__(256) void heavy_store_emit_kernel(const HeavyDesc *
                     const unsigned long long mask = __ballot(surv);
                     if (mask == 0ull) break;
                     if (kQueued) {
-                        if (surv) queue[wave][kk][fill[kk] + bits_below(mask)] = e[q];
+                        if (surv) queue[wave][kk][fill[kk] + bits_below(mask)] = v[q];
                         fill[kk] += __popcll(mask);
                         if (fill[kk] >= 64) {  // a full row out, the rest moves down
                             wave_lds_sync();
                             flush(kk, 64);
-                            const E rest = lane < fill[kk] - 64 ? queue[wave][kk][64 + lane] : E(0);
+                            const Q rest = lane < fill[kk] - 64 ? queue[wave][kk][64 + lane] : Q(0);
                             wave_lds_sync();
                             if (lane < fill[kk] - 64) queue[wave][kk][lane] = rest;
                             fill[kk] -= 64;
                         }
                     } else if (surv) {
                         const int64_t pos = b[kk] + bits_below(mask);
-                        as_global(sp.col[kk])[pos] = partner(e[q]);
+                        as_global(sp.col[kk])[pos] = partner(v[q]);
                         as_global(sp.w[kk])[pos] = c;
                         if (sp.row[kk]) as_global(sp.row[kk])[pos] = i - id0;
                     }
@@ -1824,7 +1843,8 @@ __global__ __launch_bounds__(256) void heavy_store_emit_kernel(const HeavyDesc *
                 if (kk < K && fill[kk] > 0) flush(kk, fill[kk]);
             wave_lds_sync();  // the queues are reused by the next slot
         }
-    }
+    };
+    for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; t < count; t += nwaves) emit_slot(t);
 }
 
 __global__ void sum_i32_kernel(const int32_t *__restrict__ n, int64_t count, unsigned long long *__restrict__ out) {
@@ -2069,7 +2089,7 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
     }
     __syncthreads();
     const int K = sp.k;
-    const bool store = cs.ent64 != nullptr;
+    const bool store = cs.ent != nullptr;
     // the slot of ticket tk: its position in desc (window-major order) and
     // descriptor; this thread's member segment of its first batch
     auto slot_of = [&](int64_t tk) -> int64_t { return order ? (int64_t)order[tk] : tk; };
@@ -2206,12 +2226,12 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
                 as_global(cs.n)[t] = (n > 0 && b < 0) ? -1 : n;
             }
             __syncthreads();
-            if (store) {  // partner id << 16 | overlap (the window's ids are in L2)
+            if (store) {  // window position | overlap << 16
                 const long long base = sm.base;
-                const auto ent = as_global(cs.ent64);
+                const auto ent = as_global(cs.ent);
                 long long q0 = base + pos0;
                 for_words(true, [&](int x, unsigned v) {
-                    if (base >= 0 && v >= s0) ent[q0++] = ((unsigned long long)(uint32_t)crow[x] << 16) | v;
+                    if (base >= 0 && v >= s0) ent[q0++] = (uint32_t)x | (v << 16);
                 });
             }
             if (tid < K) slot_cnt[(int64_t)tid * S + d.slot] = (int64_t)sm.tally[tid];
@@ -2773,20 +2793,21 @@ hipError_t launch_slot_work(const HeavyDesc *desc, int64_t count, const int32_t 
 }
 
 hipError_t launch_heavy_store_emit(const HeavyDesc *desc, int64_t count, int64_t slots, const CountStore &store,
-                                   const EmitParams &ep, const int64_t *slot_off, hipStream_t st) {
+                                   const EmitParams &ep, const int64_t *slot_off, const int32_t *cid_row,
+                                   hipStream_t st) {
     if (count <= 0) return hipSuccess;
     const unsigned grid = wave_grid(count, 4, 16384);
-    if (store.ent64) {
+    if (cid_row) {
         if (ep.k <= 4)
-            heavy_store_emit_kernel<4, unsigned long long><<<grid, 256, 0, st>>>(desc, count, slots, store, ep,
-                                                                                 slot_off);
+            heavy_store_emit_kernel<4, true><<<grid, 256, 0, st>>>(desc, count, slots, store, ep, slot_off, cid_row);
         else
-            heavy_store_emit_kernel<SLG_MAX_S, unsigned long long><<<grid, 256, 0, st>>>(desc, count, slots, store,
-                                                                                         ep, slot_off);
+            heavy_store_emit_kernel<SLG_MAX_S, true><<<grid, 256, 0, st>>>(desc, count, slots, store, ep, slot_off,
+                                                                           cid_row);
     } else if (ep.k <= 4) {
-        heavy_store_emit_kernel<4, uint32_t><<<grid, 256, 0, st>>>(desc, count, slots, store, ep, slot_off);
+        heavy_store_emit_kernel<4, false><<<grid, 256, 0, st>>>(desc, count, slots, store, ep, slot_off, nullptr);
     } else {
-        heavy_store_emit_kernel<SLG_MAX_S, uint32_t><<<grid, 256, 0, st>>>(desc, count, slots, store, ep, slot_off);
+        heavy_store_emit_kernel<SLG_MAX_S, false><<<grid, 256, 0, st>>>(desc, count, slots, store, ep, slot_off,
+                                                                        nullptr);
     }
     return hipGetLastError();
 }

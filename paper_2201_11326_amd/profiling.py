@@ -131,8 +131,8 @@ def counter_per_kernel(db: str, counter: str):
 
 
 HEAVY_KERNELS = ("heavy_kernel<false, false, true>", "heavy_kernel<false, false, false>",
-                 "heavy_store_emit_kernel<4, unsigned int>", "heavy_kernel<true, false, false>")
-DENSE_KERNELS = ("dense_kernel<false>", "heavy_store_emit_kernel<4, unsigned long long>", "dense_kernel<true>")
+                 "heavy_store_emit_kernel<4, false>", "heavy_kernel<true, false, false>")
+DENSE_KERNELS = ("dense_kernel<false>", "heavy_store_emit_kernel<4, true>", "dense_kernel<true>")
 WORKLOADS = {  # probe -> (title, kernels)
     "power_law": ("the heavy-tier kernels (power-law ensemble S={1,2,4,8})", HEAVY_KERNELS),
     "large_skewed": ("the dense-tier kernels (large skewed workload at full size, one row range, S={8,16})",
