@@ -356,6 +356,7 @@ struct slg_plan {
     int64_t store_limit = 0;
     int64_t store_min = 0;
     int64_t list_shortfall = 0;
+    int64_t plan_lo = 0, plan_hi = -1;  // rows the rows phase plans (-1: to the last)
     int64_t stored_ranks = 0;
     int64_t two_paths = 0;
     int64_t heavy_two_paths = 0;
@@ -618,7 +619,8 @@ hipError_t enqueue_rows(slg_plan *p, hipStream_t st) {
     }
     {
         StageTimer tm(ctx, kStRowPlan, st);
-        if ((e = launch_row_plan(p->pr, p->s_min, p->light_max, p->slot_work, p->dense ? p->dense_ratio : 0,
+        if ((e = launch_row_plan(p->pr, p->s_min, p->light_max, p->slot_work, p->plan_lo,
+                                 p->plan_hi < 0 ? m : p->plan_hi, p->dense ? p->dense_ratio : 0,
                                  p->dense_min, b.tail_beg, b.work, b.jmax, b.nslots, b.rclass, b.bsize,
                                  reinterpret_cast<unsigned long long *>(b.counters + kCntClass),
                                  reinterpret_cast<int *>(b.counters + kCntErr),
@@ -1288,6 +1290,10 @@ slg_status stream_rows(slg_context *ctx, slg_graph *g, const int32_t *s, int32_t
             return cleanup(fail(ctx, e_ == hipErrorOutOfMemory ? SLG_ERR_OUT_OF_MEMORY : SLG_ERR_DEVICE, \
                                 "%s: %s", #call, hipGetErrorString(e_)));                           \
     } while (0)
+    // the rows phase plans the call's rows only (the E_s positions still
+    // cover every row: partners lie anywhere after a row)
+    p->plan_lo = row_begin;
+    p->plan_hi = row_end;
     slg_status rc = plan_rows(p);
     if (rc != SLG_OK) return cleanup(rc);
     for (int t = 0; t < 2; ++t) {

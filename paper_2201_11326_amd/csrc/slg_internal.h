@@ -154,11 +154,14 @@ hipError_t launch_vs_cid(int64_t n, int64_t m, int64_t nnz, const int64_t *vs_pt
 // K1/K2: per kept row, tail offsets, 2-path work, last partner, slot count.
 // dense_ratio = 0 keeps every row off the dense tier (then g.cid may be
 // null); dense_work gets the 2-paths of dense rows.
-hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t light_max, int64_t slot_work,
-                           int32_t dense_ratio, int32_t dense_min, int32_t *tail_beg, int64_t *work, int32_t *jmax,
-                           int32_t *nslots, uint8_t *rclass, int64_t *bsize, unsigned long long *class_count,
-                           int *err, unsigned long long *heavy_work, unsigned long long *dense_work, int64_t *pieces,
-                           unsigned long long *num_pieces, hipStream_t st);
+// Rows outside [row_lo, row_hi) are planned as pruned rows (no work, no
+// slots); their member tails are not located.
+hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t light_max, int64_t slot_work, int64_t row_lo,
+                           int64_t row_hi, int32_t dense_ratio, int32_t dense_min, int32_t *tail_beg, int64_t *work,
+                           int32_t *jmax, int32_t *nslots, uint8_t *rclass, int64_t *bsize,
+                           unsigned long long *class_count, int *err, unsigned long long *heavy_work,
+                           unsigned long long *dense_work, int64_t *pieces, unsigned long long *num_pieces,
+                           hipStream_t st);
 // Light lists and heavy descriptors (heavy lists in slot order). hat:
 // int64[3 (m + 1)] and hcnt: int32[3 m] scratch, partials: scan_partials_size(m).
 hipError_t launch_fill_slots(int64_t m, const int64_t *he_ptr, const int64_t *slot_base,

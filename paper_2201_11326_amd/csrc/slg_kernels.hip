@@ -415,7 +415,8 @@ __device__ __forceinline__ void plan_finish(const Pruned &g, int64_t i, int64_t 
 // appends ceil(size / kPlanPiece) entries (row | piece << 32), one row's
 // pieces side by side.
 __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min, int32_t light_max,
-                                                       int64_t slot_work, RowPlanOut o,
+                                                       int64_t slot_work, int64_t row_lo, int64_t row_hi,
+                                                       RowPlanOut o,
                                                        unsigned long long *__restrict__ class_count,
                                                        int *__restrict__ err,
                                                        unsigned long long *__restrict__ heavy_work,
@@ -438,7 +439,8 @@ __global__ __launch_bounds__(256) void row_plan_kernel(Pruned g, int32_t s_min, 
                 plan_finish(g, i, p0, p1, 0, -1, true, light_max, slot_work, o, ccount, &hwork, err);
             } else {
                 const int64_t size = p1 - p0;
-                const bool kept = size > 0 && size >= (g.row_s ? g.row_s[i] : s_min);
+                // rows outside [row_lo, row_hi) are planned as pruned ones
+                const bool kept = size > 0 && size >= (g.row_s ? g.row_s[i] : s_min) && i >= row_lo && i < row_hi;
                 if (kept && size > kWaveRow) {
                     np = (unsigned long long)((size + kPlanPiece - 1) / kPlanPiece);
                 } else if (kept && size > kSmallRow) {
@@ -2635,17 +2637,19 @@ hipError_t launch_vs_cid(int64_t n, int64_t m, int64_t nnz, const int64_t *vs_pt
     return hipGetLastError();
 }
 
-hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t light_max, int64_t slot_work,
-                           int32_t dense_ratio, int32_t dense_min, int32_t *tail_beg, int64_t *work, int32_t *jmax,
-                           int32_t *nslots, uint8_t *rclass, int64_t *bsize, unsigned long long *class_count,
-                           int *err, unsigned long long *heavy_work, unsigned long long *dense_work, int64_t *pieces,
-                           unsigned long long *num_pieces, hipStream_t st) {
+hipError_t launch_row_plan(const Pruned &g, int32_t s_min, int32_t light_max, int64_t slot_work, int64_t row_lo,
+                           int64_t row_hi, int32_t dense_ratio, int32_t dense_min, int32_t *tail_beg, int64_t *work,
+                           int32_t *jmax, int32_t *nslots, uint8_t *rclass, int64_t *bsize,
+                           unsigned long long *class_count, int *err, unsigned long long *heavy_work,
+                           unsigned long long *dense_work, int64_t *pieces, unsigned long long *num_pieces,
+                           hipStream_t st) {
     if (g.m <= 0) return hipSuccess;
     if (light_max <= 0 || light_max > kLightMax) light_max = kLightMax;
     if (slot_work <= 0) slot_work = kSlotWork;
     if (!g.cid) dense_ratio = 0;
     const RowPlanOut o{tail_beg, work, jmax, nslots, rclass, bsize, dense_ratio, dense_min, dense_work};
-    row_plan_kernel<<<wave_grid((g.m + 63) / 64, 4, 8192), 256, 0, st>>>(g, s_min, light_max, slot_work, o,
+    row_plan_kernel<<<wave_grid((g.m + 63) / 64, 4, 8192), 256, 0, st>>>(g, s_min, light_max, slot_work, row_lo,
+                                                                          row_hi, o,
                                                                           class_count, err, heavy_work, pieces,
                                                                           plan_pieces_cap(g.nnz), num_pieces);
     // the piece count is known on the device only: grids for the bound
