@@ -840,6 +840,8 @@ def bench_large_skewed(args) -> int:
                 "algorithmic_bytes_per_launch": dense_bytes / max(launches, 1),
                 "overhead_bytes_per_launch": {"dense_store_written": 4 * work["dense_stored"] / max(launches, 1)},
                 "sq_counters": measured_sq("dense_kernel<false>", DENSE_SQ_PROFILE),
+                "note": "window-major order serves most of the 2-paths' bytes from L2, so the algorithmic "
+                        "bytes can exceed what HBM delivers; `traffic` is the measured HBM bytes per launch",
                 "emit": {"kernel": "heavy_store_emit_kernel<4, true> (emit_dense)",
                          "launches": emit_launches, "ms": emit_ms,
                          "algorithmic_bytes": 12 * work["dense_edges"],
