@@ -1,5 +1,6 @@
 // Served form: a request loop with memory-budget admission and several
-// queries in flight on their own streams (continuous batching).
+// queries in flight, each on its own slot's stream (queries are not merged
+// into shared launches).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
