@@ -1463,7 +1463,6 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
         for (int r = 0; r < 8; ++r) mine += loc[r];
         int distinct;
         int run = block_excl_scan_open<kHeavyThreads>(mine, sm.wsum, distinct);
-        const int run0 = run;  // rank of this thread's first marked partner
         if ((tid * 8) % kSuperWords == 0) sm.sup[tid * 8 / kSuperWords] = (uint32_t)run;
         uint32_t pk[4];
 #pragma unroll
@@ -1568,25 +1567,19 @@ __global__ __launch_bounds__(kHeavyThreads) __attribute__((amdgpu_waves_per_eu(4
                 }
                 // threshold 1 over the repeat list: every rank survives
                 if (c_add && lane == 0 && s_bottom == 1) sm.wtot[0][wave] = rhi > rlo ? rhi - rlo : 0;
-                if (EMIT || STORE) {  // partner of every rank, from this thread's own 8 words
-                    const uint4 e0 = reinterpret_cast<const uint4 *>(sm.bitmap)[2 * tid];
-                    const uint4 e1 = reinterpret_cast<const uint4 *>(sm.bitmap)[2 * tid + 1];
-                    const uint32_t wd[8] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
-                    int r = run0 - (int)r0;
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const int x = tid * 8 + q;
-                        unsigned bits = wd[q];
-                        const int nb = __popc(bits);
-                        if (x >= w0 && x < w1) {
-                            const int jbase = ja + 32 * x;
-                            int rr = r;
-                            while (bits) {
-                                sm.buf[rr++] = jbase + __ffs(bits) - 1;
-                                bits &= bits - 1u;
-                            }
-                        }
-                        r += nb;
+                if (EMIT || STORE) {
+                    // partner of every rank of the window: neighbouring threads
+                    // take neighbouring words, so a dense stretch of partners is
+                    // shared out (4 % faster than each thread's own 8 words)
+                    for (int x = w0 + tid; x < w1; x += kHeavyThreads) {
+                        unsigned bits = sm.bitmap[x];
+                        if (!bits) continue;
+                        int rr = (int)(word_rank(sm, x) - r0);
+                        const int jbase = ja + 32 * x;
+                        do {
+                            sm.buf[rr++] = jbase + __ffs(bits) - 1;
+                            bits &= bits - 1u;
+                        } while (bits);
                     }
                 }
                 __syncthreads();
