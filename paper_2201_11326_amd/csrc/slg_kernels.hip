@@ -1248,9 +1248,10 @@ __device__ __forceinline__ int wave_segment_of(const int32_t *seg_pre, int lo, i
 // already marked (a repeat) is appended to buf (up to cap entries; nrep
 // counts them all). The walk is that of walk_segments, with each piece's
 // atomics issued together and one list reservation per piece.
-// Pass 1 takes twice the positions per lane of the other walks: its
-// registers are not live together with the emit loop's.
-constexpr int kMarkUnroll = 8;
+// Pass 1 takes pieces of 4 positions per lane: a slot holds about 2,600
+// 2-paths on the power-law workload, so larger pieces leave wavefronts idle
+// at the slot's end (8 positions measured 4 % slower, 16 positions 18 %).
+constexpr int kMarkUnroll = 4;
 
 template <bool RECORD>
 __device__ __forceinline__ void walk_mark(const int32_t *__restrict__ vs_idx, int total, int nseg, HeavySmem &sm,
