@@ -1936,6 +1936,7 @@ struct DenseSmem {
     long long base;                      // store room of the slot (or -1)
     long long chunk_at, chunk_end;       // the workgroup's store room not yet handed out
     int64_t next[2];                     // tickets claimed ahead, by slot parity
+    int32_t tn;                          // the following slot's position in the descriptor list
 };
 
 // Exclusive scan over the dense workgroup. wsum is read after the scan's
@@ -2098,6 +2099,10 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
             len = b > a ? b - a : 0;
         }
     };
+    // zero, in a form the compiler treats as varying by lane: a load indexed
+    // with it is a vector load (waited for with the vector loads, not with
+    // every LDS access as a scalar load would be)
+    const int64_t lane_zero = (int64_t)lane * (count >> 62);
     int64_t tk = uniform((long long)sm.next[0]);
     if (tid == 0) sm.next[1] = (int64_t)atomicAdd(ticket, 1ull);  // the following slot
     int par = 1;  // next[par] holds the following slot's ticket
@@ -2114,12 +2119,16 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
         // counters are cleared and its reads of the shared arrays are done
         __syncthreads();
         const int64_t tkn = uniform((long long)sm.next[par]);
-        const int64_t tn = tkn < count ? uniform((long long)slot_of(tkn)) : 0;  // used after the walk
+        // the following slot's position, loaded by one lane now and shared
+        // through LDS after the walk (a scalar load would be waited for at
+        // the walk's first LDS access)
+        int tn_v = 0;
+        if (tid == 0 && tkn < count) tn_v = order ? order[tkn + lane_zero] : (int)tkn;
         const int ja = d.ja, k = d.k;
         bool skip = false;
         if (EMIT) skip = d.slot < sp.slot_lo || d.slot >= sp.slot_hi || (store && as_global(cs.n)[t] >= 0);
         if (tid < SLG_MAX_S) sm.tally[tid] = 0ull;
-        if (!skip) {  // workgroup-uniform
+        if (!skip && k > 0) {  // workgroup-uniform
             // count: every member's part of its tail inside the window
             for (int qb = 0; qb < k; qb += kDenseThreads) {
                 int a = a0, len = len0;
@@ -2140,12 +2149,17 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
                 if (tid == 0) sm.seg_pre[kDenseThreads] = total;
                 __syncthreads();
                 dense_walk(vs_cid, total, k - qb, sm, ja);
+                if (tid == 0) sm.tn = tn_v;
                 __syncthreads();
             }
+        } else {
+            if (tid == 0) sm.tn = tn_v;
+            __syncthreads();
         }
         // the slot after the following one (next[par ^ 1] was read before this slot's first barrier)
         if (tid == 0) sm.next[par ^ 1] = (int64_t)atomicAdd(ticket, 1ull);
         par ^= 1;
+        const int64_t tn = tkn < count ? (int64_t)sm.tn : 0;
         HeavyDesc dn{};
         if (tkn < count) dn = desc[tn];
         int an = 0, lenn = 0;
