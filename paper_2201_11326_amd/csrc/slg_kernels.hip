@@ -2124,7 +2124,7 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
         // the walk's first LDS access)
         int tn_v = 0;
         if (tid == 0 && tkn < count) tn_v = order ? order[tkn + lane_zero] : (int)tkn;
-        const int ja = d.ja, k = d.k;
+        const int ja = uniform(d.ja), k = uniform(d.k);
         bool skip = false;
         if (EMIT) skip = d.slot < sp.slot_lo || d.slot >= sp.slot_hi || (store && as_global(cs.n)[t] >= 0);
         if (tid < SLG_MAX_S) sm.tally[tid] = 0ull;
@@ -2161,7 +2161,7 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
         par ^= 1;
         const int64_t tn = tkn < count ? (int64_t)sm.tn : 0;
         HeavyDesc dn{};
-        if (tkn < count) dn = desc[tn];
+        if (tkn < count) dn = desc[tn + lane_zero];  // vector loads: waited for at the next slot's start
         int an = 0, lenn = 0;
         // this thread's counters: positions [tid * 32, tid * 32 + 32), read
         // 16 bytes at a time; `f(position, count)` sees each in order, and
