@@ -893,7 +893,7 @@ def main() -> int:
                          "loop; components: components, squeezing and symmetric CSR of the power-law L_s; "
                          "preprocess: relabel-by-degree and toplexes of the power-law hypergraph")
     ap.add_argument("--dense-ratio", type=int, default=None,
-                    help="large_skewed: the dense tier's 2-paths per candidate partner (default: the library's)")
+                    help="large_skewed: the dense tier's 2-paths per eight candidate partners (default: the library's)")
     ap.add_argument("--store-gib", type=float, default=LARGE_STORE_GIB,
                     help="large_skewed: count-store limit of the context in GiB; half of it is the dense "
                          "store whose room cuts the row blocks (the library's default: 32)")

@@ -329,11 +329,12 @@ slg_status slg_context_set_count_store(slg_context *ctx, int64_t max_bytes, int6
  * Dense tier (an implementation choice, not in the paper): a heavy row whose
  * candidate partners (the hyperedges of E_{s_min} with ids in (i, j_max])
  * number at least min_range, and which has at least min_ratio 2-paths per
- * candidate, counts its overlaps in direct counters over windows of 2^14
- * consecutive hyperedges of E_{s_min}, and keeps only the partners that
- * reach s_min for the emit pass (within the count-store limit; slots that
- * find it full walk their 2-paths again). min_ratio = 0 turns the tier off;
- * min_range = 0 restores its default. Defaults: 2 and 8192. Results are
+ * eight candidates (min_ratio / 8 per candidate), counts its overlaps in
+ * direct counters over windows of 2^14 consecutive hyperedges of E_{s_min},
+ * and keeps only the partners that reach s_min for the emit pass (within
+ * the count-store limit; slots that find it full walk their 2-paths again).
+ * min_ratio = 0 turns the tier off; min_range = 0 restores its default.
+ * Defaults: 4 (half a 2-path per candidate) and 8192. Results are
  * identical either way. Applies to plans created afterwards.
  */
 slg_status slg_context_set_dense(slg_context *ctx, int32_t min_ratio, int32_t min_range);

@@ -343,8 +343,9 @@ class Context:
     def set_tuning(self, light_max: int = 0, slot_work: int = 0, heavy_grid: int = 0):
         self._check(lib().slg_context_set_tuning(self.handle, light_max, slot_work, heavy_grid))
 
-    def set_dense(self, min_ratio: int = 2, min_range: int = 0):
-        """The dense tier's rule (min_ratio 0 turns it off; min_range 0 = its
+    def set_dense(self, min_ratio: int = 4, min_range: int = 0):
+        """The dense tier's rule: at least min_ratio 2-paths per eight candidate
+        partners (0 turns it off) and at least min_range candidates (0 = its
         default); results are identical either way."""
         self._check(lib().slg_context_set_dense(self.handle, int(min_ratio), int(min_range)))
 

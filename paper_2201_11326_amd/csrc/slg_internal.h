@@ -26,7 +26,7 @@ constexpr int kWideMembers = 65535;    // rows this large need u32 overlap count
 constexpr int kDenseBits = 14;
 constexpr int kDenseWindow = 1 << kDenseBits;  // E_s positions per dense slot (u32 counters, 64 KB)
 constexpr int kDenseThreads = 512;            // workgroup of the dense tier (2 per CU)
-constexpr int kDenseRatio = 2;                // default: 2-paths per candidate partner to go dense
+constexpr int kDenseRatio = 4;                // default: 2-paths per 8 candidate partners to go dense
 constexpr int kDenseMinRange = 8192;          // default: fewest candidate partners to go dense
 constexpr int kDensePad = 1024;  // entries past the end of the E_s-position lists the dense walk may load
 constexpr long long kDenseChunk = 1 << 16;  // dense-store entries a workgroup takes at a time

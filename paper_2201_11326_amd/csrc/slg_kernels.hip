@@ -370,7 +370,7 @@ __device__ __forceinline__ bool plan_member(const Pruned &g, int64_t i, int64_t 
 // Tier, slot count and boundary-table size of row i from its totals. A
 // heavy row goes to the dense tier when its candidate partners (the kept
 // rows in (i, jm]) number at least dense_min and it has at least
-// dense_ratio 2-paths per candidate: its slots are then the aligned
+// dense_ratio 2-paths per eight candidates: its slots are then the aligned
 // kDenseWindow windows of E_s positions that (i, jm] touches.
 __device__ __forceinline__ void plan_finish(const Pruned &g, int64_t i, int64_t p0, int64_t p1, int64_t w, int jm,
                                             bool bad, int32_t light_max, int64_t slot_work, const RowPlanOut &o,
@@ -389,7 +389,7 @@ __device__ __forceinline__ void plan_finish(const Pruned &g, int64_t i, int64_t 
         if (w <= light_max) {
             cls = kLight0 + light_class(w);
             ns = 1;
-        } else if (ci >= 0 && cj > ci && crange >= o.dense_min && w >= (int64_t)o.dense_ratio * crange) {
+        } else if (ci >= 0 && cj > ci && crange >= o.dense_min && 8 * w >= (int64_t)o.dense_ratio * crange) {
             cls = kDense;
             ns = (cj >> kDenseBits) - ((ci + 1) >> kDenseBits) + 1;
         } else {

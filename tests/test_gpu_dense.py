@@ -34,7 +34,7 @@ def skewed():
 def test_dense_forced_small_graph_matches_oracle():
     """Rows sharing vertex 0 (every other row), all on the dense tier."""
     inc = planted(6000, 20000, [([0], 2, 0), ([1, 2], 3, 1)], 3, seed=17)
-    ctx = _ctx((1, 1))
+    ctx = _ctx((8, 1))
     g = ctx.register_incidence(inc)
     p = ctx.plan(g, [1, 2, 3])
     st = p.stats()
@@ -53,7 +53,7 @@ def test_dense_store_overflow_matches_oracle():
     """A dense store with room for about a third of the survivors: the slots
     that find it full write their edges by walking their 2-paths again."""
     inc = planted(6000, 20000, [([0], 2, 0), ([1, 2], 3, 1)], 3, seed=18)
-    probe = _ctx((1, 1), store_min=1 << 62)  # heavy and light stores off, the dense one on
+    probe = _ctx((8, 1), store_min=1 << 62)  # heavy and light stores off, the dense one on
     g = probe.register_incidence(inc)
     p = probe.plan(g, [1, 2])
     st = p.stats()
@@ -62,7 +62,7 @@ def test_dense_store_overflow_matches_oracle():
     probe.close()
     assert st["dense_slots"] > 0 and st["dense_stored"] > 30, st
     limit = 12 * st["dense_slots"] + 16 + 4 * (st["dense_stored"] // 3)
-    ctx = _ctx((1, 1), store_limit=limit, store_min=1 << 62)
+    ctx = _ctx((8, 1), store_limit=limit, store_min=1 << 62)
     g = ctx.register_incidence(inc)
     p = ctx.plan(g, [1, 2])
     assert p.stats()["dense_store_full"] == 1

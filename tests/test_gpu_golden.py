@@ -50,7 +50,7 @@ def _ctx(dense=None):
     return c
 
 
-@pytest.mark.parametrize("dense", [None, (1, 1)], ids=["own_tiers", "dense_forced"])
+@pytest.mark.parametrize("dense", [None, (8, 1)], ids=["own_tiers", "dense_forced"])
 def test_power_law_every_edge_by_block_digest(dense):
     rows, two_paths = _read("power_law_block_digests.txt")
     S = [1, 2, 4, 8]

@@ -13,7 +13,7 @@ from gpu_util import assert_matches_oracle, planted
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("dense", [(0, 0), (1, 1)], ids=["bitmap_tier", "dense_tier"])
+@pytest.mark.parametrize("dense", [(0, 0), (8, 1)], ids=["bitmap_tier", "dense_tier"])
 def test_refused_append_fails_cleanly_and_context_recovers(dense):
     import paper_2201_11326_amd as slg
     inc = planted(6000, 20000, [([0], 1, 0)], 3, seed=17)  # vertex 0 in every row: heavy rows

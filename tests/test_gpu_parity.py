@@ -28,7 +28,7 @@ def ctx(request):
     else:  # the stores on every graph with heavy or dense slots, however small
         c.set_count_store(32 << 30, 0)
     if request.param.startswith("dense"):
-        c.set_dense(1, 1)
+        c.set_dense(8, 1)
     c.store_mode = "rewalk" if request.param.endswith("rewalk") else "store"
     c.dense_mode = request.param.startswith("dense")
     yield c

@@ -21,7 +21,7 @@ def contexts():
     store.set_count_store(32 << 30, 0)  # the store wherever there are heavy slots
     rewalk.set_count_store(0)
     dense.set_count_store(32 << 30, 0)
-    dense.set_dense(1, 1)  # every heavy row with a 2-path per candidate on the dense tier
+    dense.set_dense(8, 1)  # every heavy row with a 2-path per candidate on the dense tier
     yield {"store": store, "rewalk": rewalk, "dense": dense}
     store.close()
     rewalk.close()
