@@ -305,6 +305,7 @@ struct PlanBufs {
     uint8_t *keep = nullptr;     // E_s positions (dense tier): kept-row flags,
     int64_t *kpre = nullptr;     // their exclusive scan,
     int32_t *cid = nullptr, *cid_row = nullptr, *vs_cid = nullptr;  // ranks, rows of ranks, lists in ranks
+    uint16_t *vs_win = nullptr;  // the lists' ranks modulo the dense window
 };
 
 struct slg_plan {
@@ -615,7 +616,7 @@ hipError_t enqueue_rows(slg_plan *p, hipStream_t st) {
         if ((e = launch_row_keep(m, inc.he_ptr, p->s_min, p->pr.row_s, b.keep, st)) != hipSuccess) return e;
         if ((e = launch_exclusive_scan_u8(b.keep, m, b.kpre, b.part_m, st)) != hipSuccess) return e;
         if ((e = launch_cid(m, b.keep, b.kpre, b.cid, b.cid_row, st)) != hipSuccess) return e;
-        if ((e = launch_vs_cid(n, m, nnz, p->pr.vs_ptr, p->pr.vs_idx, b.cid, b.vs_cid, st)) != hipSuccess) return e;
+        if ((e = launch_vs_cid(n, m, nnz, p->pr.vs_ptr, p->pr.vs_idx, b.cid, b.vs_cid, b.vs_win, st)) != hipSuccess) return e;
     }
     {
         StageTimer tm(ctx, kStRowPlan, st);
@@ -851,7 +852,8 @@ slg_status plan_rows(slg_plan *p) {
         phase1.add(&b.kpre, m + 1);
         phase1.add(&b.cid, m);
         phase1.add(&b.cid_row, m);
-        phase1.add(&b.vs_cid, nnz + kDensePad);  // the dense walk may load (not count) past the end
+        phase1.add(&b.vs_cid, nnz + kDensePad);
+        phase1.add(&b.vs_win, nnz + kDensePad);  // the dense walk may load (not count) past the end
     }
     if (p->blocks) {
         phase1.add(&b.nslots_all, m);
@@ -878,6 +880,7 @@ slg_status plan_rows(slg_plan *p) {
     pr.cid = b.cid;
     pr.cid_row = b.cid_row;
     pr.vs_cid = b.vs_cid;
+    pr.vs_win = b.vs_win;
     BUILD_HIP(enqueue_rows(p, st));
     if (p->blocks && m > 0) {
         BUILD_HIP(hipMemcpyAsync(b.nslots_all, b.nslots, m * sizeof(int32_t), hipMemcpyDeviceToDevice, st));

@@ -70,10 +70,13 @@ struct Pruned {
     // E_s positions (the dense tier; null when the plan has none): cid[i] =
     // rank of row i among the kept rows (-1 if pruned), cid_row[c] = the row
     // of rank c, and vs_cid = vs_idx with every id replaced by its rank
-    // (ranks keep the id order, so the lists stay sorted).
+    // (ranks keep the id order, so the lists stay sorted). vs_win = vs_cid
+    // modulo kDenseWindow: a rank's place in its (aligned) window, all that
+    // the dense walk needs, in half the bytes.
     const int32_t *cid;
     const int32_t *cid_row;
     const int32_t *vs_cid;
+    const uint16_t *vs_win;
 };
 
 // Slot table: a slot is (row i, hyperedge-id range) with its own output
@@ -142,14 +145,14 @@ hipError_t launch_compact_vertex_lists(int64_t n, int64_t nnz, const int64_t *v_
                                        hipStream_t st);
 
 // E_s positions: flag[i] = row i kept at s_min (or its own threshold), pre =
-// its exclusive scan (int64[m+1]), then cid / cid_row, and vs_cid over the
-// pruned lists (vs_ptr[n] entries).
+// its exclusive scan (int64[m+1]), then cid / cid_row, and vs_cid and vs_win
+// over the pruned lists (vs_ptr[n] entries).
 hipError_t launch_row_keep(int64_t m, const int64_t *he_ptr, int32_t s_min, const int32_t *row_s, uint8_t *flag,
                            hipStream_t st);
 hipError_t launch_cid(int64_t m, const uint8_t *flag, const int64_t *pre, int32_t *cid, int32_t *cid_row,
                       hipStream_t st);
 hipError_t launch_vs_cid(int64_t n, int64_t m, int64_t nnz, const int64_t *vs_ptr, const int32_t *vs_idx,
-                         const int32_t *cid, int32_t *vs_cid, hipStream_t st);
+                         const int32_t *cid, int32_t *vs_cid, uint16_t *vs_win, hipStream_t st);
 
 // K1/K2: per kept row, tail offsets, 2-path work, last partner, slot count.
 // dense_ratio = 0 keeps every row off the dense tier (then g.cid may be

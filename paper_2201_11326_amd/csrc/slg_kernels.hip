@@ -298,16 +298,19 @@ __global__ void cid_kernel(int64_t m, const uint8_t *__restrict__ flag, const in
 }
 
 // An id outside [0, m) (a malformed vertex CSR, which the row plan flags)
-// gets -1, which no window holds.
+// gets -1, which no window holds. vs_win keeps the low kDenseBits bits of
+// each rank: windows are aligned, so that is the rank's place in its window.
 __global__ void vs_cid_kernel(int64_t n, int64_t m, int64_t cap, const int64_t *__restrict__ vs_ptr,
                               const int32_t *__restrict__ vs_idx, const int32_t *__restrict__ cid,
-                              int32_t *__restrict__ vs_cid) {
+                              int32_t *__restrict__ vs_cid, uint16_t *__restrict__ vs_win) {
     int64_t total = vs_ptr[n];
     if (total > cap) total = cap;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < total; p += stride) {
         const int32_t r = vs_idx[p];
-        vs_cid[p] = (r >= 0 && r < m) ? cid[r] : -1;
+        const int32_t c = (r >= 0 && r < m) ? cid[r] : -1;
+        vs_cid[p] = c;
+        vs_win[p] = (uint16_t)(c & (kDenseWindow - 1));
     }
 }
 
@@ -1913,22 +1916,25 @@ __global__ __launch_bounds__(256) void bounds_kernel(
 // A dense slot is a row i and an aligned window [ja, ja + kDenseWindow) of
 // E_s positions; its 2-paths are the parts of its members' tails that fall
 // in the window (vertex lists in E_s positions, so the counter of partner c
-// is c - ja with no search). One u32 counter per position: the byte address
-// of partner c's counter is 4c - 4ja, one shift-add, so that a 2-path costs
-// one load, two vector instructions and one LDS add. A row of fewer than
+// is c - ja with no search). One u32 counter per position. The walk reads
+// the lists as 16-bit places in the window (c - ja = c mod kDenseWindow,
+// since windows are aligned): 2 bytes per 2-path instead of 4 (6.5 % off
+// the counting pass), and the counter's byte address is one shift, so a
+// 2-path costs one load, one shift and one LDS add.
+// A row of fewer than
 // 2^16 members cannot reach 2^16 in a counter (the store keeps 16 bits).
 constexpr int kDW = kDenseThreads / 64;                       // wavefronts per dense workgroup
 constexpr int kDenseWordsPer = kDenseWindow / kDenseThreads;  // counters per thread (32)
 constexpr int kDenseUnroll = 16;                              // loads in flight per lane
 constexpr int kDensePiece = 64 * kDenseUnroll;                // 2-paths per wavefront step
-// vs_cid is allocated kDensePad entries longer: a step inside one tail
+// vs_win is allocated kDensePad entries longer: a step inside one tail
 // loads whole rows past the tail's end (those values are not counted)
 static_assert(kDensePad >= kDensePiece, "padding of the E_s-position lists");
 static_assert(kDenseWordsPer % 4 == 0, "16-byte LDS accesses");
 static_assert(kWideMembers < (1 << 16), "16-bit overlaps in the dense store");
 
 struct DenseSmem {
-    uint32_t cnt[kDenseWindow + 4];      // counters; cnt[kDenseWindow] takes out-of-window adds (none arise)
+    uint32_t cnt[kDenseWindow + 4];      // counters (4 more words keep the layout's 16-byte steps)
     int32_t seg_a[kDenseThreads];        // segment start per member of the batch
     int32_t seg_pre[kDenseThreads + 1];  // flattened start per member of the batch
     int32_t wsum[2][kDW];                // wavefront totals of a scan (two, used in turn)
@@ -1964,7 +1970,8 @@ __device__ __forceinline__ void dense_add(DenseSmem &sm, uint32_t a) {
 }
 
 // Walks the laid-out segments (2-path f of the batch is member u's tail
-// position seg_a[u] + f - seg_pre[u]) and adds one to the counter of each
+// position seg_a[u] + f - seg_pre[u], whose place in the window is
+// vs_win[that position]) and adds one to the counter of each
 // partner. Each wavefront takes an equal share of the flattened list, in
 // steps of kDensePiece positions whose loads are all issued first. The
 // wavefront keeps its current tail (start and end) in scalar registers: a
@@ -1973,8 +1980,8 @@ __device__ __forceinline__ void dense_add(DenseSmem &sm, uint32_t a) {
 // no LDS lookup; a step across tails finds each position's tail by binary
 // search. (Keeping the next step's loads in flight while adding the
 // current one's measured the same: the walk is not bound by load latency.)
-__device__ __forceinline__ void dense_walk(const int32_t *__restrict__ vs_cid, int total, int nseg, DenseSmem &sm,
-                                           int ja) {
+__device__ __forceinline__ void dense_walk(const uint16_t *__restrict__ vs_win, int total, int nseg,
+                                           DenseSmem &sm) {
     if (total <= 0) return;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     const int per = (total + kDW - 1) / kDW;
@@ -1982,10 +1989,8 @@ __device__ __forceinline__ void dense_walk(const int32_t *__restrict__ vs_cid, i
     const int c1 = min(total, c0 + per);
     if (c0 >= c1) return;
     const int useg = min(nseg, kDenseThreads) - 1;
-    const uint32_t nja4 = 0u - 4u * (uint32_t)ja;
-    constexpr uint32_t kStray = 4u * kDenseWindow;
     // tail u covers flattened positions [seg_pre[u], uend); position f of it
-    // is vs_cid[ubase + f]
+    // is vs_win[ubase + f]
     int u = wave_segment_of(sm.seg_pre, 0, useg, c0);
     int uend = uniform(sm.seg_pre[u + 1]);
     int ubase = uniform(sm.seg_a[u] - sm.seg_pre[u]);
@@ -1994,11 +1999,11 @@ __device__ __forceinline__ void dense_walk(const int32_t *__restrict__ vs_cid, i
         const int last = min(c1, b + kDensePiece) - 1;
         if (last == b + kDensePiece - 1) {  // wave-uniform: every position of the step counts
 #pragma unroll
-            for (int r = 0; r < kDenseUnroll; ++r) dense_add(sm, min((uint32_t)c[r] * 4u + nja4, kStray));
+            for (int r = 0; r < kDenseUnroll; ++r) dense_add(sm, (uint32_t)c[r] * 4u);
         } else {
 #pragma unroll
             for (int r = 0; r < kDenseUnroll; ++r)
-                if (b + lane + 64 * r <= last) dense_add(sm, min((uint32_t)c[r] * 4u + nja4, kStray));
+                if (b + lane + 64 * r <= last) dense_add(sm, (uint32_t)c[r] * 4u);
         }
     };
     int pb = c0;
@@ -2011,7 +2016,7 @@ __device__ __forceinline__ void dense_walk(const int32_t *__restrict__ vs_cid, i
         const int plast = min(c1, pb + kDensePiece) - 1;
         if (plast < uend) {
             // a step inside tail u
-            const int32_t *src = vs_cid + ((int64_t)ubase + lane);
+            const uint16_t *src = vs_win + ((int64_t)ubase + lane);
             int ca[kDenseUnroll];
 #pragma unroll
             for (int r = 0; r < kDenseUnroll; ++r) ca[r] = src[pb + 64 * r];
@@ -2038,10 +2043,10 @@ __device__ __forceinline__ void dense_walk(const int32_t *__restrict__ vs_cid, i
                     len -= half;
                 }
 #pragma unroll
-                for (int r = 0; r < kHalf; ++r) c[r] = vs_cid[sm.seg_a[uq[r]] + (fq[r] - sm.seg_pre[uq[r]])];
+                for (int r = 0; r < kHalf; ++r) c[r] = vs_win[sm.seg_a[uq[r]] + (fq[r] - sm.seg_pre[uq[r]])];
 #pragma unroll
                 for (int r = 0; r < kHalf; ++r)
-                    if (hb + lane + 64 * r <= plast) dense_add(sm, min((uint32_t)c[r] * 4u + nja4, kStray));
+                    if (hb + lane + 64 * r <= plast) dense_add(sm, (uint32_t)c[r] * 4u);
             }
             u = ulast;
             uend = uniform(sm.seg_pre[u + 1]);
@@ -2067,7 +2072,7 @@ template <bool EMIT>
 __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4))) void dense_kernel(const HeavyDesc *__restrict__ desc, int64_t count,
                                                               const int32_t *__restrict__ order,
                                                               int64_t S, const int32_t *__restrict__ bounds,
-                                                              const int32_t *__restrict__ vs_cid,
+                                                              const uint16_t *__restrict__ vs_win,
                                                               const int32_t *__restrict__ cid_row, EmitParams prm,
                                                               int64_t *__restrict__ slot_cnt,
                                                               const int64_t *__restrict__ slot_off,
@@ -2148,7 +2153,7 @@ __global__ __launch_bounds__(kDenseThreads) __attribute__((amdgpu_waves_per_eu(4
                 sm.seg_pre[tid] = excl;
                 if (tid == 0) sm.seg_pre[kDenseThreads] = total;
                 __syncthreads();
-                dense_walk(vs_cid, total, k - qb, sm, ja);
+                dense_walk(vs_win, total, k - qb, sm);
                 if (tid == 0) sm.tn = tn_v;
                 __syncthreads();
             }
@@ -2639,9 +2644,9 @@ hipError_t launch_cid(int64_t m, const uint8_t *flag, const int64_t *pre, int32_
 }
 
 hipError_t launch_vs_cid(int64_t n, int64_t m, int64_t nnz, const int64_t *vs_ptr, const int32_t *vs_idx,
-                         const int32_t *cid, int32_t *vs_cid, hipStream_t st) {
+                         const int32_t *cid, int32_t *vs_cid, uint16_t *vs_win, hipStream_t st) {
     if (nnz <= 0) return hipSuccess;
-    vs_cid_kernel<<<stride_grid(nnz), 256, 0, st>>>(n, m, nnz, vs_ptr, vs_idx, cid, vs_cid);
+    vs_cid_kernel<<<stride_grid(nnz), 256, 0, st>>>(n, m, nnz, vs_ptr, vs_idx, cid, vs_cid, vs_win);
     return hipGetLastError();
 }
 
@@ -2835,17 +2840,17 @@ hipError_t launch_dense(bool emit, const HeavyDesc *desc, int64_t count, const i
                         const int64_t *slot_off, int64_t *ticket, int resident, const CountStore *store,
                         int64_t *store_cursor, int64_t store_cap, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    if (!g.vs_cid || !g.cid_row || (store && !emit && !store_cursor)) return hipErrorInvalidValue;
+    if (!g.vs_win || !g.cid_row || (store && !emit && !store_cursor)) return hipErrorInvalidValue;
     const int64_t want = resident > 0 ? resident : 512;
     const unsigned grid = (unsigned)(count < want ? count : want);
     unsigned long long *tk = reinterpret_cast<unsigned long long *>(ticket);
     unsigned long long *cur = reinterpret_cast<unsigned long long *>(store_cursor);
     const CountStore cs = store ? *store : CountStore{};
     if (emit)
-        dense_kernel<true><<<grid, kDenseThreads, 0, st>>>(desc, count, order, slots, bounds, g.vs_cid, g.cid_row, ep,
+        dense_kernel<true><<<grid, kDenseThreads, 0, st>>>(desc, count, order, slots, bounds, g.vs_win, g.cid_row, ep,
                                                             slot_cnt, slot_off, tk, cs, cur, store_cap);
     else
-        dense_kernel<false><<<grid, kDenseThreads, 0, st>>>(desc, count, order, slots, bounds, g.vs_cid, g.cid_row, ep,
+        dense_kernel<false><<<grid, kDenseThreads, 0, st>>>(desc, count, order, slots, bounds, g.vs_win, g.cid_row, ep,
                                                              slot_cnt, slot_off, tk, cs, cur, store_cap);
     return hipGetLastError();
 }
