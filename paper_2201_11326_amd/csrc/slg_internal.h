@@ -21,7 +21,7 @@ constexpr int kRankCap = 4096;         // overlap counters per rank window (LDS,
 constexpr int64_t kSlotWork = 4096;    // 2-paths per heavy slot before a row is split
 constexpr int kWideMembers = 65535;    // rows this large need u32 overlap counters
 // Dense tier: a row whose partners fill most of E_s (at least dense_ratio
-// 2-paths per candidate partner) counts into direct LDS counters over
+// 2-paths per eight candidate partners) counts into direct LDS counters over
 // aligned windows of kDenseWindow consecutive E_s positions.
 constexpr int kDenseBits = 14;
 constexpr int kDenseWindow = 1 << kDenseBits;  // E_s positions per dense slot (u32 counters, 64 KB)

@@ -1920,8 +1920,7 @@ __global__ __launch_bounds__(256) void bounds_kernel(
 // the lists as 16-bit places in the window (c - ja = c mod kDenseWindow,
 // since windows are aligned): 2 bytes per 2-path instead of 4 (6.5 % off
 // the counting pass), and the counter's byte address is one shift, so a
-// 2-path costs one load, one shift and one LDS add.
-// A row of fewer than
+// 2-path costs one load, one shift and one LDS add. A row of fewer than
 // 2^16 members cannot reach 2^16 in a counter (the store keeps 16 bits).
 constexpr int kDW = kDenseThreads / 64;                       // wavefronts per dense workgroup
 constexpr int kDenseWordsPer = kDenseWindow / kDenseThreads;  // counters per thread (32)
@@ -1934,7 +1933,7 @@ static_assert(kDenseWordsPer % 4 == 0, "16-byte LDS accesses");
 static_assert(kWideMembers < (1 << 16), "16-bit overlaps in the dense store");
 
 struct DenseSmem {
-    uint32_t cnt[kDenseWindow + 4];      // counters (4 more words keep the layout's 16-byte steps)
+    uint32_t cnt[kDenseWindow + 4];      // counters (and 4 spare words)
     int32_t seg_a[kDenseThreads];        // segment start per member of the batch
     int32_t seg_pre[kDenseThreads + 1];  // flattened start per member of the batch
     int32_t wsum[2][kDW];                // wavefront totals of a scan (two, used in turn)
