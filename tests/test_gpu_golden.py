@@ -57,6 +57,13 @@ def test_power_law_every_edge_by_block_digest(dense):
     inc = hg.power_law()
     ctx = _ctx(dense)
     g = ctx.register_incidence(inc)
+    p = ctx.plan(g, S)
+    st = p.stats()
+    p.destroy()
+    # the library's own rule mixes tiers in one plan: the rows with at least
+    # half a 2-path per candidate on the dense tier, the other heavy rows on
+    # the bitmap tier
+    assert st["dense_slots"] > 0 and (dense is not None or st["heavy_slots"] > 0), st
     outs = ctx.line_graph(g, S)
     assert outs[0].two_paths == two_paths[1] == oracle.two_paths(inc, 1)
     rp = {lg.s: lg.row_ptr.cpu().numpy() for lg in outs}
